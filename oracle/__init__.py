@@ -1,0 +1,19 @@
+"""FP64 CPU oracle of the level-set LLG forward/adjoint path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call this
+package: only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark use it.  It shares no code with the HIP library; the two meet only
+through the seeded input arrays of ``paper_2411_19109_amd.workloads`` (which
+holds no arithmetic of the method).
+
+Plain, slow, obviously-correct NumPy in float64.  Every function accepts
+complex arrays too, so that complex-step differentiation can pin the adjoint
+against the forward map to machine precision.
+
+Modules
+  newell     cell-averaged demagnetisation tensor (Newell closed form near,
+             Gauss-Legendre quadrature of the tent-weighted dipole kernel far)
+  micromag   effective field, LLG right-hand side, RK4, energies
+  adjoint    discrete adjoint of the RK4 map, objectives and gradients
+  levelset   smoothed Heaviside map phi -> psi and its derivative
+"""

@@ -1,0 +1,181 @@
+"""Objectives and the discrete adjoint of the RK4 forward map.
+
+Oracle (test infrastructure only).
+
+The paper obtains dJ/ds from the adjoint system (Eq. 6: forward LLG, adjoint
+state a = dJ/dm integrated backwards from a(T) = dJ/dm(T)) and the gradient
+integral (Eq. 7).  Here the same idea is applied to the *discrete* forward map:
+the adjoint state after step n is lambda_n = dJ/dm_n, propagated backwards
+through the transpose of each RK4 step, and the parameter gradient is the sum
+over steps and stages of the stage adjoints contracted with the parameter
+derivative of the right-hand side.  The result is the exact gradient of the
+discrete objective.
+
+RK4 step transpose, with lambda' = lambda_{n+1} and stage states y_s:
+  l4 = dt/6 lambda'            mu4 = J_f(y4)^T l4
+  l3 = dt/3 lambda' + dt mu4   mu3 = J_f(y3)^T l3
+  l2 = dt/3 lambda' + dt/2 mu3 mu2 = J_f(y2)^T l2
+  l1 = dt/6 lambda' + dt/2 mu2 mu1 = J_f(y1)^T l1
+  lambda_n = lambda' + mu1 + mu2 + mu3 + mu4 (+ dJ/dm_n of a running cost)
+  dJ/dpsi += sum_s l_s . df/dpsi(y_s)
+
+Transpose of f(m) = -g' [m x B + alpha m x (m x B)] applied to v, with
+w = v x m and c = m x B:
+  u  = -g' (w + alpha w x m)                 (adjoint of the field)
+  mu = -g' (B x v + alpha c x v + alpha B x w) + J_B^T u
+and u . dB/dpsi gives the psi-gradient of the stage.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .micromag import MU0, TERM_ANIS, TERM_DEMAG, TERM_EXCH, cross, dot
+
+OBJ_NONE, OBJ_ENERGY_AREA, OBJ_PORT_MY2 = 0, 1, 2
+
+
+class Objective:
+    """kind: OBJ_ENERGY_AREA -> J = (E_ex + E_d)(m_T)/E_ref + lam (mean psi - area)^2
+             OBJ_PORT_MY2    -> J = 1/|W| sum_{n in W} [mean_P1 m_y^2 - mean_P2 m_y^2],
+                                W = {n : n_start < n <= n_steps}."""
+
+    def __init__(self, kind, E_ref=1.0, lam=1.0, area=0.4, n_start=0, port1=None, port2=None):
+        self.kind = kind
+        self.E_ref = E_ref
+        self.lam = lam
+        self.area = area
+        self.n_start = n_start
+        self.port1 = None if port1 is None else np.asarray(port1, float)
+        self.port2 = None if port2 is None else np.asarray(port2, float)
+
+
+# -- objective values and their explicit derivatives --------------------------
+
+def energy_area_value(sim, m, psi, obj):
+    e = sim.energies(m, psi, 0.0, terms=sim.terms & (TERM_EXCH | TERM_DEMAG))
+    return (e["ex"] + e["d"]) / obj.E_ref + obj.lam * (psi.mean() - obj.area) ** 2
+
+
+def energy_area_grad(sim, m, psi, obj):
+    """(dJ/dm, dJ/dpsi) of the energy + area objective, from the energy sums."""
+    p = sim.p
+    V = sim.V
+    gm = np.zeros(m.shape, dtype=np.result_type(m, psi, float))
+    gp = np.zeros(psi.shape, dtype=np.result_type(m, psi, float))
+    if sim.terms & TERM_EXCH:
+        for ax, h, a, b in sim._edges():
+            pa, pb, s, nz = sim._pair(psi, ax, h)
+            dm = m[b] - m[a]
+            coef = np.where(nz, V * p.A * 2.0 * pa * pb / s, 0.0) / (h * h)
+            gm[b] += 2.0 * coef * dm
+            gm[a] -= 2.0 * coef * dm
+            d2 = dot(dm, dm)
+            sl_a = a[1:]
+            sl_b = b[1:]
+            gp[sl_a] += np.where(nz, V * p.A * 2.0 * pb * pb / (s * s), 0.0) * d2 / (h * h)
+            gp[sl_b] += np.where(nz, V * p.A * 2.0 * pa * pa / (s * s), 0.0) * d2 / (h * h)
+    if sim.terms & TERM_DEMAG:
+        conv = sim.demag.conv(psi * m)
+        gm = gm + MU0 * p.Ms ** 2 * V * psi * conv
+        gp = gp + MU0 * p.Ms ** 2 * V * dot(m, conv)
+    gm = gm / obj.E_ref
+    gp = gp / obj.E_ref + 2.0 * obj.lam * (psi.mean() - obj.area) / psi.size
+    return gm, gp
+
+
+def port_value(m, obj):
+    my2 = m[1] * m[1]
+    return (my2 * obj.port1).sum() / obj.port1.sum() - (my2 * obj.port2).sum() / obj.port2.sum()
+
+
+def port_source(m, obj, n_window):
+    g = np.zeros(m.shape, dtype=m.dtype)
+    g[1] = 2.0 * m[1] * (obj.port1 / obj.port1.sum() - obj.port2 / obj.port2.sum()) / n_window
+    return g
+
+
+# -- transpose of one right-hand-side evaluation -------------------------------
+
+def rhs_vjp(sim, m, B, psi, v):
+    """(mu, g_psi): J_f(m)^T v and v . df/dpsi at the state m with field B."""
+    gp_ = sim.gp
+    al = sim.alpha
+    frozen = (psi == 0)
+    w = cross(v, m)
+    c = cross(m, B)
+    u = -gp_ * (w + al * cross(w, m))
+    u = np.where(frozen, 0.0, u)
+    mu = -gp_ * (cross(B, v) + al * cross(c, v) + al * cross(B, w))
+    mu = np.where(frozen, 0.0, mu)
+    g = np.zeros(psi.shape, dtype=np.result_type(m, v, psi, float))
+    if sim.terms & TERM_EXCH:
+        k = sim.kappa
+        for ax, h, a, b in sim._edges():
+            pa, pb, s, nz = sim._pair(psi, ax, h)
+            cab = np.where(nz, 2.0 * pb / (s * h * h), 0.0)
+            cba = np.where(nz, 2.0 * pa / (s * h * h), 0.0)
+            mu[a] += k * (cba * u[b] - cab * u[a])
+            mu[b] += k * (cab * u[a] - cba * u[b])
+            dm = m[b] - m[a]
+            us = dot(u[a] + u[b], dm)
+            sl_a = a[1:]
+            sl_b = b[1:]
+            g[sl_a] += np.where(nz, -k * 2.0 * pb / (s * s * h * h), 0.0) * us
+            g[sl_b] += np.where(nz, k * 2.0 * pa / (s * s * h * h), 0.0) * us
+    if sim.terms & TERM_DEMAG:
+        cu = -MU0 * sim.p.Ms * sim.demag.conv(u)
+        mu = mu + psi * cu
+        g = g + dot(m, cu)
+    if sim.terms & TERM_ANIS:
+        coef = 2.0 * sim.p.K / sim.p.Ms
+        uu = sim.u[:, None, None, None]
+        mu = mu + coef * dot(u, uu) * uu
+    return mu, g
+
+
+# -- forward + objective + adjoint ---------------------------------------------
+
+def objective_value(sim, traj, psi, obj, n_steps):
+    if obj.kind == OBJ_ENERGY_AREA:
+        return energy_area_value(sim, traj[-1], psi, obj)
+    if obj.kind == OBJ_PORT_MY2:
+        win = range(obj.n_start + 1, n_steps + 1)
+        return sum(port_value(traj[n], obj) for n in win) / len(win)
+    return 0.0
+
+
+def forward_objective(sim, m0, psi, n_steps, obj, t0=0.0):
+    """J of the discrete forward map (stores the whole trajectory)."""
+    m, traj = sim.integrate(m0, psi, n_steps, t0=t0, keep=True)
+    return objective_value(sim, traj, psi, obj, n_steps), traj
+
+
+def gradient(sim, m0, psi, n_steps, obj, t0=0.0):
+    """J, dJ/dpsi and dJ/dm0 by the discrete adjoint (store-all trajectory)."""
+    dt = sim.p.dt
+    J, traj = forward_objective(sim, m0, psi, n_steps, obj, t0)
+    n_window = max(1, n_steps - obj.n_start)
+    lam = np.zeros(m0.shape, dtype=np.result_type(m0, psi, float))
+    g_psi = np.zeros(psi.shape, dtype=np.result_type(m0, psi, float))
+    if obj.kind == OBJ_ENERGY_AREA:
+        gm, gp = energy_area_grad(sim, traj[-1], psi, obj)
+        lam = lam + gm
+        g_psi = g_psi + gp
+    if obj.kind == OBJ_PORT_MY2 and n_steps > obj.n_start:
+        lam = lam + port_source(traj[n_steps], obj, n_window)
+    for n in range(n_steps - 1, -1, -1):
+        t = t0 + n * dt
+        _, ys, Bs = sim.rk4_step(traj[n], psi, t)
+        l4 = dt / 6.0 * lam
+        mu4, g4 = rhs_vjp(sim, ys[3], Bs[3], psi, l4)
+        l3 = dt / 3.0 * lam + dt * mu4
+        mu3, g3 = rhs_vjp(sim, ys[2], Bs[2], psi, l3)
+        l2 = dt / 3.0 * lam + 0.5 * dt * mu3
+        mu2, g2 = rhs_vjp(sim, ys[1], Bs[1], psi, l2)
+        l1 = dt / 6.0 * lam + 0.5 * dt * mu2
+        mu1, g1 = rhs_vjp(sim, ys[0], Bs[0], psi, l1)
+        lam = lam + mu1 + mu2 + mu3 + mu4
+        g_psi = g_psi + g1 + g2 + g3 + g4
+        if obj.kind == OBJ_PORT_MY2 and obj.n_start < n <= n_steps:
+            lam = lam + port_source(traj[n], obj, n_window)
+    return J, g_psi, lam

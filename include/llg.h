@@ -1,0 +1,199 @@
+/*
+ * llg.h -- C ABI of the MI355X (gfx950) level-set LLG forward/adjoint library.
+ *
+ * The library integrates the Landau-Lifshitz-Gilbert equation (paper: Methods,
+ * Eq. 11) on a nodal finite-difference grid whose material maps follow a
+ * level-set function through a smoothed Heaviside (Eq. 4 and the paragraph
+ * after it), evaluates an objective of the trajectory, and returns the
+ * gradient of that objective with respect to the material map by an adjoint
+ * integration backwards in time (Eqs. 6-7; here the exact discrete adjoint of
+ * the fixed-step RK4 map, with checkpointing so memory grows like
+ * sqrt(n_steps) rather than n_steps).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: LLG_OK (0) or a negative LLG_E* code.  llg_last_error()
+ *     returns a message for the calling thread's last failure.  Arguments are
+ *     validated on the host before any device work is enqueued; on error no
+ *     work is enqueued and no output is modified.
+ *   - Arrays are caller-owned DEVICE pointers unless stated otherwise.  The
+ *     library never frees them and keeps no reference after the call returns.
+ *     It owns only the workspace inside an llg_handle.
+ *   - Floating-point arrays are in the handle's precision (LLG_F32 -> float,
+ *     LLG_F64 -> double) unless the parameter is declared double*.
+ *   - Layout: node (ix, iy, iz) has flat index ix + nx*(iy + ny*iz) (x fastest).
+ *     Vector fields are component-major: component c of node i at
+ *     c*N + i, N = nx*ny*nz.
+ *   - Work is enqueued asynchronously on the given hipStream_t (0 = the null
+ *     stream); scalar results go to device memory, so no call blocks the host
+ *     except llg_create/llg_destroy.
+ *   - SI units: m, s, A/m, J/m, J/m^3, T, Hz.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LLG_H
+#define LLG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define LLG_OK 0
+#define LLG_EINVAL (-1)     /* invalid argument (null pointer, bad value)          */
+#define LLG_ESHAPE (-2)     /* unsupported or inconsistent grid / FFT size         */
+#define LLG_ENOMEM (-3)     /* device allocation failed or capacity exceeded       */
+#define LLG_EHIP (-4)       /* a HIP runtime call failed                           */
+#define LLG_ENONFINITE (-5) /* non-finite value found where one is checked         */
+#define LLG_ENOTSUP (-6)    /* feature not supported for this configuration        */
+#define LLG_ESTATE (-7)     /* call order violated (e.g. adjoint without forward)  */
+
+/* ---- enums ----------------------------------------------------------- */
+#define LLG_F32 0
+#define LLG_F64 1
+
+/* effective-field terms (bitmask) */
+#define LLG_TERM_EXCH 1   /* exchange: kappa sum_j c_ij (m_j - m_i), harmonic-mean psi weights */
+#define LLG_TERM_DEMAG 2  /* dipole-dipole field by zero-padded FFT convolution with the Newell tensor */
+#define LLG_TERM_ZEEMAN 4 /* uniform bias B0 plus the drive on the antenna mask */
+#define LLG_TERM_ANIS 8   /* uniaxial anisotropy (2 K / Ms)(m.u) u */
+
+/* faces carrying the absorbing damping ramp (bitmask) */
+#define LLG_FACE_XLO 1
+#define LLG_FACE_XHI 2
+#define LLG_FACE_YLO 4
+#define LLG_FACE_YHI 8
+#define LLG_FACE_ZLO 16
+#define LLG_FACE_ZHI 32
+
+/* checkpoint policies of the adjoint */
+#define LLG_CKPT_SQRT 0 /* snapshots every K steps (K = ckpt_param or ceil(sqrt(n))), segments recomputed */
+#define LLG_CKPT_ALL 1  /* one segment: every stage state of the run is kept (memory ~ n_steps) */
+
+/* objectives */
+#define LLG_OBJ_NONE 0
+#define LLG_OBJ_ENERGY_AREA 1 /* J = (E_ex + E_d)(m_T)/E_ref + lambda (mean psi - area)^2            */
+#define LLG_OBJ_PORT_MY2 2    /* J = 1/|W| sum_{n in W} [mean_P1 m_y^2 - mean_P2 m_y^2], W = (n_start, n_steps] */
+
+/* ---- problem description --------------------------------------------- */
+typedef struct llg_problem {
+    int32_t nx, ny, nz;       /* nodes per axis, each >= 1                                  */
+    double dx, dy, dz;        /* node spacing = control-volume edges, m                     */
+    double Ms;                /* saturation magnetisation of the full material, A/m (> 0)    */
+    double A;                 /* exchange stiffness, J/m                                    */
+    double K;                 /* uniaxial anisotropy constant, J/m^3                         */
+    double ku[3];             /* anisotropy axis (normalised by the library)                */
+    double gamma;             /* gyromagnetic ratio, rad/(s T)                              */
+    double alpha0;            /* Gilbert damping in the bulk                                */
+    double alpha_max;         /* damping on a ramped face                                   */
+    int32_t ramp_cells;       /* ramp width W in nodes: alpha0 + (alpha_max-alpha0) max(0,(W-d)/W) */
+    int32_t ramp_faces;       /* LLG_FACE_* bitmask                                         */
+    double B0[3];             /* uniform bias field, T                                      */
+    double b_rf[3];           /* drive amplitude, T: b_rf sin(phase(t)) on the antenna mask */
+    double f1, f2, t_switch;  /* drive frequency f1, switching to f2 at t_switch (> 0) with a continuous phase */
+    int32_t terms;            /* LLG_TERM_* bitmask                                         */
+    int32_t dtype;            /* LLG_F32 or LLG_F64                                         */
+    double dt;                /* RK4 step, s (> 0)                                          */
+    int64_t max_steps;        /* largest n_steps a later llg_forward may use (sizes snapshots) */
+    int32_t ckpt_policy;      /* LLG_CKPT_*                                                 */
+    int32_t ckpt_param;       /* SQRT: segment length K (0 = ceil(sqrt(n_steps)))           */
+} llg_problem;
+
+/* Host-side copies of the u8 masks (length N, values 0/1); NULL = all zero.
+ * They are copied into the handle by llg_create. */
+typedef struct llg_masks {
+    const uint8_t* antenna; /* nodes that receive the drive field            */
+    const uint8_t* port1;   /* output window 1 of the port objective          */
+    const uint8_t* port2;   /* output window 2 of the port objective          */
+    const uint8_t* design;  /* nodes whose psi follows the level set          */
+} llg_masks;
+
+typedef struct llg_objective_spec {
+    int32_t kind;     /* LLG_OBJ_*                                                   */
+    double E_ref;     /* energy normalisation of LLG_OBJ_ENERGY_AREA, J (> 0)        */
+    double lambda;    /* weight of the area penalty                                  */
+    double area;      /* target mean psi of the area penalty                         */
+    int64_t n_start;  /* LLG_OBJ_PORT_MY2: steps n with n_start < n <= n_steps count */
+} llg_objective_spec;
+
+typedef struct llg_handle llg_handle;
+
+/* Message of the calling thread's most recent failure ("" if none). */
+const char* llg_last_error(void);
+
+/* Library version string. */
+const char* llg_version(void);
+
+/* Create a solver for one problem: validates the parameters, allocates the
+ * workspace on the current HIP device, builds the Newell tensor (float64 on
+ * the host) and its Fourier spectrum, and copies the masks.  Blocks the host.
+ * Errors: LLG_EINVAL (bad parameter), LLG_ESHAPE (grid larger than the FFT
+ * kernels support), LLG_ENOMEM, LLG_EHIP. */
+int llg_create(const llg_problem* p, const llg_masks* masks, llg_handle** out);
+
+/* Free the handle and its workspace (synchronises the device).  NULL is a no-op. */
+int llg_destroy(llg_handle* h);
+
+/* Material map of the level set (Eq. 4 and the paragraph after it):
+ *   psi_i = D_i / (1 + exp(-a phi_i)) + (1 - D_i) psi_fixed_i,
+ * D = design mask of the handle.  phi has nx*ny entries when extrude_z != 0
+ * (one 2D level set repeated through the thickness), else N.  psi_fixed and
+ * psi_out have N entries.  Ms, A and K of a node scale with its psi. */
+int llg_levelset_to_Ms(llg_handle* h, const void* phi, const void* psi_fixed, double a, int extrude_z,
+                       void* psi_out, hipStream_t stream);
+
+/* Chain rule through the map above: dJdphi = D a H (1 - H) dJdpsi, summed over
+ * z when extrude_z != 0.  dJdpsi (N) and dJdphi_out (nx*ny or N) are float64. */
+int llg_levelset_to_Ms_vjp(llg_handle* h, const void* phi, const double* dJdpsi, double a, int extrude_z,
+                           double* dJdphi_out, hipStream_t stream);
+
+/* Effective field B (T, 3N) at the state m (3N) and time t, from the enabled
+ * terms; the LL right-hand side dm/dt (3N) too if rhs_out is not NULL.
+ * Nodes with psi = 0 have dm/dt = 0. */
+int llg_field(llg_handle* h, const void* psi, const void* m, double t, void* B_out, void* rhs_out,
+              hipStream_t stream);
+
+/* Integrate n_steps classic RK4 steps of the LL form of Eq. 11 from m0 (3N) at
+ * time t0 (step n runs from t0 + n dt).  Writes m(t0 + n_steps dt) to m_out
+ * (may alias m0).  Records what llg_adjoint needs (psi, t0, n_steps,
+ * checkpoints per the handle's policy).  If obj is LLG_OBJ_PORT_MY2 its
+ * running cost is accumulated and written to *J_dev (device double) at the
+ * end; J_dev may be NULL otherwise.  1 <= n_steps <= max_steps.
+ * Errors: LLG_EINVAL, LLG_ENOMEM (checkpoint capacity), LLG_EHIP. */
+int llg_forward(llg_handle* h, const void* psi, const void* m0, double t0, int64_t n_steps,
+                const llg_objective_spec* obj, void* m_out, double* J_dev, hipStream_t stream);
+
+/* Terminal objective at the state m (3N): for LLG_OBJ_ENERGY_AREA writes J to
+ * *J_dev, dJ/dm to dJdm_out (3N, handle precision) and the explicit dJ/dpsi
+ * to dJdpsi_out (N, float64); energies_dev (device double[5]: exchange, demag,
+ * Zeeman at t, anisotropy, total; J) receives the energy terms when not NULL.
+ * For LLG_OBJ_PORT_MY2 the objective is a running cost: J_dev receives the
+ * value accumulated by the last llg_forward, dJdm_out and dJdpsi_out are
+ * zeroed (its sources are injected by llg_adjoint). */
+int llg_objective(llg_handle* h, const llg_objective_spec* obj, const void* psi, const void* m, double t,
+                  double* J_dev, void* dJdm_out, double* dJdpsi_out, double* energies_dev, hipStream_t stream);
+
+/* Discrete adjoint of the last llg_forward on this handle (same psi, same
+ * stream order).  Starts from lambda_N = dJdm_T (+ the port source at n_steps)
+ * and walks the RK4 steps backwards, recomputing checkpointed segments; adds
+ * dJdpsi_expl (may be NULL).  Writes dJ/dpsi (N, float64) to dJdpsi_out and,
+ * if not NULL, dJ/dm0 (3N, handle precision) to dJdm0_out.
+ * Errors: LLG_ESTATE (no forward recorded), LLG_EINVAL, LLG_EHIP. */
+int llg_adjoint(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl,
+                const llg_objective_spec* obj, double* dJdpsi_out, void* dJdm0_out, hipStream_t stream);
+
+/* Device bytes the checkpoint store needs for n_steps under a policy
+ * (snapshots + recomputed stage states), without allocating anything. */
+int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int32_t ckpt_param, size_t* bytes);
+
+/* Padded FFT sizes the handle uses (Px, Py, Pz). */
+int llg_fft_sizes(const llg_handle* h, int32_t* P3);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLG_H */

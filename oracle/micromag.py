@@ -62,20 +62,18 @@ class DemagKernel:
                         iy = np.arange(ny) if sy > 0 else (-np.arange(ny)) % Py
                         ix = np.arange(nx) if sx > 0 else (-np.arange(nx)) % Px
                         K[c][np.ix_(iz, iy, ix)] = sign * Nq[c]
-        self.Khat = np.fft.fftn(K, axes=(1, 2, 3))
+        self.Khat = np.fft.rfftn(K, axes=(1, 2, 3))
         self.tensor_octant = Nq
 
     def _conv_real(self, x):
         nz, ny, nx = self.n
         Pz, Py, Px = self.P
-        xp = np.zeros((3, Pz, Py, Px))
-        xp[:, :nz, :ny, :nx] = x
-        X = np.fft.fftn(xp, axes=(1, 2, 3))
+        X = np.fft.rfftn(x, s=(Pz, Py, Px), axes=(1, 2, 3))
         xx, yy, zz, xy, xz, yz = self.Khat
         Y = np.stack([xx * X[0] + xy * X[1] + xz * X[2],
                       xy * X[0] + yy * X[1] + yz * X[2],
                       xz * X[0] + yz * X[1] + zz * X[2]])
-        return np.fft.ifftn(Y, axes=(1, 2, 3))[:, :nz, :ny, :nx].real
+        return np.fft.irfftn(Y, s=(Pz, Py, Px), axes=(1, 2, 3))[:, :nz, :ny, :nx]
 
     def conv(self, x):
         """(N * x)_i = sum_j N(r_i - r_j) x_j for a 3-vector field x (3, nz, ny, nx)."""

@@ -1,0 +1,250 @@
+"""Thin ctypes binding of the HIP library (include/llg.h).
+
+Argument marshalling only: every step of the path runs in the library's
+kernels.  PyTorch supplies device memory (tensors on ``cuda``) and the current
+HIP stream.  The library must have been built (``python -m
+paper_2411_19109_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libllg.so")
+
+LLG_OK, LLG_EINVAL, LLG_ESHAPE, LLG_ENOMEM, LLG_EHIP, LLG_ENONFINITE, LLG_ENOTSUP, LLG_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+LLG_F32, LLG_F64 = 0, 1
+LLG_CKPT_SQRT, LLG_CKPT_ALL = 0, 1
+LLG_OBJ_NONE, LLG_OBJ_ENERGY_AREA, LLG_OBJ_PORT_MY2 = 0, 1, 2
+
+EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_levelset_to_Ms",
+           "llg_levelset_to_Ms_vjp", "llg_field", "llg_forward", "llg_objective", "llg_adjoint",
+           "llg_query_memory", "llg_fft_sizes"]
+
+
+class LLGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"llg error {code}: {msg}")
+        self.code = code
+
+
+class Problem_c(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("Ms", ctypes.c_double), ("A", ctypes.c_double), ("K", ctypes.c_double),
+                ("ku", ctypes.c_double * 3), ("gamma", ctypes.c_double),
+                ("alpha0", ctypes.c_double), ("alpha_max", ctypes.c_double),
+                ("ramp_cells", ctypes.c_int32), ("ramp_faces", ctypes.c_int32),
+                ("B0", ctypes.c_double * 3), ("b_rf", ctypes.c_double * 3),
+                ("f1", ctypes.c_double), ("f2", ctypes.c_double), ("t_switch", ctypes.c_double),
+                ("terms", ctypes.c_int32), ("dtype", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("max_steps", ctypes.c_int64), ("ckpt_policy", ctypes.c_int32), ("ckpt_param", ctypes.c_int32)]
+
+
+class Masks_c(ctypes.Structure):
+    _fields_ = [("antenna", ctypes.c_void_p), ("port1", ctypes.c_void_p), ("port2", ctypes.c_void_p),
+                ("design", ctypes.c_void_p)]
+
+
+class Objective_c(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("E_ref", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("area", ctypes.c_double), ("n_start", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libllg.so once (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run `python -m paper_2411_19109_amd.build`)")
+    # PyTorch ships its own HIP runtime; load it first so that the library binds
+    # to the same libamdhip64 instance (one runtime per process).
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.llg_last_error.restype = ctypes.c_char_p
+    L.llg_version.restype = ctypes.c_char_p
+    sig = {
+        "llg_create": [ctypes.POINTER(Problem_c), ctypes.POINTER(Masks_c), ctypes.POINTER(vp)],
+        "llg_destroy": [vp],
+        "llg_levelset_to_Ms": [vp, vp, vp, dbl, ctypes.c_int, vp, vp],
+        "llg_levelset_to_Ms_vjp": [vp, vp, vp, dbl, ctypes.c_int, vp, vp],
+        "llg_field": [vp, vp, vp, dbl, vp, vp, vp],
+        "llg_forward": [vp, vp, vp, dbl, i64, ctypes.POINTER(Objective_c), vp, vp, vp],
+        "llg_objective": [vp, ctypes.POINTER(Objective_c), vp, vp, dbl, vp, vp, vp, vp, vp],
+        "llg_adjoint": [vp, vp, vp, vp, ctypes.POINTER(Objective_c), vp, vp, vp],
+        "llg_query_memory": [ctypes.POINTER(Problem_c), i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "llg_fft_sizes": [vp, ctypes.POINTER(ctypes.c_int32)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(rc):
+    if rc != LLG_OK:
+        raise LLGError(rc, lib().llg_last_error().decode())
+
+
+def make_problem(prob, dtype="f32", max_steps=1, ckpt_policy=LLG_CKPT_SQRT, ckpt_param=0) -> Problem_c:
+    """Problem_c from any object with the attributes of workloads.Problem."""
+    c = Problem_c()
+    c.nx, c.ny, c.nz = prob.nx, prob.ny, prob.nz
+    c.dx, c.dy, c.dz = prob.dx, prob.dy, prob.dz
+    c.Ms, c.A, c.K = prob.Ms, prob.A, prob.K
+    c.ku = (ctypes.c_double * 3)(*prob.ku)
+    c.gamma = prob.gamma
+    c.alpha0, c.alpha_max = prob.alpha0, prob.alpha_max
+    c.ramp_cells, c.ramp_faces = prob.ramp_cells, prob.ramp_faces
+    c.B0 = (ctypes.c_double * 3)(*prob.B0)
+    c.b_rf = (ctypes.c_double * 3)(*prob.b_rf)
+    c.f1, c.f2, c.t_switch = prob.f1, prob.f2, prob.t_switch
+    c.terms = prob.terms
+    c.dtype = LLG_F64 if dtype in ("f64", "float64", LLG_F64) else LLG_F32
+    c.dt = prob.dt
+    c.max_steps = max_steps
+    c.ckpt_policy = ckpt_policy
+    c.ckpt_param = ckpt_param
+    return c
+
+
+def make_objective(kind=LLG_OBJ_NONE, E_ref=1.0, lam=1.0, area=0.4, n_start=0) -> Objective_c:
+    o = Objective_c()
+    o.kind, o.E_ref, o.lambda_, o.area, o.n_start = kind, E_ref, lam, area, n_start
+    return o
+
+
+def query_memory(prob, n_steps, policy=LLG_CKPT_SQRT, ckpt_param=0, dtype="f32") -> int:
+    b = ctypes.c_size_t(0)
+    check(lib().llg_query_memory(ctypes.byref(make_problem(prob, dtype, max(1, n_steps))), n_steps, policy,
+                                 ckpt_param, ctypes.byref(b)))
+    return b.value
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Solver:
+    """One problem instance on the current HIP device (wraps llg_handle)."""
+
+    def __init__(self, prob, dtype="f32", max_steps=1, antenna=None, port1=None, port2=None, design=None,
+                 ckpt_policy=LLG_CKPT_SQRT, ckpt_param=0):
+        import torch
+        self.prob = prob
+        self.dtype = dtype
+        self.tdtype = torch.float64 if dtype == "f64" else torch.float32
+        self.N = prob.nx * prob.ny * prob.nz
+        self._pc = make_problem(prob, dtype, max_steps, ckpt_policy, ckpt_param)
+        keep = []
+
+        def mask(a):
+            if a is None:
+                return None
+            arr = np.ascontiguousarray(np.asarray(a, dtype=np.uint8).reshape(-1))
+            if arr.size != self.N:
+                raise ValueError("mask size mismatch")
+            keep.append(arr)
+            return arr.ctypes.data
+
+        self._mk = Masks_c(mask(antenna), mask(port1), mask(port2), mask(design))
+        h = ctypes.c_void_p()
+        check(lib().llg_create(ctypes.byref(self._pc), ctypes.byref(self._mk), ctypes.byref(h)))
+        self.h = h
+        del keep
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().llg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------
+    def _t(self, x, n):
+        import torch
+        if x.dtype != self.tdtype or not x.is_cuda or not x.is_contiguous() or x.numel() != n:
+            raise ValueError(f"expected a contiguous cuda tensor of {n} {self.tdtype}")
+        return x
+
+    def fft_sizes(self):
+        a = (ctypes.c_int32 * 3)()
+        check(lib().llg_fft_sizes(self.h, a))
+        return tuple(a)
+
+    # -- entry points ------------------------------------------------------
+    def levelset_to_psi(self, phi, a, psi_fixed=None, extrude_z=True, out=None):
+        import torch
+        npsi = self.prob.nx * self.prob.ny if extrude_z else self.N
+        self._t(phi, npsi)
+        if psi_fixed is not None:
+            self._t(psi_fixed, self.N)
+        out = torch.empty(self.N, dtype=self.tdtype, device=phi.device) if out is None else out
+        check(lib().llg_levelset_to_Ms(self.h, _ptr(phi), _ptr(psi_fixed), float(a), int(extrude_z), _ptr(out), _stream()))
+        return out
+
+    def levelset_vjp(self, phi, dJdpsi, a, extrude_z=True):
+        import torch
+        out = torch.empty(phi.numel(), dtype=torch.float64, device=phi.device)
+        check(lib().llg_levelset_to_Ms_vjp(self.h, _ptr(phi), _ptr(dJdpsi), float(a), int(extrude_z), _ptr(out), _stream()))
+        return out
+
+    def field(self, psi, m, t=0.0, want_rhs=False):
+        import torch
+        self._t(psi, self.N)
+        self._t(m, 3 * self.N)
+        B = torch.empty(3 * self.N, dtype=self.tdtype, device=m.device)
+        rhs = torch.empty_like(B) if want_rhs else None
+        check(lib().llg_field(self.h, _ptr(psi), _ptr(m), float(t), _ptr(B), _ptr(rhs), _stream()))
+        return (B, rhs) if want_rhs else B
+
+    def forward(self, psi, m0, n_steps, t0=0.0, obj: Optional[Objective_c] = None, m_out=None):
+        import torch
+        self._t(psi, self.N)
+        self._t(m0, 3 * self.N)
+        m_out = torch.empty_like(m0) if m_out is None else m_out
+        J = torch.zeros(1, dtype=torch.float64, device=m0.device)
+        check(lib().llg_forward(self.h, _ptr(psi), _ptr(m0), float(t0), int(n_steps),
+                                ctypes.byref(obj) if obj is not None else None, _ptr(m_out), _ptr(J), _stream()))
+        return m_out, J
+
+    def objective(self, obj: Objective_c, psi, m, t=0.0):
+        import torch
+        dev = m.device
+        J = torch.zeros(1, dtype=torch.float64, device=dev)
+        dJdm = torch.empty(3 * self.N, dtype=self.tdtype, device=dev)
+        dJdpsi = torch.empty(self.N, dtype=torch.float64, device=dev)
+        en = torch.zeros(5, dtype=torch.float64, device=dev)
+        check(lib().llg_objective(self.h, ctypes.byref(obj), _ptr(psi), _ptr(m), float(t), _ptr(J), _ptr(dJdm),
+                                  _ptr(dJdpsi), _ptr(en), _stream()))
+        return J, dJdm, dJdpsi, en
+
+    def adjoint(self, psi, obj: Optional[Objective_c] = None, dJdm_T=None, dJdpsi_expl=None, want_dm0=False):
+        import torch
+        dev = psi.device
+        dJdpsi = torch.empty(self.N, dtype=torch.float64, device=dev)
+        dm0 = torch.empty(3 * self.N, dtype=self.tdtype, device=dev) if want_dm0 else None
+        check(lib().llg_adjoint(self.h, _ptr(psi), _ptr(dJdm_T), _ptr(dJdpsi_expl),
+                                ctypes.byref(obj) if obj is not None else None, _ptr(dJdpsi), _ptr(dm0), _stream()))
+        return (dJdpsi, dm0) if want_dm0 else dJdpsi

@@ -1,0 +1,163 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances: FP64 runs match the oracle to 1e-10 relative max-norm (the field
+to 1e-12); FP32 runs match the magnetisation to 1e-4 absolute after the stated
+step count and the gradient to 1e-3 relative L2.
+"""
+import numpy as np
+import pytest
+
+from _helpers import (gpu_gradient, gpu_objective, gpu_solver, oracle_gradient, oracle_psi, oracle_sim, rel_l2,
+                      rel_max, say, to_dev, to_np)
+from oracle import adjoint as oadj
+from paper_2411_19109_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def tiny_workload(nx, ny, nz, kind=wl.OBJ_ENERGY_AREA, terms=wl.TERM_ALL, n_steps=12, seed=5):
+    rng = np.random.default_rng(seed)
+    p = wl.Problem(nx=nx, ny=ny, nz=nz, dx=3e-9, dy=3e-9, dz=4e-9, Ms=8e5, A=1.3e-11, K=5e4, ku=(0.6, 0.8, 0.0),
+                   alpha0=0.1, alpha_max=0.4, ramp_cells=3, ramp_faces=wl.FACE_XLO | wl.FACE_XHI | wl.FACE_YHI,
+                   B0=(0.05, 0.02, 0.1), b_rf=(0.0, 0.01, 0.0), f1=5e9, terms=terms, dt=5e-14)
+    sh = p.shape
+    ant = np.zeros(sh, np.uint8)
+    ant[:, :, min(1, nx - 1)] = 1
+    design = np.ones(sh, np.uint8)
+    design[:, 0, :] = 0
+    psif = np.full(sh, 0.7)
+    psif[:, 0, : max(1, nx // 3)] = 0.0
+    m0 = rng.standard_normal((3,) + sh)
+    m0[2] += 1.0
+    m0 /= np.sqrt((m0 ** 2).sum(0))
+    p1 = np.zeros(sh, np.uint8)
+    p1[:, ny // 2:, nx // 2:] = 1
+    p2 = np.zeros(sh, np.uint8)
+    p2[:, : max(1, ny // 2), nx // 2:] = 1
+    p2[:, 0, :] = 0
+    p2[:, min(1, ny - 1), -1] = 1
+    return wl.Workload(name=f"tiny{nx}x{ny}x{nz}", problem=p, n_steps=n_steps, dtype="f64", heaviside_a=3.0,
+                       phi=rng.standard_normal((ny, nx)) * 0.5, extrude_z=True, design=design, psi_fixed=psif,
+                       antenna=ant, port1=p1, port2=p2, m0=m0, objective=kind, obj_lambda=0.7, obj_area=0.4,
+                       obj_n_start=n_steps // 3)
+
+
+SHAPES = [(7, 5, 1), (13, 9, 1), (16, 8, 1), (1, 1, 1), (33, 1, 1), (1, 6, 1), (6, 5, 2), (9, 4, 3), (5, 3, 4)]
+
+
+def test_library_loads():
+    from paper_2411_19109_amd import llg
+    say("load library")
+    assert llg.lib().llg_version().decode().startswith("llg-mi355x")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_levelset_map_and_vjp(dtype):
+    import torch
+    w = tiny_workload(13, 9, 2)
+    say("levelset", dtype)
+    s = gpu_solver(w, dtype)
+    phi = to_dev(w.phi, dtype)
+    psi = to_np(s.levelset_to_psi(phi, w.heaviside_a, to_dev(w.psi_fixed, dtype)))
+    ref = oracle_psi(w).reshape(-1)
+    tol = 1e-15 if dtype == "f64" else 1e-6
+    assert np.abs(psi - ref).max() <= tol
+    g = np.random.default_rng(1).standard_normal(w.problem.n)
+    from oracle import levelset as ols
+    out = to_np(s.levelset_vjp(phi, torch.as_tensor(g, device="cuda"), w.heaviside_a))
+    ref = ols.levelset_vjp(w.phi, w.heaviside_a, w.design, g.reshape(w.problem.shape)).reshape(-1)
+    assert rel_max(out, ref) <= (1e-14 if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_effective_field_and_rhs(dtype, shape):
+    nx, ny, nz = shape
+    w = tiny_workload(nx, ny, nz)
+    say("field", dtype, shape)
+    s = gpu_solver(w, dtype)
+    psi = oracle_psi(w)
+    sim = oracle_sim(w)
+    t = 3.3e-11
+    B, rhs = s.field(to_dev(psi, dtype), to_dev(w.m0, dtype), t, want_rhs=True)
+    Bref = sim.field(w.m0, psi, t)
+    fref = sim.rhs_from_field(w.m0, Bref, psi)
+    tol = 1e-12 if dtype == "f64" else 2e-6
+    assert rel_max(to_np(B), Bref.reshape(-1)) <= tol
+    assert rel_max(to_np(rhs), fref.reshape(-1)) <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(13, 9, 1), (1, 1, 1), (33, 1, 1), (9, 4, 3)])
+def test_forward_steps(dtype, shape):
+    w = tiny_workload(*shape, n_steps=30)
+    say("forward", dtype, shape)
+    s = gpu_solver(w, dtype)
+    psi = oracle_psi(w)
+    mT, _ = s.forward(to_dev(psi, dtype), to_dev(w.m0, dtype), 30, t0=1e-12)
+    ref = oracle_sim(w).integrate(w.m0, psi, 30, t0=1e-12)
+    if dtype == "f64":
+        assert rel_max(to_np(mT), ref.reshape(-1)) <= 1e-12
+    else:
+        assert np.abs(to_np(mT) - ref.reshape(-1)).max() <= 1e-5
+
+
+def test_yig_waveguide_fp64_500_steps():
+    w = wl.yig_waveguide_plain()
+    say("yig waveguide 64x16 fp64, 500 steps")
+    s = gpu_solver(w, "f64")
+    psi = np.ones(w.problem.shape)
+    mT, _ = s.forward(to_dev(psi, "f64"), to_dev(w.m0, "f64"), w.n_steps)
+    ref = oracle_sim(w).integrate(w.m0, psi, w.n_steps)
+    assert rel_max(to_np(mT), ref.reshape(-1)) <= 1e-10
+
+
+@pytest.mark.parametrize("kind", [wl.OBJ_ENERGY_AREA, wl.OBJ_PORT_MY2])
+@pytest.mark.parametrize("shape", [(7, 5, 1), (6, 5, 2)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gradient_tiny(kind, shape, dtype):
+    w = tiny_workload(*shape, kind=kind, n_steps=14)
+    say("gradient", dtype, shape, "kind", kind)
+    g = gpu_gradient(w, dtype, ckpt_param=4)
+    r = oracle_gradient(w)
+    if dtype == "f64":
+        assert abs(g["J"] - r["J"]) <= 1e-12 * abs(r["J"])
+        assert rel_l2(g["dpsi"], r["dpsi"]) <= 1e-10
+        assert rel_l2(g["dm0"], r["dm0"]) <= 1e-10
+        assert rel_l2(g["dphi"], r["dphi"]) <= 1e-10
+    else:
+        assert abs(g["J"] - r["J"]) <= 1e-5 * abs(r["J"]) + 1e-7
+        assert rel_l2(g["dpsi"], r["dpsi"]) <= 1e-3
+        assert rel_l2(g["dphi"], r["dphi"]) <= 1e-3
+
+
+def test_checkpoint_policies_bitwise():
+    from paper_2411_19109_amd import llg
+    w = tiny_workload(13, 9, 1, kind=wl.OBJ_PORT_MY2, n_steps=40)
+    say("checkpoint policies")
+    outs = []
+    for pol, par in [(llg.LLG_CKPT_ALL, 0), (llg.LLG_CKPT_SQRT, 0), (llg.LLG_CKPT_SQRT, 3), (llg.LLG_CKPT_SQRT, 40)]:
+        g = gpu_gradient(w, "f32", ckpt_policy=pol, ckpt_param=par)
+        outs.append(g)
+    for g in outs[1:]:
+        assert np.array_equal(g["dpsi"], outs[0]["dpsi"])
+        assert np.array_equal(g["dm0"], outs[0]["dm0"])
+        assert g["J"] == outs[0]["J"]
+
+
+def test_energy_terms_match_oracle():
+    w = tiny_workload(13, 9, 2)
+    say("energies")
+    s = gpu_solver(w, "f64")
+    psi = oracle_psi(w)
+    obj = gpu_objective(w, wl.OBJ_ENERGY_AREA)
+    J, dJdm, dJdpsi, en = s.objective(obj, to_dev(psi, "f64"), to_dev(w.m0, "f64"), t=2e-11)
+    e = oracle_sim(w).energies(w.m0, psi, 2e-11)
+    got = to_np(en)
+    for k, name in enumerate(["ex", "d", "Z", "an", "tot"]):
+        assert abs(got[k] - e[name]) <= 1e-12 * max(abs(e[name]), abs(e["tot"]))
+    o = oadj.Objective(wl.OBJ_ENERGY_AREA, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area)
+    gm, gp = oadj.energy_area_grad(oracle_sim(w), w.m0, psi, o)
+    assert rel_max(to_np(dJdm), gm.reshape(-1)) <= 1e-12
+    assert rel_max(to_np(dJdpsi), gp.reshape(-1)) <= 1e-12
+    assert abs(float(J.item()) - oadj.energy_area_value(oracle_sim(w), w.m0, psi, o)) <= 1e-12

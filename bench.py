@@ -1,0 +1,181 @@
+"""Throughput of the level-set LLG gradient path on one MI355X.
+
+One "step" is one full gradient evaluation of the workload: level set -> psi,
+n RK4 steps of the LLG equation with checkpoints, the objective, the
+checkpointed discrete adjoint back to t0, and the chain rule to dJ/dphi.
+Inputs are resident in device memory before the timed region starts.
+
+  python bench.py [--steps K] [--warmup W] [--workload particle|waveguide|demux]
+
+Prints ONE JSON line.  The metric is LLG cell-steps per second of the forward
++ adjoint run: nodes * RK4 steps / wall time of one gradient evaluation.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "LLG cell-steps/s fwd+adjoint; grad time/iter, batched vs plain at stated tol"
+HBM_PEAK_GBS = 8000.0
+
+
+def make_workload(name):
+    from paper_2411_19109_amd import workloads as wl
+    if name == "particle":
+        return wl.permalloy_particle()
+    if name == "waveguide":
+        w = wl.yig_waveguide_plain()
+        w.objective = wl.OBJ_ENERGY_AREA
+        return w
+    if name == "demux":
+        return wl.yig_demux()
+    raise SystemExit(f"unknown workload {name}")
+
+
+class GradientStep:
+    """Device-resident inputs and one gradient evaluation through the C ABI."""
+
+    def __init__(self, w):
+        import torch
+        from paper_2411_19109_amd import llg, workloads as wl
+        self.w = w
+        self.td = torch.float64 if w.dtype == "f64" else torch.float32
+        dev = torch.device("cuda:0")
+        self.solver = llg.Solver(w.problem, dtype=w.dtype, max_steps=w.n_steps, antenna=w.antenna, port1=w.port1,
+                                 port2=w.port2, design=w.design)
+        self.phi = torch.as_tensor(w.phi.reshape(-1), dtype=self.td, device=dev).contiguous()
+        self.psi_fixed = torch.as_tensor(w.psi_fixed.reshape(-1), dtype=self.td, device=dev).contiguous()
+        self.m0 = torch.as_tensor(w.m0.reshape(-1), dtype=self.td, device=dev).contiguous()
+        self.obj = llg.make_objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area,
+                                      n_start=w.obj_n_start)
+        self.energy = w.objective == wl.OBJ_ENERGY_AREA
+
+    def __call__(self):
+        s, w = self.solver, self.w
+        psi = s.levelset_to_psi(self.phi, w.heaviside_a, self.psi_fixed, extrude_z=True)
+        mT, Jp = s.forward(psi, self.m0, w.n_steps, obj=self.obj)
+        if self.energy:
+            J, dJdm, dJdpsi_e, _ = s.objective(self.obj, psi, mT)
+        else:
+            J, dJdm, dJdpsi_e = Jp, None, None
+        dJdpsi = s.adjoint(psi, self.obj, dJdm_T=dJdm, dJdpsi_expl=dJdpsi_e)
+        return J, s.levelset_vjp(self.phi, dJdpsi, w.heaviside_a, extrude_z=True)
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The oracle as it stands, timed on the host on a bounded prefix of the
+    same workload (forward + adjoint over the first n steps)."""
+    from oracle import adjoint as oadj
+    from oracle import levelset as ols
+    from oracle import micromag as omm
+    from paper_2411_19109_amd import workloads as wl
+    sim = omm.Sim(w.problem, antenna=w.antenna)
+    psi = ols.levelset_to_psi(w.phi, w.heaviside_a, w.design, w.psi_fixed)
+    obj = oadj.Objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area,
+                         n_start=0, port1=w.port1, port2=w.port2)
+    n = 10
+    t0 = time.perf_counter()
+    oadj.gradient(sim, w.m0, psi, n, obj)
+    dt = time.perf_counter() - t0
+    n = max(10, min(w.n_steps, int(n * budget_s / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    oadj.gradient(sim, w.m0, psi, n, obj)
+    dt = time.perf_counter() - t0
+    return dict(value=w.problem.n * n / dt, unit="cell-steps/s", cores=1, kind="oracle",
+                sample=f"float64 NumPy oracle, forward+adjoint of the first {n} of {w.n_steps} RK4 steps "
+                       f"({dt:.1f} s, one host thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="particle")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2411_19109_amd import llg
+
+    w = make_workload(args.workload)
+    step = GradientStep(w)
+    print(f"[bench] workload {w.name}: {w.problem.nx}x{w.problem.ny}x{w.problem.nz} nodes, {w.n_steps} steps, "
+          f"{w.dtype}", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        J, g = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / args.steps
+    print(f"[bench] timed {args.steps} steps: {sec * 1e3:.2f} ms per gradient", file=sys.stderr, flush=True)
+
+    # per-kernel device time over one more gradient with event bracketing
+    s = step.solver
+    s.profile(True)
+    step()
+    torch.cuda.synchronize()
+    s.profile(False)
+    kinds = {}
+    for k, name in llg.KIND_NAMES.items():
+        ms, n, b = s.profile_read(k)
+        if n:
+            kinds[name] = dict(ms=ms, launches=n, bytes=b, avg_us=1e3 * ms / n, gbs=b / (ms * 1e-3) / 1e9)
+    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+    d = kinds[dom]
+    roofline = dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(d["gbs"] / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
+                    avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"]))
+    for name, v in kinds.items():
+        print(f"[bench] {name}: {v['launches']} launches, avg {v['avg_us']:.2f} us, "
+              f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, args.cpu_budget)
+        print(f"[bench] cpu baseline: {cpu['sample']}", file=sys.stderr, flush=True)
+
+    N = w.problem.n
+    out = {
+        "metric": METRIC,
+        "value": N * w.n_steps / sec,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if w.dtype == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nodes": [w.problem.nx, w.problem.ny, w.problem.nz],
+                   "rk4_steps": w.n_steps, "checkpoint": "sqrt", "grad_ms": round(sec * 1e3, 3),
+                   "objective_J": float(J.item())},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -189,6 +189,21 @@ int llg_adjoint(llg_handle* h, const void* psi, const void* dJdm_T, const double
  * (snapshots + recomputed stage states), without allocating anything. */
 int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int32_t ckpt_param, size_t* bytes);
 
+/* Kernel classes reported by the profiling counters. */
+#define LLG_KIND_STAGE_FWD 0 /* forward local kernel: row FFTs + fields + LL RHS + RK4 stage */
+#define LLG_KIND_COLUMN 1    /* column kernel: y/z FFTs and tensor-spectrum multiply       */
+#define LLG_KIND_STAGE_BWD 2 /* backward local kernel of the discrete adjoint              */
+#define LLG_KIND_COUNT 3
+
+/* Profiling: while enabled, every kernel launch of the handle is bracketed by
+ * two HIP events on the call's stream; llg_profile_read synchronises on the
+ * recorded events and returns, for one kernel class, the summed device time
+ * (ms), the number of launches, and the algorithmic HBM bytes of those
+ * launches (every array element the kernel must read or write counted once).
+ * reset != 0 clears the class's totals after reading. */
+int llg_profile(llg_handle* h, int enable);
+int llg_profile_read(llg_handle* h, int32_t kind, double* ms, int64_t* launches, double* bytes, int reset);
+
 /* Padded FFT sizes the handle uses (Px, Py, Pz). */
 int llg_fft_sizes(const llg_handle* h, int32_t* P3);
 

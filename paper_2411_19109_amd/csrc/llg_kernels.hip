@@ -34,86 +34,134 @@ template <typename C> __device__ __forceinline__ C cmul_mi(C a) { return cmk<C>(
 // ---------------------------------------------------------------------------
 // LDS Stockham FFT
 // ---------------------------------------------------------------------------
-// Signal b occupies buf[(b / n0) * s1 + (b % n0) * s0 + e * es], e in [0, L).
+// Signal b occupies buf[(b >> ln0) * s1 + (b & (2^ln0 - 1)) * s0 + e * es], e in [0, L).
 struct SigMap {
-    int n0, s1, s0, es;
-    __device__ __forceinline__ int off(int b) const { return (b / n0) * s1 + (b % n0) * s0; }
+    int ln0, s1, s0, es;
+    __device__ __forceinline__ int off(int b) const { return (b >> ln0) * s1 + (b & ((1 << ln0) - 1)) * s0; }
 };
 
+// cos / sin of 2 pi m / 16, m = 0..15 (exact constants)
+__device__ constexpr double kC16[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                        0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                                        -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                                        0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+__device__ constexpr double kS16[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                                        1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                        0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                                        -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+constexpr int bitrev(int i, int lg) {
+    int r = 0;
+    for (int k = 0; k < lg; ++k) r |= ((i >> k) & 1) << (lg - 1 - k);
+    return r;
+}
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+__device__ __forceinline__ int ilog2_rt(int v) { return 31 - __clz(v); }
+
+// In-register DFT of size R (power of two <= 16): radix-2 decimation in time
+// with constant twiddles; forward sign -1, inverse +1, unnormalised.
 template <typename C, bool INV, int R>
 __device__ __forceinline__ void dft_small(C* v) {
-    if constexpr (R == 2) {
-        C a = v[0], b = v[1];
-        v[0] = cadd(a, b);
-        v[1] = csub(a, b);
-    } else {
-        C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-        C t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
-        v[0] = cadd(t0, t2);
-        v[2] = csub(t0, t2);
-        if constexpr (INV) {
-            v[1] = cadd(t1, cmul_i(t3));
-            v[3] = csub(t1, cmul_i(t3));
-        } else {
-            v[1] = cadd(t1, cmul_mi(t3));
-            v[3] = csub(t1, cmul_mi(t3));
+    using T = decltype(C().x);
+    constexpr int LG = ilog2(R);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int j = bitrev(i, LG);
+        if (j > i) {
+            C t = v[i];
+            v[i] = v[j];
+            v[j] = t;
+        }
+    }
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+#pragma unroll
+        for (int i = 0; i < R; i += len) {
+#pragma unroll
+            for (int k = 0; k < len / 2; ++k) {
+                const C u = v[i + k];
+                C t = v[i + k + len / 2];
+                const int m = k * (16 / len);  // exp(-+2 pi i k / len) = entry m of the 16-point table
+                if (m == 0) {
+                } else if (m == 4) {
+                    t = INV ? cmul_i(t) : cmul_mi(t);
+                } else {
+                    const C w = cmk<C>((T)kC16[m], INV ? (T)kS16[m] : -(T)kS16[m]);
+                    t = cmul(t, w);
+                }
+                v[i + k] = cadd(u, t);
+                v[i + k + len / 2] = csub(u, t);
+            }
         }
     }
 }
 
-// One Stockham pass of radix R over nsig signals of length L (in place via
-// registers).  Requires nsig * L <= MAXREG * blockDim.x.
+// One Stockham pass of radix R over nsig signals of length L = 2^lL (in place
+// via registers).  Requires nsig * L <= MAXREG * blockDim.x.
 template <typename C, bool INV, int R, int MAXREG>
-__device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int L, int Ns, int nsig, const C* __restrict__ tw) {
+__device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lNs, int nsig, const C* __restrict__ tw) {
     constexpr int IPT = MAXREG / R;
-    const int nbf = L / R;
-    const int total = nsig * nbf;
+    constexpr int LR = ilog2(R);
+    const int lnbf = lL - LR;
+    const int nbf = 1 << lnbf;
+    const int total = nsig << lnbf;
     C v[IPT][R];
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
         if (it < total) {
-            const int b = it / nbf, j = it - b * nbf;
+            const int b = it >> lnbf, j = it & (nbf - 1);
             const C* s = buf + sm.off(b);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = s[(j + r * nbf) * sm.es];
+            for (int r = 0; r < R; ++r) v[q][r] = s[(j + (r << lnbf)) * sm.es];
         }
     }
     __syncthreads();
-    const int stride = L / (Ns * R);
+    const int lstride = lL - lNs - LR;  // twiddle index step L / (Ns R)
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
         if (it < total) {
-            const int b = it / nbf, j = it - b * nbf;
-            const int jm = j & (Ns - 1);
+            const int b = it >> lnbf, j = it & (nbf - 1);
+            const int jm = j & ((1 << lNs) - 1);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                C w = tw[r * jm * stride];
+                C w = tw[(r * jm) << lstride];
                 if (INV) w = cconj(w);
                 v[q][r] = cmul(v[q][r], w);
             }
             dft_small<C, INV, R>(v[q]);
             C* d = buf + sm.off(b);
-            const int base = (j - jm) * R + jm;
+            const int base = ((j - jm) << LR) + jm;
 #pragma unroll
-            for (int r = 0; r < R; ++r) d[(base + r * Ns) * sm.es] = v[q][r];
+            for (int r = 0; r < R; ++r) d[(base + (r << lNs)) * sm.es] = v[q][r];
         }
     }
     __syncthreads();
 }
 
 // Full FFT of length L (power of two) of nsig signals; tw = exp(-2 pi i k / L).
+// Radix-16 passes while at least 16 points remain per sub-transform, then one
+// pass of the remaining radix (8, 4 or 2).
 template <typename C, bool INV, int MAXREG>
 __device__ void fft_lds(C* buf, const SigMap sm, int L, int nsig, const C* __restrict__ tw) {
-    int Ns = 1;
-    while (Ns < L) {
-        if ((L / Ns) % 4 == 0) {
-            fft_pass<C, INV, 4, MAXREG>(buf, sm, L, Ns, nsig, tw);
-            Ns *= 4;
+    int lL = 0;
+    while ((1 << lL) < L) ++lL;
+    int lNs = 0;
+    while (lNs < lL) {
+        const int rem = lL - lNs;
+        if (rem >= 4) {
+            fft_pass<C, INV, 16, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+            lNs += 4;
+        } else if (rem == 3) {
+            fft_pass<C, INV, 8, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+            lNs += 3;
+        } else if (rem == 2) {
+            fft_pass<C, INV, 4, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+            lNs += 2;
         } else {
-            fft_pass<C, INV, 2, MAXREG>(buf, sm, L, Ns, nsig, tw);
-            Ns *= 2;
+            fft_pass<C, INV, 2, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+            lNs += 1;
         }
     }
 }
@@ -250,6 +298,47 @@ __device__ __forceinline__ void pack_lds_to_rows(const KParams<T>& p, cplx<T>* _
 }
 
 // ---------------------------------------------------------------------------
+// shared-memory layout of the local (row-pair) kernels
+//   Z  [3 * Px] complex  three packed row signals (demag only)
+//   Tw [Px]     complex  x twiddles (demag only)
+//   R  [4][NV][nx] real  rows r0-1 .. r0+2 of NV staged node values
+// Staging the two own rows and their two y-neighbour rows lets every x and y
+// neighbour of the stencil come from LDS; the loads are issued together with
+// the spectrum loads, before the first FFT pass.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct LocalSmem {
+    cplx<T>* Z;
+    cplx<T>* Tw;
+    T* R;
+};
+
+template <typename T>
+__device__ __forceinline__ LocalSmem<T> local_smem(unsigned char* raw, int Px, bool demag) {
+    LocalSmem<T> L;
+    L.Z = reinterpret_cast<cplx<T>*>(raw);
+    L.Tw = L.Z + (demag ? 3 * Px : 0);
+    L.R = reinterpret_cast<T*>(L.Tw + (demag ? Px : 0));
+    return L;
+}
+
+// Stage rows r0-1 .. r0+2 of NV arrays src[v] (component-major vectors use
+// stride N) into R; rows outside the grid are left unset (never read).
+template <typename T, int NV>
+__device__ __forceinline__ void stage_rows(const KParams<T>& p, int r0, const T* const (&src)[NV], const int (&comp)[NV],
+                                           T* R) {
+    const int nx = p.nx;
+    for (int e = threadIdx.x; e < 4 * nx; e += blockDim.x) {
+        const int q = e / nx, x = e - q * nx;
+        const int r = r0 - 1 + q;
+        if (r < 0 || r >= p.nrows) continue;
+        const int i = r * nx + x;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) R[(q * NV + v) * nx + x] = src[v][comp[v] * p.N + i];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // forward local kernel: inverse x-FFT (demag) + local field + LL RHS + RK4
 // stage update + forward x-FFT of the next stage's magnetisation
 // ---------------------------------------------------------------------------
@@ -257,23 +346,31 @@ template <typename T>
 __global__ void __launch_bounds__(512) k_stage_fwd(const KParams<T> p, const StageFwdArgs<T> a,
                                                    const cplx<T>* __restrict__ twx) {
     using C = cplx<T>;
+    constexpr int NV = 4;  // m_x, m_y, m_z, psi
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* Z = reinterpret_cast<C*>(smem_raw);
     __shared__ double red[2][512 / 64];
+    const int Px = p.Px, nx = p.nx, N = p.N;
+    const bool demag_in = a.do_inv != 0, demag_any = (a.do_inv | a.do_fwd) != 0;
+    const LocalSmem<T> L = local_smem<T>(smem_raw, Px, demag_any);
+    C* Z = L.Z;
+    T* R = L.R;
     const int r0 = 2 * blockIdx.x;
     const bool v1 = r0 + 1 < p.nrows;
-    const int Px = p.Px;
     constexpr int MR = MaxReg<T>::v;
-    const SigMap sm{1, Px, 0, 1};
+    const SigMap sm{0, Px, 0, 1};
 
-    if (a.do_inv) {
-        unpack_rows_to_lds(p, a.S, r0, v1, Z);
-        __syncthreads();
-        fft_lds<C, true, MR>(Z, sm, Px, 3, twx);
+    {
+        const T* const src[NV] = {a.ys, a.ys, a.ys, a.psi};
+        const int comp[NV] = {0, 1, 2, 0};
+        stage_rows<T, NV>(p, r0, src, comp, R);
     }
+    if (demag_any)
+        for (int k = threadIdx.x; k < Px; k += blockDim.x) L.Tw[k] = twx[k];
+    if (demag_in) unpack_rows_to_lds(p, a.S, r0, v1, Z);
+    __syncthreads();
+    if (demag_in) fft_lds<C, true, MR>(Z, sm, Px, 3, L.Tw);
 
     const T drv = (T)drive_value(p.f1, p.f2, p.t_switch, a.t);
-    const int N = p.N, nx = p.nx;
     const T dt = p.dt;
     double s1 = 0.0, s2 = 0.0;
     for (int x = threadIdx.x; x < nx; x += blockDim.x) {
@@ -282,17 +379,36 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const KParams<T> p, const Sta
         for (int rr = 0; rr < 2; ++rr) {
             const int r = r0 + rr;
             if (rr == 1 && !v1) break;
+            const int q = rr + 1;
             const int iy = r % p.ny, iz = r / p.ny;
             const int i = r * nx + x;
-            const V3<T> m = ld3(a.ys, N, i);
-            const T pi = a.psi[i];
+            auto RM = [&](int qq, int xx) {
+                return v3<T>(R[(qq * NV + 0) * nx + xx], R[(qq * NV + 1) * nx + xx], R[(qq * NV + 2) * nx + xx]);
+            };
+            auto RP = [&](int qq, int xx) { return R[(qq * NV + 3) * nx + xx]; };
+            const V3<T> m = RM(q, x);
+            const T pi = RP(q, x);
             V3<T> B = v3<T>(0, 0, 0);
-            if (a.do_inv) {
+            if (demag_in) {
                 const C z01 = Z[rr * Px + x];
                 const C z2 = Z[2 * Px + x];
                 B = v3<T>(z01.x, z01.y, rr == 0 ? z2.x : z2.y);
             }
-            if (p.terms & 1) B = B + exchange_field(p, a.ys, a.psi, i, x, iy, iz, m, pi);
+            if (p.terms & 1) {
+                // exchange: sum_j exw_d psi_j/(psi_i+psi_j) (m_j - m_i), free ends
+                V3<T> Be = v3<T>(0, 0, 0);
+                auto add = [&](V3<T> mj, T pj, T w) {
+                    const T s = pi + pj;
+                    if (s != (T)0) Be = Be + (w * pj / s) * (mj - m);
+                };
+                if (x > 0) add(RM(q, x - 1), RP(q, x - 1), p.exw[0]);
+                if (x < nx - 1) add(RM(q, x + 1), RP(q, x + 1), p.exw[0]);
+                if (iy > 0) add(RM(q - 1, x), RP(q - 1, x), p.exw[1]);
+                if (iy < p.ny - 1) add(RM(q + 1, x), RP(q + 1, x), p.exw[1]);
+                if (iz > 0) add(ld3(a.ys, N, i - nx * p.ny), a.psi[i - nx * p.ny], p.exw[2]);
+                if (iz < p.nz - 1) add(ld3(a.ys, N, i + nx * p.ny), a.psi[i + nx * p.ny], p.exw[2]);
+                B = B + Be;
+            }
             if (p.terms & 4) {
                 B = B + v3<T>(p.B0[0], p.B0[1], p.B0[2]);
                 if (a.antenna && a.antenna[i]) B = B + drv * v3<T>(p.brf[0], p.brf[1], p.brf[2]);
@@ -333,9 +449,9 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const KParams<T> p, const Sta
                 if (a.port1[i]) s1 += my2;
                 if (a.port2[i]) s2 += my2;
             }
-            out[rr][0] = a.psi[i] * yn.x;
-            out[rr][1] = a.psi[i] * yn.y;
-            out[rr][2] = a.psi[i] * yn.z;
+            out[rr][0] = pi * yn.x;
+            out[rr][1] = pi * yn.y;
+            out[rr][2] = pi * yn.z;
         }
         if (a.do_fwd) {
             Z[x] = cmk<C>(out[0][0], out[0][1]);
@@ -372,7 +488,7 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const KParams<T> p, const Sta
             Z[2 * Px + x] = cmk<C>(0, 0);
         }
         __syncthreads();
-        fft_lds<C, false, MR>(Z, sm, Px, 3, twx);
+        fft_lds<C, false, MR>(Z, sm, Px, 3, L.Tw);
         pack_lds_to_rows(p, a.S, r0, v1, Z);
     }
 }
@@ -395,21 +511,30 @@ template <typename T>
 __global__ void __launch_bounds__(512) k_stage_bwd(const KParams<T> p, const StageBwdArgs<T> a,
                                                    const cplx<T>* __restrict__ twx) {
     using C = cplx<T>;
+    constexpr int NV = 4;  // u_x, u_y, u_z, psi
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* Z = reinterpret_cast<C*>(smem_raw);
+    const int Px = p.Px, nx = p.nx, N = p.N;
+    const bool seed = a.stage < 0;
+    const bool demag_in = a.do_inv && !seed, demag_any = (a.do_inv | a.do_fwd) != 0;
+    const LocalSmem<T> L = local_smem<T>(smem_raw, Px, demag_any);
+    C* Z = L.Z;
+    T* R = L.R;
     const int r0 = 2 * blockIdx.x;
     const bool v1 = r0 + 1 < p.nrows;
-    const int Px = p.Px;
     constexpr int MR = MaxReg<T>::v;
-    const SigMap sm{1, Px, 0, 1};
-    const bool seed = a.stage < 0;
+    const SigMap sm{0, Px, 0, 1};
 
-    if (a.do_inv && !seed) {
-        unpack_rows_to_lds(p, a.S, r0, v1, Z);
-        __syncthreads();
-        fft_lds<C, true, MR>(Z, sm, Px, 3, twx);
+    if (!seed && (p.terms & 1)) {
+        const T* const src[NV] = {a.u_cur, a.u_cur, a.u_cur, a.psi};
+        const int comp[NV] = {0, 1, 2, 0};
+        stage_rows<T, NV>(p, r0, src, comp, R);
     }
-    const int N = p.N, nx = p.nx;
+    if (demag_any)
+        for (int k = threadIdx.x; k < Px; k += blockDim.x) L.Tw[k] = twx[k];
+    if (demag_in) unpack_rows_to_lds(p, a.S, r0, v1, Z);
+    __syncthreads();
+    if (demag_in) fft_lds<C, true, MR>(Z, sm, Px, 3, L.Tw);
+
     const T dt = p.dt;
     // l_{s-1} = cl lambda' + cm mu_s (0-based stages): RK4 weights b = (1,2,2,1)/6 and nodes c = (0,1/2,1/2,1)
     const T cl = (a.stage == 1) ? dt / (T)6 : dt / (T)3;
@@ -421,6 +546,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const KParams<T> p, const Sta
         for (int rr = 0; rr < 2; ++rr) {
             const int r = r0 + rr;
             if (rr == 1 && !v1) break;
+            const int q = rr + 1;
             const int iy = r % p.ny, iz = r / p.ny;
             const int i = r * nx + x;
             const T pi = a.psi[i];
@@ -449,25 +575,27 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const KParams<T> p, const Sta
                     // exchange transpose and psi-gradient over the neighbours j of i:
                     //   mu_i += exw psi_i/s u_j - exw psi_j/s u_i
                     //   g_i  -= exw psi_j/s^2 (u_i + u_j).(m_j - m_i),   s = psi_i + psi_j
-                    auto nb = [&](int j, T w) {
-                        const T pj = a.psi[j];
+                    auto RU = [&](int qq, int xx) {
+                        return v3<T>(R[(qq * NV + 0) * nx + xx], R[(qq * NV + 1) * nx + xx], R[(qq * NV + 2) * nx + xx]);
+                    };
+                    auto RP = [&](int qq, int xx) { return R[(qq * NV + 3) * nx + xx]; };
+                    auto nb = [&](V3<T> uj, T pj, int j, T w) {
                         const T s = pi + pj;
                         if (s != (T)0) {
-                            const V3<T> uj = ld3(a.u_cur, N, j);
                             const V3<T> mj = ld3(a.ys, N, j);
                             const T is = (T)1 / s;
                             mu = mu + (w * pi * is) * uj - (w * pj * is) * uk;
                             g -= (double)(w * pj * is * is) * (double)dot(uk + uj, mj - m);
                         }
                     };
-                    if (x > 0) nb(i - 1, p.exw[0]);
-                    if (x < nx - 1) nb(i + 1, p.exw[0]);
-                    if (iy > 0) nb(i - nx, p.exw[1]);
-                    if (iy < p.ny - 1) nb(i + nx, p.exw[1]);
-                    if (iz > 0) nb(i - nx * p.ny, p.exw[2]);
-                    if (iz < p.nz - 1) nb(i + nx * p.ny, p.exw[2]);
+                    if (x > 0) nb(RU(q, x - 1), RP(q, x - 1), i - 1, p.exw[0]);
+                    if (x < nx - 1) nb(RU(q, x + 1), RP(q, x + 1), i + 1, p.exw[0]);
+                    if (iy > 0) nb(RU(q - 1, x), RP(q - 1, x), i - nx, p.exw[1]);
+                    if (iy < p.ny - 1) nb(RU(q + 1, x), RP(q + 1, x), i + nx, p.exw[1]);
+                    if (iz > 0) nb(ld3(a.u_cur, N, i - nx * p.ny), a.psi[i - nx * p.ny], i - nx * p.ny, p.exw[2]);
+                    if (iz < p.nz - 1) nb(ld3(a.u_cur, N, i + nx * p.ny), a.psi[i + nx * p.ny], i + nx * p.ny, p.exw[2]);
                 }
-                if (a.do_inv) {
+                if (demag_in) {
                     const C z01 = Z[rr * Px + x];
                     const C z2 = Z[2 * Px + x];
                     const V3<T> cu = v3<T>(z01.x, z01.y, rr == 0 ? z2.x : z2.y);
@@ -519,13 +647,15 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const KParams<T> p, const Sta
             Z[2 * Px + x] = cmk<C>(0, 0);
         }
         __syncthreads();
-        fft_lds<C, false, MR>(Z, sm, Px, 3, twx);
+        fft_lds<C, false, MR>(Z, sm, Px, 3, L.Tw);
         pack_lds_to_rows(p, a.S, r0, v1, Z);
     }
 }
 
 // ---------------------------------------------------------------------------
 // column kernel: y (and z) transforms + tensor-spectrum multiply, in place
+// shared memory: Z [c][z < nz][y < Py][tk] complex, Tw [Py] complex,
+//                Nt [comp][kz <= Pz/2][ky <= Py/2][tk] real
 // ---------------------------------------------------------------------------
 template <typename T, int NZ>
 __global__ void __launch_bounds__(512) k_col_conv(const KParams<T> p, cplx<T>* __restrict__ S,
@@ -533,13 +663,15 @@ __global__ void __launch_bounds__(512) k_col_conv(const KParams<T> p, cplx<T>* _
                                                   const cplx<T>* __restrict__ twz, int TK) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    C* Z = reinterpret_cast<C*>(smem_raw);  // [c][z < nz][y < Py][tk]
     constexpr int MR = MaxReg<T>::v;
     const int Kx = p.Kx, Py = p.Py, Pz = p.Pz, ny = p.ny, nz = p.nz;
+    const int plane = Py * TK;
+    C* Z = reinterpret_cast<C*>(smem_raw);
+    C* Tw = Z + 3 * nz * plane;
+    T* Nt = reinterpret_cast<T*>(Tw + Py);
     const int k0 = blockIdx.x * TK;
     const size_t cs = (size_t)p.nrows * Kx;
-    const int plane = Py * TK;
-    // load (zero-padded in y)
+    // load the columns (zero-padded in y), the twiddles and this tile of the tensor spectrum
     const int nload = 3 * nz * Py * TK;
     for (int e = threadIdx.x; e < nload; e += blockDim.x) {
         const int tk = e % TK;
@@ -551,12 +683,19 @@ __global__ void __launch_bounds__(512) k_col_conv(const KParams<T> p, cplx<T>* _
         if (y < ny && k0 + tk < Kx) v = S[c * cs + (size_t)(z * ny + y) * Kx + k0 + tk];
         Z[e] = v;
     }
+    for (int k = threadIdx.x; k < Py; k += blockDim.x) Tw[k] = twy[k];
+    const int ntile = p.ncomp * p.Kz2 * p.Ky2 * TK;
+    for (int e = threadIdx.x; e < ntile; e += blockDim.x) {
+        const int tk = e % TK, row = e / TK;  // row = (comp * Kz2 + kz) * Ky2 + ky
+        Nt[e] = (k0 + tk < Kx) ? nhat[(size_t)row * Kx + k0 + tk] : (T)0;
+    }
     __syncthreads();
-    const SigMap smy{TK, plane, 1, TK};
-    if (Py > 1) fft_lds<C, false, MR>(Z, smy, Py, 3 * nz * TK, twy);
+    const SigMap smy{ilog2_rt(TK), plane, 1, TK};
+    if (Py > 1) fft_lds<C, false, MR>(Z, smy, Py, 3 * nz * TK, Tw);
 
     // per (ky, tk): z transform in registers, tensor multiply, inverse z transform
     const int npair = Py * TK;
+    const int cstr = p.Kz2 * p.Ky2 * TK;
     for (int e = threadIdx.x; e < npair; e += blockDim.x) {
         const int tk = e % TK, ky = e / TK;
         const int kx = k0 + tk;
@@ -587,14 +726,13 @@ __global__ void __launch_bounds__(512) k_col_conv(const KParams<T> p, cplx<T>* _
             }
             const bool fz = kz > Pz / 2;
             const int kzr = fz ? Pz - kz : kz;
-            const size_t cstr = (size_t)p.Kz2 * p.Ky2 * Kx;
-            const size_t base = ((size_t)kzr * p.Ky2 + kyr) * Kx + kx;
-            const T nxx = nhat[base], nyy = nhat[cstr + base], nzz = nhat[2 * cstr + base];
-            const T nxy = (fy ? -nhat[3 * cstr + base] : nhat[3 * cstr + base]);
+            const int base = (kzr * p.Ky2 + kyr) * TK + tk;
+            const T nxx = Nt[base], nyy = Nt[cstr + base], nzz = Nt[2 * cstr + base];
+            const T nxy = fy ? -Nt[3 * cstr + base] : Nt[3 * cstr + base];
             T nxz = 0, nyz = 0;
             if (p.ncomp == 6) {
-                nxz = fz ? -nhat[4 * cstr + base] : nhat[4 * cstr + base];
-                nyz = nhat[5 * cstr + base];
+                nxz = fz ? -Nt[4 * cstr + base] : Nt[4 * cstr + base];
+                nyz = Nt[5 * cstr + base];
                 if (fy != fz) nyz = -nyz;
             }
             const C hx = cmk<C>(nxx * h[0].x + nxy * h[1].x + nxz * h[2].x, nxx * h[0].y + nxy * h[1].y + nxz * h[2].y);
@@ -617,7 +755,7 @@ __global__ void __launch_bounds__(512) k_col_conv(const KParams<T> p, cplx<T>* _
                 if (z < nz) Z[(c * nz + z) * plane + ky * TK + tk] = Y[c][z];
     }
     __syncthreads();
-    if (Py > 1) fft_lds<C, true, MR>(Z, smy, Py, 3 * nz * TK, twy);
+    if (Py > 1) fft_lds<C, true, MR>(Z, smy, Py, 3 * nz * TK, Tw);
     const int nstore = 3 * nz * ny * TK;
     for (int e = threadIdx.x; e < nstore; e += blockDim.x) {
         const int tk = e % TK;
@@ -679,7 +817,7 @@ __global__ void __launch_bounds__(512) k_energy(const KParams<T> p, double t, co
     if (demag) {
         unpack_rows_to_lds(p, S, r0, v1, Z);
         __syncthreads();
-        fft_lds<C, true, MR>(Z, SigMap{1, Px, 0, 1}, Px, 3, twx);
+        fft_lds<C, true, MR>(Z, SigMap{0, Px, 0, 1}, Px, 3, twx);
     }
     const T drv = (T)drive_value(p.f1, p.f2, p.t_switch, t);
     const int N = p.N, nx = p.nx;

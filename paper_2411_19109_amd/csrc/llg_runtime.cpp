@@ -103,6 +103,14 @@ struct llg_handle {
     void* U0 = nullptr;
     void* U1 = nullptr;
     double* gpsi = nullptr;
+    // per-kernel profiling (events around every launch while enabled)
+    struct ProfRec { int kind; double bytes; hipEvent_t a, b; };
+    bool prof_on = false;
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> ev_pool;
+    double prof_ms[LLG_KIND_COUNT] = {0};
+    double prof_bytes[LLG_KIND_COUNT] = {0};
+    int64_t prof_n[LLG_KIND_COUNT] = {0};
     // forward record
     bool fwd_valid = false;
     double t0 = 0.0;
@@ -225,25 +233,29 @@ int upload_tables(llg_handle* h) {
 int choose_launch(llg_handle* h) {
     const int maxreg = h->dtype == LLG_F32 ? 32 : 16;
     const size_t csz = 2 * h->tsz;
-    // local kernels: two rows per block, three complex signals of length Px
+    const int nx = h->prob.nx, nz = h->prob.nz;
+    // local kernels: two rows per block; LDS = three packed complex signals of
+    // length Px + Px twiddles (demag) + four staged rows of four values
     {
         int thr = (3 * h->Px + maxreg - 1) / maxreg;
-        thr = std::max(thr, std::min(h->prob.nx, 256));
+        thr = std::max(thr, std::min(nx, 512));
         thr = std::min(512, std::max(64, round_up(thr, 64)));
         h->loc.blocks = (h->nrows + 1) / 2;
         h->loc.threads = thr;
-        h->loc.lds = h->demag ? (size_t)3 * h->Px * csz : 0;
+        h->loc.lds = (h->demag ? (size_t)4 * h->Px * csz : 0) + (size_t)16 * nx * h->tsz;
         if (3 * h->Px > maxreg * 512 || h->loc.lds > 163840)
-            return fail(LLG_ESHAPE, "x extent too large for the row FFT (Px = " + std::to_string(h->Px) + ")");
+            return fail(LLG_ESHAPE, "x extent too large for the row kernels (nx = " + std::to_string(nx) + ")");
     }
-    // column kernel: TK adjacent x-bins per block
+    // column kernel: TK adjacent x-bins per block, as many as keep >= 256 blocks
     {
-        const int nz = h->prob.nz;
-        int tk = h->dtype == LLG_F32 ? 8 : 4;
-        while (tk > 1 && (tk > h->Kx || (size_t)3 * nz * h->Py * tk * csz > 65536 ||
-                          3 * nz * h->Py * tk > maxreg * 512))
+        const int Ky2 = h->Py / 2 + 1, Kz2 = h->Pz / 2 + 1;
+        auto lds_of = [&](int tk) {
+            return (size_t)3 * nz * h->Py * tk * csz + (size_t)h->Py * csz + (size_t)h->ncomp * Kz2 * Ky2 * tk * h->tsz;
+        };
+        int tk = 8;
+        while (tk > 1 && ((h->Kx + tk - 1) / tk < 256 || lds_of(tk) > 163840 || 3 * nz * h->Py * tk > maxreg * 512))
             tk /= 2;
-        if ((size_t)3 * nz * h->Py * tk * csz > 163840 || 3 * nz * h->Py * tk > maxreg * 512)
+        if (lds_of(tk) > 163840 || 3 * nz * h->Py * tk > maxreg * 512)
             return fail(LLG_ESHAPE, "y/z extent too large for the column FFT (Py = " + std::to_string(h->Py) +
                                         ", nz = " + std::to_string(nz) + ")");
         int thr = (3 * nz * h->Py * tk + maxreg - 1) / maxreg;
@@ -252,7 +264,7 @@ int choose_launch(llg_handle* h) {
         h->col.tk = tk;
         h->col.threads = thr;
         h->col.blocks = (h->Kx + tk - 1) / tk;
-        h->col.lds = (size_t)3 * nz * h->Py * tk * csz;
+        h->col.lds = lds_of(tk);
     }
     return LLG_OK;
 }
@@ -280,6 +292,34 @@ int validate_problem(const llg_problem* p) {
     return LLG_OK;
 }
 
+int take_events(llg_handle* h, hipEvent_t* a, hipEvent_t* b) {
+    for (hipEvent_t* e : {a, b}) {
+        if (!h->ev_pool.empty()) {
+            *e = h->ev_pool.back();
+            h->ev_pool.pop_back();
+        } else {
+            HIPCHK(hipEventCreate(e));
+        }
+    }
+    return LLG_OK;
+}
+
+// move finished profiling records into the per-kind totals
+int drain_profile(llg_handle* h) {
+    for (auto& r : h->prof) {
+        HIPCHK(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        h->prof_ms[r.kind] += ms;
+        h->prof_bytes[r.kind] += r.bytes;
+        h->prof_n[r.kind] += 1;
+        h->ev_pool.push_back(r.a);
+        h->ev_pool.push_back(r.b);
+    }
+    h->prof.clear();
+    return LLG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // typed orchestration
 // ---------------------------------------------------------------------------
@@ -292,10 +332,72 @@ struct Ops {
     size_t N3() const { return (size_t)3 * h->N; }
     T* tp(void* p, size_t off = 0) const { return static_cast<T*>(p) + off; }
 
+    // every kernel launch goes through here: optional event bracketing for profiling
+    template <typename F>
+    int run(int kind, double bytes, F&& launch) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (h->prof_on) {
+            if (int rc = take_events(h, &a, &b)) return rc;
+            HIPCHK(hipEventRecord(a, s));
+        }
+        hipError_t e = launch();
+        if (e != hipSuccess) return fail(LLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+        if (h->prof_on) {
+            HIPCHK(hipEventRecord(b, s));
+            h->prof.push_back({kind, bytes, a, b});
+        }
+        return LLG_OK;
+    }
+
+    // algorithmic HBM bytes of one launch (each array element read or written once)
+    double spec_bytes() const { return 3.0 * h->nrows * h->Kx * 2.0 * sizeof(T); }
+    double fwd_bytes(const StageFwdArgs<T>& a) const {
+        const double t = sizeof(T), n = h->N;
+        double b = n * 4 * t;  // ys, psi
+        if (a.do_inv) b += spec_bytes();
+        if (a.do_fwd) b += spec_bytes();
+        switch (a.stage) {
+            case 0: b += n * 6 * t; break;
+            case 1: case 2: b += n * 12 * t; break;
+            case 3: b += n * 6 * t; break;
+            case -1: b += n * 3 * t * (a.ynext ? 2 : 1); break;
+            default: break;
+        }
+        if (a.ys_store) b += n * 3 * t;
+        if (a.Bs_store && a.stage >= 0) b += n * 3 * t;
+        if (a.antenna) b += n;
+        if (a.port_part) b += 2 * n;
+        return b;
+    }
+    double bwd_bytes(const StageBwdArgs<T>& a) const {
+        const double t = sizeof(T), n = h->N;
+        double b = 0;
+        if (a.stage < 0) {
+            b = n * 13 * t + spec_bytes();
+        } else {
+            b = n * (16 * t + 16) + (a.stage == 3 ? 0 : n * 3 * t);
+            if (a.y_prev) b += n * 9 * t;
+            if (a.do_inv) b += spec_bytes();
+            if (a.do_fwd) b += spec_bytes();
+            if (a.port1) b += 2 * n;
+        }
+        return b;
+    }
+    double col_bytes() const {
+        return 2 * spec_bytes() + (double)h->ncomp * (h->Pz / 2 + 1) * (h->Py / 2 + 1) * h->Kx * sizeof(T);
+    }
+
     int col() {
         if (!h->demag) return LLG_OK;
-        HIPCHK(launch_col_conv<T>(P(), (C*)h->S, (const T*)h->nhat, (const C*)h->twy, (const C*)h->twz, h->col, s));
-        return LLG_OK;
+        return run(LLG_KIND_COLUMN, col_bytes(), [&] {
+            return launch_col_conv<T>(P(), (C*)h->S, (const T*)h->nhat, (const C*)h->twy, (const C*)h->twz, h->col, s);
+        });
+    }
+    int fwd(const StageFwdArgs<T>& a) {
+        return run(LLG_KIND_STAGE_FWD, fwd_bytes(a), [&] { return launch_stage_fwd<T>(P(), a, (const C*)h->twx, h->loc, s); });
+    }
+    int bwd(const StageBwdArgs<T>& a) {
+        return run(LLG_KIND_STAGE_BWD, bwd_bytes(a), [&] { return launch_stage_bwd<T>(P(), a, (const C*)h->twx, h->loc, s); });
     }
 
     // spectrum of psi * m into S
@@ -307,8 +409,7 @@ struct Ops {
         a.ys = m;
         a.S = (C*)h->S;
         a.do_fwd = 1;
-        HIPCHK(launch_stage_fwd<T>(P(), a, (const C*)h->twx, h->loc, s));
-        return LLG_OK;
+        return fwd(a);
     }
 
     // one RK4 step from h->m (spectrum of psi*m already in S); optional stage store
@@ -339,7 +440,7 @@ struct Ops {
             }
             a.do_inv = h->demag;
             a.do_fwd = h->demag && !(last && st == 3);
-            HIPCHK(launch_stage_fwd<T>(P(), a, (const C*)h->twx, h->loc, s));
+            if (int rc2 = fwd(a)) return rc2;
         }
         return LLG_OK;
     }
@@ -393,8 +494,7 @@ struct Ops {
         a.Bs_store = B;
         a.do_inv = h->demag;
         a.do_fwd = 0;
-        HIPCHK(launch_stage_fwd<T>(P(), a, (const C*)h->twx, h->loc, s));
-        return LLG_OK;
+        return fwd(a);
     }
 
     int objective(const llg_objective_spec* obj, const T* psi, const T* m, double t, double* J, T* dJdm, double* dJdpsi,
@@ -463,7 +563,7 @@ struct Ops {
                 a.u_next = Uc;
                 a.S = (C*)h->S;
                 a.do_fwd = h->demag;
-                HIPCHK(launch_stage_bwd<T>(P(), a, (const C*)h->twx, h->loc, s));
+                if (int rc2 = bwd(a)) return rc2;
             }
             for (int64_t k = n1 - 1; k >= n0; --k) {
                 const int64_t j = k - n0;
@@ -492,7 +592,7 @@ struct Ops {
                     }
                     a.do_inv = h->demag;
                     a.do_fwd = h->demag && a.y_prev != nullptr;
-                    HIPCHK(launch_stage_bwd<T>(P(), a, (const C*)h->twx, h->loc, s));
+                    if (int rc2 = bwd(a)) return rc2;
                     if (a.y_prev) std::swap(Uc, Uo);
                 }
                 std::swap(Lc, Lo);  // lambda_k is the lambda' of step k-1
@@ -627,8 +727,35 @@ int llg_create(const llg_problem* p, const llg_masks* masks, llg_handle** out) {
 int llg_destroy(llg_handle* h) {
     if (!h) return LLG_OK;
     (void)hipDeviceSynchronize();
+    for (auto& r : h->prof) {
+        h->ev_pool.push_back(r.a);
+        h->ev_pool.push_back(r.b);
+    }
+    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
     free_all(h);
     delete h;
+    return LLG_OK;
+}
+
+int llg_profile(llg_handle* h, int enable) {
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (int rc = drain_profile(h)) return rc;
+    h->prof_on = enable != 0;
+    return LLG_OK;
+}
+
+int llg_profile_read(llg_handle* h, int32_t kind, double* ms, int64_t* launches, double* bytes, int reset) {
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (kind < 0 || kind >= LLG_KIND_COUNT) return fail(LLG_EINVAL, "unknown kernel kind");
+    if (int rc = drain_profile(h)) return rc;
+    if (ms) *ms = h->prof_ms[kind];
+    if (launches) *launches = h->prof_n[kind];
+    if (bytes) *bytes = h->prof_bytes[kind];
+    if (reset) {
+        h->prof_ms[kind] = 0;
+        h->prof_n[kind] = 0;
+        h->prof_bytes[kind] = 0;
+    }
     return LLG_OK;
 }
 

@@ -23,7 +23,9 @@ LLG_OBJ_NONE, LLG_OBJ_ENERGY_AREA, LLG_OBJ_PORT_MY2 = 0, 1, 2
 
 EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_levelset_to_Ms",
            "llg_levelset_to_Ms_vjp", "llg_field", "llg_forward", "llg_objective", "llg_adjoint",
-           "llg_query_memory", "llg_fft_sizes"]
+           "llg_query_memory", "llg_fft_sizes", "llg_profile", "llg_profile_read"]
+KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
+KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col_conv", KIND_STAGE_BWD: "k_stage_bwd"}
 
 
 class LLGError(RuntimeError):
@@ -84,6 +86,8 @@ def lib():
         "llg_adjoint": [vp, vp, vp, vp, ctypes.POINTER(Objective_c), vp, vp, vp],
         "llg_query_memory": [ctypes.POINTER(Problem_c), i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
         "llg_fft_sizes": [vp, ctypes.POINTER(ctypes.c_int32)],
+        "llg_profile": [vp, ctypes.c_int],
+        "llg_profile_read": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -187,6 +191,15 @@ class Solver:
         if x.dtype != self.tdtype or not x.is_cuda or not x.is_contiguous() or x.numel() != n:
             raise ValueError(f"expected a contiguous cuda tensor of {n} {self.tdtype}")
         return x
+
+    def profile(self, enable: bool):
+        check(lib().llg_profile(self.h, int(enable)))
+
+    def profile_read(self, kind, reset=True):
+        """(device ms, launches, algorithmic bytes) summed over profiled launches of one kernel class."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        check(lib().llg_profile_read(self.h, kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b), int(reset)))
+        return ms.value, n.value, b.value
 
     def fft_sizes(self):
         a = (ctypes.c_int32 * 3)()

@@ -71,6 +71,48 @@ class GradientStep:
         return J, s.levelset_vjp(self.phi, dJdpsi, w.heaviside_a, extrude_z=True)
 
 
+class SweepStep:
+    """The batched sweep: 32 seeded designs x 2 drive frequencies on ragged grids,
+    one gradient evaluation of every instance with one launch sequence."""
+
+    def __init__(self, n_steps):
+        import torch
+        from paper_2411_19109_amd import llg, workloads as wl
+        self.ws = wl.yig_demux_sweep(n_steps=n_steps)
+        for w in self.ws:
+            w.obj_n_start = n_steps // 2
+        self.n_steps = n_steps
+        dev = torch.device("cuda:0")
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=torch.float32, device=dev)
+        self.batch = llg.Batch([w.problem for w in self.ws], dtype="f32", max_steps=n_steps,
+                               masks=[dict(antenna=w.antenna, port1=w.port1, port2=w.port2, design=w.design)
+                                      for w in self.ws])
+        self.phi = [t(w.phi) for w in self.ws]
+        self.psif = [t(w.psi_fixed) for w in self.ws]
+        self.m0 = [t(w.m0) for w in self.ws]
+        self.obj = llg.make_objective(wl.OBJ_PORT_MY2, n_start=n_steps // 2)
+        self.nodes = sum(w.problem.n for w in self.ws)
+
+    def __call__(self):
+        b = self.batch
+        a = self.ws[0].heaviside_a
+        psis = b.levelset_to_psi(self.phi, a, self.psif)
+        _, J = b.forward(psis, self.m0, self.n_steps, obj=self.obj, want_m=False)
+        g = b.adjoint(psis, self.obj)
+        return J, b.levelset_vjp(self.phi, g, a)
+
+
+def sweep_plain(n_steps, count):
+    """The same instances as single-instance solves, one after the other."""
+    from paper_2411_19109_amd import workloads as wl
+    ws = wl.yig_demux_sweep(n_steps=n_steps)
+    steps = []
+    for w in ws[:count]:
+        w.obj_n_start = n_steps // 2
+        steps.append(GradientStep(w))
+    return steps, sum(w.problem.n for w in ws[:count])
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The oracle as it stands, timed on the host on a bounded prefix of the
     same workload (forward + adjoint over the first n steps)."""
@@ -103,6 +145,10 @@ def main():
     ap.add_argument("--workload", default="particle")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--sweep-steps", type=int, default=200, help="RK4 steps per instance of the sweep workload")
+    ap.add_argument("--sweep-plain", type=int, default=8, help="instances timed one after the other for the plain rate")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -112,6 +158,15 @@ def main():
     import torch
     from paper_2411_19109_amd import llg
 
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 268435456 bytes read, 268435456 bytes written", file=sys.stderr, flush=True)
+        del src, dst
+    if args.workload == "sweep":
+        return run_sweep(args)
     w = make_workload(args.workload)
     step = GradientStep(w)
     print(f"[bench] workload {w.name}: {w.problem.nx}x{w.problem.ny}x{w.problem.nz} nodes, {w.n_steps} steps, "
@@ -173,6 +228,78 @@ def main():
                    "objective_J": float(J.item())},
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _kernel_stats(solver):
+    from paper_2411_19109_amd import llg
+    kinds = {}
+    for k, name in llg.KIND_NAMES.items():
+        ms, n, b = solver.profile_read(k)
+        if n:
+            kinds[name] = dict(ms=ms, launches=n, bytes=b, avg_us=1e3 * ms / n, gbs=b / (ms * 1e-3) / 1e9)
+    return kinds
+
+
+def run_sweep(args):
+    """Batched vs plain on the sweep workload (prefix of --sweep-steps RK4 steps
+    per instance; the per-step cost is constant, so the ratio holds for the full run)."""
+    import torch
+    from paper_2411_19109_amd import llg
+    n = args.sweep_steps
+    step = SweepStep(n)
+    print(f"[bench] sweep: {len(step.ws)} instances, {step.nodes} nodes, {n} steps", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] batched: {tb * 1e3:.1f} ms per sweep gradient", file=sys.stderr, flush=True)
+    step.batch.profile(True)
+    step()
+    torch.cuda.synchronize()
+    step.batch.profile(False)
+    kinds = _kernel_stats(step.batch)
+    for name, v in kinds.items():
+        print(f"[bench] batched {name}: {v['launches']} launches, avg {v['avg_us']:.2f} us, "
+              f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
+    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+    d = kinds[dom]
+    plain, nodes_p = sweep_plain(n, args.sweep_plain)
+    for p in plain[:1]:
+        p()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in plain:
+        p()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    rate_b = step.nodes * n / tb
+    rate_p = nodes_p * n / tp
+    print(f"[bench] plain: {tp * 1e3:.1f} ms for {len(plain)} sequential instances", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC,
+        "value": rate_b,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tb * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"yig_demux_sweep_64x_prefix{n}", "instances": len(step.ws), "nodes": step.nodes,
+                   "rk4_steps": n, "plain_cell_steps_per_s": rate_p, "plain_instances_timed": len(plain),
+                   "batched_over_plain": rate_b / rate_p},
+        "roofline": dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(d["gbs"] / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
+                         avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"])),
     }
     print(json.dumps(out), flush=True)
 

@@ -120,6 +120,9 @@ typedef struct llg_objective_spec {
 } llg_objective_spec;
 
 typedef struct llg_handle llg_handle;
+/* A batch of instances integrated together: every kernel launch of a batch
+ * call serves all of its instances (one launch per stage for the whole batch). */
+typedef struct llg_handle llg_batch;
 
 /* Message of the calling thread's most recent failure ("" if none). */
 const char* llg_last_error(void);
@@ -204,8 +207,31 @@ int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int3
 int llg_profile(llg_handle* h, int enable);
 int llg_profile_read(llg_handle* h, int32_t kind, double* ms, int64_t* launches, double* bytes, int reset);
 
-/* Padded FFT sizes the handle uses (Px, Py, Pz). */
+/* Padded FFT sizes the handle uses (Px, Py, Pz); of the first instance of a batch. */
 int llg_fft_sizes(const llg_handle* h, int32_t* P3);
+
+/* ---- batched execution ------------------------------------------------
+ * Many level-set designs and drive frequencies, on grids of different sizes,
+ * integrated together (the optimisation sweep of many initial level sets at
+ * once).  Instances must share dtype, terms, dt, max_steps and the checkpoint
+ * policy; grid, cell, material, field and drive parameters may differ.  The
+ * pointer arguments are HOST arrays of n device pointers (one per instance,
+ * sized for that instance as in the single-instance call); an array argument
+ * documented as nullable may be NULL as a whole.  J_dev receives n doubles.
+ * Results per instance are identical to running that instance alone. */
+int llg_batch_create(const llg_problem* probs, const llg_masks* masks, int32_t n, llg_batch** out);
+int llg_batch_destroy(llg_batch* b);
+int llg_batch_size(const llg_batch* b, int32_t* n);
+int llg_batch_levelset_to_Ms(llg_batch* b, const void* const* phi, const void* const* psi_fixed /* nullable */,
+                             double a, int extrude_z, void* const* psi_out, hipStream_t stream);
+int llg_batch_levelset_to_Ms_vjp(llg_batch* b, const void* const* phi, const double* const* dJdpsi, double a,
+                                 int extrude_z, double* const* dJdphi_out, hipStream_t stream);
+int llg_batch_forward(llg_batch* b, const void* const* psi, const void* const* m0, double t0, int64_t n_steps,
+                      const llg_objective_spec* obj, void* const* m_out /* nullable */, double* J_dev /* nullable */,
+                      hipStream_t stream);
+int llg_batch_adjoint(llg_batch* b, const void* const* psi, const void* const* dJdm_T /* nullable */,
+                      const double* const* dJdpsi_expl /* nullable */, const llg_objective_spec* obj,
+                      double* const* dJdpsi_out, void* const* dJdm0_out /* nullable */, hipStream_t stream);
 
 #ifdef __cplusplus
 }

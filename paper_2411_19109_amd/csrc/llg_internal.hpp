@@ -1,4 +1,11 @@
 // Internal declarations shared by the host runtime and the device kernels.
+//
+// Every kernel works on a *batch* of problem instances (a single-instance
+// solver is a batch of one).  Per-instance constants (KParams) and device
+// buffer pointers (InstTab) sit in device tables; a work list maps each
+// thread block to (instance, row pair) or (instance, column tile).  Launch
+// arguments shared by all instances (stage, time, which buffer plays which
+// role) travel by value, so the same launch sequence serves every instance.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -15,16 +22,58 @@ template <> struct Cx<float> { using type = float2; };
 template <> struct Cx<double> { using type = double2; };
 template <typename T> using cplx = typename Cx<T>::type;
 
-// Per-problem constants handed to every kernel by value (precision T).
+// Per-instance device buffers, addressed by role.
+enum BufId : int {
+    B_PSI = 0,  // material map psi (N)
+    B_PHI,      // level-set input (N or nx*ny)
+    B_PSIF,     // psi outside the design region (N)
+    B_DES,      // design mask (u8, N)
+    B_ANT,      // antenna mask (u8, N)
+    B_P1,       // port-1 mask (u8, N)
+    B_P2,       // port-2 mask (u8, N)
+    B_M,        // magnetisation m_n (3N)
+    B_ACC,      // RK accumulator (3N)
+    B_YA,       // stage state (3N)
+    B_YB,       // stage state (3N)
+    B_S,        // x-spectrum rows (3 * nrows * Kx complex)
+    B_TWX,      // twiddles (Px), (Py), (Pz)
+    B_TWY,
+    B_TWZ,
+    B_NHAT,     // tensor spectrum
+    B_SNAP,     // checkpoint snapshots (nsnap * 3N)
+    B_YS,       // stage states of a recomputed segment (K * 4 * 3N)
+    B_BS,       // fields of those stage states (K * 4 * 3N)
+    B_ELL,      // stage adjoint l_s (3N)
+    B_U0,       // field adjoint u (3N), ping-pong
+    B_U1,
+    B_L0,       // adjoint state lambda (3N), ping-pong
+    B_L1,
+    B_GPSI,     // dJ/dpsi accumulator (double, N)
+    B_DJDM,     // terminal dJ/dm input (3N)
+    B_DPSIE,    // explicit dJ/dpsi input (double, N)
+    B_DPSI,     // dJ/dpsi output (double, N)
+    B_DPHI,     // dJ/dphi output (double, N or nx*ny)
+    B_PPART,    // port partial sums (double, 2 per row-pair block)
+    B_EPART,    // energy partial sums (double, 5 per row-pair block)
+    B_SCAL,     // scalars (double[8]): [0] J, [1] area coefficient
+    B_COUNT
+};
+struct InstTab {
+    void* b[B_COUNT];
+};
+
+// Per-instance constants (precision T).
 template <typename T>
 struct KParams {
     int nx, ny, nz, N, nrows;      // nodes; rows = ny*nz lines along x
     int Px, Kx, Py, Pz, Ky2, Kz2;  // padded FFT sizes; Kx = Px/2+1; Ky2 = Py/2+1; Kz2 = Pz/2+1
     int ncomp;                     // stored tensor-spectrum components (4 in 2D, 6 in 3D)
     int terms;
-    T exw[3];          // 2 kappa / h_d^2, kappa = 2 A / Ms
-    T anis;            // 2 K / Ms
-    T u[3];            // anisotropy axis
+    int nloc;                      // row-pair blocks of this instance
+    int has_ant, n_p1, n_p2;       // mask populations
+    T exw[3];                      // 2 kappa / h_d^2, kappa = 2 A / Ms
+    T anis;                        // 2 K / Ms
+    T u[3];                        // anisotropy axis
     T B0[3];
     T brf[3];
     T alpha0, alpha_max;
@@ -34,86 +83,119 @@ struct KParams {
     double f1, f2, t_switch;
 };
 
-// Launch geometry chosen on the host.
-struct LocalLaunch { int blocks, threads; size_t lds; };
-struct ColLaunch { int blocks, threads, tk; size_t lds; };
-
-// Buffers of one RK stage (forward) evaluation.
-template <typename T>
-struct StageFwdArgs {
-    int stage;             // 0..3 (RK4 stage); -1: field evaluation; -3: spectrum of psi*ys only
-    double t;              // time of the stage
-    const T* psi;
-    const T* ys;           // stage input state (3N)
-    const T* mn;           // state at the start of the step (stages 1, 2)
-    T* acc;                // RK accumulator
-    T* ynext;              // next stage input / m_{n+1} at stage 3 / rhs output for stage -1
-    cplx<T>* S;            // x-spectrum rows (in place)
-    const uint8_t* antenna;
-    T* ys_store;           // optional copy of ys (adjoint recompute)
-    T* Bs_store;           // optional copy of B(ys) (adjoint recompute / field output)
-    const uint8_t* port1;  // optional port running cost (stage 3)
-    const uint8_t* port2;
-    double* port_part;     // per-block partial sums (2 per block)
-    int do_inv;            // inverse x-FFT of S gives the demag field
-    int do_fwd;            // forward x-FFT of psi*ynext into S
+// One forward-stage launch (shared by every instance of the batch).
+struct FwdL {
+    int stage;            // 0..3 RK4 stage; -1 field evaluation; -3 spectrum of psi*ys only
+    double t;             // time of the stage
+    int ys, mn, acc, ynext;  // BufId roles (-1 = none)
+    int store_j;          // >= 0: copy ys and B(ys) to slot store_j of YS / BS
+    int port;             // accumulate the port running cost (stage 3)
+    int do_inv, do_fwd;   // inverse x-FFT of S (demag in) / forward x-FFT of psi*ynext into S
+    void* ext_ys;         // single-instance overrides (field evaluation)
+    void* ext_ynext;
+    void* ext_B;
 };
 
+// One backward-stage launch.
+struct BwdL {
+    int stage;            // 3..0, or -2 seed (l = dt/6 lambda', u from y_prev)
+    int j;                // slot of this step's stage states in YS / BS
+    int prev_j, prev_st;  // slot and stage of y_prev (prev_j < 0: none)
+    int ucur, unext, lamp, lacc;  // BufId roles
+    int port_src;         // add the port running-cost source at stage 0
+    int W;                // port window length (steps)
+    int do_inv, do_fwd;
+};
+
+// Resolved per-instance arguments (built inside the kernels).
 template <typename T>
-struct StageBwdArgs {
-    int stage;             // 3..0, or -2: seed only (l = dt/6 lambda', u from y_prev)
+struct StageFwdArgs {
+    int stage;
+    double t;
     const T* psi;
-    const T* ys;           // stage state y_s
-    const T* Bs;           // field at y_s
-    const T* u_cur;        // u_s at every node
-    T* ell;                // in: l_s, out: l_{s-1} (or l_4 of the previous step)
-    const T* lamp;         // lambda' of the step
-    const T* lacc_in;      // running lambda sum (stage 3 reads lamp instead)
-    T* lacc_out;
-    double* gpsi;          // dJ/dpsi accumulator
-    const T* y_prev;       // y_{s-1}, or y_4 of step n-1 at stage 0; NULL = no chaining
-    T* u_next;
-    cplx<T>* S;            // conv(u_s) spectrum in, spectrum of u_next out
-    const uint8_t* port1;  // port source at stage 0 (NULL = none)
+    const T* ys;
+    const T* mn;
+    T* acc;
+    T* ynext;
+    cplx<T>* S;
+    const uint8_t* antenna;
+    T* ys_store;
+    T* Bs_store;
+    const uint8_t* port1;
     const uint8_t* port2;
-    T src1, src2;          // 2/(|W| |P1|), 2/(|W| |P2|)
+    double* port_part;
     int do_inv;
     int do_fwd;
 };
 
 template <typename T>
-hipError_t launch_stage_fwd(const KParams<T>& p, const StageFwdArgs<T>& a, const cplx<T>* twx,
-                            const LocalLaunch& L, hipStream_t s);
+struct StageBwdArgs {
+    int stage;
+    const T* psi;
+    const T* ys;
+    const T* Bs;
+    const T* u_cur;
+    T* ell;
+    const T* lamp;
+    const T* lacc_in;
+    T* lacc_out;
+    double* gpsi;
+    const T* y_prev;
+    T* u_next;
+    cplx<T>* S;
+    const uint8_t* port1;
+    const uint8_t* port2;
+    T src1, src2;
+    int do_inv;
+    int do_fwd;
+};
+
+// Table pointers handed to the kernels; a batch of one passes its instance
+// by value so that a block needs no dependent table loads before its work.
 template <typename T>
-hipError_t launch_stage_bwd(const KParams<T>& p, const StageBwdArgs<T>& a, const cplx<T>* twx,
-                            const LocalLaunch& L, hipStream_t s);
+struct BatchArgs {
+    const KParams<T>* ptab;
+    const InstTab* itab;
+    const int2* work;
+    int single;
+    KParams<T> p0;
+    InstTab t0;
+};
+
+// Device-side description of a batch.
 template <typename T>
-hipError_t launch_col_conv(const KParams<T>& p, cplx<T>* S, const T* nhat, const cplx<T>* twy,
-                           const cplx<T>* twz, const ColLaunch& L, hipStream_t s);
+struct BatchDev {
+    const KParams<T>* ptab;
+    const InstTab* itab;
+    const int2* work_loc;  // (instance, row pair)
+    const int2* work_col;  // (instance, column tile)
+    int nloc, ncol, ninst;
+    int max_n3;            // max 3N over instances (grid of element-wise kernels)
+    int loc_threads, col_threads, col_tk;
+    size_t loc_lds, col_lds;
+    KParams<T> p0;  // instance 0, by value
+    InstTab t0;
+};
+
+template <typename T> hipError_t launch_stage_fwd(const BatchDev<T>& b, const FwdL& L, hipStream_t s);
+template <typename T> hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s);
+template <typename T> hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, hipStream_t s);
+template <typename T> hipError_t launch_levelset(const BatchDev<T>& b, double a, int extrude, hipStream_t s);
+template <typename T> hipError_t launch_levelset_vjp(const BatchDev<T>& b, double a, int extrude, hipStream_t s);
 template <typename T>
-hipError_t launch_levelset(const KParams<T>& p, const T* phi, const T* psi_fixed, const uint8_t* design, double a,
-                           int extrude, T* psi_out, hipStream_t s);
+hipError_t launch_adj_init(const BatchDev<T>& b, int lam_sel, int use_djdm, int port, int W, hipStream_t s);
+template <typename T> hipError_t launch_psi_grad_out(const BatchDev<T>& b, int use_expl, hipStream_t s);
+template <typename T> hipError_t launch_zero(const BatchDev<T>& b, int sel, int what, hipStream_t s);
 template <typename T>
-hipError_t launch_levelset_vjp(const KParams<T>& p, const T* phi, const double* g, const uint8_t* design, double a,
-                               int extrude, double* out, hipStream_t s);
+hipError_t launch_copy(const BatchDev<T>& b, int src, int src_slot, int dst, int dst_slot, hipStream_t s);
+template <typename T> hipError_t launch_port_finish(const BatchDev<T>& b, int W, hipStream_t s);
 template <typename T>
-hipError_t launch_energy(const KParams<T>& p, double t, const T* psi, const T* m, const cplx<T>* S,
-                         const cplx<T>* twx, const uint8_t* antenna, double scale, T* dJdm, double* dJdpsi,
-                         double* part, const LocalLaunch& L, hipStream_t s);
-hipError_t launch_energy_finish_raw(const double* part, int nb, double MsV, double lam, double area, int N,
-                                    double E_ref, double* J, double* en, double* coef, double* dJdpsi,
-                                    hipStream_t s);
-hipError_t set_lds_limits(int bytes);
+hipError_t launch_energy(const BatchDev<T>& b, double t, const T* m, double scale, T* dJdm, double* dJdpsi,
+                         hipStream_t s);
 template <typename T>
-hipError_t launch_port_finish(const double* part, int nblocks, double inv1, double inv2, double invW, double* J,
-                              hipStream_t s);
-template <typename T>
-hipError_t launch_adj_init(const KParams<T>& p, const T* dJdm_T, const T* mN, const uint8_t* port1,
-                           const uint8_t* port2, T src1, T src2, T* lam, hipStream_t s);
-template <typename T>
-hipError_t launch_psi_grad_out(const KParams<T>& p, const double* gacc, const double* expl, double* out,
-                               hipStream_t s);
-hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s);
+hipError_t launch_energy_finish(const BatchDev<T>& b, double MsV, double lam, double area, double E_ref, double* J,
+                                double* en, double* dJdpsi, hipStream_t s);
+template <typename T> hipError_t set_lds_limits(size_t bytes);
 
 // Host side: tensor spectrum (float64) in the kernel layout, scaled by -mu0 Ms / (Px Py Pz).
 void build_tensor_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, int Px, int Py, int Pz,

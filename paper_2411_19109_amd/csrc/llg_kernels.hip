@@ -141,19 +141,23 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
 }
 
 // Full FFT of length L (power of two) of nsig signals; tw = exp(-2 pi i k / L).
-// Radix-16 passes while at least 16 points remain per sub-transform, then one
-// pass of the remaining radix (8, 4 or 2).
+// Passes of the largest radix the register budget allows (16 in float, 8 in
+// double) while enough points remain, then one pass of the remaining radix.
 template <typename C, bool INV, int MAXREG>
-__device__ void fft_lds(C* buf, const SigMap sm, int L, int nsig, const C* __restrict__ tw) {
+__device__ __forceinline__ void fft_lds(C* buf, const SigMap sm, int L, int nsig, const C* __restrict__ tw) {
     int lL = 0;
     while ((1 << lL) < L) ++lL;
     int lNs = 0;
     while (lNs < lL) {
         const int rem = lL - lNs;
-        if (rem >= 4) {
-            fft_pass<C, INV, 16, MAXREG>(buf, sm, lL, lNs, nsig, tw);
-            lNs += 4;
-        } else if (rem == 3) {
+        if constexpr (MAXREG >= 16) {
+            if (rem >= 4) {
+                fft_pass<C, INV, 16, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+                lNs += 4;
+                continue;
+            }
+        }
+        if (rem >= 3) {
             fft_pass<C, INV, 8, MAXREG>(buf, sm, lL, lNs, nsig, tw);
             lNs += 3;
         } else if (rem == 2) {
@@ -167,8 +171,8 @@ __device__ void fft_lds(C* buf, const SigMap sm, int L, int nsig, const C* __res
 }
 
 template <typename T> struct MaxReg;
-template <> struct MaxReg<float> { static constexpr int v = 32; };
-template <> struct MaxReg<double> { static constexpr int v = 16; };
+template <> struct MaxReg<float> { static constexpr int v = 16; };
+template <> struct MaxReg<double> { static constexpr int v = 8; };
 
 // ---------------------------------------------------------------------------
 // node-local physics helpers
@@ -338,23 +342,89 @@ __device__ __forceinline__ void stage_rows(const KParams<T>& p, int r0, const T*
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// batch addressing: thread block -> (instance, unit), role -> buffer
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T* role(const InstTab& tb, int id) {
+    return id < 0 ? nullptr : static_cast<T*>(tb.b[id]);
+}
+
+template <typename T>
+__device__ __forceinline__ StageFwdArgs<T> resolve_fwd(const KParams<T>& p, const InstTab& tb, const FwdL& L) {
+    StageFwdArgs<T> a;
+    const size_t n3 = (size_t)3 * p.N;
+    a.stage = L.stage;
+    a.t = L.t;
+    a.psi = role<T>(tb, B_PSI);
+    a.ys = L.ext_ys ? static_cast<const T*>(L.ext_ys) : role<T>(tb, L.ys);
+    a.mn = role<T>(tb, L.mn);
+    a.acc = role<T>(tb, L.acc);
+    a.ynext = L.ext_ynext ? static_cast<T*>(L.ext_ynext) : role<T>(tb, L.ynext);
+    a.S = role<cplx<T>>(tb, B_S);
+    a.antenna = p.has_ant ? role<uint8_t>(tb, B_ANT) : nullptr;
+    a.ys_store = L.store_j >= 0 ? role<T>(tb, B_YS) + ((size_t)L.store_j * 4 + L.stage) * n3 : nullptr;
+    a.Bs_store = L.ext_B ? static_cast<T*>(L.ext_B)
+                         : (L.store_j >= 0 ? role<T>(tb, B_BS) + ((size_t)L.store_j * 4 + L.stage) * n3 : nullptr);
+    const bool port = L.port && (p.n_p1 + p.n_p2) > 0;
+    a.port1 = port ? role<uint8_t>(tb, B_P1) : nullptr;
+    a.port2 = port ? role<uint8_t>(tb, B_P2) : nullptr;
+    a.port_part = port ? role<double>(tb, B_PPART) : nullptr;
+    a.do_inv = L.do_inv;
+    a.do_fwd = L.do_fwd;
+    return a;
+}
+
+template <typename T>
+__device__ __forceinline__ StageBwdArgs<T> resolve_bwd(const KParams<T>& p, const InstTab& tb, const BwdL& L) {
+    StageBwdArgs<T> a;
+    const size_t n3 = (size_t)3 * p.N;
+    const int st = L.stage < 0 ? 0 : L.stage;
+    a.stage = L.stage;
+    a.psi = role<T>(tb, B_PSI);
+    a.ys = role<T>(tb, B_YS) + ((size_t)L.j * 4 + st) * n3;
+    a.Bs = role<T>(tb, B_BS) + ((size_t)L.j * 4 + st) * n3;
+    a.u_cur = role<T>(tb, L.ucur);
+    a.ell = role<T>(tb, B_ELL);
+    a.lamp = role<T>(tb, L.lamp);
+    a.lacc_in = role<T>(tb, L.lacc);
+    a.lacc_out = role<T>(tb, L.lacc);
+    a.gpsi = role<double>(tb, B_GPSI);
+    a.y_prev = L.prev_j >= 0 ? role<T>(tb, B_YS) + ((size_t)L.prev_j * 4 + L.prev_st) * n3 : nullptr;
+    a.u_next = role<T>(tb, L.unext);
+    a.S = role<cplx<T>>(tb, B_S);
+    const bool port = L.port_src && (p.n_p1 + p.n_p2) > 0 && L.W > 0;
+    a.port1 = port ? role<uint8_t>(tb, B_P1) : nullptr;
+    a.port2 = port ? role<uint8_t>(tb, B_P2) : nullptr;
+    a.src1 = port && p.n_p1 > 0 ? (T)(2.0 / ((double)L.W * p.n_p1)) : (T)0;
+    a.src2 = port && p.n_p2 > 0 ? (T)(2.0 / ((double)L.W * p.n_p2)) : (T)0;
+    a.do_inv = L.do_inv;
+    a.do_fwd = L.do_fwd;
+    return a;
+}
+
 // ---------------------------------------------------------------------------
 // forward local kernel: inverse x-FFT (demag) + local field + LL RHS + RK4
 // stage update + forward x-FFT of the next stage's magnetisation
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(512) k_stage_fwd(const KParams<T> p, const StageFwdArgs<T> a,
-                                                   const cplx<T>* __restrict__ twx) {
+__global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const FwdL L) {
     using C = cplx<T>;
     constexpr int NV = 4;  // m_x, m_y, m_z, psi
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[2][512 / 64];
+    const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
+    const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
+    const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
+    const StageFwdArgs<T> a = resolve_fwd<T>(p, tb, L);
+    const cplx<T>* __restrict__ twx = role<cplx<T>>(tb, B_TWX);
     const int Px = p.Px, nx = p.nx, N = p.N;
     const bool demag_in = a.do_inv != 0, demag_any = (a.do_inv | a.do_fwd) != 0;
-    const LocalSmem<T> L = local_smem<T>(smem_raw, Px, demag_any);
-    C* Z = L.Z;
-    T* R = L.R;
-    const int r0 = 2 * blockIdx.x;
+    const LocalSmem<T> LS = local_smem<T>(smem_raw, Px, demag_any);
+    C* Z = LS.Z;
+    T* R = LS.R;
+    const int r0 = 2 * wk.y;
     const bool v1 = r0 + 1 < p.nrows;
     constexpr int MR = MaxReg<T>::v;
     const SigMap sm{0, Px, 0, 1};
@@ -364,11 +434,24 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const KParams<T> p, const Sta
         const int comp[NV] = {0, 1, 2, 0};
         stage_rows<T, NV>(p, r0, src, comp, R);
     }
+    // the accumulator and the step-start state of the first column this thread
+    // updates are loaded now, so their latency overlaps the inverse FFT
+    V3<T> pre_acc[2], pre_mn[2];
+    const bool need_acc = a.stage >= 1 && a.stage <= 3, need_mn = a.stage == 1 || a.stage == 2;
+    if ((int)threadIdx.x < nx) {
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const int i = (r0 + rr) * nx + threadIdx.x;
+            if (rr == 1 && !v1) break;
+            if (need_acc) pre_acc[rr] = ld3(a.acc, N, i);
+            if (need_mn) pre_mn[rr] = ld3(a.mn, N, i);
+        }
+    }
     if (demag_any)
-        for (int k = threadIdx.x; k < Px; k += blockDim.x) L.Tw[k] = twx[k];
+        for (int k = threadIdx.x; k < Px; k += blockDim.x) LS.Tw[k] = twx[k];
     if (demag_in) unpack_rows_to_lds(p, a.S, r0, v1, Z);
     __syncthreads();
-    if (demag_in) fft_lds<C, true, MR>(Z, sm, Px, 3, L.Tw);
+    if (demag_in) fft_lds<C, true, MR>(Z, sm, Px, 3, LS.Tw);
 
     const T drv = (T)drive_value(p.f1, p.f2, p.t_switch, a.t);
     const T dt = p.dt;
@@ -426,6 +509,9 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const KParams<T> p, const Sta
             }
             if (a.ys_store) st3(a.ys_store, N, i, m);
             if (a.Bs_store) st3(a.Bs_store, N, i, B);
+            const bool first = x == (int)threadIdx.x;
+            const V3<T> accv = need_acc ? (first ? pre_acc[rr] : ld3(a.acc, N, i)) : v3<T>(0, 0, 0);
+            const V3<T> mnv = need_mn ? (first ? pre_mn[rr] : ld3(a.mn, N, i)) : v3<T>(0, 0, 0);
             V3<T> yn;
             if (a.stage == -3) {
                 yn = m;  // prologue: spectrum of psi * m only
@@ -435,13 +521,13 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const KParams<T> p, const Sta
                 st3(a.acc, N, i, m + (dt / (T)6) * f);
                 yn = m + (dt / (T)2) * f;
             } else if (a.stage == 1) {
-                st3(a.acc, N, i, ld3(a.acc, N, i) + (dt / (T)3) * f);
-                yn = ld3(a.mn, N, i) + (dt / (T)2) * f;
+                st3(a.acc, N, i, accv + (dt / (T)3) * f);
+                yn = mnv + (dt / (T)2) * f;
             } else if (a.stage == 2) {
-                st3(a.acc, N, i, ld3(a.acc, N, i) + (dt / (T)3) * f);
-                yn = ld3(a.mn, N, i) + dt * f;
+                st3(a.acc, N, i, accv + (dt / (T)3) * f);
+                yn = mnv + dt * f;
             } else {
-                yn = ld3(a.acc, N, i) + (dt / (T)6) * f;
+                yn = accv + (dt / (T)6) * f;
             }
             if (a.ynext) st3(a.ynext, N, i, yn);
             if (a.port_part) {
@@ -477,8 +563,8 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const KParams<T> p, const Sta
                 t1 += red[0][k];
                 t2 += red[1][k];
             }
-            a.port_part[2 * blockIdx.x] += t1;
-            a.port_part[2 * blockIdx.x + 1] += t2;
+            a.port_part[2 * wk.y] += t1;
+            a.port_part[2 * wk.y + 1] += t2;
         }
     }
     if (a.do_fwd) {
@@ -488,7 +574,7 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const KParams<T> p, const Sta
             Z[2 * Px + x] = cmk<C>(0, 0);
         }
         __syncthreads();
-        fft_lds<C, false, MR>(Z, sm, Px, 3, L.Tw);
+        fft_lds<C, false, MR>(Z, sm, Px, 3, LS.Tw);
         pack_lds_to_rows(p, a.S, r0, v1, Z);
     }
 }
@@ -508,18 +594,22 @@ __device__ __forceinline__ V3<T> field_adjoint(const KParams<T>& p, V3<T> ell, V
 }
 
 template <typename T>
-__global__ void __launch_bounds__(512) k_stage_bwd(const KParams<T> p, const StageBwdArgs<T> a,
-                                                   const cplx<T>* __restrict__ twx) {
+__global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const BwdL L) {
     using C = cplx<T>;
     constexpr int NV = 4;  // u_x, u_y, u_z, psi
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
+    const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
+    const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
+    const StageBwdArgs<T> a = resolve_bwd<T>(p, tb, L);
+    const cplx<T>* __restrict__ twx = role<cplx<T>>(tb, B_TWX);
     const int Px = p.Px, nx = p.nx, N = p.N;
     const bool seed = a.stage < 0;
     const bool demag_in = a.do_inv && !seed, demag_any = (a.do_inv | a.do_fwd) != 0;
-    const LocalSmem<T> L = local_smem<T>(smem_raw, Px, demag_any);
-    C* Z = L.Z;
-    T* R = L.R;
-    const int r0 = 2 * blockIdx.x;
+    const LocalSmem<T> LS = local_smem<T>(smem_raw, Px, demag_any);
+    C* Z = LS.Z;
+    T* R = LS.R;
+    const int r0 = 2 * wk.y;
     const bool v1 = r0 + 1 < p.nrows;
     constexpr int MR = MaxReg<T>::v;
     const SigMap sm{0, Px, 0, 1};
@@ -530,10 +620,10 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const KParams<T> p, const Sta
         stage_rows<T, NV>(p, r0, src, comp, R);
     }
     if (demag_any)
-        for (int k = threadIdx.x; k < Px; k += blockDim.x) L.Tw[k] = twx[k];
+        for (int k = threadIdx.x; k < Px; k += blockDim.x) LS.Tw[k] = twx[k];
     if (demag_in) unpack_rows_to_lds(p, a.S, r0, v1, Z);
     __syncthreads();
-    if (demag_in) fft_lds<C, true, MR>(Z, sm, Px, 3, L.Tw);
+    if (demag_in) fft_lds<C, true, MR>(Z, sm, Px, 3, LS.Tw);
 
     const T dt = p.dt;
     // l_{s-1} = cl lambda' + cm mu_s (0-based stages): RK4 weights b = (1,2,2,1)/6 and nodes c = (0,1/2,1/2,1)
@@ -647,7 +737,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const KParams<T> p, const Sta
             Z[2 * Px + x] = cmk<C>(0, 0);
         }
         __syncthreads();
-        fft_lds<C, false, MR>(Z, sm, Px, 3, L.Tw);
+        fft_lds<C, false, MR>(Z, sm, Px, 3, LS.Tw);
         pack_lds_to_rows(p, a.S, r0, v1, Z);
     }
 }
@@ -658,18 +748,23 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const KParams<T> p, const Sta
 //                Nt [comp][kz <= Pz/2][ky <= Py/2][tk] real
 // ---------------------------------------------------------------------------
 template <typename T, int NZ>
-__global__ void __launch_bounds__(512) k_col_conv(const KParams<T> p, cplx<T>* __restrict__ S,
-                                                  const T* __restrict__ nhat, const cplx<T>* __restrict__ twy,
-                                                  const cplx<T>* __restrict__ twz, int TK) {
+__global__ void __launch_bounds__(1024) k_col_conv(const BatchArgs<T> ba, int TK) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int MR = MaxReg<T>::v;
+    const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
+    const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
+    const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
+    C* __restrict__ S = role<C>(tb, B_S);
+    const T* __restrict__ nhat = role<T>(tb, B_NHAT);
+    const C* __restrict__ twy = role<C>(tb, B_TWY);
+    const C* __restrict__ twz = role<C>(tb, B_TWZ);
     const int Kx = p.Kx, Py = p.Py, Pz = p.Pz, ny = p.ny, nz = p.nz;
     const int plane = Py * TK;
     C* Z = reinterpret_cast<C*>(smem_raw);
     C* Tw = Z + 3 * nz * plane;
     T* Nt = reinterpret_cast<T*>(Tw + Py);
-    const int k0 = blockIdx.x * TK;
+    const int k0 = wk.y * TK;
     const size_t cs = (size_t)p.nrows * Kx;
     // load the columns (zero-padded in y), the twiddles and this tile of the tensor spectrum
     const int nload = 3 * nz * Py * TK;
@@ -768,56 +863,149 @@ __global__ void __launch_bounds__(512) k_col_conv(const KParams<T> p, cplx<T>* _
 }
 
 // ---------------------------------------------------------------------------
-// level set, objectives, small helpers
+// element-wise kernels over (element, instance) grids
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_levelset(const KParams<T> p, const T* __restrict__ phi, const T* __restrict__ psi_fixed,
-                           const uint8_t* __restrict__ design, T a, int extrude, T* __restrict__ psi) {
+__global__ void k_levelset(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, T a, int extrude) {
+    const int inst = blockIdx.y;
+    const KParams<T>& p = ptab[inst];
+    const InstTab& tb = itab[inst];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.N) return;
     const int j = extrude ? i % (p.nx * p.ny) : i;
-    const T fixed = psi_fixed ? psi_fixed[i] : (T)0;
-    psi[i] = (design && design[i]) ? (T)1 / ((T)1 + exp(-a * phi[j])) : fixed;
+    const T* phi = role<T>(tb, B_PHI);
+    const T* pf = role<T>(tb, B_PSIF);
+    const uint8_t* des = role<uint8_t>(tb, B_DES);
+    role<T>(tb, B_PSI)[i] = des[i] ? (T)1 / ((T)1 + exp(-a * phi[j])) : pf[i];
 }
 
 template <typename T>
-__global__ void k_levelset_vjp(const KParams<T> p, const T* __restrict__ phi, const double* __restrict__ g,
-                               const uint8_t* __restrict__ design, double a, int extrude, double* __restrict__ out) {
+__global__ void k_levelset_vjp(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, double a,
+                               int extrude) {
+    const int inst = blockIdx.y;
+    const KParams<T>& p = ptab[inst];
+    const InstTab& tb = itab[inst];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int M = extrude ? p.nx * p.ny : p.N;
     if (j >= M) return;
     const int nl = extrude ? p.nz : 1;
+    const T* phi = role<T>(tb, B_PHI);
+    const double* g = role<double>(tb, B_DPSI);
+    const uint8_t* des = role<uint8_t>(tb, B_DES);
     const double H = 1.0 / (1.0 + exp(-a * (double)phi[j]));
     const double hp = a * H * (1.0 - H);
     double s = 0.0;
     for (int l = 0; l < nl; ++l) {
         const int i = j + l * M;
-        if (design && design[i]) s += hp * g[i];
+        if (des[i]) s += hp * g[i];
     }
-    out[j] = s;
+    role<double>(tb, B_DPHI)[j] = s;
 }
 
-// Energy terms, dJ/dm and explicit dJ/dpsi of the energy + area objective,
-// with per-block partial sums (ex, d, Z, an, psi) in fixed order.
 template <typename T>
-__global__ void __launch_bounds__(512) k_energy(const KParams<T> p, double t, const T* __restrict__ psi,
-                                                const T* __restrict__ m, const cplx<T>* __restrict__ S,
-                                                const cplx<T>* __restrict__ twx, const uint8_t* __restrict__ antenna,
-                                                double scale, T* __restrict__ dJdm, double* __restrict__ dJdpsi,
-                                                double* __restrict__ part) {
+__global__ void k_adj_init(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, int lam_sel,
+                           int use_djdm, int port, int W) {
+    const int inst = blockIdx.y;
+    const KParams<T>& p = ptab[inst];
+    const InstTab& tb = itab[inst];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.N) return;
+    const int N = p.N;
+    V3<T> l = use_djdm ? ld3(role<T>(tb, B_DJDM), N, i) : v3<T>(0, 0, 0);
+    if (port && W > 0 && (p.n_p1 + p.n_p2) > 0) {
+        const T s1 = p.n_p1 > 0 ? (T)(2.0 / ((double)W * p.n_p1)) : (T)0;
+        const T s2 = p.n_p2 > 0 ? (T)(2.0 / ((double)W * p.n_p2)) : (T)0;
+        const T src = (role<uint8_t>(tb, B_P1)[i] ? s1 : (T)0) - (role<uint8_t>(tb, B_P2)[i] ? s2 : (T)0);
+        l.y = l.y + src * role<T>(tb, B_M)[N + i];
+    }
+    st3(role<T>(tb, lam_sel), N, i, l);
+}
+
+template <typename T>
+__global__ void k_psi_grad_out(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, int use_expl) {
+    const int inst = blockIdx.y;
+    const KParams<T>& p = ptab[inst];
+    const InstTab& tb = itab[inst];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.N) return;
+    role<double>(tb, B_DPSI)[i] = role<double>(tb, B_GPSI)[i] + (use_expl ? role<double>(tb, B_DPSIE)[i] : 0.0);
+}
+
+// what: 0 = N doubles, 1 = 2 * nloc doubles (port partials)
+template <typename T>
+__global__ void k_zero(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, int sel, int what) {
+    const int inst = blockIdx.y;
+    const KParams<T>& p = ptab[inst];
+    const int n = what == 0 ? p.N : 2 * p.nloc;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) role<double>(itab[inst], sel)[i] = 0.0;
+}
+
+template <typename T>
+__global__ void k_copy(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, int src, int src_slot,
+                       int dst, int dst_slot) {
+    const int inst = blockIdx.y;
+    const size_t n3 = (size_t)3 * ptab[inst].N;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    const InstTab& tb = itab[inst];
+    role<T>(tb, dst)[dst_slot * n3 + i] = role<T>(tb, src)[src_slot * n3 + i];
+}
+
+// one block per instance: J = (sum part1 / |P1| - sum part2 / |P2|) / W, fixed order
+template <typename T>
+__global__ void k_port_finish(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, int W) {
+    __shared__ double red[2][256];
+    const int inst = blockIdx.x;
+    const KParams<T>& p = ptab[inst];
+    const InstTab& tb = itab[inst];
+    const double* part = role<double>(tb, B_PPART);
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = threadIdx.x; b < p.nloc; b += blockDim.x) {
+        s1 += part[2 * b];
+        s2 += part[2 * b + 1];
+    }
+    red[0][threadIdx.x] = s1;
+    red[1][threadIdx.x] = s2;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double i1 = p.n_p1 > 0 ? 1.0 / p.n_p1 : 0.0, i2 = p.n_p2 > 0 ? 1.0 / p.n_p2 : 0.0;
+        role<double>(tb, B_SCAL)[0] = W > 0 ? (red[0][0] * i1 - red[1][0] * i2) / W : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// energy + area objective (single instance): energy terms, dJ/dm and the
+// explicit dJ/dpsi, with per-block partial sums (ex, d, Z, an, psi)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(512) k_energy(const BatchArgs<T> ba, double t, const T* __restrict__ m,
+                                                double scale, T* __restrict__ dJdm, double* __restrict__ dJdpsi) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C* Z = reinterpret_cast<C*>(smem_raw);
     __shared__ double red[5][512 / 64];
-    const int r0 = 2 * blockIdx.x;
+    const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
+    const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
+    const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
+    const T* __restrict__ psi = role<T>(tb, B_PSI);
+    const uint8_t* antenna = p.has_ant ? role<uint8_t>(tb, B_ANT) : nullptr;
+    const int r0 = 2 * wk.y;
     const bool v1 = r0 + 1 < p.nrows;
     const int Px = p.Px;
     constexpr int MR = MaxReg<T>::v;
     const bool demag = (p.terms & 2) != 0;
     if (demag) {
-        unpack_rows_to_lds(p, S, r0, v1, Z);
+        unpack_rows_to_lds(p, role<C>(tb, B_S), r0, v1, Z);
         __syncthreads();
-        fft_lds<C, true, MR>(Z, SigMap{0, Px, 0, 1}, Px, 3, twx);
+        fft_lds<C, true, MR>(Z, SigMap{0, Px, 0, 1}, Px, 3, role<C>(tb, B_TWX));
     }
     const T drv = (T)drive_value(p.f1, p.f2, p.t_switch, t);
     const int N = p.N, nx = p.nx;
@@ -885,22 +1073,26 @@ __global__ void __launch_bounds__(512) k_energy(const KParams<T> p, double t, co
         for (int q = 0; q < 5; ++q) red[q][w] = e[q];
     __syncthreads();
     if (threadIdx.x == 0) {
+        double* part = role<double>(tb, B_EPART);
         for (int q = 0; q < 5; ++q) {
             double s = 0.0;
             for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[q][k];
-            part[5 * blockIdx.x + q] = s;
+            part[5 * wk.y + q] = s;
         }
     }
 }
 
-// Single-block fixed-order reduction of the energy partials.
-// part entries are in units of Ms*V (exchange: in units of Ms*V as well, see k_energy).
-__global__ void k_energy_finish(const double* __restrict__ part, int nb, double MsV, double lam, double area, int N,
-                                double E_ref, double* __restrict__ J, double* __restrict__ en,
-                                double* __restrict__ coef_out) {
+// Single-block fixed-order reduction of the energy partials (units of Ms V).
+template <typename T>
+__global__ void k_energy_finish(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, double MsV,
+                                double lam, double area, double E_ref, double* __restrict__ J,
+                                double* __restrict__ en) {
     __shared__ double red[5][256];
+    const KParams<T>& p = ptab[0];
+    const InstTab& tb = itab[0];
+    const double* part = role<double>(tb, B_EPART);
     double s[5] = {0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+    for (int b = threadIdx.x; b < p.nloc; b += blockDim.x)
         for (int q = 0; q < 5; ++q) s[q] += part[5 * b + q];
     for (int q = 0; q < 5; ++q) red[q][threadIdx.x] = s[q];
     __syncthreads();
@@ -911,7 +1103,7 @@ __global__ void k_energy_finish(const double* __restrict__ part, int nb, double 
     }
     if (threadIdx.x == 0) {
         const double ex = red[0][0] * MsV, d = red[1][0] * MsV, z = red[2][0] * MsV, an = red[3][0] * MsV;
-        const double mean = red[4][0] / N;
+        const double mean = red[4][0] / p.N;
         if (en) {
             en[0] = ex;
             en[1] = d;
@@ -919,185 +1111,149 @@ __global__ void k_energy_finish(const double* __restrict__ part, int nb, double 
             en[3] = an;
             en[4] = ex + d + z + an;
         }
-        if (J) *J = (ex + d) / E_ref + lam * (mean - area) * (mean - area);
-        *coef_out = 2.0 * lam * (mean - area) / N;
+        const double Jv = (ex + d) / E_ref + lam * (mean - area) * (mean - area);
+        if (J) *J = Jv;
+        double* sc = role<double>(tb, B_SCAL);
+        sc[0] = Jv;
+        sc[1] = 2.0 * lam * (mean - area) / p.N;
     }
-}
-
-__global__ void k_add_coef(double* __restrict__ g, const double* __restrict__ coef, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) g[i] += *coef;
-}
-
-__global__ void k_port_finish(const double* __restrict__ part, int nb, double inv1, double inv2, double invW,
-                              double* __restrict__ J) {
-    __shared__ double red[2][256];
-    double s1 = 0.0, s2 = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        s1 += part[2 * b];
-        s2 += part[2 * b + 1];
-    }
-    red[0][threadIdx.x] = s1;
-    red[1][threadIdx.x] = s2;
-    __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + h];
-            red[1][threadIdx.x] += red[1][threadIdx.x + h];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *J = invW * (red[0][0] * inv1 - red[1][0] * inv2);
 }
 
 template <typename T>
-__global__ void k_adj_init(const KParams<T> p, const T* __restrict__ dJdm, const T* __restrict__ mN,
-                           const uint8_t* __restrict__ port1, const uint8_t* __restrict__ port2, T src1, T src2,
-                           T* __restrict__ lam) {
+__global__ void k_add_area(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab,
+                           double* __restrict__ g) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.N) return;
-    const int N = p.N;
-    V3<T> l = dJdm ? ld3(dJdm, N, i) : v3<T>(0, 0, 0);
-    if (port1) {
-        const T src = (port1[i] ? src1 : (T)0) - (port2[i] ? src2 : (T)0);
-        l.y = l.y + src * mN[N + i];
-    }
-    st3(lam, N, i, l);
-}
-
-template <typename T>
-__global__ void k_psi_grad_out(int n, const double* __restrict__ gacc, const double* __restrict__ expl,
-                               double* __restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = gacc[i] + (expl ? expl[i] : 0.0);
-}
-
-__global__ void k_zero_f64(double* __restrict__ p, size_t n) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0;
+    if (i < ptab[0].N) g[i] += role<double>(itab[0], B_SCAL)[1];
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_stage_fwd(const KParams<T>& p, const StageFwdArgs<T>& a, const cplx<T>* twx, const LocalLaunch& L,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_stage_fwd<T>, dim3(L.blocks), dim3(L.threads), L.lds, s, p, a, twx);
+static BatchArgs<T> bargs(const BatchDev<T>& b, const int2* work) {
+    BatchArgs<T> a;
+    a.ptab = b.ptab;
+    a.itab = b.itab;
+    a.work = work;
+    a.single = b.ninst == 1;
+    a.p0 = b.p0;
+    a.t0 = b.t0;
+    return a;
+}
+template <typename T>
+hipError_t launch_stage_fwd(const BatchDev<T>& b, const FwdL& L, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_fwd<T>, dim3(b.nloc), dim3(b.loc_threads), b.loc_lds, s, bargs(b, b.work_loc), L);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_stage_bwd(const KParams<T>& p, const StageBwdArgs<T>& a, const cplx<T>* twx, const LocalLaunch& L,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_stage_bwd<T>, dim3(L.blocks), dim3(L.threads), L.lds, s, p, a, twx);
+hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_bwd<T>, dim3(b.nloc), dim3(b.loc_threads), b.loc_lds, s, bargs(b, b.work_loc), L);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_col_conv(const KParams<T>& p, cplx<T>* S, const T* nhat, const cplx<T>* twy, const cplx<T>* twz,
-                           const ColLaunch& L, hipStream_t s) {
-    if (p.nz == 1)
-        hipLaunchKernelGGL((k_col_conv<T, 1>), dim3(L.blocks), dim3(L.threads), L.lds, s, p, S, nhat, twy, twz, L.tk);
-    else if (p.nz == 2)
-        hipLaunchKernelGGL((k_col_conv<T, 2>), dim3(L.blocks), dim3(L.threads), L.lds, s, p, S, nhat, twy, twz, L.tk);
-    else if (p.nz <= 4)
-        hipLaunchKernelGGL((k_col_conv<T, 4>), dim3(L.blocks), dim3(L.threads), L.lds, s, p, S, nhat, twy, twz, L.tk);
+hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, hipStream_t s) {
+    const dim3 g(b.ncol), t(b.col_threads);
+    const BatchArgs<T> a = bargs(b, b.work_col);
+    if (max_nz == 1)
+        hipLaunchKernelGGL((k_col_conv<T, 1>), g, t, b.col_lds, s, a, b.col_tk);
+    else if (max_nz == 2)
+        hipLaunchKernelGGL((k_col_conv<T, 2>), g, t, b.col_lds, s, a, b.col_tk);
+    else if (max_nz <= 4)
+        hipLaunchKernelGGL((k_col_conv<T, 4>), g, t, b.col_lds, s, a, b.col_tk);
     else
-        hipLaunchKernelGGL((k_col_conv<T, 8>), dim3(L.blocks), dim3(L.threads), L.lds, s, p, S, nhat, twy, twz, L.tk);
+        hipLaunchKernelGGL((k_col_conv<T, 8>), g, t, b.col_lds, s, a, b.col_tk);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_levelset(const KParams<T>& p, const T* phi, const T* psi_fixed, const uint8_t* design, double a,
-                           int extrude, T* psi_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_levelset<T>, dim3((p.N + 255) / 256), dim3(256), 0, s, p, phi, psi_fixed, design, (T)a,
-                       extrude, psi_out);
+static dim3 elem_grid(const BatchDev<T>& b, int per_inst) {
+    return dim3((unsigned)((per_inst + 255) / 256), (unsigned)b.ninst);
+}
+template <typename T>
+hipError_t launch_levelset(const BatchDev<T>& b, double a, int extrude, hipStream_t s) {
+    hipLaunchKernelGGL(k_levelset<T>, elem_grid(b, b.max_n3 / 3), dim3(256), 0, s, b.ptab, b.itab, (T)a, extrude);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_levelset_vjp(const KParams<T>& p, const T* phi, const double* g, const uint8_t* design, double a,
-                               int extrude, double* out, hipStream_t s) {
-    const int M = extrude ? p.nx * p.ny : p.N;
-    hipLaunchKernelGGL(k_levelset_vjp<T>, dim3((M + 255) / 256), dim3(256), 0, s, p, phi, g, design, a, extrude, out);
+hipError_t launch_levelset_vjp(const BatchDev<T>& b, double a, int extrude, hipStream_t s) {
+    hipLaunchKernelGGL(k_levelset_vjp<T>, elem_grid(b, b.max_n3 / 3), dim3(256), 0, s, b.ptab, b.itab, a, extrude);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_energy(const KParams<T>& p, double t, const T* psi, const T* m, const cplx<T>* S, const cplx<T>* twx,
-                         const uint8_t* antenna, double scale, T* dJdm, double* dJdpsi, double* part,
-                         const LocalLaunch& L, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy<T>, dim3(L.blocks), dim3(L.threads), L.lds, s, p, t, psi, m, S, twx, antenna,
-                       scale, dJdm, dJdpsi, part);
+hipError_t launch_adj_init(const BatchDev<T>& b, int lam_sel, int use_djdm, int port, int W, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_init<T>, elem_grid(b, b.max_n3 / 3), dim3(256), 0, s, b.ptab, b.itab, lam_sel, use_djdm,
+                       port, W);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_port_finish(const double* part, int nblocks, double inv1, double inv2, double invW, double* J,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(k_port_finish, dim3(1), dim3(256), 0, s, part, nblocks, inv1, inv2, invW, J);
+hipError_t launch_psi_grad_out(const BatchDev<T>& b, int use_expl, hipStream_t s) {
+    hipLaunchKernelGGL(k_psi_grad_out<T>, elem_grid(b, b.max_n3 / 3), dim3(256), 0, s, b.ptab, b.itab, use_expl);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_adj_init(const KParams<T>& p, const T* dJdm_T, const T* mN, const uint8_t* port1,
-                           const uint8_t* port2, T src1, T src2, T* lam, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_init<T>, dim3((p.N + 255) / 256), dim3(256), 0, s, p, dJdm_T, mN, port1, port2, src1,
-                       src2, lam);
+hipError_t launch_zero(const BatchDev<T>& b, int sel, int what, hipStream_t s) {
+    const int n = what == 0 ? b.max_n3 / 3 : 2 * b.nloc;
+    hipLaunchKernelGGL(k_zero<T>, elem_grid(b, n), dim3(256), 0, s, b.ptab, b.itab, sel, what);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_psi_grad_out(const KParams<T>& p, const double* gacc, const double* expl, double* out,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(k_psi_grad_out<T>, dim3((p.N + 255) / 256), dim3(256), 0, s, p.N, gacc, expl, out);
+hipError_t launch_copy(const BatchDev<T>& b, int src, int src_slot, int dst, int dst_slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy<T>, elem_grid(b, b.max_n3), dim3(256), 0, s, b.ptab, b.itab, src, src_slot, dst, dst_slot);
     return hipGetLastError();
 }
-hipError_t launch_zero_f64(double* ptr, size_t n, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ptr, n);
+template <typename T>
+hipError_t launch_port_finish(const BatchDev<T>& b, int W, hipStream_t s) {
+    hipLaunchKernelGGL(k_port_finish<T>, dim3(b.ninst), dim3(256), 0, s, b.ptab, b.itab, W);
     return hipGetLastError();
 }
-
-// energy finish needs Ms*V and the objective constants; declared here for the runtime
-hipError_t launch_energy_finish_raw(const double* part, int nb, double MsV, double lam, double area, int N,
-                                    double E_ref, double* J, double* en, double* coef, double* dJdpsi,
-                                    hipStream_t s) {
-    hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(256), 0, s, part, nb, MsV, lam, area, N, E_ref, J, en, coef);
+template <typename T>
+hipError_t launch_energy(const BatchDev<T>& b, double t, const T* m, double scale, T* dJdm, double* dJdpsi,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_energy<T>, dim3(b.nloc), dim3(b.loc_threads), b.loc_lds, s, bargs(b, b.work_loc), t, m,
+                       scale, dJdm, dJdpsi);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_energy_finish(const BatchDev<T>& b, double MsV, double lam, double area, double E_ref, double* J,
+                                double* en, double* dJdpsi, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_finish<T>, dim3(1), dim3(256), 0, s, b.ptab, b.itab, MsV, lam, area, E_ref, J, en);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (dJdpsi) {
-        hipLaunchKernelGGL(k_add_coef, dim3((N + 255) / 256), dim3(256), 0, s, dJdpsi, coef, N);
-        e = hipGetLastError();
-    }
-    return e;
+    if (e != hipSuccess || !dJdpsi) return e;
+    hipLaunchKernelGGL(k_add_area<T>, elem_grid(b, b.max_n3 / 3), dim3(256), 0, s, b.ptab, b.itab, dJdpsi);
+    return hipGetLastError();
 }
 
-hipError_t set_lds_limits(int bytes) {
+template <typename T>
+hipError_t set_lds_limits(size_t bytes) {
     hipError_t e = hipSuccess;
+    const int v = (int)bytes;
 #define LLG_ATTR(K) \
-    if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void*>(K), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    LLG_ATTR(k_stage_fwd<float>) LLG_ATTR(k_stage_fwd<double>)
-    LLG_ATTR(k_stage_bwd<float>) LLG_ATTR(k_stage_bwd<double>)
-    LLG_ATTR((k_col_conv<float, 1>)) LLG_ATTR((k_col_conv<float, 2>)) LLG_ATTR((k_col_conv<float, 4>))
-    LLG_ATTR((k_col_conv<float, 8>)) LLG_ATTR((k_col_conv<double, 1>)) LLG_ATTR((k_col_conv<double, 2>))
-    LLG_ATTR((k_col_conv<double, 4>)) LLG_ATTR((k_col_conv<double, 8>))
-    LLG_ATTR(k_energy<float>) LLG_ATTR(k_energy<double>)
+    if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void*>(K), hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    LLG_ATTR(k_stage_fwd<T>)
+    LLG_ATTR(k_stage_bwd<T>)
+    LLG_ATTR((k_col_conv<T, 1>))
+    LLG_ATTR((k_col_conv<T, 2>))
+    LLG_ATTR((k_col_conv<T, 4>))
+    LLG_ATTR((k_col_conv<T, 8>))
+    LLG_ATTR(k_energy<T>)
 #undef LLG_ATTR
     return e;
 }
 
-#define LLG_INST(T)                                                                                                   \
-    template hipError_t launch_stage_fwd<T>(const KParams<T>&, const StageFwdArgs<T>&, const cplx<T>*,                \
-                                            const LocalLaunch&, hipStream_t);                                         \
-    template hipError_t launch_stage_bwd<T>(const KParams<T>&, const StageBwdArgs<T>&, const cplx<T>*,                \
-                                            const LocalLaunch&, hipStream_t);                                         \
-    template hipError_t launch_col_conv<T>(const KParams<T>&, cplx<T>*, const T*, const cplx<T>*, const cplx<T>*,     \
-                                           const ColLaunch&, hipStream_t);                                            \
-    template hipError_t launch_levelset<T>(const KParams<T>&, const T*, const T*, const uint8_t*, double, int, T*,    \
-                                           hipStream_t);                                                              \
-    template hipError_t launch_levelset_vjp<T>(const KParams<T>&, const T*, const double*, const uint8_t*, double,    \
-                                               int, double*, hipStream_t);                                            \
-    template hipError_t launch_energy<T>(const KParams<T>&, double, const T*, const T*, const cplx<T>*,               \
-                                         const cplx<T>*, const uint8_t*, double, T*, double*, double*,                \
-                                         const LocalLaunch&, hipStream_t);                                            \
-    template hipError_t launch_port_finish<T>(const double*, int, double, double, double, double*, hipStream_t);      \
-    template hipError_t launch_adj_init<T>(const KParams<T>&, const T*, const T*, const uint8_t*, const uint8_t*, T,   \
-                                           T, T*, hipStream_t);                                                       \
-    template hipError_t launch_psi_grad_out<T>(const KParams<T>&, const double*, const double*, double*, hipStream_t);
+#define LLG_INST(T)                                                                                                 \
+    template hipError_t launch_stage_fwd<T>(const BatchDev<T>&, const FwdL&, hipStream_t);                          \
+    template hipError_t launch_stage_bwd<T>(const BatchDev<T>&, const BwdL&, hipStream_t);                          \
+    template hipError_t launch_col_conv<T>(const BatchDev<T>&, int, hipStream_t);                                   \
+    template hipError_t launch_levelset<T>(const BatchDev<T>&, double, int, hipStream_t);                           \
+    template hipError_t launch_levelset_vjp<T>(const BatchDev<T>&, double, int, hipStream_t);                       \
+    template hipError_t launch_adj_init<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                     \
+    template hipError_t launch_psi_grad_out<T>(const BatchDev<T>&, int, hipStream_t);                               \
+    template hipError_t launch_zero<T>(const BatchDev<T>&, int, int, hipStream_t);                                  \
+    template hipError_t launch_copy<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                        \
+    template hipError_t launch_port_finish<T>(const BatchDev<T>&, int, hipStream_t);                                \
+    template hipError_t launch_energy<T>(const BatchDev<T>&, double, const T*, double, T*, double*, hipStream_t);   \
+    template hipError_t launch_energy_finish<T>(const BatchDev<T>&, double, double, double, double, double*,        \
+                                                double*, double*, hipStream_t);                                     \
+    template hipError_t set_lds_limits<T>(size_t);
 
 LLG_INST(float)
 LLG_INST(double)

@@ -1,6 +1,8 @@
-// Host runtime of the level-set LLG library: handle, workspace, argument
-// validation, stream-ordered orchestration of the forward run, the objective,
-// and the checkpointed discrete adjoint, and the extern "C" entry points.
+// Host runtime of the level-set LLG library: batches of problem instances,
+// their device workspace and tables, argument validation, stream-ordered
+// orchestration of the forward run, the objectives and the checkpointed
+// discrete adjoint, and the extern "C" entry points.  A single-instance
+// handle is a batch of one; every launch serves all instances of a batch.
 //
 // Discrete adjoint (the exact gradient of the fixed-step RK4 map; the discrete
 // counterpart of the paper's adjoint system, Eq. 6, and gradient integral,
@@ -58,52 +60,55 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+int64_t segment_length(int64_t n, int32_t policy, int32_t param) {
+    if (n <= 0) return 1;
+    if (policy == LLG_CKPT_ALL) return n;
+    if (param > 0) return std::min<int64_t>(param, n);
+    int64_t K = (int64_t)std::ceil(std::sqrt((double)n));
+    return std::max<int64_t>(1, K);
+}
+
+size_t store_bytes(int64_t N3, size_t tsz, int64_t n, int32_t policy, int32_t param) {
+    const int64_t K = segment_length(n, policy, param);
+    const int64_t nsnap = (n + K - 1) / K;
+    return (size_t)(nsnap * N3 + 8 * K * N3) * tsz;
+}
+
+struct Instance {
+    llg_problem prob{};
+    int N = 0, nrows = 0, Px = 1, Py = 1, Pz = 1, Kx = 1, ncomp = 4;
+    int nloc = 0;
+    long long n_p1 = 0, n_p2 = 0;
+    bool has_ant = false, has_design = false;
+    KParams<float> pf{};
+    KParams<double> pd{};
+    InstTab tab{};
+};
+
 }  // namespace
 
 struct llg_handle {
-    llg_problem prob{};
     int dtype = LLG_F32;
-    size_t tsz = 4;  // sizeof(T)
-    int N = 0, nrows = 0, Px = 1, Py = 1, Pz = 1, Kx = 1, ncomp = 4;
+    size_t tsz = 4;
     bool demag = false;
-    KParams<float> pf{};
-    KParams<double> pd{};
-    LocalLaunch loc{};
-    ColLaunch col{};
-    // device workspace
+    int terms = 0;
+    std::vector<Instance> inst;
     std::vector<DevBuf> bufs;
-    void* twx = nullptr;
-    void* twy = nullptr;
-    void* twz = nullptr;
-    void* nhat = nullptr;
-    void* S = nullptr;
-    void* m = nullptr;
-    void* acc = nullptr;
-    void* yA = nullptr;
-    void* yB = nullptr;
-    uint8_t* antenna = nullptr;
-    uint8_t* port1 = nullptr;
-    uint8_t* port2 = nullptr;
-    uint8_t* design = nullptr;
-    bool has_antenna = false, has_ports = false, has_design = false;
-    long long n_p1 = 0, n_p2 = 0;
-    double* port_part = nullptr;
-    double* en_part = nullptr;
-    double* scalars = nullptr;  // [0] area coefficient
+    // device tables
+    void* ptab = nullptr;
+    InstTab* itab = nullptr;
+    int2* work_loc = nullptr;
+    int2* work_col = nullptr;
+    BatchDev<float> bf{};
+    BatchDev<double> bd{};
+    int max_nz = 1;
+    // byte sums over instances (profiling)
+    double sumN = 0, sumSpec = 0, sumNhat = 0;
     // checkpoint store
-    int64_t K = 1;        // segment length
-    int64_t nsnap = 0;    // snapshot slots
-    void* snaps = nullptr;
-    void* YS = nullptr;   // [K][4][3N]
-    void* BS = nullptr;
-    // adjoint buffers
-    void* L0 = nullptr;
-    void* L1 = nullptr;
-    void* ell = nullptr;
-    void* U0 = nullptr;
-    void* U1 = nullptr;
-    double* gpsi = nullptr;
-    // per-kernel profiling (events around every launch while enabled)
+    int64_t K = 1, nsnap = 0;
+    int32_t policy = LLG_CKPT_SQRT, ckpt_param = 0;
+    int64_t max_steps = 1;
+    // per-kernel profiling
     struct ProfRec { int kind; double bytes; hipEvent_t a, b; };
     bool prof_on = false;
     std::vector<ProfRec> prof;
@@ -121,9 +126,12 @@ struct llg_handle {
 
 namespace {
 
-template <typename T> KParams<T>& kp(llg_handle* h);
-template <> KParams<float>& kp<float>(llg_handle* h) { return h->pf; }
-template <> KParams<double>& kp<double>(llg_handle* h) { return h->pd; }
+template <typename T> KParams<T>& kp(Instance& I);
+template <> KParams<float>& kp<float>(Instance& I) { return I.pf; }
+template <> KParams<double>& kp<double>(Instance& I) { return I.pd; }
+template <typename T> BatchDev<T>& bdev(llg_handle* h);
+template <> BatchDev<float>& bdev<float>(llg_handle* h) { return h->bf; }
+template <> BatchDev<double>& bdev<double>(llg_handle* h) { return h->bd; }
 
 int alloc(llg_handle* h, void** out, size_t bytes) {
     *out = nullptr;
@@ -144,42 +152,32 @@ void free_all(llg_handle* h) {
     h->bufs.clear();
 }
 
-int64_t segment_length(int64_t n, int32_t policy, int32_t param) {
-    if (n <= 0) return 1;
-    if (policy == LLG_CKPT_ALL) return n;
-    if (param > 0) return std::min<int64_t>(param, n);
-    int64_t K = (int64_t)std::ceil(std::sqrt((double)n));
-    return std::max<int64_t>(1, K);
-}
-
-size_t store_bytes(int64_t N3, size_t tsz, int64_t n, int32_t policy, int32_t param) {
-    const int64_t K = segment_length(n, policy, param);
-    const int64_t nsnap = (n + K - 1) / K;
-    return (size_t)(nsnap * N3 + 8 * K * N3) * tsz;
-}
-
 template <typename T>
-void fill_params(llg_handle* h) {
-    KParams<T>& p = kp<T>(h);
-    const llg_problem& q = h->prob;
+void fill_params(Instance& I) {
+    KParams<T>& p = kp<T>(I);
+    const llg_problem& q = I.prob;
     p.nx = q.nx;
     p.ny = q.ny;
     p.nz = q.nz;
-    p.N = h->N;
-    p.nrows = h->nrows;
-    p.Px = h->Px;
-    p.Kx = h->Kx;
-    p.Py = h->Py;
-    p.Pz = h->Pz;
-    p.Ky2 = h->Py / 2 + 1;
-    p.Kz2 = h->Pz / 2 + 1;
-    p.ncomp = h->ncomp;
+    p.N = I.N;
+    p.nrows = I.nrows;
+    p.Px = I.Px;
+    p.Kx = I.Kx;
+    p.Py = I.Py;
+    p.Pz = I.Pz;
+    p.Ky2 = I.Py / 2 + 1;
+    p.Kz2 = I.Pz / 2 + 1;
+    p.ncomp = I.ncomp;
     p.terms = q.terms;
+    p.nloc = I.nloc;
+    p.has_ant = I.has_ant;
+    p.n_p1 = (int)I.n_p1;
+    p.n_p2 = (int)I.n_p2;
     const double kappa = 2.0 * q.A / q.Ms;
     const double hh[3] = {q.dx, q.dy, q.dz};
     for (int d = 0; d < 3; ++d) p.exw[d] = (T)(2.0 * kappa / (hh[d] * hh[d]));
     p.anis = (T)(2.0 * q.K / q.Ms);
-    double un = std::sqrt(q.ku[0] * q.ku[0] + q.ku[1] * q.ku[1] + q.ku[2] * q.ku[2]);
+    const double un = std::sqrt(q.ku[0] * q.ku[0] + q.ku[1] * q.ku[1] + q.ku[2] * q.ku[2]);
     for (int d = 0; d < 3; ++d) {
         p.u[d] = (T)(un > 0 ? q.ku[d] / un : 0.0);
         p.B0[d] = (T)q.B0[d];
@@ -197,74 +195,120 @@ void fill_params(llg_handle* h) {
 }
 
 template <typename T>
-int upload_tables(llg_handle* h) {
+int upload_tables(llg_handle* h, Instance& I) {
     using C = cplx<T>;
-    auto twiddles = [&](int L, void** out) -> int {
+    auto twiddles = [&](int L, int id) -> int {
         std::vector<C> tw(L);
         for (int k = 0; k < L; ++k) {
             const double th = -2.0 * 3.14159265358979323846 * (double)k / (double)L;
             tw[k].x = (T)std::cos(th);
             tw[k].y = (T)std::sin(th);
         }
-        int rc = alloc(h, out, sizeof(C) * L);
+        int rc = alloc(h, &I.tab.b[id], sizeof(C) * L);
         if (rc) return rc;
-        HIPCHK(hipMemcpy(*out, tw.data(), sizeof(C) * L, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(I.tab.b[id], tw.data(), sizeof(C) * L, hipMemcpyHostToDevice));
         return LLG_OK;
     };
     int rc;
-    if ((rc = twiddles(h->Px, &h->twx))) return rc;
-    if ((rc = twiddles(h->Py, &h->twy))) return rc;
-    if ((rc = twiddles(h->Pz, &h->twz))) return rc;
+    if ((rc = twiddles(I.Px, B_TWX))) return rc;
+    if ((rc = twiddles(I.Py, B_TWY))) return rc;
+    if ((rc = twiddles(I.Pz, B_TWZ))) return rc;
     if (h->demag) {
-        const llg_problem& q = h->prob;
+        const llg_problem& q = I.prob;
         std::vector<double> spec;
         int nc = 4;
-        const double scale = -kMu0 * q.Ms / ((double)h->Px * h->Py * h->Pz);
-        build_tensor_spectrum(q.nx, q.ny, q.nz, q.dx, q.dy, q.dz, h->Px, h->Py, h->Pz, scale, spec, nc);
-        h->ncomp = nc;
+        const double scale = -kMu0 * q.Ms / ((double)I.Px * I.Py * I.Pz);
+        build_tensor_spectrum(q.nx, q.ny, q.nz, q.dx, q.dy, q.dz, I.Px, I.Py, I.Pz, scale, spec, nc);
+        I.ncomp = nc;
         std::vector<T> st(spec.size());
         for (size_t i = 0; i < spec.size(); ++i) st[i] = (T)spec[i];
-        if ((rc = alloc(h, &h->nhat, sizeof(T) * st.size()))) return rc;
-        HIPCHK(hipMemcpy(h->nhat, st.data(), sizeof(T) * st.size(), hipMemcpyHostToDevice));
+        if ((rc = alloc(h, &I.tab.b[B_NHAT], sizeof(T) * st.size()))) return rc;
+        HIPCHK(hipMemcpy(I.tab.b[B_NHAT], st.data(), sizeof(T) * st.size(), hipMemcpyHostToDevice));
     }
     return LLG_OK;
 }
 
+// Launch geometry of the batch: the most demanding instance sets block size and LDS.
 int choose_launch(llg_handle* h) {
-    const int maxreg = h->dtype == LLG_F32 ? 32 : 16;
+    const int maxreg = h->dtype == LLG_F32 ? 16 : 8;
     const size_t csz = 2 * h->tsz;
-    const int nx = h->prob.nx, nz = h->prob.nz;
-    // local kernels: two rows per block; LDS = three packed complex signals of
-    // length Px + Px twiddles (demag) + four staged rows of four values
-    {
-        int thr = (3 * h->Px + maxreg - 1) / maxreg;
+    int loc_thr = 64;
+    size_t loc_lds = 0;
+    for (auto& I : h->inst) {
+        const int nx = I.prob.nx;
+        int thr = (3 * I.Px + maxreg - 1) / maxreg;
         thr = std::max(thr, std::min(nx, 512));
-        thr = std::min(512, std::max(64, round_up(thr, 64)));
-        h->loc.blocks = (h->nrows + 1) / 2;
-        h->loc.threads = thr;
-        h->loc.lds = (h->demag ? (size_t)4 * h->Px * csz : 0) + (size_t)16 * nx * h->tsz;
-        if (3 * h->Px > maxreg * 512 || h->loc.lds > 163840)
-            return fail(LLG_ESHAPE, "x extent too large for the row kernels (nx = " + std::to_string(nx) + ")");
+        thr = std::max(64, round_up(thr, 64));
+        if (thr > 512) return fail(LLG_ESHAPE, "x extent too large for the row kernels (nx = " + std::to_string(nx) + ")");
+        loc_thr = std::max(loc_thr, thr);
+        const size_t lds = (h->demag ? (size_t)4 * I.Px * csz : 0) + (size_t)16 * nx * h->tsz;
+        if (lds > 163840) return fail(LLG_ESHAPE, "row kernels need more than 160 KiB of LDS");
+        loc_lds = std::max(loc_lds, lds);
     }
-    // column kernel: TK adjacent x-bins per block, as many as keep >= 256 blocks
-    {
-        const int Ky2 = h->Py / 2 + 1, Kz2 = h->Pz / 2 + 1;
-        auto lds_of = [&](int tk) {
-            return (size_t)3 * nz * h->Py * tk * csz + (size_t)h->Py * csz + (size_t)h->ncomp * Kz2 * Ky2 * tk * h->tsz;
-        };
-        int tk = 8;
-        while (tk > 1 && ((h->Kx + tk - 1) / tk < 256 || lds_of(tk) > 163840 || 3 * nz * h->Py * tk > maxreg * 512))
-            tk /= 2;
-        if (lds_of(tk) > 163840 || 3 * nz * h->Py * tk > maxreg * 512)
-            return fail(LLG_ESHAPE, "y/z extent too large for the column FFT (Py = " + std::to_string(h->Py) +
-                                        ", nz = " + std::to_string(nz) + ")");
-        int thr = (3 * nz * h->Py * tk + maxreg - 1) / maxreg;
-        thr = std::max(thr, std::min(h->Py * tk, 256));
-        thr = std::min(512, std::max(64, round_up(thr, 64)));
-        h->col.tk = tk;
-        h->col.threads = thr;
-        h->col.blocks = (h->Kx + tk - 1) / tk;
-        h->col.lds = lds_of(tk);
+    // column tile width: one value for the batch, as wide as keeps >= 256 blocks
+    auto lds_of = [&](const Instance& I, int tk) {
+        const int Ky2 = I.Py / 2 + 1, Kz2 = I.Pz / 2 + 1;
+        return (size_t)3 * I.prob.nz * I.Py * tk * csz + (size_t)I.Py * csz + (size_t)I.ncomp * Kz2 * Ky2 * tk * h->tsz;
+    };
+    auto fits = [&](int tk) {
+        for (auto& I : h->inst)
+            if (lds_of(I, tk) > 163840 || 3 * I.prob.nz * I.Py * tk > maxreg * 1024) return false;
+        return true;
+    };
+    auto blocks_of = [&](int tk) {
+        long long b = 0;
+        for (auto& I : h->inst) b += (I.Kx + tk - 1) / tk;
+        return b;
+    };
+    int tk = 8;
+    while (tk > 1 && (blocks_of(tk) < 256 || !fits(tk))) tk /= 2;
+    if (!fits(tk)) return fail(LLG_ESHAPE, "y/z extent too large for the column FFT");
+    int col_thr = 64;
+    size_t col_lds = 0;
+    for (auto& I : h->inst) {
+        int thr = (3 * I.prob.nz * I.Py * tk + maxreg - 1) / maxreg;
+        thr = std::max(thr, std::min(I.Py * tk, 256));
+        col_thr = std::max(col_thr, std::min(1024, std::max(64, round_up(thr, 64))));
+        col_lds = std::max(col_lds, lds_of(I, tk));
+    }
+    // work lists
+    std::vector<int2> wl, wc;
+    for (int i = 0; i < (int)h->inst.size(); ++i) {
+        for (int r = 0; r < h->inst[i].nloc; ++r) wl.push_back(make_int2(i, r));
+        for (int c = 0; c < (h->inst[i].Kx + tk - 1) / tk; ++c) wc.push_back(make_int2(i, c));
+    }
+    int rc;
+    void* p;
+    if ((rc = alloc(h, &p, wl.size() * sizeof(int2)))) return rc;
+    h->work_loc = (int2*)p;
+    HIPCHK(hipMemcpy(p, wl.data(), wl.size() * sizeof(int2), hipMemcpyHostToDevice));
+    if ((rc = alloc(h, &p, wc.size() * sizeof(int2)))) return rc;
+    h->work_col = (int2*)p;
+    HIPCHK(hipMemcpy(p, wc.data(), wc.size() * sizeof(int2), hipMemcpyHostToDevice));
+    int max_n3 = 0;
+    for (auto& I : h->inst) max_n3 = std::max(max_n3, 3 * I.N);
+    auto fill = [&](auto& b) {
+        b.work_loc = h->work_loc;
+        b.work_col = h->work_col;
+        b.nloc = (int)wl.size();
+        b.ncol = (int)wc.size();
+        b.ninst = (int)h->inst.size();
+        b.max_n3 = max_n3;
+        b.loc_threads = loc_thr;
+        b.col_threads = col_thr;
+        b.col_tk = tk;
+        b.loc_lds = loc_lds;
+        b.col_lds = col_lds;
+    };
+    fill(h->bf);
+    fill(h->bd);
+    const size_t need = std::max(loc_lds, col_lds);
+    if (need > 65536) {
+        hipError_t e = h->dtype == LLG_F32 ? set_lds_limits<float>(need) : set_lds_limits<double>(need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LLG_ESHAPE, "kernels need " + std::to_string(need) + " bytes of LDS: " + hipGetErrorString(e));
+        }
     }
     return LLG_OK;
 }
@@ -272,7 +316,7 @@ int choose_launch(llg_handle* h) {
 int validate_problem(const llg_problem* p) {
     if (!p) return fail(LLG_EINVAL, "problem is NULL");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LLG_EINVAL, "grid extents must be >= 1");
-    if ((long long)p->nx * p->ny * p->nz > (1LL << 30)) return fail(LLG_ESHAPE, "grid too large");
+    if ((long long)p->nx * p->ny * p->nz > (1LL << 28)) return fail(LLG_ESHAPE, "grid too large");
     if (!(p->dx > 0 && p->dy > 0 && p->dz > 0)) return fail(LLG_EINVAL, "cell sizes must be > 0");
     if (!(p->Ms > 0)) return fail(LLG_EINVAL, "Ms must be > 0");
     if (!(p->dt > 0) || !std::isfinite(p->dt)) return fail(LLG_EINVAL, "dt must be finite and > 0");
@@ -321,154 +365,140 @@ int drain_profile(llg_handle* h) {
 }
 
 // ---------------------------------------------------------------------------
-// typed orchestration
+// typed orchestration (all instances of the batch at once)
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Ops {
     using C = cplx<T>;
     llg_handle* h;
     hipStream_t s;
-    const KParams<T>& P() const { return kp<T>(h); }
-    size_t N3() const { return (size_t)3 * h->N; }
-    T* tp(void* p, size_t off = 0) const { return static_cast<T*>(p) + off; }
+    int adj_lambda0 = B_L0;
+    const BatchDev<T>& B() const { return bdev<T>(h); }
 
     // every kernel launch goes through here: optional event bracketing for profiling
     template <typename F>
     int run(int kind, double bytes, F&& launch) {
         hipEvent_t a = nullptr, b = nullptr;
-        if (h->prof_on) {
+        if (h->prof_on && kind >= 0) {
             if (int rc = take_events(h, &a, &b)) return rc;
             HIPCHK(hipEventRecord(a, s));
         }
         hipError_t e = launch();
         if (e != hipSuccess) return fail(LLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
-        if (h->prof_on) {
+        if (h->prof_on && kind >= 0) {
             HIPCHK(hipEventRecord(b, s));
             h->prof.push_back({kind, bytes, a, b});
         }
         return LLG_OK;
     }
 
-    // algorithmic HBM bytes of one launch (each array element read or written once)
-    double spec_bytes() const { return 3.0 * h->nrows * h->Kx * 2.0 * sizeof(T); }
-    double fwd_bytes(const StageFwdArgs<T>& a) const {
-        const double t = sizeof(T), n = h->N;
+    // algorithmic HBM bytes of one launch over the batch (each element read or written once)
+    double fwd_bytes(const FwdL& L) const {
+        const double t = sizeof(T), n = h->sumN;
         double b = n * 4 * t;  // ys, psi
-        if (a.do_inv) b += spec_bytes();
-        if (a.do_fwd) b += spec_bytes();
-        switch (a.stage) {
+        if (L.do_inv) b += h->sumSpec;
+        if (L.do_fwd) b += h->sumSpec;
+        switch (L.stage) {
             case 0: b += n * 6 * t; break;
             case 1: case 2: b += n * 12 * t; break;
             case 3: b += n * 6 * t; break;
-            case -1: b += n * 3 * t * (a.ynext ? 2 : 1); break;
+            case -1: b += n * 3 * t * (L.ext_ynext ? 2 : 1); break;
             default: break;
         }
-        if (a.ys_store) b += n * 3 * t;
-        if (a.Bs_store && a.stage >= 0) b += n * 3 * t;
-        if (a.antenna) b += n;
-        if (a.port_part) b += 2 * n;
+        if (L.store_j >= 0) b += n * 6 * t;
+        if (L.port) b += 2 * n;
         return b;
     }
-    double bwd_bytes(const StageBwdArgs<T>& a) const {
-        const double t = sizeof(T), n = h->N;
-        double b = 0;
-        if (a.stage < 0) {
-            b = n * 13 * t + spec_bytes();
+    double bwd_bytes(const BwdL& L) const {
+        const double t = sizeof(T), n = h->sumN;
+        double b;
+        if (L.stage < 0) {
+            b = n * 13 * t + h->sumSpec;
         } else {
-            b = n * (16 * t + 16) + (a.stage == 3 ? 0 : n * 3 * t);
-            if (a.y_prev) b += n * 9 * t;
-            if (a.do_inv) b += spec_bytes();
-            if (a.do_fwd) b += spec_bytes();
-            if (a.port1) b += 2 * n;
+            b = n * (16 * t + 16) + (L.stage == 3 ? 0 : n * 3 * t);
+            if (L.prev_j >= 0) b += n * 9 * t;
+            if (L.do_inv) b += h->sumSpec;
+            if (L.do_fwd) b += h->sumSpec;
+            if (L.port_src) b += 2 * n;
         }
         return b;
     }
-    double col_bytes() const {
-        return 2 * spec_bytes() + (double)h->ncomp * (h->Pz / 2 + 1) * (h->Py / 2 + 1) * h->Kx * sizeof(T);
-    }
+    double col_bytes() const { return 2 * h->sumSpec + h->sumNhat; }
 
     int col() {
         if (!h->demag) return LLG_OK;
-        return run(LLG_KIND_COLUMN, col_bytes(), [&] {
-            return launch_col_conv<T>(P(), (C*)h->S, (const T*)h->nhat, (const C*)h->twy, (const C*)h->twz, h->col, s);
-        });
+        return run(LLG_KIND_COLUMN, col_bytes(), [&] { return launch_col_conv<T>(B(), h->max_nz, s); });
     }
-    int fwd(const StageFwdArgs<T>& a) {
-        return run(LLG_KIND_STAGE_FWD, fwd_bytes(a), [&] { return launch_stage_fwd<T>(P(), a, (const C*)h->twx, h->loc, s); });
+    int fwd(const FwdL& L) {
+        return run(LLG_KIND_STAGE_FWD, fwd_bytes(L), [&] { return launch_stage_fwd<T>(B(), L, s); });
     }
-    int bwd(const StageBwdArgs<T>& a) {
-        return run(LLG_KIND_STAGE_BWD, bwd_bytes(a), [&] { return launch_stage_bwd<T>(P(), a, (const C*)h->twx, h->loc, s); });
+    int bwd(const BwdL& L) {
+        return run(LLG_KIND_STAGE_BWD, bwd_bytes(L), [&] { return launch_stage_bwd<T>(B(), L, s); });
+    }
+    int copy(int src, int src_slot, int dst, int dst_slot) {
+        return run(-1, 0, [&] { return launch_copy<T>(B(), src, src_slot, dst, dst_slot, s); });
+    }
+
+    static FwdL fwd_launch(int stage) {
+        FwdL L{};
+        L.stage = stage;
+        L.ys = L.mn = L.acc = L.ynext = -1;
+        L.store_j = -1;
+        return L;
     }
 
     // spectrum of psi * m into S
-    int prologue(const T* psi, const T* m) {
+    int prologue(void* ext_m = nullptr) {
         if (!h->demag) return LLG_OK;
-        StageFwdArgs<T> a{};
-        a.stage = -3;
-        a.psi = psi;
-        a.ys = m;
-        a.S = (C*)h->S;
-        a.do_fwd = 1;
-        return fwd(a);
+        FwdL L = fwd_launch(-3);
+        L.ys = B_M;
+        L.ext_ys = ext_m;
+        L.do_fwd = 1;
+        return fwd(L);
     }
 
-    // one RK4 step from h->m (spectrum of psi*m already in S); optional stage store
-    int step(const T* psi, double t, bool last, T* ys_store, T* bs_store, bool port) {
-        const double dt = h->prob.dt;
+    // one RK4 step from B_M (spectrum of psi*m already in S); optional stage store
+    int step(double t, bool last, int store_j, bool port) {
+        const double dt = h->inst[0].prob.dt;
         const double cs[4] = {0.0, 0.5, 0.5, 1.0};
-        T* y_in[4] = {tp(h->m), tp(h->yA), tp(h->yB), tp(h->yA)};
-        T* y_out[4] = {tp(h->yA), tp(h->yB), tp(h->yA), tp(h->m)};
+        const int y_in[4] = {B_M, B_YA, B_YB, B_YA};
+        const int y_out[4] = {B_YA, B_YB, B_YA, B_M};
         for (int st = 0; st < 4; ++st) {
-            int rc = col();
-            if (rc) return rc;
-            StageFwdArgs<T> a{};
-            a.stage = st;
-            a.t = t + cs[st] * dt;
-            a.psi = psi;
-            a.ys = y_in[st];
-            a.mn = tp(h->m);
-            a.acc = tp(h->acc);
-            a.ynext = y_out[st];
-            a.S = (C*)h->S;
-            a.antenna = h->has_antenna ? h->antenna : nullptr;
-            a.ys_store = ys_store ? ys_store + st * N3() : nullptr;
-            a.Bs_store = bs_store ? bs_store + st * N3() : nullptr;
-            if (st == 3 && port) {
-                a.port1 = h->port1;
-                a.port2 = h->port2;
-                a.port_part = h->port_part;
-            }
-            a.do_inv = h->demag;
-            a.do_fwd = h->demag && !(last && st == 3);
-            if (int rc2 = fwd(a)) return rc2;
+            if (int rc = col()) return rc;
+            FwdL L = fwd_launch(st);
+            L.t = t + cs[st] * dt;
+            L.ys = y_in[st];
+            L.mn = B_M;
+            L.acc = B_ACC;
+            L.ynext = y_out[st];
+            L.store_j = store_j;
+            L.port = st == 3 && port;
+            L.do_inv = h->demag;
+            L.do_fwd = h->demag && !(last && st == 3);
+            if (int rc = fwd(L)) return rc;
         }
         return LLG_OK;
     }
 
-    int forward(const T* psi, const T* m0, double t0, int64_t n, const llg_objective_spec* obj, T* m_out, double* J) {
+    int forward(double t0, int64_t n, const llg_objective_spec* obj) {
         const bool port = obj && obj->kind == LLG_OBJ_PORT_MY2;
-        const int64_t K = segment_length(n, h->prob.ckpt_policy, h->prob.ckpt_param);
+        const int64_t K = segment_length(n, h->policy, h->ckpt_param);
         const int64_t nsnap = (n + K - 1) / K;
         if (nsnap > h->nsnap || K > h->K)
             return fail(LLG_ENOMEM, "checkpoint store too small for n_steps (raise max_steps at create)");
-        if (m0 != tp(h->m)) HIPCHK(hipMemcpyAsync(h->m, m0, N3() * sizeof(T), hipMemcpyDeviceToDevice, s));
-        if (port) HIPCHK(launch_zero_f64(h->port_part, 2 * (size_t)h->loc.blocks, s));
-        int rc = prologue(psi, tp(h->m));
-        if (rc) return rc;
+        if (port)
+            if (int rc = run(-1, 0, [&] { return launch_zero<T>(B(), B_PPART, 1, s); })) return rc;
+        if (int rc = prologue()) return rc;
+        const double dt = h->inst[0].prob.dt;
         for (int64_t k = 0; k < n; ++k) {
             if (k % K == 0)
-                HIPCHK(hipMemcpyAsync(tp(h->snaps, (k / K) * N3()), h->m, N3() * sizeof(T), hipMemcpyDeviceToDevice, s));
+                if (int rc = copy(B_M, 0, B_SNAP, (int)(k / K))) return rc;
             const bool in_win = port && (k + 1) > obj->n_start;
-            rc = step(psi, t0 + (double)k * h->prob.dt, k == n - 1, nullptr, nullptr, in_win);
-            if (rc) return rc;
+            if (int rc = step(t0 + (double)k * dt, k == n - 1, -1, in_win)) return rc;
         }
-        if (m_out && m_out != tp(h->m))
-            HIPCHK(hipMemcpyAsync(m_out, h->m, N3() * sizeof(T), hipMemcpyDeviceToDevice, s));
-        if (port && J) {
-            const int64_t W = n - obj->n_start;
-            const double inv1 = h->n_p1 > 0 ? 1.0 / (double)h->n_p1 : 0.0;
-            const double inv2 = h->n_p2 > 0 ? 1.0 / (double)h->n_p2 : 0.0;
-            HIPCHK(launch_port_finish<T>(h->port_part, h->loc.blocks, inv1, inv2, W > 0 ? 1.0 / (double)W : 0.0, J, s));
+        if (port) {
+            const int W = (int)(n - obj->n_start);
+            if (int rc = run(-1, 0, [&] { return launch_port_finish<T>(B(), W, s); })) return rc;
         }
         h->fwd_valid = true;
         h->t0 = t0;
@@ -478,128 +508,88 @@ struct Ops {
         return LLG_OK;
     }
 
-    int field(const T* psi, const T* m, double t, T* B, T* rhs) {
-        int rc = prologue(psi, m);
-        if (rc) return rc;
-        rc = col();
-        if (rc) return rc;
-        StageFwdArgs<T> a{};
-        a.stage = -1;
-        a.t = t;
-        a.psi = psi;
-        a.ys = m;
-        a.ynext = rhs;
-        a.S = (C*)h->S;
-        a.antenna = h->has_antenna ? h->antenna : nullptr;
-        a.Bs_store = B;
-        a.do_inv = h->demag;
-        a.do_fwd = 0;
-        return fwd(a);
+    int field(const void* m, double t, void* Bout, void* rhs) {
+        if (int rc = prologue(const_cast<void*>(m))) return rc;
+        if (int rc = col()) return rc;
+        FwdL L = fwd_launch(-1);
+        L.t = t;
+        L.ys = B_M;
+        L.ext_ys = const_cast<void*>(m);
+        L.ext_ynext = rhs;
+        L.ext_B = Bout;
+        L.do_inv = h->demag;
+        return fwd(L);
     }
 
-    int objective(const llg_objective_spec* obj, const T* psi, const T* m, double t, double* J, T* dJdm, double* dJdpsi,
-                  double* en) {
-        if (obj->kind == LLG_OBJ_PORT_MY2) {
-            if (!h->fwd_valid) return fail(LLG_ESTATE, "port objective needs a preceding llg_forward");
-            const int64_t W = h->n_steps - obj->n_start;
-            const double inv1 = h->n_p1 > 0 ? 1.0 / (double)h->n_p1 : 0.0;
-            const double inv2 = h->n_p2 > 0 ? 1.0 / (double)h->n_p2 : 0.0;
-            if (J) HIPCHK(launch_port_finish<T>(h->port_part, h->loc.blocks, inv1, inv2, W > 0 ? 1.0 / W : 0.0, J, s));
-            if (dJdm) HIPCHK(hipMemsetAsync(dJdm, 0, N3() * sizeof(T), s));
-            if (dJdpsi) HIPCHK(hipMemsetAsync(dJdpsi, 0, (size_t)h->N * sizeof(double), s));
-            return LLG_OK;
-        }
-        int rc = prologue(psi, m);
-        if (rc) return rc;
-        rc = col();
-        if (rc) return rc;
-        const llg_problem& q = h->prob;
+    int energy(const llg_objective_spec* obj, const T* m, double t, double* J, T* dJdm, double* dJdpsi, double* en) {
+        if (int rc = prologue(const_cast<T*>(m))) return rc;
+        if (int rc = col()) return rc;
+        const llg_problem& q = h->inst[0].prob;
         const double MsV = q.Ms * q.dx * q.dy * q.dz;
-        HIPCHK(launch_energy<T>(P(), t, psi, m, (const C*)h->S, (const C*)h->twx, h->has_antenna ? h->antenna : nullptr,
-                                MsV / obj->E_ref, dJdm, dJdpsi, h->en_part, h->loc, s));
-        HIPCHK(launch_energy_finish_raw(h->en_part, h->loc.blocks, MsV, obj->lambda, obj->area, h->N, obj->E_ref, J, en,
-                                        h->scalars, dJdpsi, s));
-        return LLG_OK;
+        if (int rc = run(-1, 0, [&] { return launch_energy<T>(B(), t, m, MsV / obj->E_ref, dJdm, dJdpsi, s); }))
+            return rc;
+        return run(-1, 0, [&] {
+            return launch_energy_finish<T>(B(), MsV, obj->lambda, obj->area, obj->E_ref, J, en, dJdpsi, s);
+        });
     }
 
-    int adjoint(const T* psi, const T* dJdm_T, const double* expl, const llg_objective_spec* obj, double* dJdpsi,
-                T* dJdm0) {
+    int adjoint(const llg_objective_spec* obj, bool use_djdm, bool use_expl) {
         if (!h->fwd_valid) return fail(LLG_ESTATE, "llg_adjoint needs a preceding llg_forward on this handle");
         const int64_t n = h->n_steps, K = h->K_used;
-        const double dt = h->prob.dt;
-        const bool port = obj && obj->kind == LLG_OBJ_PORT_MY2 && h->has_ports;
+        const double dt = h->inst[0].prob.dt;
+        const bool port = obj && obj->kind == LLG_OBJ_PORT_MY2;
         const int64_t nstart = port ? obj->n_start : n;
-        const int64_t W = n - nstart;
-        const T src1 = (T)(port && W > 0 && h->n_p1 > 0 ? 2.0 / ((double)W * h->n_p1) : 0.0);
-        const T src2 = (T)(port && W > 0 && h->n_p2 > 0 ? 2.0 / ((double)W * h->n_p2) : 0.0);
-        T* Lc = tp(h->L0);
-        T* Lo = tp(h->L1);
-        T* Uc = tp(h->U0);
-        T* Uo = tp(h->U1);
-        // lambda_N = dJ/dm_N (+ port source at N); h->m holds m_N
-        HIPCHK(launch_adj_init<T>(P(), dJdm_T, tp(h->m), (port && W > 0) ? h->port1 : nullptr, h->port2, src1, src2, Lc, s));
-        HIPCHK(launch_zero_f64(h->gpsi, (size_t)h->N, s));
+        const int W = (int)(n - nstart);
+        int Lc = B_L0, Lo = B_L1, Uc = B_U0, Uo = B_U1;
+        // lambda_N = dJ/dm_N (+ port source at N); B_M holds m_N
+        if (int rc = run(-1, 0, [&] { return launch_adj_init<T>(B(), Lc, use_djdm, port, W, s); })) return rc;
+        if (int rc = run(-1, 0, [&] { return launch_zero<T>(B(), B_GPSI, 0, s); })) return rc;
         const int64_t nseg = (n + K - 1) / K;
-        auto YS = [&](int64_t j, int st) { return tp(h->YS, ((size_t)j * 4 + st) * N3()); };
-        auto BS = [&](int64_t j, int st) { return tp(h->BS, ((size_t)j * 4 + st) * N3()); };
         for (int64_t seg = nseg - 1; seg >= 0; --seg) {
             const int64_t n0 = seg * K, n1 = std::min(n, n0 + K);
             // recompute the segment, storing every stage state and field
-            HIPCHK(hipMemcpyAsync(h->m, tp(h->snaps, seg * N3()), N3() * sizeof(T), hipMemcpyDeviceToDevice, s));
-            int rc = prologue(psi, tp(h->m));
-            if (rc) return rc;
-            for (int64_t k = n0; k < n1; ++k) {
-                rc = step(psi, h->t0 + (double)k * dt, k == n1 - 1, YS(k - n0, 0), BS(k - n0, 0), false);
-                if (rc) return rc;
-            }
+            if (int rc = copy(B_SNAP, (int)seg, B_M, 0)) return rc;
+            if (int rc = prologue()) return rc;
+            for (int64_t k = n0; k < n1; ++k)
+                if (int rc = step(h->t0 + (double)k * dt, k == n1 - 1, (int)(k - n0), false)) return rc;
             // seed: l_4 and u_4 of the segment's last step
             {
-                StageBwdArgs<T> a{};
-                a.stage = -2;
-                a.psi = psi;
-                a.lamp = Lc;
-                a.ell = tp(h->ell);
-                a.y_prev = YS(n1 - 1 - n0, 3);
-                a.u_next = Uc;
-                a.S = (C*)h->S;
-                a.do_fwd = h->demag;
-                if (int rc2 = bwd(a)) return rc2;
+                BwdL L{};
+                L.stage = -2;
+                L.j = L.prev_j = (int)(n1 - 1 - n0);
+                L.prev_st = 3;
+                L.ucur = -1;
+                L.unext = Uc;
+                L.lamp = Lc;
+                L.lacc = -1;
+                L.do_fwd = h->demag;
+                if (int rc = bwd(L)) return rc;
             }
             for (int64_t k = n1 - 1; k >= n0; --k) {
-                const int64_t j = k - n0;
+                const int j = (int)(k - n0);
                 for (int st = 3; st >= 0; --st) {
-                    rc = col();
-                    if (rc) return rc;
-                    StageBwdArgs<T> a{};
-                    a.stage = st;
-                    a.psi = psi;
-                    a.ys = YS(j, st);
-                    a.Bs = BS(j, st);
-                    a.u_cur = Uc;
-                    a.ell = tp(h->ell);
-                    a.lamp = Lc;
-                    a.lacc_in = Lo;
-                    a.lacc_out = Lo;
-                    a.gpsi = h->gpsi;
-                    a.y_prev = st > 0 ? YS(j, st - 1) : (k > n0 ? YS(j - 1, 3) : nullptr);
-                    a.u_next = Uo;
-                    a.S = (C*)h->S;
-                    if (st == 0 && port && k > nstart) {
-                        a.port1 = h->port1;
-                        a.port2 = h->port2;
-                        a.src1 = src1;
-                        a.src2 = src2;
-                    }
-                    a.do_inv = h->demag;
-                    a.do_fwd = h->demag && a.y_prev != nullptr;
-                    if (int rc2 = bwd(a)) return rc2;
-                    if (a.y_prev) std::swap(Uc, Uo);
+                    if (int rc = col()) return rc;
+                    BwdL L{};
+                    L.stage = st;
+                    L.j = j;
+                    L.prev_j = st > 0 ? j : (k > n0 ? j - 1 : -1);
+                    L.prev_st = st > 0 ? st - 1 : 3;
+                    L.ucur = Uc;
+                    L.unext = Uo;
+                    L.lamp = Lc;
+                    L.lacc = Lo;
+                    L.port_src = st == 0 && port && k > nstart;
+                    L.W = W;
+                    L.do_inv = h->demag;
+                    L.do_fwd = h->demag && L.prev_j >= 0;
+                    if (int rc = bwd(L)) return rc;
+                    if (L.prev_j >= 0) std::swap(Uc, Uo);
                 }
                 std::swap(Lc, Lo);  // lambda_k is the lambda' of step k-1
             }
         }
-        HIPCHK(launch_psi_grad_out<T>(P(), h->gpsi, expl, dJdpsi, s));
-        if (dJdm0) HIPCHK(hipMemcpyAsync(dJdm0, Lc, N3() * sizeof(T), hipMemcpyDeviceToDevice, s));
+        if (int rc = run(-1, 0, [&] { return launch_psi_grad_out<T>(B(), use_expl, s); })) return rc;
+        adj_lambda0 = Lc;
         return LLG_OK;
     }
 };
@@ -609,13 +599,283 @@ int check_ptr(const void* p, const char* name) {
     return LLG_OK;
 }
 
+// copy a caller array into / out of an instance buffer
+int put(llg_handle* h, int i, int id, const void* src, size_t bytes, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(h->inst[i].tab.b[id], src, bytes, hipMemcpyDeviceToDevice, s));
+    return LLG_OK;
+}
+int get(llg_handle* h, int i, int id, void* dst, size_t bytes, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(dst, h->inst[i].tab.b[id], bytes, hipMemcpyDeviceToDevice, s));
+    return LLG_OK;
+}
+
+int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_handle** out) {
+    if (!out) return fail(LLG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!probs) return fail(LLG_EINVAL, "problem is NULL");
+    if (n < 1) return fail(LLG_EINVAL, "a batch needs at least one instance");
+    for (int i = 0; i < n; ++i)
+        if (int rc = validate_problem(&probs[i])) return rc;
+    const llg_problem& p0 = probs[0];
+    for (int i = 1; i < n; ++i) {
+        const llg_problem& q = probs[i];
+        if (q.dtype != p0.dtype || q.terms != p0.terms || q.dt != p0.dt || q.max_steps != p0.max_steps ||
+            q.ckpt_policy != p0.ckpt_policy || q.ckpt_param != p0.ckpt_param)
+            return fail(LLG_EINVAL, "batch instances must share dtype, terms, dt, max_steps and checkpoint policy");
+    }
+    auto* h = new llg_handle();
+    auto bail = [&](int code) {
+        free_all(h);
+        delete h;
+        return code;
+    };
+    h->dtype = p0.dtype;
+    h->tsz = p0.dtype == LLG_F64 ? 8 : 4;
+    h->terms = p0.terms;
+    h->demag = (p0.terms & LLG_TERM_DEMAG) != 0;
+    h->policy = p0.ckpt_policy;
+    h->ckpt_param = p0.ckpt_param;
+    h->max_steps = p0.max_steps;
+    h->K = segment_length(p0.max_steps, p0.ckpt_policy, p0.ckpt_param);
+    h->nsnap = (p0.max_steps + h->K - 1) / h->K;
+    if (p0.ckpt_policy == LLG_CKPT_SQRT && p0.ckpt_param == 0) h->nsnap = std::max<int64_t>(h->nsnap, h->K);
+    h->inst.resize(n);
+    for (int i = 0; i < n; ++i) {
+        Instance& I = h->inst[i];
+        I.prob = probs[i];
+        I.N = I.prob.nx * I.prob.ny * I.prob.nz;
+        I.nrows = I.prob.ny * I.prob.nz;
+        I.Px = padded(I.prob.nx);
+        I.Py = padded(I.prob.ny);
+        I.Pz = padded(I.prob.nz);
+        I.Kx = I.Px / 2 + 1;
+        I.ncomp = I.prob.nz > 1 ? 6 : 4;
+        I.nloc = (I.nrows + 1) / 2;
+        h->max_nz = std::max(h->max_nz, I.prob.nz);
+        if (I.Pz > 16) return bail(fail(LLG_ESHAPE, "nz too large"));
+    }
+    int rc;
+    for (int i = 0; i < n; ++i) {
+        Instance& I = h->inst[i];
+        const size_t t = h->tsz, N = I.N, N3b = 3 * N * t;
+        // masks
+        const llg_masks* mk = masks ? &masks[i] : nullptr;
+        const uint8_t* src[4] = {mk ? mk->antenna : nullptr, mk ? mk->port1 : nullptr, mk ? mk->port2 : nullptr,
+                                 mk ? mk->design : nullptr};
+        const int ids[4] = {B_ANT, B_P1, B_P2, B_DES};
+        for (int k = 0; k < 4; ++k) {
+            std::vector<uint8_t> host(N, 0);
+            if (src[k])
+                for (size_t e = 0; e < N; ++e) {
+                    if (src[k][e] > 1) return bail(fail(LLG_EINVAL, "mask values must be 0 or 1"));
+                    host[e] = src[k][e];
+                }
+            if ((rc = alloc(h, &I.tab.b[ids[k]], N))) return bail(rc);
+            if (hipMemcpy(I.tab.b[ids[k]], host.data(), N, hipMemcpyHostToDevice) != hipSuccess)
+                return bail(fail(LLG_EHIP, "mask upload failed"));
+            long long cnt = 0;
+            for (auto v : host) cnt += v;
+            if (k == 0) I.has_ant = cnt > 0;
+            if (k == 1) I.n_p1 = cnt;
+            if (k == 2) I.n_p2 = cnt;
+            if (k == 3) I.has_design = cnt > 0;
+        }
+        const std::pair<int, size_t> sizes[] = {
+            {B_PSI, N * t}, {B_PHI, N * t}, {B_PSIF, N * t}, {B_M, N3b}, {B_ACC, N3b}, {B_YA, N3b}, {B_YB, N3b},
+            {B_S, h->demag ? (size_t)3 * I.nrows * I.Kx * 2 * t : 0}, {B_SNAP, (size_t)h->nsnap * N3b},
+            {B_YS, (size_t)h->K * 4 * N3b}, {B_BS, (size_t)h->K * 4 * N3b}, {B_ELL, N3b}, {B_U0, N3b}, {B_U1, N3b},
+            {B_L0, N3b}, {B_L1, N3b}, {B_GPSI, N * 8}, {B_DJDM, N3b}, {B_DPSIE, N * 8}, {B_DPSI, N * 8},
+            {B_DPHI, N * 8}, {B_PPART, (size_t)I.nloc * 2 * 8}, {B_EPART, (size_t)I.nloc * 5 * 8}, {B_SCAL, 8 * 8}};
+        for (auto& sz : sizes)
+            if ((rc = alloc(h, &I.tab.b[sz.first], sz.second))) return bail(rc);
+        if (h->dtype == LLG_F32) {
+            fill_params<float>(I);
+            rc = upload_tables<float>(h, I);
+        } else {
+            fill_params<double>(I);
+            rc = upload_tables<double>(h, I);
+        }
+        if (rc) return bail(rc);
+        I.pf.ncomp = I.pd.ncomp = I.ncomp;
+        h->sumN += N;
+        h->sumSpec += 3.0 * I.nrows * I.Kx * 2.0 * t;
+        h->sumNhat += (double)I.ncomp * (I.Pz / 2 + 1) * (I.Py / 2 + 1) * I.Kx * t;
+    }
+    if ((rc = choose_launch(h))) return bail(rc);
+    // parameter and pointer tables
+    {
+        void* p;
+        const size_t psz = h->dtype == LLG_F32 ? sizeof(KParams<float>) : sizeof(KParams<double>);
+        if ((rc = alloc(h, &p, psz * n))) return bail(rc);
+        h->ptab = p;
+        std::vector<unsigned char> host(psz * n);
+        for (int i = 0; i < n; ++i) {
+            if (h->dtype == LLG_F32)
+                std::memcpy(&host[psz * i], &h->inst[i].pf, psz);
+            else
+                std::memcpy(&host[psz * i], &h->inst[i].pd, psz);
+        }
+        if (hipMemcpy(p, host.data(), psz * n, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(LLG_EHIP, "parameter table upload failed"));
+        if ((rc = alloc(h, &p, sizeof(InstTab) * n))) return bail(rc);
+        h->itab = (InstTab*)p;
+        std::vector<InstTab> tabs(n);
+        for (int i = 0; i < n; ++i) tabs[i] = h->inst[i].tab;
+        if (hipMemcpy(p, tabs.data(), sizeof(InstTab) * n, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(LLG_EHIP, "pointer table upload failed"));
+        h->bf.ptab = (const KParams<float>*)h->ptab;
+        h->bd.ptab = (const KParams<double>*)h->ptab;
+        h->bf.itab = h->bd.itab = h->itab;
+        h->bf.p0 = h->inst[0].pf;
+        h->bd.p0 = h->inst[0].pd;
+        h->bf.t0 = h->bd.t0 = h->inst[0].tab;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) return bail(fail(LLG_EHIP, "device sync after create failed"));
+    *out = h;
+    return LLG_OK;
+}
+
+// ---- batched entry points (shared by the single-instance ABI) -------------
+
+int b_levelset(llg_handle* h, const void* const* phi, const void* const* psi_fixed, double a, int extrude,
+               void* const* psi_out, hipStream_t s) {
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (!phi || !psi_out) return fail(LLG_EINVAL, "pointer array is NULL");
+    if (!std::isfinite(a)) return fail(LLG_EINVAL, "a must be finite");
+    const int n = (int)h->inst.size();
+    for (int i = 0; i < n; ++i) {
+        if (int rc = check_ptr(phi[i], "phi")) return rc;
+        if (int rc = check_ptr(psi_out[i], "psi_out")) return rc;
+    }
+    for (int i = 0; i < n; ++i) {
+        const Instance& I = h->inst[i];
+        const size_t np = (size_t)(extrude ? I.prob.nx * I.prob.ny : I.N) * h->tsz;
+        if (int rc = put(h, i, B_PHI, phi[i], np, s)) return rc;
+        if (psi_fixed && psi_fixed[i]) {
+            if (int rc = put(h, i, B_PSIF, psi_fixed[i], (size_t)I.N * h->tsz, s)) return rc;
+        } else {
+            HIPCHK(hipMemsetAsync(I.tab.b[B_PSIF], 0, (size_t)I.N * h->tsz, s));
+        }
+    }
+    if (h->dtype == LLG_F32)
+        HIPCHK(launch_levelset<float>(h->bf, a, extrude, s));
+    else
+        HIPCHK(launch_levelset<double>(h->bd, a, extrude, s));
+    for (int i = 0; i < n; ++i)
+        if (int rc = get(h, i, B_PSI, psi_out[i], (size_t)h->inst[i].N * h->tsz, s)) return rc;
+    return LLG_OK;
+}
+
+int b_levelset_vjp(llg_handle* h, const void* const* phi, const double* const* g, double a, int extrude,
+                   double* const* out, hipStream_t s) {
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (!phi || !g || !out) return fail(LLG_EINVAL, "pointer array is NULL");
+    const int n = (int)h->inst.size();
+    for (int i = 0; i < n; ++i) {
+        if (int rc = check_ptr(phi[i], "phi")) return rc;
+        if (int rc = check_ptr(g[i], "dJdpsi")) return rc;
+        if (int rc = check_ptr(out[i], "dJdphi_out")) return rc;
+    }
+    for (int i = 0; i < n; ++i) {
+        const Instance& I = h->inst[i];
+        const size_t np = (size_t)(extrude ? I.prob.nx * I.prob.ny : I.N);
+        if (int rc = put(h, i, B_PHI, phi[i], np * h->tsz, s)) return rc;
+        if (int rc = put(h, i, B_DPSI, g[i], (size_t)I.N * 8, s)) return rc;
+    }
+    if (h->dtype == LLG_F32)
+        HIPCHK(launch_levelset_vjp<float>(h->bf, a, extrude, s));
+    else
+        HIPCHK(launch_levelset_vjp<double>(h->bd, a, extrude, s));
+    for (int i = 0; i < n; ++i) {
+        const Instance& I = h->inst[i];
+        const size_t np = (size_t)(extrude ? I.prob.nx * I.prob.ny : I.N);
+        if (int rc = get(h, i, B_DPHI, out[i], np * 8, s)) return rc;
+    }
+    return LLG_OK;
+}
+
+int b_forward(llg_handle* h, const void* const* psi, const void* const* m0, double t0, int64_t n_steps,
+              const llg_objective_spec* obj, void* const* m_out, double* J_dev, hipStream_t s) {
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (!psi || !m0) return fail(LLG_EINVAL, "pointer array is NULL");
+    const int n = (int)h->inst.size();
+    for (int i = 0; i < n; ++i) {
+        if (int rc = check_ptr(psi[i], "psi")) return rc;
+        if (int rc = check_ptr(m0[i], "m0")) return rc;
+    }
+    if (n_steps < 1 || n_steps > h->max_steps) return fail(LLG_EINVAL, "n_steps must be in [1, max_steps]");
+    if (!std::isfinite(t0)) return fail(LLG_EINVAL, "t0 must be finite");
+    if (obj && (obj->kind < LLG_OBJ_NONE || obj->kind > LLG_OBJ_PORT_MY2)) return fail(LLG_EINVAL, "unknown objective");
+    if (obj && obj->kind == LLG_OBJ_PORT_MY2 && (obj->n_start < 0 || obj->n_start >= n_steps))
+        return fail(LLG_EINVAL, "n_start must be in [0, n_steps)");
+    h->fwd_valid = false;
+    for (int i = 0; i < n; ++i) {
+        const size_t N = h->inst[i].N;
+        if (int rc = put(h, i, B_PSI, psi[i], N * h->tsz, s)) return rc;
+        if (int rc = put(h, i, B_M, m0[i], 3 * N * h->tsz, s)) return rc;
+    }
+    int rc = h->dtype == LLG_F32 ? Ops<float>{h, s}.forward(t0, n_steps, obj) : Ops<double>{h, s}.forward(t0, n_steps, obj);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        if (m_out && m_out[i])
+            if ((rc = get(h, i, B_M, m_out[i], 3 * (size_t)h->inst[i].N * h->tsz, s))) return rc;
+        if (J_dev && obj && obj->kind == LLG_OBJ_PORT_MY2)
+            if ((rc = get(h, i, B_SCAL, J_dev + i, sizeof(double), s))) return rc;
+    }
+    return LLG_OK;
+}
+
+int b_adjoint(llg_handle* h, const void* const* psi, const void* const* dJdm_T, const double* const* expl,
+              const llg_objective_spec* obj, double* const* dJdpsi_out, void* const* dJdm0_out, hipStream_t s) {
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (!psi || !dJdpsi_out) return fail(LLG_EINVAL, "pointer array is NULL");
+    const int n = (int)h->inst.size();
+    for (int i = 0; i < n; ++i) {
+        if (int rc = check_ptr(psi[i], "psi")) return rc;
+        if (int rc = check_ptr(dJdpsi_out[i], "dJdpsi_out")) return rc;
+    }
+    if (!h->fwd_valid) return fail(LLG_ESTATE, "llg_adjoint needs a preceding llg_forward on this handle");
+    if (obj && obj->kind == LLG_OBJ_PORT_MY2 && (obj->n_start < 0 || obj->n_start >= h->n_steps))
+        return fail(LLG_EINVAL, "n_start must be in [0, n_steps)");
+    bool use_djdm = dJdm_T != nullptr, use_expl = expl != nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (use_djdm && !dJdm_T[i]) use_djdm = false;
+        if (use_expl && !expl[i]) use_expl = false;
+    }
+    for (int i = 0; i < n; ++i) {
+        const size_t N = h->inst[i].N;
+        if (int rc = put(h, i, B_PSI, psi[i], N * h->tsz, s)) return rc;
+        if (use_djdm)
+            if (int rc = put(h, i, B_DJDM, dJdm_T[i], 3 * N * h->tsz, s)) return rc;
+        if (use_expl)
+            if (int rc = put(h, i, B_DPSIE, expl[i], N * 8, s)) return rc;
+    }
+    int lam0 = B_L0;
+    if (h->dtype == LLG_F32) {
+        Ops<float> o{h, s};
+        if (int rc = o.adjoint(obj, use_djdm, use_expl)) return rc;
+        lam0 = o.adj_lambda0;
+    } else {
+        Ops<double> o{h, s};
+        if (int rc = o.adjoint(obj, use_djdm, use_expl)) return rc;
+        lam0 = o.adj_lambda0;
+    }
+    for (int i = 0; i < n; ++i) {
+        const size_t N = h->inst[i].N;
+        if (int rc = get(h, i, B_DPSI, dJdpsi_out[i], N * 8, s)) return rc;
+        if (dJdm0_out && dJdm0_out[i])
+            if (int rc = get(h, i, lam0, dJdm0_out[i], 3 * N * h->tsz, s)) return rc;
+    }
+    return LLG_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* llg_last_error(void) { return g_err.c_str(); }
 
-const char* llg_version(void) { return "llg-mi355x 0.1 (gfx950)"; }
+const char* llg_version(void) { return "llg-mi355x 0.2 (gfx950, batched)"; }
 
 int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int32_t ckpt_param, size_t* bytes) {
     if (!p || !bytes) return fail(LLG_EINVAL, "NULL argument");
@@ -626,102 +886,10 @@ int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int3
     return LLG_OK;
 }
 
-int llg_create(const llg_problem* p, const llg_masks* masks, llg_handle** out) {
-    if (!out) return fail(LLG_EINVAL, "out is NULL");
-    *out = nullptr;
-    int rc = validate_problem(p);
-    if (rc) return rc;
-    auto* h = new llg_handle();
-    h->prob = *p;
-    h->dtype = p->dtype;
-    h->tsz = p->dtype == LLG_F64 ? 8 : 4;
-    h->N = p->nx * p->ny * p->nz;
-    h->nrows = p->ny * p->nz;
-    h->Px = padded(p->nx);
-    h->Py = padded(p->ny);
-    h->Pz = padded(p->nz);
-    h->Kx = h->Px / 2 + 1;
-    h->demag = (p->terms & LLG_TERM_DEMAG) != 0;
-    h->ncomp = p->nz > 1 ? 6 : 4;
-    auto bail = [&](int code) {
-        free_all(h);
-        delete h;
-        return code;
-    };
-    if (h->Pz > 16) return bail(fail(LLG_ESHAPE, "nz too large"));
-    if ((rc = choose_launch(h))) return bail(rc);
-    {
-        // kernels may use more than the default 64 KiB of dynamic LDS only after opting in
-        const size_t need = std::max(h->loc.lds, h->col.lds);
-        if (need > 65536) {
-            hipError_t e = set_lds_limits((int)need);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return bail(fail(LLG_ESHAPE, "kernel needs " + std::to_string(need) +
-                                                 " bytes of LDS: " + hipGetErrorString(e)));
-            }
-        }
-    }
-    if (h->dtype == LLG_F32) {
-        fill_params<float>(h);
-        rc = upload_tables<float>(h);
-    } else {
-        fill_params<double>(h);
-        rc = upload_tables<double>(h);
-    }
-    if (rc) return bail(rc);
-    h->pf.ncomp = h->ncomp;
-    h->pd.ncomp = h->ncomp;
-    const size_t N3b = (size_t)3 * h->N * h->tsz;
-    const size_t Sb = (size_t)3 * h->nrows * h->Kx * 2 * h->tsz;
-    void** vecs[] = {&h->m, &h->acc, &h->yA, &h->yB, &h->L0, &h->L1, &h->ell, &h->U0, &h->U1};
-    for (auto v : vecs)
-        if ((rc = alloc(h, v, N3b))) return bail(rc);
-    if (h->demag && (rc = alloc(h, &h->S, Sb))) return bail(rc);
-    void* tmp;
-    if ((rc = alloc(h, &tmp, (size_t)h->N * sizeof(double)))) return bail(rc);
-    h->gpsi = (double*)tmp;
-    if ((rc = alloc(h, &tmp, (size_t)h->loc.blocks * 2 * sizeof(double)))) return bail(rc);
-    h->port_part = (double*)tmp;
-    if ((rc = alloc(h, &tmp, (size_t)h->loc.blocks * 5 * sizeof(double)))) return bail(rc);
-    h->en_part = (double*)tmp;
-    if ((rc = alloc(h, &tmp, 8 * sizeof(double)))) return bail(rc);
-    h->scalars = (double*)tmp;
-    // masks
-    const uint8_t* src[4] = {masks ? masks->antenna : nullptr, masks ? masks->port1 : nullptr,
-                             masks ? masks->port2 : nullptr, masks ? masks->design : nullptr};
-    uint8_t** dst[4] = {&h->antenna, &h->port1, &h->port2, &h->design};
-    for (int k = 0; k < 4; ++k) {
-        if ((rc = alloc(h, &tmp, (size_t)h->N))) return bail(rc);
-        *dst[k] = (uint8_t*)tmp;
-        std::vector<uint8_t> host((size_t)h->N, 0);
-        if (src[k]) {
-            for (int i = 0; i < h->N; ++i) {
-                if (src[k][i] > 1) return bail(fail(LLG_EINVAL, "mask values must be 0 or 1"));
-                host[i] = src[k][i];
-            }
-        }
-        if (hipMemcpy(tmp, host.data(), (size_t)h->N, hipMemcpyHostToDevice) != hipSuccess)
-            return bail(fail(LLG_EHIP, "mask upload failed"));
-        long long cnt = 0;
-        for (auto v : host) cnt += v;
-        if (k == 0) h->has_antenna = cnt > 0;
-        if (k == 1) h->n_p1 = cnt;
-        if (k == 2) h->n_p2 = cnt;
-        if (k == 3) h->has_design = cnt > 0;
-    }
-    h->has_ports = (h->n_p1 + h->n_p2) > 0;
-    // checkpoint store sized for max_steps
-    h->K = segment_length(p->max_steps, p->ckpt_policy, p->ckpt_param);
-    h->nsnap = (p->max_steps + h->K - 1) / h->K;
-    // a shorter run under the SQRT policy uses a shorter K but more segments are never needed than for max_steps
-    if (p->ckpt_policy == LLG_CKPT_SQRT && p->ckpt_param == 0) h->nsnap = std::max<int64_t>(h->nsnap, h->K);
-    if ((rc = alloc(h, &h->snaps, (size_t)h->nsnap * N3b))) return bail(rc);
-    if ((rc = alloc(h, &h->YS, (size_t)h->K * 4 * N3b))) return bail(rc);
-    if ((rc = alloc(h, &h->BS, (size_t)h->K * 4 * N3b))) return bail(rc);
-    if (hipDeviceSynchronize() != hipSuccess) return bail(fail(LLG_EHIP, "device sync after create failed"));
-    *out = h;
-    return LLG_OK;
+int llg_create(const llg_problem* p, const llg_masks* masks, llg_handle** out) { return create_batch(p, masks, 1, out); }
+
+int llg_batch_create(const llg_problem* probs, const llg_masks* masks, int32_t n, llg_batch** out) {
+    return create_batch(probs, masks, n, out);
 }
 
 int llg_destroy(llg_handle* h) {
@@ -734,6 +902,14 @@ int llg_destroy(llg_handle* h) {
     for (auto e : h->ev_pool) (void)hipEventDestroy(e);
     free_all(h);
     delete h;
+    return LLG_OK;
+}
+
+int llg_batch_destroy(llg_batch* b) { return llg_destroy(b); }
+
+int llg_batch_size(const llg_batch* b, int32_t* n) {
+    if (!b || !n) return fail(LLG_EINVAL, "NULL argument");
+    *n = (int32_t)b->inst.size();
     return LLG_OK;
 }
 
@@ -761,94 +937,94 @@ int llg_profile_read(llg_handle* h, int32_t kind, double* ms, int64_t* launches,
 
 int llg_fft_sizes(const llg_handle* h, int32_t* P3) {
     if (!h || !P3) return fail(LLG_EINVAL, "NULL argument");
-    P3[0] = h->Px;
-    P3[1] = h->Py;
-    P3[2] = h->Pz;
+    P3[0] = h->inst[0].Px;
+    P3[1] = h->inst[0].Py;
+    P3[2] = h->inst[0].Pz;
     return LLG_OK;
 }
 
 int llg_levelset_to_Ms(llg_handle* h, const void* phi, const void* psi_fixed, double a, int extrude_z, void* psi_out,
                        hipStream_t stream) {
-    int rc;
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
-    if ((rc = check_ptr(phi, "phi")) || (rc = check_ptr(psi_out, "psi_out"))) return rc;
-    if (!std::isfinite(a)) return fail(LLG_EINVAL, "a must be finite");
-    if (h->dtype == LLG_F32)
-        HIPCHK(launch_levelset<float>(h->pf, (const float*)phi, (const float*)psi_fixed, h->design, a, extrude_z,
-                                      (float*)psi_out, stream));
-    else
-        HIPCHK(launch_levelset<double>(h->pd, (const double*)phi, (const double*)psi_fixed, h->design, a, extrude_z,
-                                       (double*)psi_out, stream));
-    return LLG_OK;
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
+    return b_levelset(h, &phi, &psi_fixed, a, extrude_z, &psi_out, stream);
 }
 
 int llg_levelset_to_Ms_vjp(llg_handle* h, const void* phi, const double* dJdpsi, double a, int extrude_z,
                            double* dJdphi_out, hipStream_t stream) {
-    int rc;
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
-    if ((rc = check_ptr(phi, "phi")) || (rc = check_ptr(dJdpsi, "dJdpsi")) || (rc = check_ptr(dJdphi_out, "dJdphi_out")))
-        return rc;
-    if (h->dtype == LLG_F32)
-        HIPCHK(launch_levelset_vjp<float>(h->pf, (const float*)phi, dJdpsi, h->design, a, extrude_z, dJdphi_out, stream));
-    else
-        HIPCHK(launch_levelset_vjp<double>(h->pd, (const double*)phi, dJdpsi, h->design, a, extrude_z, dJdphi_out, stream));
-    return LLG_OK;
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
+    return b_levelset_vjp(h, &phi, &dJdpsi, a, extrude_z, &dJdphi_out, stream);
 }
 
 int llg_field(llg_handle* h, const void* psi, const void* m, double t, void* B_out, void* rhs_out, hipStream_t stream) {
     int rc;
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
     if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(m, "m")) || (rc = check_ptr(B_out, "B_out"))) return rc;
-    if (h->dtype == LLG_F32)
-        return Ops<float>{h, stream}.field((const float*)psi, (const float*)m, t, (float*)B_out, (float*)rhs_out);
-    return Ops<double>{h, stream}.field((const double*)psi, (const double*)m, t, (double*)B_out, (double*)rhs_out);
+    if ((rc = put(h, 0, B_PSI, psi, (size_t)h->inst[0].N * h->tsz, stream))) return rc;
+    if (h->dtype == LLG_F32) return Ops<float>{h, stream}.field(m, t, B_out, rhs_out);
+    return Ops<double>{h, stream}.field(m, t, B_out, rhs_out);
 }
 
 int llg_forward(llg_handle* h, const void* psi, const void* m0, double t0, int64_t n_steps, const llg_objective_spec* obj,
                 void* m_out, double* J_dev, hipStream_t stream) {
-    int rc;
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
-    if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(m0, "m0"))) return rc;
-    if (n_steps < 1 || n_steps > h->prob.max_steps)
-        return fail(LLG_EINVAL, "n_steps must be in [1, max_steps]");
-    if (!std::isfinite(t0)) return fail(LLG_EINVAL, "t0 must be finite");
-    if (obj && (obj->kind < LLG_OBJ_NONE || obj->kind > LLG_OBJ_PORT_MY2)) return fail(LLG_EINVAL, "unknown objective");
-    if (obj && obj->kind == LLG_OBJ_PORT_MY2 && (obj->n_start < 0 || obj->n_start >= n_steps))
-        return fail(LLG_EINVAL, "n_start must be in [0, n_steps)");
-    h->fwd_valid = false;
-    if (h->dtype == LLG_F32)
-        return Ops<float>{h, stream}.forward((const float*)psi, (const float*)m0, t0, n_steps, obj, (float*)m_out, J_dev);
-    return Ops<double>{h, stream}.forward((const double*)psi, (const double*)m0, t0, n_steps, obj, (double*)m_out, J_dev);
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
+    return b_forward(h, &psi, &m0, t0, n_steps, obj, &m_out, J_dev, stream);
 }
 
 int llg_objective(llg_handle* h, const llg_objective_spec* obj, const void* psi, const void* m, double t, double* J_dev,
                   void* dJdm_out, double* dJdpsi_out, double* energies_dev, hipStream_t stream) {
     int rc;
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
     if ((rc = check_ptr(obj, "obj"))) return rc;
     if (obj->kind != LLG_OBJ_ENERGY_AREA && obj->kind != LLG_OBJ_PORT_MY2)
         return fail(LLG_EINVAL, "objective kind must be ENERGY_AREA or PORT_MY2");
-    if (obj->kind == LLG_OBJ_ENERGY_AREA) {
-        if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(m, "m"))) return rc;
-        if (!(obj->E_ref > 0)) return fail(LLG_EINVAL, "E_ref must be > 0");
+    const size_t N = h->inst[0].N;
+    if (obj->kind == LLG_OBJ_PORT_MY2) {
+        if (!h->fwd_valid) return fail(LLG_ESTATE, "port objective needs a preceding llg_forward");
+        if (J_dev && (rc = get(h, 0, B_SCAL, J_dev, sizeof(double), stream))) return rc;
+        if (dJdm_out) HIPCHK(hipMemsetAsync(dJdm_out, 0, 3 * N * h->tsz, stream));
+        if (dJdpsi_out) HIPCHK(hipMemsetAsync(dJdpsi_out, 0, N * sizeof(double), stream));
+        return LLG_OK;
     }
+    if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(m, "m"))) return rc;
+    if (!(obj->E_ref > 0)) return fail(LLG_EINVAL, "E_ref must be > 0");
+    if ((rc = put(h, 0, B_PSI, psi, N * h->tsz, stream))) return rc;
     if (h->dtype == LLG_F32)
-        return Ops<float>{h, stream}.objective(obj, (const float*)psi, (const float*)m, t, J_dev, (float*)dJdm_out,
-                                               dJdpsi_out, energies_dev);
-    return Ops<double>{h, stream}.objective(obj, (const double*)psi, (const double*)m, t, J_dev, (double*)dJdm_out,
-                                            dJdpsi_out, energies_dev);
+        return Ops<float>{h, stream}.energy(obj, (const float*)m, t, J_dev, (float*)dJdm_out, dJdpsi_out, energies_dev);
+    return Ops<double>{h, stream}.energy(obj, (const double*)m, t, J_dev, (double*)dJdm_out, dJdpsi_out, energies_dev);
 }
 
 int llg_adjoint(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl, const llg_objective_spec* obj,
                 double* dJdpsi_out, void* dJdm0_out, hipStream_t stream) {
-    int rc;
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
-    if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(dJdpsi_out, "dJdpsi_out"))) return rc;
-    if (h->dtype == LLG_F32)
-        return Ops<float>{h, stream}.adjoint((const float*)psi, (const float*)dJdm_T, dJdpsi_expl, obj, dJdpsi_out,
-                                             (float*)dJdm0_out);
-    return Ops<double>{h, stream}.adjoint((const double*)psi, (const double*)dJdm_T, dJdpsi_expl, obj, dJdpsi_out,
-                                          (double*)dJdm0_out);
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
+    return b_adjoint(h, &psi, dJdm_T ? &dJdm_T : nullptr, dJdpsi_expl ? &dJdpsi_expl : nullptr, obj, &dJdpsi_out,
+                     &dJdm0_out, stream);
+}
+
+int llg_batch_levelset_to_Ms(llg_batch* b, const void* const* phi, const void* const* psi_fixed, double a, int extrude_z,
+                             void* const* psi_out, hipStream_t stream) {
+    return b_levelset(b, phi, psi_fixed, a, extrude_z, psi_out, stream);
+}
+
+int llg_batch_levelset_to_Ms_vjp(llg_batch* b, const void* const* phi, const double* const* dJdpsi, double a,
+                                 int extrude_z, double* const* dJdphi_out, hipStream_t stream) {
+    return b_levelset_vjp(b, phi, dJdpsi, a, extrude_z, dJdphi_out, stream);
+}
+
+int llg_batch_forward(llg_batch* b, const void* const* psi, const void* const* m0, double t0, int64_t n_steps,
+                      const llg_objective_spec* obj, void* const* m_out, double* J_dev, hipStream_t stream) {
+    return b_forward(b, psi, m0, t0, n_steps, obj, m_out, J_dev, stream);
+}
+
+int llg_batch_adjoint(llg_batch* b, const void* const* psi, const void* const* dJdm_T, const double* const* dJdpsi_expl,
+                      const llg_objective_spec* obj, double* const* dJdpsi_out, void* const* dJdm0_out,
+                      hipStream_t stream) {
+    return b_adjoint(b, psi, dJdm_T, dJdpsi_expl, obj, dJdpsi_out, dJdm0_out, stream);
 }
 
 }  // extern "C"

@@ -23,7 +23,9 @@ LLG_OBJ_NONE, LLG_OBJ_ENERGY_AREA, LLG_OBJ_PORT_MY2 = 0, 1, 2
 
 EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_levelset_to_Ms",
            "llg_levelset_to_Ms_vjp", "llg_field", "llg_forward", "llg_objective", "llg_adjoint",
-           "llg_query_memory", "llg_fft_sizes", "llg_profile", "llg_profile_read"]
+           "llg_query_memory", "llg_fft_sizes", "llg_profile", "llg_profile_read", "llg_batch_create",
+           "llg_batch_destroy", "llg_batch_size", "llg_batch_levelset_to_Ms", "llg_batch_levelset_to_Ms_vjp",
+           "llg_batch_forward", "llg_batch_adjoint"]
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
 KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col_conv", KIND_STAGE_BWD: "k_stage_bwd"}
 
@@ -87,6 +89,13 @@ def lib():
         "llg_query_memory": [ctypes.POINTER(Problem_c), i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
         "llg_fft_sizes": [vp, ctypes.POINTER(ctypes.c_int32)],
         "llg_profile": [vp, ctypes.c_int],
+        "llg_batch_create": [ctypes.POINTER(Problem_c), ctypes.POINTER(Masks_c), i32, ctypes.POINTER(vp)],
+        "llg_batch_destroy": [vp],
+        "llg_batch_size": [vp, ctypes.POINTER(i32)],
+        "llg_batch_levelset_to_Ms": [vp, vp, vp, dbl, ctypes.c_int, vp, vp],
+        "llg_batch_levelset_to_Ms_vjp": [vp, vp, vp, dbl, ctypes.c_int, vp, vp],
+        "llg_batch_forward": [vp, vp, vp, dbl, i64, ctypes.POINTER(Objective_c), vp, vp, vp],
+        "llg_batch_adjoint": [vp, vp, vp, vp, ctypes.POINTER(Objective_c), vp, vp, vp],
         "llg_profile_read": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
     }
     for name, args in sig.items():
@@ -261,3 +270,97 @@ class Solver:
         check(lib().llg_adjoint(self.h, _ptr(psi), _ptr(dJdm_T), _ptr(dJdpsi_expl),
                                 ctypes.byref(obj) if obj is not None else None, _ptr(dJdpsi), _ptr(dm0), _stream()))
         return (dJdpsi, dm0) if want_dm0 else dJdpsi
+
+
+def _parr(ts):
+    """Host array of device pointers (None entries allowed)."""
+    return (ctypes.c_void_p * len(ts))(*[None if t is None else t.data_ptr() for t in ts])
+
+
+class Batch:
+    """Many instances (designs x frequencies, ragged grids) integrated together;
+    every kernel launch serves all of them (wraps llg_batch)."""
+
+    def __init__(self, probs, dtype="f32", max_steps=1, masks=None, ckpt_policy=LLG_CKPT_SQRT, ckpt_param=0):
+        import torch
+        self.probs = list(probs)
+        self.n = len(self.probs)
+        self.dtype = dtype
+        self.tdtype = torch.float64 if dtype == "f64" else torch.float32
+        self.N = [p.nx * p.ny * p.nz for p in self.probs]
+        pcs = (Problem_c * self.n)(*[make_problem(p, dtype, max_steps, ckpt_policy, ckpt_param) for p in self.probs])
+        keep = []
+        mks = (Masks_c * self.n)()
+        for i in range(self.n):
+            mk = (masks or [{}] * self.n)[i] or {}
+            vals = []
+            for key in ("antenna", "port1", "port2", "design"):
+                a = mk.get(key)
+                if a is None:
+                    vals.append(None)
+                    continue
+                arr = np.ascontiguousarray(np.asarray(a, dtype=np.uint8).reshape(-1))
+                if arr.size != self.N[i]:
+                    raise ValueError("mask size mismatch")
+                keep.append(arr)
+                vals.append(arr.ctypes.data)
+            mks[i] = Masks_c(*vals)
+        h = ctypes.c_void_p()
+        check(lib().llg_batch_create(pcs, mks, self.n, ctypes.byref(h)))
+        self.h = h
+        del keep
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().llg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool):
+        check(lib().llg_profile(self.h, int(enable)))
+
+    def profile_read(self, kind, reset=True):
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        check(lib().llg_profile_read(self.h, kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b), int(reset)))
+        return ms.value, n.value, b.value
+
+    def levelset_to_psi(self, phis, a, psi_fixed=None, extrude_z=True):
+        import torch
+        outs = [torch.empty(n, dtype=self.tdtype, device=phis[0].device) for n in self.N]
+        pf = _parr(psi_fixed) if psi_fixed is not None else None
+        check(lib().llg_batch_levelset_to_Ms(self.h, _parr(phis), pf, float(a), int(extrude_z), _parr(outs), _stream()))
+        return outs
+
+    def levelset_vjp(self, phis, dJdpsis, a, extrude_z=True):
+        import torch
+        outs = [torch.empty(p.numel(), dtype=torch.float64, device=p.device) for p in phis]
+        check(lib().llg_batch_levelset_to_Ms_vjp(self.h, _parr(phis), _parr(dJdpsis), float(a), int(extrude_z),
+                                                 _parr(outs), _stream()))
+        return outs
+
+    def forward(self, psis, m0s, n_steps, t0=0.0, obj: Optional[Objective_c] = None, want_m=True):
+        import torch
+        dev = psis[0].device
+        m_out = [torch.empty(3 * n, dtype=self.tdtype, device=dev) for n in self.N] if want_m else None
+        J = torch.zeros(self.n, dtype=torch.float64, device=dev)
+        check(lib().llg_batch_forward(self.h, _parr(psis), _parr(m0s), float(t0), int(n_steps),
+                                      ctypes.byref(obj) if obj is not None else None,
+                                      _parr(m_out) if m_out is not None else None, ctypes.c_void_p(J.data_ptr()),
+                                      _stream()))
+        return m_out, J
+
+    def adjoint(self, psis, obj: Optional[Objective_c] = None, dJdm_T=None, dJdpsi_expl=None, want_dm0=False):
+        import torch
+        dev = psis[0].device
+        g = [torch.empty(n, dtype=torch.float64, device=dev) for n in self.N]
+        dm0 = [torch.empty(3 * n, dtype=self.tdtype, device=dev) for n in self.N] if want_dm0 else None
+        check(lib().llg_batch_adjoint(self.h, _parr(psis), _parr(dJdm_T) if dJdm_T is not None else None,
+                                      _parr(dJdpsi_expl) if dJdpsi_expl is not None else None,
+                                      ctypes.byref(obj) if obj is not None else None, _parr(g),
+                                      _parr(dm0) if dm0 is not None else None, _stream()))
+        return (g, dm0) if want_dm0 else g

@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/llg.h declares, and rejects invalid arguments on the
+host before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2411_19109_amd import llg
+from paper_2411_19109_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "llg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|int)\s+(llg_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_documented_boundary():
+    names = declared_functions()
+    for need in ["llg_create", "llg_destroy", "llg_levelset_to_Ms", "llg_levelset_to_Ms_vjp", "llg_forward",
+                 "llg_objective", "llg_adjoint", "llg_field", "llg_query_memory", "llg_last_error"]:
+        assert need in names
+    assert set(names) == set(llg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = llg.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert L.llg_version().decode().startswith("llg-mi355x")
+
+
+def _bad(**kw):
+    p = wl.yig_waveguide_plain().problem
+    pc = llg.make_problem(p, "f32", 10)
+    for k, v in kw.items():
+        setattr(pc, k, v)
+    h = ctypes.c_void_p()
+    rc = llg.lib().llg_create(ctypes.byref(pc), None, ctypes.byref(h))
+    return rc, llg.lib().llg_last_error().decode(), h
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("dt", 0.0), ("dt", float("nan")), ("Ms", -1.0),
+                                         ("dtype", 7), ("terms", 64), ("max_steps", 0), ("ckpt_policy", 9),
+                                         ("nz", 9), ("alpha0", -0.1), ("dx", 0.0)])
+def test_create_rejects_invalid_problem_on_host(field, value):
+    rc, msg, h = _bad(**{field: value})
+    assert rc in (llg.LLG_EINVAL, llg.LLG_ESHAPE)
+    assert msg
+    assert not h.value
+
+
+def test_null_arguments_are_rejected():
+    L = llg.lib()
+    assert L.llg_create(None, None, None) == llg.LLG_EINVAL
+    assert L.llg_forward(None, None, None, 0.0, 1, None, None, None, None) == llg.LLG_EINVAL
+    assert L.llg_adjoint(None, None, None, None, None, None, None, None) == llg.LLG_EINVAL
+    assert L.llg_destroy(None) == llg.LLG_OK
+    assert "NULL" in L.llg_last_error().decode()
+
+
+def test_query_memory_matches_checkpoint_layout():
+    p = wl.permalloy_particle().problem
+    n = 2000
+    K = math.ceil(math.sqrt(n))
+    nsnap = math.ceil(n / K)
+    N3 = 3 * p.n
+    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT) == (nsnap * N3 + 8 * K * N3) * 4
+    assert llg.query_memory(p, n, llg.LLG_CKPT_ALL) == (N3 + 8 * n * N3) * 4
+    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT, dtype="f64") == (nsnap * N3 + 8 * K * N3) * 8
+    # sqrt(n) growth: 100x more steps costs ~10x the store
+    r = llg.query_memory(p, 200000, llg.LLG_CKPT_SQRT) / llg.query_memory(p, 2000, llg.LLG_CKPT_SQRT)
+    assert 8 < r < 12
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(llg, "_lib", None)
+    monkeypatch.setattr(llg, "LIB_PATH", os.path.join(ROOT, "no_such_libllg.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        llg.lib()

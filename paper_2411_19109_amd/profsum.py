@@ -26,7 +26,7 @@ def _short(name: str) -> str:
 
 
 def stats(d: str) -> str:
-    f = glob.glob(os.path.join(d, "*kernel_stats.csv"))[0]
+    f = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)[0]
     rows = list(csv.DictReader(open(f)))
     out = ["kernel | calls | avg_us | min_us | max_us | total_ms | percent"]
     for r in rows:
@@ -37,7 +37,7 @@ def stats(d: str) -> str:
 
 
 def pmc(d: str) -> str:
-    f = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+    f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
     agg = collections.defaultdict(list)
     with open(f) as fh:
         for r in csv.DictReader(fh):

@@ -177,9 +177,14 @@ struct BatchDev {
     InstTab t0;
 };
 
-template <typename T> hipError_t launch_stage_fwd(const BatchDev<T>& b, const FwdL& L, hipStream_t s);
-template <typename T> hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s);
-template <typename T> hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, hipStream_t s);
+// The three per-stage kernels take an optional event pair that the runtime
+// binds to the dispatch itself (start and end of the kernel on the device).
+template <typename T>
+hipError_t launch_stage_fwd(const BatchDev<T>& b, const FwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T> hipError_t launch_levelset(const BatchDev<T>& b, double a, int extrude, hipStream_t s);
 template <typename T> hipError_t launch_levelset_vjp(const BatchDev<T>& b, double a, int extrude, hipStream_t s);
 template <typename T>

@@ -13,6 +13,7 @@
 // into complex signals (x,y components of one row; z components of two rows),
 // so every row FFT is a complex FFT of length Px.  All FFTs are radix-4/2
 // Stockham passes in LDS with precomputed float64-accurate twiddles.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "llg_internal.hpp"
@@ -1141,27 +1142,30 @@ static BatchArgs<T> bargs(const BatchDev<T>& b, const int2* work) {
     return a;
 }
 template <typename T>
-hipError_t launch_stage_fwd(const BatchDev<T>& b, const FwdL& L, hipStream_t s) {
-    hipLaunchKernelGGL(k_stage_fwd<T>, dim3(b.nloc), dim3(b.loc_threads), b.loc_lds, s, bargs(b, b.work_loc), L);
+hipError_t launch_stage_fwd(const BatchDev<T>& b, const FwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL(k_stage_fwd<T>, dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.loc_lds, s, e0, e1, 0,
+                          bargs(b, b.work_loc), L);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s) {
-    hipLaunchKernelGGL(k_stage_bwd<T>, dim3(b.nloc), dim3(b.loc_threads), b.loc_lds, s, bargs(b, b.work_loc), L);
+hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL(k_stage_bwd<T>, dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.loc_lds, s, e0, e1, 0,
+                          bargs(b, b.work_loc), L);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, hipStream_t s) {
+hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g(b.ncol), t(b.col_threads);
     const BatchArgs<T> a = bargs(b, b.work_col);
+    const uint32_t lds = (uint32_t)b.col_lds;
     if (max_nz == 1)
-        hipLaunchKernelGGL((k_col_conv<T, 1>), g, t, b.col_lds, s, a, b.col_tk);
+        hipExtLaunchKernelGGL((k_col_conv<T, 1>), g, t, lds, s, e0, e1, 0, a, b.col_tk);
     else if (max_nz == 2)
-        hipLaunchKernelGGL((k_col_conv<T, 2>), g, t, b.col_lds, s, a, b.col_tk);
+        hipExtLaunchKernelGGL((k_col_conv<T, 2>), g, t, lds, s, e0, e1, 0, a, b.col_tk);
     else if (max_nz <= 4)
-        hipLaunchKernelGGL((k_col_conv<T, 4>), g, t, b.col_lds, s, a, b.col_tk);
+        hipExtLaunchKernelGGL((k_col_conv<T, 4>), g, t, lds, s, e0, e1, 0, a, b.col_tk);
     else
-        hipLaunchKernelGGL((k_col_conv<T, 8>), g, t, b.col_lds, s, a, b.col_tk);
+        hipExtLaunchKernelGGL((k_col_conv<T, 8>), g, t, lds, s, e0, e1, 0, a, b.col_tk);
     return hipGetLastError();
 }
 template <typename T>
@@ -1240,9 +1244,9 @@ hipError_t set_lds_limits(size_t bytes) {
 }
 
 #define LLG_INST(T)                                                                                                 \
-    template hipError_t launch_stage_fwd<T>(const BatchDev<T>&, const FwdL&, hipStream_t);                          \
-    template hipError_t launch_stage_bwd<T>(const BatchDev<T>&, const BwdL&, hipStream_t);                          \
-    template hipError_t launch_col_conv<T>(const BatchDev<T>&, int, hipStream_t);                                   \
+    template hipError_t launch_stage_fwd<T>(const BatchDev<T>&, const FwdL&, hipStream_t, hipEvent_t, hipEvent_t);  \
+    template hipError_t launch_stage_bwd<T>(const BatchDev<T>&, const BwdL&, hipStream_t, hipEvent_t, hipEvent_t);  \
+    template hipError_t launch_col_conv<T>(const BatchDev<T>&, int, hipStream_t, hipEvent_t, hipEvent_t);           \
     template hipError_t launch_levelset<T>(const BatchDev<T>&, double, int, hipStream_t);                           \
     template hipError_t launch_levelset_vjp<T>(const BatchDev<T>&, double, int, hipStream_t);                       \
     template hipError_t launch_adj_init<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                     \

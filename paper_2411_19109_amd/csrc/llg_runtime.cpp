@@ -376,19 +376,18 @@ struct Ops {
     const BatchDev<T>& B() const { return bdev<T>(h); }
 
     // every kernel launch goes through here: optional event bracketing for profiling
+    // every kernel launch goes through here.  Profiling binds an event pair to
+    // the dispatch of the three per-stage kernels (device start/end of the
+    // kernel itself, not of the surrounding queue activity).
     template <typename F>
     int run(int kind, double bytes, F&& launch) {
         hipEvent_t a = nullptr, b = nullptr;
-        if (h->prof_on && kind >= 0) {
+        const bool rec = h->prof_on && kind >= 0;
+        if (rec)
             if (int rc = take_events(h, &a, &b)) return rc;
-            HIPCHK(hipEventRecord(a, s));
-        }
-        hipError_t e = launch();
+        hipError_t e = launch(a, b);
         if (e != hipSuccess) return fail(LLG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
-        if (h->prof_on && kind >= 0) {
-            HIPCHK(hipEventRecord(b, s));
-            h->prof.push_back({kind, bytes, a, b});
-        }
+        if (rec) h->prof.push_back({kind, bytes, a, b});
         return LLG_OK;
     }
 
@@ -427,16 +426,16 @@ struct Ops {
 
     int col() {
         if (!h->demag) return LLG_OK;
-        return run(LLG_KIND_COLUMN, col_bytes(), [&] { return launch_col_conv<T>(B(), h->max_nz, s); });
+        return run(LLG_KIND_COLUMN, col_bytes(), [&](hipEvent_t a, hipEvent_t b) { return launch_col_conv<T>(B(), h->max_nz, s, a, b); });
     }
     int fwd(const FwdL& L) {
-        return run(LLG_KIND_STAGE_FWD, fwd_bytes(L), [&] { return launch_stage_fwd<T>(B(), L, s); });
+        return run(LLG_KIND_STAGE_FWD, fwd_bytes(L), [&](hipEvent_t a, hipEvent_t b) { return launch_stage_fwd<T>(B(), L, s, a, b); });
     }
     int bwd(const BwdL& L) {
-        return run(LLG_KIND_STAGE_BWD, bwd_bytes(L), [&] { return launch_stage_bwd<T>(B(), L, s); });
+        return run(LLG_KIND_STAGE_BWD, bwd_bytes(L), [&](hipEvent_t a, hipEvent_t b) { return launch_stage_bwd<T>(B(), L, s, a, b); });
     }
     int copy(int src, int src_slot, int dst, int dst_slot) {
-        return run(-1, 0, [&] { return launch_copy<T>(B(), src, src_slot, dst, dst_slot, s); });
+        return run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_copy<T>(B(), src, src_slot, dst, dst_slot, s); });
     }
 
     static FwdL fwd_launch(int stage) {
@@ -487,7 +486,7 @@ struct Ops {
         if (nsnap > h->nsnap || K > h->K)
             return fail(LLG_ENOMEM, "checkpoint store too small for n_steps (raise max_steps at create)");
         if (port)
-            if (int rc = run(-1, 0, [&] { return launch_zero<T>(B(), B_PPART, 1, s); })) return rc;
+            if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_PPART, 1, s); })) return rc;
         if (int rc = prologue()) return rc;
         const double dt = h->inst[0].prob.dt;
         for (int64_t k = 0; k < n; ++k) {
@@ -498,7 +497,7 @@ struct Ops {
         }
         if (port) {
             const int W = (int)(n - obj->n_start);
-            if (int rc = run(-1, 0, [&] { return launch_port_finish<T>(B(), W, s); })) return rc;
+            if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_port_finish<T>(B(), W, s); })) return rc;
         }
         h->fwd_valid = true;
         h->t0 = t0;
@@ -526,9 +525,9 @@ struct Ops {
         if (int rc = col()) return rc;
         const llg_problem& q = h->inst[0].prob;
         const double MsV = q.Ms * q.dx * q.dy * q.dz;
-        if (int rc = run(-1, 0, [&] { return launch_energy<T>(B(), t, m, MsV / obj->E_ref, dJdm, dJdpsi, s); }))
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_energy<T>(B(), t, m, MsV / obj->E_ref, dJdm, dJdpsi, s); }))
             return rc;
-        return run(-1, 0, [&] {
+        return run(-1, 0, [&](hipEvent_t, hipEvent_t) {
             return launch_energy_finish<T>(B(), MsV, obj->lambda, obj->area, obj->E_ref, J, en, dJdpsi, s);
         });
     }
@@ -542,8 +541,8 @@ struct Ops {
         const int W = (int)(n - nstart);
         int Lc = B_L0, Lo = B_L1, Uc = B_U0, Uo = B_U1;
         // lambda_N = dJ/dm_N (+ port source at N); B_M holds m_N
-        if (int rc = run(-1, 0, [&] { return launch_adj_init<T>(B(), Lc, use_djdm, port, W, s); })) return rc;
-        if (int rc = run(-1, 0, [&] { return launch_zero<T>(B(), B_GPSI, 0, s); })) return rc;
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_adj_init<T>(B(), Lc, use_djdm, port, W, s); })) return rc;
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_GPSI, 0, s); })) return rc;
         const int64_t nseg = (n + K - 1) / K;
         for (int64_t seg = nseg - 1; seg >= 0; --seg) {
             const int64_t n0 = seg * K, n1 = std::min(n, n0 + K);
@@ -588,7 +587,7 @@ struct Ops {
                 std::swap(Lc, Lo);  // lambda_k is the lambda' of step k-1
             }
         }
-        if (int rc = run(-1, 0, [&] { return launch_psi_grad_out<T>(B(), use_expl, s); })) return rc;
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_psi_grad_out<T>(B(), use_expl, s); })) return rc;
         adj_lambda0 = Lc;
         return LLG_OK;
     }

@@ -5,7 +5,7 @@
 
 ``stats`` prints, per kernel, the call count and the average / total device
 time from the *_kernel_stats.csv file.  ``pmc`` prints, per kernel, the number
-of dispatches and the mean counter value per dispatch from the
+of dispatches and the mean and largest counter value per dispatch from the
 *_counter_collection.csv file (FETCH_SIZE / WRITE_SIZE are in KiB).
 """
 from __future__ import annotations
@@ -42,9 +42,9 @@ def pmc(d: str) -> str:
     with open(f) as fh:
         for r in csv.DictReader(fh):
             agg[(_short(r["Kernel_Name"]), r["Counter_Name"])].append(float(r["Counter_Value"]))
-    out = ["kernel | counter | dispatches | mean_per_dispatch"]
+    out = ["kernel | counter | dispatches | mean_per_dispatch | max_per_dispatch"]
     for (k, c), v in sorted(agg.items()):
-        out.append(f"{k} | {c} | {len(v)} | {sum(v) / len(v):.3f}")
+        out.append(f"{k} | {c} | {len(v)} | {sum(v) / len(v):.3f} | {max(v):.3f}")
     return "\n".join(out)
 
 

@@ -70,8 +70,13 @@ extern "C" {
 #define LLG_FACE_ZHI 32
 
 /* checkpoint policies of the adjoint */
-#define LLG_CKPT_SQRT 0 /* snapshots every K steps (K = ckpt_param or ceil(sqrt(n))), segments recomputed */
-#define LLG_CKPT_ALL 1  /* one segment: every stage state of the run is kept (memory ~ n_steps) */
+#define LLG_CKPT_SQRT 0     /* snapshots every K steps (K = ckpt_param or ceil(sqrt(n))), segments recomputed;
+                               with more than one segment the stage store is double-buffered so the next
+                               segment is recomputed on a second stream while the current one is transposed */
+#define LLG_CKPT_ALL 1      /* one segment: every stage state of the run is kept (memory ~ n_steps) */
+#define LLG_CKPT_BINOMIAL 2 /* ckpt_param snapshot slots (0 = 32) and the stage store of one step; binomial
+                               (Revolve-type) recomputation schedule: memory independent of n_steps, each
+                               step recomputed at most r times with C(s + r, s) >= n_steps */
 
 /* objectives */
 #define LLG_OBJ_NONE 0
@@ -99,7 +104,8 @@ typedef struct llg_problem {
     double dt;                /* RK4 step, s (> 0)                                          */
     int64_t max_steps;        /* largest n_steps a later llg_forward may use (sizes snapshots) */
     int32_t ckpt_policy;      /* LLG_CKPT_*                                                 */
-    int32_t ckpt_param;       /* SQRT: segment length K (0 = ceil(sqrt(n_steps)))           */
+    int32_t ckpt_param;       /* SQRT: segment length K (0 = ceil(sqrt(n_steps)));
+                                 BINOMIAL: snapshot slots (0 = 32)                            */
 } llg_problem;
 
 /* Host-side copies of the u8 masks (length N, values 0/1); NULL = all zero.
@@ -191,6 +197,22 @@ int llg_adjoint(llg_handle* h, const void* psi, const void* dJdm_T, const double
 /* Device bytes the checkpoint store needs for n_steps under a policy
  * (snapshots + recomputed stage states), without allocating anything. */
 int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int32_t ckpt_param, size_t* bytes);
+
+/* Forward RK4 steps that llg_adjoint recomputes after a forward run of n_steps
+ * under a checkpoint policy (host only; n_steps for SQRT and ALL). */
+int llg_query_recompute(int64_t n_steps, int32_t policy, int32_t ckpt_param, int64_t* steps);
+
+/* HIP graphs (default off).  While enabled, the launch sequence of
+ * llg_forward / llg_adjoint (and their batch forms) is captured into a HIP
+ * graph on the first call with a given signature (n_steps, t0, objective kind
+ * and window, adjoint inputs present) and replayed on later calls, on a stream
+ * of the handle ordered after the caller's stream (event fork/join), so no
+ * per-launch host work remains.  Up to 8 graphs are cached per handle; the
+ * copies of the caller's arrays in and out stay ordinary stream operations.
+ * Disabling synchronises the handle's graph stream and frees the graphs.
+ * Profiling (llg_profile) runs the sequences without graphs.
+ * Errors: LLG_EINVAL (NULL handle), LLG_EHIP (capture or instantiation failed). */
+int llg_set_graphs(llg_handle* h, int enable);
 
 /* Kernel classes reported by the profiling counters. */
 #define LLG_KIND_STAGE_FWD 0 /* forward local kernel: row FFTs + fields + LL RHS + RK4 stage */

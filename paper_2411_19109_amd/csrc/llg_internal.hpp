@@ -36,13 +36,14 @@ enum BufId : int {
     B_YA,       // stage state (3N)
     B_YB,       // stage state (3N)
     B_S,        // x-spectrum rows (3 * nrows * Kx complex)
+    B_S2,       // second x-spectrum (segment recomputation on the second stream)
     B_TWX,      // twiddles (Px), (Py), (Pz)
     B_TWY,
     B_TWZ,
     B_NHAT,     // tensor spectrum
     B_SNAP,     // checkpoint snapshots (nsnap * 3N)
-    B_YS,       // stage states of a recomputed segment (K * 4 * 3N)
-    B_BS,       // fields of those stage states (K * 4 * 3N)
+    B_YS,       // stage states of recomputed steps (slots * 4 * 3N)
+    B_BS,       // fields of those stage states (slots * 4 * 3N)
     B_ELL,      // stage adjoint l_s (3N)
     B_U0,       // field adjoint u (3N), ping-pong
     B_U1,
@@ -91,6 +92,7 @@ struct FwdL {
     int store_j;          // >= 0: copy ys and B(ys) to slot store_j of YS / BS
     int port;             // accumulate the port running cost (stage 3)
     int do_inv, do_fwd;   // inverse x-FFT of S (demag in) / forward x-FFT of psi*ynext into S
+    int spec;             // BufId of S (B_S or B_S2)
     void* ext_ys;         // single-instance overrides (field evaluation)
     void* ext_ynext;
     void* ext_B;
@@ -184,7 +186,7 @@ hipError_t launch_stage_fwd(const BatchDev<T>& b, const FwdL& L, hipStream_t s, 
 template <typename T>
 hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T>
-hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T> hipError_t launch_levelset(const BatchDev<T>& b, double a, int extrude, hipStream_t s);
 template <typename T> hipError_t launch_levelset_vjp(const BatchDev<T>& b, double a, int extrude, hipStream_t s);
 template <typename T>

@@ -363,7 +363,7 @@ __device__ __forceinline__ StageFwdArgs<T> resolve_fwd(const KParams<T>& p, cons
     a.mn = role<T>(tb, L.mn);
     a.acc = role<T>(tb, L.acc);
     a.ynext = L.ext_ynext ? static_cast<T*>(L.ext_ynext) : role<T>(tb, L.ynext);
-    a.S = role<cplx<T>>(tb, B_S);
+    a.S = role<cplx<T>>(tb, L.spec);
     a.antenna = p.has_ant ? role<uint8_t>(tb, B_ANT) : nullptr;
     a.ys_store = L.store_j >= 0 ? role<T>(tb, B_YS) + ((size_t)L.store_j * 4 + L.stage) * n3 : nullptr;
     a.Bs_store = L.ext_B ? static_cast<T*>(L.ext_B)
@@ -749,14 +749,14 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
 //                Nt [comp][kz <= Pz/2][ky <= Py/2][tk] real
 // ---------------------------------------------------------------------------
 template <typename T, int NZ>
-__global__ void __launch_bounds__(1024) k_col_conv(const BatchArgs<T> ba, int TK) {
+__global__ void __launch_bounds__(1024) k_col_conv(const BatchArgs<T> ba, int TK, int sid) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int MR = MaxReg<T>::v;
     const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
     const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
     const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
-    C* __restrict__ S = role<C>(tb, B_S);
+    C* __restrict__ S = role<C>(tb, sid);
     const T* __restrict__ nhat = role<T>(tb, B_NHAT);
     const C* __restrict__ twy = role<C>(tb, B_TWY);
     const C* __restrict__ twz = role<C>(tb, B_TWZ);
@@ -1154,18 +1154,18 @@ hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s, 
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const dim3 g(b.ncol), t(b.col_threads);
     const BatchArgs<T> a = bargs(b, b.work_col);
     const uint32_t lds = (uint32_t)b.col_lds;
     if (max_nz == 1)
-        hipExtLaunchKernelGGL((k_col_conv<T, 1>), g, t, lds, s, e0, e1, 0, a, b.col_tk);
+        hipExtLaunchKernelGGL((k_col_conv<T, 1>), g, t, lds, s, e0, e1, 0, a, b.col_tk, spec);
     else if (max_nz == 2)
-        hipExtLaunchKernelGGL((k_col_conv<T, 2>), g, t, lds, s, e0, e1, 0, a, b.col_tk);
+        hipExtLaunchKernelGGL((k_col_conv<T, 2>), g, t, lds, s, e0, e1, 0, a, b.col_tk, spec);
     else if (max_nz <= 4)
-        hipExtLaunchKernelGGL((k_col_conv<T, 4>), g, t, lds, s, e0, e1, 0, a, b.col_tk);
+        hipExtLaunchKernelGGL((k_col_conv<T, 4>), g, t, lds, s, e0, e1, 0, a, b.col_tk, spec);
     else
-        hipExtLaunchKernelGGL((k_col_conv<T, 8>), g, t, lds, s, e0, e1, 0, a, b.col_tk);
+        hipExtLaunchKernelGGL((k_col_conv<T, 8>), g, t, lds, s, e0, e1, 0, a, b.col_tk, spec);
     return hipGetLastError();
 }
 template <typename T>
@@ -1246,7 +1246,7 @@ hipError_t set_lds_limits(size_t bytes) {
 #define LLG_INST(T)                                                                                                 \
     template hipError_t launch_stage_fwd<T>(const BatchDev<T>&, const FwdL&, hipStream_t, hipEvent_t, hipEvent_t);  \
     template hipError_t launch_stage_bwd<T>(const BatchDev<T>&, const BwdL&, hipStream_t, hipEvent_t, hipEvent_t);  \
-    template hipError_t launch_col_conv<T>(const BatchDev<T>&, int, hipStream_t, hipEvent_t, hipEvent_t);           \
+    template hipError_t launch_col_conv<T>(const BatchDev<T>&, int, int, hipStream_t, hipEvent_t, hipEvent_t);      \
     template hipError_t launch_levelset<T>(const BatchDev<T>&, double, int, hipStream_t);                           \
     template hipError_t launch_levelset_vjp<T>(const BatchDev<T>&, double, int, hipStream_t);                       \
     template hipError_t launch_adj_init<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                     \

@@ -28,6 +28,7 @@
 
 #include "../../include/llg.h"
 #include "llg_internal.hpp"
+#include "llg_schedule.hpp"
 
 using namespace llg;
 
@@ -60,20 +61,6 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
-int64_t segment_length(int64_t n, int32_t policy, int32_t param) {
-    if (n <= 0) return 1;
-    if (policy == LLG_CKPT_ALL) return n;
-    if (param > 0) return std::min<int64_t>(param, n);
-    int64_t K = (int64_t)std::ceil(std::sqrt((double)n));
-    return std::max<int64_t>(1, K);
-}
-
-size_t store_bytes(int64_t N3, size_t tsz, int64_t n, int32_t policy, int32_t param) {
-    const int64_t K = segment_length(n, policy, param);
-    const int64_t nsnap = (n + K - 1) / K;
-    return (size_t)(nsnap * N3 + 8 * K * N3) * tsz;
-}
-
 struct Instance {
     llg_problem prob{};
     int N = 0, nrows = 0, Px = 1, Py = 1, Pz = 1, Kx = 1, ncomp = 4;
@@ -104,10 +91,28 @@ struct llg_handle {
     int max_nz = 1;
     // byte sums over instances (profiling)
     double sumN = 0, sumSpec = 0, sumNhat = 0;
-    // checkpoint store
-    int64_t K = 1, nsnap = 0;
+    // checkpoint store: nsnap snapshot slots, K stage-state slots per half, halves = 2
+    // when consecutive segments are recomputed and transposed concurrently
+    int64_t K = 1, nsnap = 0, halves = 1;
     int32_t policy = LLG_CKPT_SQRT, ckpt_param = 0;
     int64_t max_steps = 1;
+    Plan plan;  // binomial schedule of the last forward run
+    int64_t plan_n = -1;
+    int plan_slots = 0;
+    // second stream (segment recomputation) and its synchronisation events
+    hipStream_t aux = nullptr;
+    std::vector<hipEvent_t> sync_ev;
+    // HIP graphs of the forward / adjoint launch sequences, keyed by the call
+    // signature; captured and replayed on a stream of the handle
+    struct GraphEntry {
+        std::vector<double> key;
+        hipGraphExec_t exec;
+        int result;
+    };
+    bool graphs_on = false;
+    hipStream_t gstream = nullptr;
+    hipEvent_t g_in = nullptr, g_out = nullptr;
+    std::vector<GraphEntry> graphs;
     // per-kernel profiling
     struct ProfRec { int kind; double bytes; hipEvent_t a, b; };
     bool prof_on = false;
@@ -327,7 +332,7 @@ int validate_problem(const llg_problem* p) {
     if (p->terms & ~15) return fail(LLG_EINVAL, "unknown term bits");
     if (p->nz > 8) return fail(LLG_ESHAPE, "nz > 8 is not supported by the column FFT");
     if (p->max_steps < 1) return fail(LLG_EINVAL, "max_steps must be >= 1");
-    if (p->ckpt_policy != LLG_CKPT_SQRT && p->ckpt_policy != LLG_CKPT_ALL)
+    if (p->ckpt_policy != LLG_CKPT_SQRT && p->ckpt_policy != LLG_CKPT_ALL && p->ckpt_policy != LLG_CKPT_BINOMIAL)
         return fail(LLG_EINVAL, "unknown checkpoint policy");
     if (p->ckpt_param < 0) return fail(LLG_EINVAL, "ckpt_param must be >= 0");
     const double* vals[] = {&p->A, &p->K, &p->f1, &p->f2, &p->t_switch};
@@ -364,6 +369,89 @@ int drain_profile(llg_handle* h) {
     return LLG_OK;
 }
 
+// Binomial schedule for a run of n steps (kept until n or the slot count changes).
+void ensure_plan(llg_handle* h, int64_t n) {
+    if (h->policy != LLG_CKPT_BINOMIAL) return;
+    const int slots = binomial_slots(n, h->ckpt_param);
+    if (h->plan_n == n && h->plan_slots == slots) return;
+    binomial_plan(n, slots, h->plan);
+    h->plan_n = n;
+    h->plan_slots = slots;
+}
+
+// What llg_adjoint needs to know about the last forward run.
+void record_forward(llg_handle* h, double t0, int64_t n, const llg_objective_spec* obj) {
+    h->fwd_valid = true;
+    h->t0 = t0;
+    h->n_steps = n;
+    h->K_used = segment_length(n, h->policy, h->ckpt_param);
+    h->last_obj = obj ? *obj : llg_objective_spec{};
+}
+
+// Second stream and events of the overlapped adjoint (created outside any capture).
+int prepare_adjoint(llg_handle* h) {
+    if (h->policy == LLG_CKPT_BINOMIAL || h->halves < 2) return LLG_OK;
+    const int64_t nseg = (h->n_steps + h->K_used - 1) / h->K_used;
+    if (!h->aux) HIPCHK(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    while (h->sync_ev.size() < (size_t)(2 * nseg + 1)) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        h->sync_ev.push_back(e);
+    }
+    return LLG_OK;
+}
+
+void drop_graphs(llg_handle* h) {
+    for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+}
+
+// Run body(stream) -- an enqueue-only launch sequence whose kernels touch only
+// handle buffers -- either directly on s or, with graphs enabled, as a cached
+// HIP graph on the handle's graph stream, ordered after s's prior work and
+// before its later work.  body returns an int status and sets *result.
+template <typename F>
+int run_sequence(llg_handle* h, hipStream_t s, const std::vector<double>& key, int* result, F&& body) {
+    if (!h->graphs_on || h->prof_on) return body(s, result);
+    if (!h->gstream) {
+        HIPCHK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&h->g_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->g_out, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(h->g_in, s));
+    HIPCHK(hipStreamWaitEvent(h->gstream, h->g_in, 0));
+    llg_handle::GraphEntry* hit = nullptr;
+    for (auto& g : h->graphs)
+        if (g.key == key) hit = &g;
+    if (!hit) {
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+        int res = 0;
+        const int rc = body(h->gstream, &res);
+        const hipError_t e = hipStreamEndCapture(h->gstream, &graph);
+        if (rc) {
+            if (e == hipSuccess && graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(LLG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(LLG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        if (h->graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(h->graphs.front().exec);
+            h->graphs.erase(h->graphs.begin());
+        }
+        h->graphs.push_back({key, exec, res});
+        hit = &h->graphs.back();
+    }
+    *result = hit->result;
+    HIPCHK(hipGraphLaunch(hit->exec, h->gstream));
+    HIPCHK(hipEventRecord(h->g_out, h->gstream));
+    HIPCHK(hipStreamWaitEvent(s, h->g_out, 0));
+    return LLG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // typed orchestration (all instances of the batch at once)
 // ---------------------------------------------------------------------------
@@ -373,6 +461,12 @@ struct Ops {
     llg_handle* h;
     hipStream_t s;
     int adj_lambda0 = B_L0;
+    int spec = B_S;  // x-spectrum buffer of this stream's forward work
+    // adjoint state: ping-pong roles of lambda and u, port window
+    int Lc = B_L0, Lo = B_L1, Uc = B_U0, Uo = B_U1;
+    bool adj_port = false;
+    int64_t adj_nstart = 0;
+    int adj_W = 0;
     const BatchDev<T>& B() const { return bdev<T>(h); }
 
     // every kernel launch goes through here: optional event bracketing for profiling
@@ -426,7 +520,7 @@ struct Ops {
 
     int col() {
         if (!h->demag) return LLG_OK;
-        return run(LLG_KIND_COLUMN, col_bytes(), [&](hipEvent_t a, hipEvent_t b) { return launch_col_conv<T>(B(), h->max_nz, s, a, b); });
+        return run(LLG_KIND_COLUMN, col_bytes(), [&](hipEvent_t a, hipEvent_t b) { return launch_col_conv<T>(B(), h->max_nz, spec, s, a, b); });
     }
     int fwd(const FwdL& L) {
         return run(LLG_KIND_STAGE_FWD, fwd_bytes(L), [&](hipEvent_t a, hipEvent_t b) { return launch_stage_fwd<T>(B(), L, s, a, b); });
@@ -438,11 +532,12 @@ struct Ops {
         return run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_copy<T>(B(), src, src_slot, dst, dst_slot, s); });
     }
 
-    static FwdL fwd_launch(int stage) {
+    FwdL fwd_launch(int stage) const {
         FwdL L{};
         L.stage = stage;
         L.ys = L.mn = L.acc = L.ynext = -1;
         L.store_j = -1;
+        L.spec = spec;
         return L;
     }
 
@@ -481,19 +576,39 @@ struct Ops {
 
     int forward(double t0, int64_t n, const llg_objective_spec* obj) {
         const bool port = obj && obj->kind == LLG_OBJ_PORT_MY2;
+        const double dt = h->inst[0].prob.dt;
+        auto in_win = [&](int64_t k) { return port && (k + 1) > obj->n_start; };
         const int64_t K = segment_length(n, h->policy, h->ckpt_param);
-        const int64_t nsnap = (n + K - 1) / K;
-        if (nsnap > h->nsnap || K > h->K)
+        if (h->policy == LLG_CKPT_BINOMIAL) {
+            if (binomial_slots(n, h->ckpt_param) > h->nsnap)
+                return fail(LLG_ENOMEM, "checkpoint store too small for n_steps (raise max_steps at create)");
+        } else if ((n + K - 1) / K > h->nsnap || K > h->K) {
             return fail(LLG_ENOMEM, "checkpoint store too small for n_steps (raise max_steps at create)");
+        }
         if (port)
             if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_PPART, 1, s); })) return rc;
         if (int rc = prologue()) return rc;
-        const double dt = h->inst[0].prob.dt;
-        for (int64_t k = 0; k < n; ++k) {
-            if (k % K == 0)
+        int64_t k = 0;
+        if (h->policy == LLG_CKPT_BINOMIAL) {
+            // the forward part of the binomial schedule: snapshots along its first descent
+            ensure_plan(h, n);
+            if (int rc = copy(B_M, 0, B_SNAP, 0)) return rc;
+            for (size_t a = 0; a < h->plan.split; ++a) {
+                const PlanAct& q = h->plan.acts[a];
+                if (q.op == P_LOAD && q.a != k) return fail(LLG_ESTATE, "internal error: checkpoint schedule");
+                if (q.op == P_ADV) {
+                    if (q.a != k) return fail(LLG_ESTATE, "internal error: checkpoint schedule");
+                    for (; k < q.b; ++k)
+                        if (int rc = step(t0 + (double)k * dt, k == n - 1, -1, in_win(k))) return rc;
+                }
+                if (q.op == P_SAVE)
+                    if (int rc = copy(B_M, 0, B_SNAP, q.slot)) return rc;
+            }
+        }
+        for (; k < n; ++k) {
+            if (h->policy != LLG_CKPT_BINOMIAL && k % K == 0)
                 if (int rc = copy(B_M, 0, B_SNAP, (int)(k / K))) return rc;
-            const bool in_win = port && (k + 1) > obj->n_start;
-            if (int rc = step(t0 + (double)k * dt, k == n - 1, -1, in_win)) return rc;
+            if (int rc = step(t0 + (double)k * dt, k == n - 1, -1, in_win(k))) return rc;
         }
         if (port) {
             const int W = (int)(n - obj->n_start);
@@ -532,59 +647,134 @@ struct Ops {
         });
     }
 
+    // Recompute steps [n0, n1) from m_{n0} (in B_M), storing the stage states
+    // and fields of step k in stage slot off + k - n0.
+    int recompute(int64_t n0, int64_t n1, int off) {
+        const double dt = h->inst[0].prob.dt;
+        if (int rc = prologue()) return rc;
+        for (int64_t k = n0; k < n1; ++k)
+            if (int rc = step(h->t0 + (double)k * dt, k == n1 - 1, off + (int)(k - n0), false)) return rc;
+        return LLG_OK;
+    }
+
+    // Transpose steps n1-1 .. n0, whose stage states sit in slots off .. off + n1 - n0 - 1.
+    int backward(int64_t n0, int64_t n1, int off) {
+        {
+            // seed: l_4 and u_4 of the last step of the range
+            BwdL L{};
+            L.stage = -2;
+            L.j = L.prev_j = off + (int)(n1 - 1 - n0);
+            L.prev_st = 3;
+            L.ucur = -1;
+            L.unext = Uc;
+            L.lamp = Lc;
+            L.lacc = -1;
+            L.do_fwd = h->demag;
+            if (int rc = bwd(L)) return rc;
+        }
+        for (int64_t k = n1 - 1; k >= n0; --k) {
+            const int j = off + (int)(k - n0);
+            for (int st = 3; st >= 0; --st) {
+                if (int rc = col()) return rc;
+                BwdL L{};
+                L.stage = st;
+                L.j = j;
+                L.prev_j = st > 0 ? j : (k > n0 ? j - 1 : -1);
+                L.prev_st = st > 0 ? st - 1 : 3;
+                L.ucur = Uc;
+                L.unext = Uo;
+                L.lamp = Lc;
+                L.lacc = Lo;
+                L.port_src = st == 0 && adj_port && k > adj_nstart;
+                L.W = adj_W;
+                L.do_inv = h->demag;
+                L.do_fwd = h->demag && L.prev_j >= 0;
+                if (int rc = bwd(L)) return rc;
+                if (L.prev_j >= 0) std::swap(Uc, Uo);
+            }
+            std::swap(Lc, Lo);  // lambda_k is the lambda' of step k-1
+        }
+        return LLG_OK;
+    }
+
+
     int adjoint(const llg_objective_spec* obj, bool use_djdm, bool use_expl) {
         if (!h->fwd_valid) return fail(LLG_ESTATE, "llg_adjoint needs a preceding llg_forward on this handle");
         const int64_t n = h->n_steps, K = h->K_used;
         const double dt = h->inst[0].prob.dt;
-        const bool port = obj && obj->kind == LLG_OBJ_PORT_MY2;
-        const int64_t nstart = port ? obj->n_start : n;
-        const int W = (int)(n - nstart);
-        int Lc = B_L0, Lo = B_L1, Uc = B_U0, Uo = B_U1;
+        adj_port = obj && obj->kind == LLG_OBJ_PORT_MY2;
+        adj_nstart = adj_port ? obj->n_start : n;
+        adj_W = (int)(n - adj_nstart);
+        Lc = B_L0, Lo = B_L1, Uc = B_U0, Uo = B_U1;
         // lambda_N = dJ/dm_N (+ port source at N); B_M holds m_N
-        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_adj_init<T>(B(), Lc, use_djdm, port, W, s); })) return rc;
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_adj_init<T>(B(), Lc, use_djdm, adj_port, adj_W, s); }))
+            return rc;
         if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_GPSI, 0, s); })) return rc;
-        const int64_t nseg = (n + K - 1) / K;
-        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-            const int64_t n0 = seg * K, n1 = std::min(n, n0 + K);
-            // recompute the segment, storing every stage state and field
-            if (int rc = copy(B_SNAP, (int)seg, B_M, 0)) return rc;
-            if (int rc = prologue()) return rc;
-            for (int64_t k = n0; k < n1; ++k)
-                if (int rc = step(h->t0 + (double)k * dt, k == n1 - 1, (int)(k - n0), false)) return rc;
-            // seed: l_4 and u_4 of the segment's last step
-            {
-                BwdL L{};
-                L.stage = -2;
-                L.j = L.prev_j = (int)(n1 - 1 - n0);
-                L.prev_st = 3;
-                L.ucur = -1;
-                L.unext = Uc;
-                L.lamp = Lc;
-                L.lacc = -1;
-                L.do_fwd = h->demag;
-                if (int rc = bwd(L)) return rc;
-            }
-            for (int64_t k = n1 - 1; k >= n0; --k) {
-                const int j = (int)(k - n0);
-                for (int st = 3; st >= 0; --st) {
-                    if (int rc = col()) return rc;
-                    BwdL L{};
-                    L.stage = st;
-                    L.j = j;
-                    L.prev_j = st > 0 ? j : (k > n0 ? j - 1 : -1);
-                    L.prev_st = st > 0 ? st - 1 : 3;
-                    L.ucur = Uc;
-                    L.unext = Uo;
-                    L.lamp = Lc;
-                    L.lacc = Lo;
-                    L.port_src = st == 0 && port && k > nstart;
-                    L.W = W;
-                    L.do_inv = h->demag;
-                    L.do_fwd = h->demag && L.prev_j >= 0;
-                    if (int rc = bwd(L)) return rc;
-                    if (L.prev_j >= 0) std::swap(Uc, Uo);
+        if (h->policy == LLG_CKPT_BINOMIAL) {
+            // the rest of the binomial schedule, on this stream
+            int64_t cur = n;
+            for (size_t a = h->plan.split; a < h->plan.acts.size(); ++a) {
+                const PlanAct& q = h->plan.acts[a];
+                if (q.op == P_LOAD) {
+                    if (cur != q.a) {
+                        if (int rc = copy(B_SNAP, q.slot, B_M, 0)) return rc;
+                        cur = q.a;
+                    }
+                } else if (q.op == P_ADV) {
+                    if (cur != q.a) return fail(LLG_ESTATE, "internal error: checkpoint schedule");
+                    if (int rc = prologue()) return rc;
+                    for (int64_t k = q.a; k < q.b; ++k)
+                        if (int rc = step(h->t0 + (double)k * dt, k == q.b - 1, -1, false)) return rc;
+                    cur = q.b;
+                } else if (q.op == P_SAVE) {
+                    if (int rc = copy(B_M, 0, B_SNAP, q.slot)) return rc;
+                } else {
+                    if (cur != q.a) return fail(LLG_ESTATE, "internal error: checkpoint schedule");
+                    if (int rc = recompute(q.a, q.a + 1, 0)) return rc;
+                    cur = q.a + 1;
+                    if (int rc = backward(q.a, q.a + 1, 0)) return rc;
                 }
-                std::swap(Lc, Lo);  // lambda_k is the lambda' of step k-1
+            }
+        } else {
+            const int64_t nseg = (n + K - 1) / K;
+            if (nseg == 1 || h->halves < 2) {
+                for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+                    const int64_t n0 = seg * K, n1 = std::min(n, n0 + K);
+                    if (int rc = copy(B_SNAP, (int)seg, B_M, 0)) return rc;
+                    if (int rc = recompute(n0, n1, 0)) return rc;
+                    if (int rc = backward(n0, n1, 0)) return rc;
+                }
+            } else {
+                // segment seg-1 is recomputed on the second stream (own spectrum
+                // buffer, other half of the stage store) while seg is transposed here
+                if (!h->aux || h->sync_ev.size() < (size_t)(2 * nseg + 1))
+                    return fail(LLG_ESTATE, "internal error: adjoint streams not prepared");
+                hipEvent_t* ev_rec = h->sync_ev.data();
+                hipEvent_t* ev_bwd = ev_rec + nseg;
+                hipEvent_t ev_init = ev_rec[2 * nseg];
+                Ops R{h, h->aux};
+                R.spec = B_S2;
+                HIPCHK(hipEventRecord(ev_init, s));
+                HIPCHK(hipStreamWaitEvent(h->aux, ev_init, 0));
+                auto rec = [&](int64_t seg) -> int {
+                    const int64_t n0 = seg * K, n1 = std::min(n, n0 + K);
+                    if (int rc = R.copy(B_SNAP, (int)seg, B_M, 0)) return rc;
+                    if (int rc = R.recompute(n0, n1, (int)(K * (seg & 1)))) return rc;
+                    HIPCHK(hipEventRecord(ev_rec[seg], h->aux));
+                    return LLG_OK;
+                };
+                if (int rc = rec(nseg - 1)) return rc;
+                for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+                    if (seg >= 1) {
+                        // the half that seg-1 overwrites was last read by the transpose of seg+1
+                        if (seg + 1 < nseg) HIPCHK(hipStreamWaitEvent(h->aux, ev_bwd[seg + 1], 0));
+                        if (int rc = rec(seg - 1)) return rc;
+                    }
+                    HIPCHK(hipStreamWaitEvent(s, ev_rec[seg], 0));
+                    const int64_t n0 = seg * K, n1 = std::min(n, n0 + K);
+                    if (int rc = backward(n0, n1, (int)(K * (seg & 1)))) return rc;
+                    HIPCHK(hipEventRecord(ev_bwd[seg], s));
+                }
             }
         }
         if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_psi_grad_out<T>(B(), use_expl, s); })) return rc;
@@ -636,8 +826,13 @@ int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_ha
     h->ckpt_param = p0.ckpt_param;
     h->max_steps = p0.max_steps;
     h->K = segment_length(p0.max_steps, p0.ckpt_policy, p0.ckpt_param);
-    h->nsnap = (p0.max_steps + h->K - 1) / h->K;
-    if (p0.ckpt_policy == LLG_CKPT_SQRT && p0.ckpt_param == 0) h->nsnap = std::max<int64_t>(h->nsnap, h->K);
+    if (p0.ckpt_policy == LLG_CKPT_BINOMIAL) {
+        h->nsnap = binomial_slots(p0.max_steps, p0.ckpt_param);
+    } else {
+        h->nsnap = (p0.max_steps + h->K - 1) / h->K;
+        if (p0.ckpt_policy == LLG_CKPT_SQRT && p0.ckpt_param == 0) h->nsnap = std::max<int64_t>(h->nsnap, h->K);
+        h->halves = h->nsnap > 1 ? 2 : 1;
+    }
     h->inst.resize(n);
     for (int i = 0; i < n; ++i) {
         Instance& I = h->inst[i];
@@ -681,8 +876,10 @@ int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_ha
         }
         const std::pair<int, size_t> sizes[] = {
             {B_PSI, N * t}, {B_PHI, N * t}, {B_PSIF, N * t}, {B_M, N3b}, {B_ACC, N3b}, {B_YA, N3b}, {B_YB, N3b},
-            {B_S, h->demag ? (size_t)3 * I.nrows * I.Kx * 2 * t : 0}, {B_SNAP, (size_t)h->nsnap * N3b},
-            {B_YS, (size_t)h->K * 4 * N3b}, {B_BS, (size_t)h->K * 4 * N3b}, {B_ELL, N3b}, {B_U0, N3b}, {B_U1, N3b},
+            {B_S, h->demag ? (size_t)3 * I.nrows * I.Kx * 2 * t : 0},
+            {B_S2, h->demag && h->halves > 1 ? (size_t)3 * I.nrows * I.Kx * 2 * t : 0},
+            {B_SNAP, (size_t)h->nsnap * N3b}, {B_YS, (size_t)(h->K * h->halves) * 4 * N3b},
+            {B_BS, (size_t)(h->K * h->halves) * 4 * N3b}, {B_ELL, N3b}, {B_U0, N3b}, {B_U1, N3b},
             {B_L0, N3b}, {B_L1, N3b}, {B_GPSI, N * 8}, {B_DJDM, N3b}, {B_DPSIE, N * 8}, {B_DPSI, N * 8},
             {B_DPHI, N * 8}, {B_PPART, (size_t)I.nloc * 2 * 8}, {B_EPART, (size_t)I.nloc * 5 * 8}, {B_SCAL, 8 * 8}};
         for (auto& sz : sizes)
@@ -813,8 +1010,17 @@ int b_forward(llg_handle* h, const void* const* psi, const void* const* m0, doub
         if (int rc = put(h, i, B_PSI, psi[i], N * h->tsz, s)) return rc;
         if (int rc = put(h, i, B_M, m0[i], 3 * N * h->tsz, s)) return rc;
     }
-    int rc = h->dtype == LLG_F32 ? Ops<float>{h, s}.forward(t0, n_steps, obj) : Ops<double>{h, s}.forward(t0, n_steps, obj);
+    ensure_plan(h, n_steps);
+    const std::vector<double> key = {0.0, (double)n_steps, t0, obj ? (double)obj->kind : -1.0,
+                                     obj ? (double)obj->n_start : -1.0};
+    int res = 0;
+    int rc = run_sequence(h, s, key, &res, [&](hipStream_t st, int* r) {
+        *r = 0;
+        return h->dtype == LLG_F32 ? Ops<float>{h, st}.forward(t0, n_steps, obj)
+                                   : Ops<double>{h, st}.forward(t0, n_steps, obj);
+    });
     if (rc) return rc;
+    record_forward(h, t0, n_steps, obj);
     for (int i = 0; i < n; ++i) {
         if (m_out && m_out[i])
             if ((rc = get(h, i, B_M, m_out[i], 3 * (size_t)h->inst[i].N * h->tsz, s))) return rc;
@@ -849,16 +1055,23 @@ int b_adjoint(llg_handle* h, const void* const* psi, const void* const* dJdm_T, 
         if (use_expl)
             if (int rc = put(h, i, B_DPSIE, expl[i], N * 8, s)) return rc;
     }
+    if (int rc = prepare_adjoint(h)) return rc;
+    const std::vector<double> key = {1.0, (double)h->n_steps, h->t0, obj ? (double)obj->kind : -1.0,
+                                     obj ? (double)obj->n_start : -1.0, (double)use_djdm, (double)use_expl};
     int lam0 = B_L0;
-    if (h->dtype == LLG_F32) {
-        Ops<float> o{h, s};
-        if (int rc = o.adjoint(obj, use_djdm, use_expl)) return rc;
-        lam0 = o.adj_lambda0;
-    } else {
-        Ops<double> o{h, s};
-        if (int rc = o.adjoint(obj, use_djdm, use_expl)) return rc;
-        lam0 = o.adj_lambda0;
-    }
+    int rc0 = run_sequence(h, s, key, &lam0, [&](hipStream_t st, int* r) {
+        if (h->dtype == LLG_F32) {
+            Ops<float> o{h, st};
+            const int rc = o.adjoint(obj, use_djdm, use_expl);
+            *r = o.adj_lambda0;
+            return rc;
+        }
+        Ops<double> o{h, st};
+        const int rc = o.adjoint(obj, use_djdm, use_expl);
+        *r = o.adj_lambda0;
+        return rc;
+    });
+    if (rc0) return rc0;
     for (int i = 0; i < n; ++i) {
         const size_t N = h->inst[i].N;
         if (int rc = get(h, i, B_DPSI, dJdpsi_out[i], N * 8, s)) return rc;
@@ -879,9 +1092,21 @@ const char* llg_version(void) { return "llg-mi355x 0.2 (gfx950, batched)"; }
 int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int32_t ckpt_param, size_t* bytes) {
     if (!p || !bytes) return fail(LLG_EINVAL, "NULL argument");
     if (n_steps < 1) return fail(LLG_EINVAL, "n_steps must be >= 1");
-    if (policy != LLG_CKPT_SQRT && policy != LLG_CKPT_ALL) return fail(LLG_EINVAL, "unknown policy");
+    if (policy != LLG_CKPT_SQRT && policy != LLG_CKPT_ALL && policy != LLG_CKPT_BINOMIAL)
+        return fail(LLG_EINVAL, "unknown policy");
+    if (ckpt_param < 0) return fail(LLG_EINVAL, "ckpt_param must be >= 0");
     const int64_t N3 = 3LL * p->nx * p->ny * p->nz;
     *bytes = store_bytes(N3, p->dtype == LLG_F64 ? 8 : 4, n_steps, policy, ckpt_param);
+    return LLG_OK;
+}
+
+int llg_query_recompute(int64_t n_steps, int32_t policy, int32_t ckpt_param, int64_t* steps) {
+    if (!steps) return fail(LLG_EINVAL, "NULL argument");
+    if (n_steps < 1) return fail(LLG_EINVAL, "n_steps must be >= 1");
+    if (policy != LLG_CKPT_SQRT && policy != LLG_CKPT_ALL && policy != LLG_CKPT_BINOMIAL)
+        return fail(LLG_EINVAL, "unknown policy");
+    if (ckpt_param < 0) return fail(LLG_EINVAL, "ckpt_param must be >= 0");
+    *steps = recompute_steps(n_steps, policy, ckpt_param);
     return LLG_OK;
 }
 
@@ -899,6 +1124,12 @@ int llg_destroy(llg_handle* h) {
         h->ev_pool.push_back(r.b);
     }
     for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+    for (auto e : h->sync_ev) (void)hipEventDestroy(e);
+    if (h->aux) (void)hipStreamDestroy(h->aux);
+    drop_graphs(h);
+    if (h->g_in) (void)hipEventDestroy(h->g_in);
+    if (h->g_out) (void)hipEventDestroy(h->g_out);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
     free_all(h);
     delete h;
     return LLG_OK;
@@ -909,6 +1140,16 @@ int llg_batch_destroy(llg_batch* b) { return llg_destroy(b); }
 int llg_batch_size(const llg_batch* b, int32_t* n) {
     if (!b || !n) return fail(LLG_EINVAL, "NULL argument");
     *n = (int32_t)b->inst.size();
+    return LLG_OK;
+}
+
+int llg_set_graphs(llg_handle* h, int enable) {
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (!enable && !h->graphs.empty()) {
+        if (h->gstream) HIPCHK(hipStreamSynchronize(h->gstream));
+        drop_graphs(h);
+    }
+    h->graphs_on = enable != 0;
     return LLG_OK;
 }
 

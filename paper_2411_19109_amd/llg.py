@@ -18,12 +18,12 @@ LIB_PATH = os.path.join(HERE, "libllg.so")
 
 LLG_OK, LLG_EINVAL, LLG_ESHAPE, LLG_ENOMEM, LLG_EHIP, LLG_ENONFINITE, LLG_ENOTSUP, LLG_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 LLG_F32, LLG_F64 = 0, 1
-LLG_CKPT_SQRT, LLG_CKPT_ALL = 0, 1
+LLG_CKPT_SQRT, LLG_CKPT_ALL, LLG_CKPT_BINOMIAL = 0, 1, 2
 LLG_OBJ_NONE, LLG_OBJ_ENERGY_AREA, LLG_OBJ_PORT_MY2 = 0, 1, 2
 
 EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_levelset_to_Ms",
            "llg_levelset_to_Ms_vjp", "llg_field", "llg_forward", "llg_objective", "llg_adjoint",
-           "llg_query_memory", "llg_fft_sizes", "llg_profile", "llg_profile_read", "llg_batch_create",
+           "llg_query_memory", "llg_query_recompute", "llg_set_graphs", "llg_fft_sizes", "llg_profile", "llg_profile_read", "llg_batch_create",
            "llg_batch_destroy", "llg_batch_size", "llg_batch_levelset_to_Ms", "llg_batch_levelset_to_Ms_vjp",
            "llg_batch_forward", "llg_batch_adjoint"]
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
@@ -87,8 +87,10 @@ def lib():
         "llg_objective": [vp, ctypes.POINTER(Objective_c), vp, vp, dbl, vp, vp, vp, vp, vp],
         "llg_adjoint": [vp, vp, vp, vp, ctypes.POINTER(Objective_c), vp, vp, vp],
         "llg_query_memory": [ctypes.POINTER(Problem_c), i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "llg_query_recompute": [i64, i32, i32, ctypes.POINTER(i64)],
         "llg_fft_sizes": [vp, ctypes.POINTER(ctypes.c_int32)],
         "llg_profile": [vp, ctypes.c_int],
+        "llg_set_graphs": [vp, ctypes.c_int],
         "llg_batch_create": [ctypes.POINTER(Problem_c), ctypes.POINTER(Masks_c), i32, ctypes.POINTER(vp)],
         "llg_batch_destroy": [vp],
         "llg_batch_size": [vp, ctypes.POINTER(i32)],
@@ -144,6 +146,13 @@ def query_memory(prob, n_steps, policy=LLG_CKPT_SQRT, ckpt_param=0, dtype="f32")
     check(lib().llg_query_memory(ctypes.byref(make_problem(prob, dtype, max(1, n_steps))), n_steps, policy,
                                  ckpt_param, ctypes.byref(b)))
     return b.value
+
+
+def query_recompute(n_steps, policy=LLG_CKPT_SQRT, ckpt_param=0) -> int:
+    """Forward RK4 steps the adjoint recomputes after a forward run of n_steps."""
+    v = ctypes.c_int64(0)
+    check(lib().llg_query_recompute(n_steps, policy, ckpt_param, ctypes.byref(v)))
+    return v.value
 
 
 def _ptr(t):
@@ -203,6 +212,10 @@ class Solver:
 
     def profile(self, enable: bool):
         check(lib().llg_profile(self.h, int(enable)))
+
+    def set_graphs(self, enable: bool):
+        """Capture forward / adjoint launch sequences in HIP graphs and replay them."""
+        check(lib().llg_set_graphs(self.h, int(enable)))
 
     def profile_read(self, kind, reset=True):
         """(device ms, launches, algorithmic bytes) summed over profiled launches of one kernel class."""
@@ -323,6 +336,10 @@ class Batch:
 
     def profile(self, enable: bool):
         check(lib().llg_profile(self.h, int(enable)))
+
+    def set_graphs(self, enable: bool):
+        """Capture forward / adjoint launch sequences in HIP graphs and replay them."""
+        check(lib().llg_set_graphs(self.h, int(enable)))
 
     def profile_read(self, kind, reset=True):
         ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()

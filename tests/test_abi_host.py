@@ -70,12 +70,68 @@ def test_query_memory_matches_checkpoint_layout():
     K = math.ceil(math.sqrt(n))
     nsnap = math.ceil(n / K)
     N3 = 3 * p.n
-    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT) == (nsnap * N3 + 8 * K * N3) * 4
+    # several segments: the stage store is double-buffered (recompute / transpose overlap)
+    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT) == (nsnap * N3 + 2 * 8 * K * N3) * 4
     assert llg.query_memory(p, n, llg.LLG_CKPT_ALL) == (N3 + 8 * n * N3) * 4
-    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT, dtype="f64") == (nsnap * N3 + 8 * K * N3) * 8
+    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT, dtype="f64") == (nsnap * N3 + 2 * 8 * K * N3) * 8
+    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT, ckpt_param=n) == (N3 + 8 * n * N3) * 4
     # sqrt(n) growth: 100x more steps costs ~10x the store
     r = llg.query_memory(p, 200000, llg.LLG_CKPT_SQRT) / llg.query_memory(p, 2000, llg.LLG_CKPT_SQRT)
     assert 8 < r < 12
+    # binomial: s snapshots + one step's stage states, independent of n
+    for steps in (64, 2000, 50000):
+        assert llg.query_memory(p, steps, llg.LLG_CKPT_BINOMIAL, 32) == (32 * N3 + 8 * N3) * 4
+    assert llg.query_memory(p, 10, llg.LLG_CKPT_BINOMIAL, 32) == (10 * N3 + 8 * N3) * 4
+
+
+def test_memory_report_large_3d_device():
+    """Checkpoint store of the 512x256x4 FP32 device over 50 000 steps: keeping
+    every stage state would need 8 * 50 000 * 3N * 4 B (> 288 GB of HBM); the sqrt
+    and binomial schedules need a few GB and a fraction of a GB."""
+    p = wl.yig_device_3d().problem
+    n = 50000
+    N3 = 3 * p.n
+    full = llg.query_memory(p, n, llg.LLG_CKPT_ALL)
+    sq = llg.query_memory(p, n, llg.LLG_CKPT_SQRT)
+    bi = llg.query_memory(p, n, llg.LLG_CKPT_BINOMIAL, 32)
+    assert full == (N3 + 8 * n * N3) * 4 and full > 288e9
+    assert sq < 25e9 and bi < 0.3e9
+    assert bi == 40 * N3 * 4
+
+
+def _optimal_reversal_steps(l, s):
+    """Fewest forward steps that reverse l steps when the state at the start is
+    kept and s further snapshots are free (dynamic programming over the split)."""
+    import functools
+
+    @functools.lru_cache(None)
+    def c(l, s):
+        if l == 1:
+            return 1
+        best = l * (l + 1) // 2  # every step reached again from the start
+        if s > 0:
+            for d in range(1, l):
+                best = min(best, d + c(l - d, s - 1) + c(d, s))
+        return best
+    return c(l, s)
+
+
+def test_binomial_schedule_recomputation():
+    from math import comb
+    assert llg.query_recompute(2000, llg.LLG_CKPT_SQRT) == 2000
+    assert llg.query_recompute(2000, llg.LLG_CKPT_ALL) == 2000
+    for n in range(1, 70):
+        for slots in range(1, 8):
+            rec = llg.query_recompute(n, llg.LLG_CKPT_BINOMIAL, slots)
+            r = next(r for r in range(n + 1) if comb(slots + r, slots) >= n)
+            assert n <= rec <= (r + 1) * n
+            # the forward pass places the first snapshots, so the adjoint never
+            # recomputes more than an optimal reversal that starts from m_0 alone
+            assert rec <= _optimal_reversal_steps(n, slots - 1)
+        assert llg.query_recompute(n, llg.LLG_CKPT_BINOMIAL, 1) == n * (n + 1) // 2
+        assert llg.query_recompute(n, llg.LLG_CKPT_BINOMIAL, n) == n
+    # the 50 000-step device with 32 snapshots: r = 4 since C(36, 4) >= 50 000
+    assert llg.query_recompute(50000, llg.LLG_CKPT_BINOMIAL, 32) <= 4 * 50000
 
 
 def test_missing_library_fails_loudly(monkeypatch):

@@ -131,18 +131,43 @@ def test_gradient_tiny(kind, shape, dtype):
         assert rel_l2(g["dphi"], r["dphi"]) <= 1e-3
 
 
-def test_checkpoint_policies_bitwise():
-    from paper_2411_19109_amd import llg
-    w = tiny_workload(13, 9, 1, kind=wl.OBJ_PORT_MY2, n_steps=40)
-    say("checkpoint policies")
+CKPT_CASES = [(0, 0), (0, 3), (0, 40), (1, 0), (2, 1), (2, 2), (2, 5), (2, 0)]  # (policy, param)
+
+
+@pytest.mark.parametrize("kind", [wl.OBJ_PORT_MY2, wl.OBJ_ENERGY_AREA])
+def test_checkpoint_policies_bitwise(kind):
+    """Store-all, sqrt segments (recomputation overlapped with the transpose on a
+    second stream) and binomial schedules with 1..32 snapshots give identical
+    bits: the recomputed steps run the same kernels in the same launch shapes."""
+    w = tiny_workload(13, 9, 1, kind=kind, n_steps=40)
+    say("checkpoint policies, objective", kind)
     outs = []
-    for pol, par in [(llg.LLG_CKPT_ALL, 0), (llg.LLG_CKPT_SQRT, 0), (llg.LLG_CKPT_SQRT, 3), (llg.LLG_CKPT_SQRT, 40)]:
+    for pol, par in CKPT_CASES:
+        say("  policy", pol, "param", par)
         g = gpu_gradient(w, "f32", ckpt_policy=pol, ckpt_param=par)
+        g["solver"].close()
         outs.append(g)
     for g in outs[1:]:
         assert np.array_equal(g["dpsi"], outs[0]["dpsi"])
         assert np.array_equal(g["dm0"], outs[0]["dm0"])
         assert g["J"] == outs[0]["J"]
+
+
+def test_binomial_schedule_shorter_run_and_repeat():
+    """A handle sized for 60 steps runs a 37-step gradient twice under the
+    binomial policy (3 snapshots) and matches the store-all run bitwise."""
+    from paper_2411_19109_amd import llg
+    w = tiny_workload(11, 7, 2, kind=wl.OBJ_PORT_MY2, n_steps=37)
+    say("binomial shorter run")
+    ref = gpu_gradient(w, "f64", n_steps=37, ckpt_policy=llg.LLG_CKPT_ALL)
+    ref["solver"].close()
+    s = gpu_solver(w, "f64", max_steps=60, ckpt_policy=llg.LLG_CKPT_BINOMIAL, ckpt_param=3)
+    for _ in range(2):
+        g = gpu_gradient(w, "f64", n_steps=37, solver=s)
+        assert np.array_equal(g["dpsi"], ref["dpsi"])
+        assert np.array_equal(g["dm0"], ref["dm0"])
+        assert g["J"] == ref["J"]
+    s.close()
 
 
 def test_energy_terms_match_oracle():

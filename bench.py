@@ -44,7 +44,7 @@ def make_workload(name):
 class GradientStep:
     """Device-resident inputs and one gradient evaluation through the C ABI."""
 
-    def __init__(self, w):
+    def __init__(self, w, graphs=True, tune=True):
         import torch
         from paper_2411_19109_amd import llg, workloads as wl
         self.w = w
@@ -52,6 +52,8 @@ class GradientStep:
         dev = torch.device("cuda:0")
         self.solver = llg.Solver(w.problem, dtype=w.dtype, max_steps=w.n_steps, antenna=w.antenna, port1=w.port1,
                                  port2=w.port2, design=w.design)
+        self.solver.set_graphs(graphs)
+        self.launch = self.solver.autotune() if tune else self.solver.launch_config()
         self.phi = torch.as_tensor(w.phi.reshape(-1), dtype=self.td, device=dev).contiguous()
         self.psi_fixed = torch.as_tensor(w.psi_fixed.reshape(-1), dtype=self.td, device=dev).contiguous()
         self.m0 = torch.as_tensor(w.m0.reshape(-1), dtype=self.td, device=dev).contiguous()
@@ -75,7 +77,7 @@ class SweepStep:
     """The batched sweep: 32 seeded designs x 2 drive frequencies on ragged grids,
     one gradient evaluation of every instance with one launch sequence."""
 
-    def __init__(self, n_steps):
+    def __init__(self, n_steps, graphs=True, tune=True):
         import torch
         from paper_2411_19109_amd import llg, workloads as wl
         self.ws = wl.yig_demux_sweep(n_steps=n_steps)
@@ -87,6 +89,8 @@ class SweepStep:
         self.batch = llg.Batch([w.problem for w in self.ws], dtype="f32", max_steps=n_steps,
                                masks=[dict(antenna=w.antenna, port1=w.port1, port2=w.port2, design=w.design)
                                       for w in self.ws])
+        self.batch.set_graphs(graphs)
+        self.launch = self.batch.autotune() if tune else self.batch.launch_config()
         self.phi = [t(w.phi) for w in self.ws]
         self.psif = [t(w.psi_fixed) for w in self.ws]
         self.m0 = [t(w.m0) for w in self.ws]
@@ -102,14 +106,14 @@ class SweepStep:
         return J, b.levelset_vjp(self.phi, g, a)
 
 
-def sweep_plain(n_steps, count):
+def sweep_plain(n_steps, count, graphs=True, tune=True):
     """The same instances as single-instance solves, one after the other."""
     from paper_2411_19109_amd import workloads as wl
     ws = wl.yig_demux_sweep(n_steps=n_steps)
     steps = []
     for w in ws[:count]:
         w.obj_n_start = n_steps // 2
-        steps.append(GradientStep(w))
+        steps.append(GradientStep(w, graphs, tune))
     return steps, sum(w.problem.n for w in ws[:count])
 
 
@@ -147,6 +151,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--sweep-steps", type=int, default=200, help="RK4 steps per instance of the sweep workload")
     ap.add_argument("--sweep-plain", type=int, default=8, help="instances timed one after the other for the plain rate")
+    ap.add_argument("--n-steps", type=int, default=0,
+                    help="override the workload's RK4 step count (short profiling runs; not a bench line)")
+    ap.add_argument("--graphs", type=int, default=0, help="1: replay forward/adjoint as captured HIP graphs")
+    ap.add_argument("--autotune", type=int, default=1, help="1: pick launch tiles with the library's autotuner at setup")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -168,9 +176,12 @@ def main():
     if args.workload == "sweep":
         return run_sweep(args)
     w = make_workload(args.workload)
-    step = GradientStep(w)
+    if args.n_steps > 0:
+        w.n_steps = args.n_steps
+        w.obj_n_start = min(w.obj_n_start, args.n_steps // 2)
+    step = GradientStep(w, bool(args.graphs), bool(args.autotune))
     print(f"[bench] workload {w.name}: {w.problem.nx}x{w.problem.ny}x{w.problem.nz} nodes, {w.n_steps} steps, "
-          f"{w.dtype}", file=sys.stderr, flush=True)
+          f"{w.dtype}, launch {step.launch}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -225,6 +236,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nodes": [w.problem.nx, w.problem.ny, w.problem.nz],
                    "rk4_steps": w.n_steps, "checkpoint": "sqrt", "grad_ms": round(sec * 1e3, 3),
+                   "hip_graphs": bool(args.graphs), "launch": list(step.launch),
                    "objective_J": float(J.item())},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -248,8 +260,9 @@ def run_sweep(args):
     import torch
     from paper_2411_19109_amd import llg
     n = args.sweep_steps
-    step = SweepStep(n)
-    print(f"[bench] sweep: {len(step.ws)} instances, {step.nodes} nodes, {n} steps", file=sys.stderr, flush=True)
+    step = SweepStep(n, bool(args.graphs), bool(args.autotune))
+    print(f"[bench] sweep: {len(step.ws)} instances, {step.nodes} nodes, {n} steps, launch {step.launch}",
+          file=sys.stderr, flush=True)
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -269,8 +282,8 @@ def run_sweep(args):
               f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
     dom = max(kinds, key=lambda k: kinds[k]["ms"])
     d = kinds[dom]
-    plain, nodes_p = sweep_plain(n, args.sweep_plain)
-    for p in plain[:1]:
+    plain, nodes_p = sweep_plain(n, max(1, args.sweep_plain), bool(args.graphs), bool(args.autotune))
+    for p in plain:  # first call of each instance captures its graphs
         p()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -296,7 +309,8 @@ def run_sweep(args):
         "data": "synthetic",
         "config": {"workload": f"yig_demux_sweep_64x_prefix{n}", "instances": len(step.ws), "nodes": step.nodes,
                    "rk4_steps": n, "plain_cell_steps_per_s": rate_p, "plain_instances_timed": len(plain),
-                   "batched_over_plain": rate_b / rate_p},
+                   "batched_over_plain": rate_b / rate_p, "hip_graphs": bool(args.graphs),
+                   "launch": list(step.launch)},
         "roofline": dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
                          frac=round(d["gbs"] / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
                          avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"])),

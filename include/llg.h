@@ -214,6 +214,29 @@ int llg_query_recompute(int64_t n_steps, int32_t policy, int32_t ckpt_param, int
  * Errors: LLG_EINVAL (NULL handle), LLG_EHIP (capture or instantiation failed). */
 int llg_set_graphs(llg_handle* h, int enable);
 
+/* Launch configuration of a handle's kernels (one for all instances of a
+ * batch): cfg[0] = column tile (x-bins per column-kernel block: 1, 2, 4, 8 or
+ * 16), cfg[1] = column-kernel threads, cfg[2] = row-kernel threads (multiples
+ * of 64), cfg[3] = node values per row the backward row kernel stages in LDS
+ * (4: field adjoint and psi; 7: also the stage state), cfg[4] / cfg[5] =
+ * largest FFT radix of the column / row kernels (4, 8, or 16 in float; a
+ * smaller radix spreads a transform over more lanes, a larger one needs fewer
+ * passes).  Configurations differ in speed only, not in the computed values
+ * beyond the rounding order of the FFT passes: a given radix gives identical
+ * bits for every tiling.  llg_set_launch_config validates (LLG_EINVAL /
+ * LLG_ESHAPE when a tile does not fit 160 KiB of LDS or the FFT register
+ * budget), synchronises the device and drops cached graphs. */
+int llg_launch_config(const llg_handle* h, int32_t cfg[6]);
+int llg_set_launch_config(llg_handle* h, const int32_t cfg[6]);
+
+/* Autotuner: times the column kernel over every valid (tile, threads) pair
+ * and one forward plus one backward row-kernel stage over the valid row block
+ * sizes, on the handle's own buffers, and keeps the fastest configuration.
+ * Blocks the host; overwrites the handle's state buffers, so the record of the
+ * last llg_forward is dropped (call it after create, before forward).
+ * Errors: LLG_EINVAL (NULL handle), LLG_EHIP. */
+int llg_autotune(llg_handle* h, hipStream_t stream);
+
 /* Kernel classes reported by the profiling counters. */
 #define LLG_KIND_STAGE_FWD 0 /* forward local kernel: row FFTs + fields + LL RHS + RK4 stage */
 #define LLG_KIND_COLUMN 1    /* column kernel: y/z FFTs and tensor-spectrum multiply       */

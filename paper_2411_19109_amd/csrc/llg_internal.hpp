@@ -17,6 +17,9 @@ namespace llg {
 
 constexpr double kMu0 = 4e-7 * 3.14159265358979323846;
 
+// Stored size of an LDS array of n complex values padded by one element per 16.
+__host__ __device__ inline int lds_pad(int n) { return n + (n >> 4) + 1; }
+
 template <typename T> struct Cx;
 template <> struct Cx<float> { using type = float2; };
 template <> struct Cx<double> { using type = double2; };
@@ -107,6 +110,7 @@ struct BwdL {
     int port_src;         // add the port running-cost source at stage 0
     int W;                // port window length (steps)
     int do_inv, do_fwd;
+    int stage_m;          // stage the y_s rows in LDS too (set by the launcher from the batch)
 };
 
 // Resolved per-instance arguments (built inside the kernels).
@@ -174,6 +178,8 @@ struct BatchDev {
     int nloc, ncol, ninst;
     int max_n3;            // max 3N over instances (grid of element-wise kernels)
     int loc_threads, col_threads, col_tk;
+    int loc_nv;            // node values per staged row in the backward row kernel (4 or 7)
+    int col_radix, loc_radix;  // largest FFT radix of the column / row kernels (4, 8 or 16)
     size_t loc_lds, col_lds;
     KParams<T> p0;  // instance 0, by value
     InstTab t0;
@@ -193,6 +199,7 @@ template <typename T>
 hipError_t launch_adj_init(const BatchDev<T>& b, int lam_sel, int use_djdm, int port, int W, hipStream_t s);
 template <typename T> hipError_t launch_psi_grad_out(const BatchDev<T>& b, int use_expl, hipStream_t s);
 template <typename T> hipError_t launch_zero(const BatchDev<T>& b, int sel, int what, hipStream_t s);
+template <typename T> hipError_t launch_fill(const BatchDev<T>& b, int sel, int mult, double v, hipStream_t s);
 template <typename T>
 hipError_t launch_copy(const BatchDev<T>& b, int src, int src_slot, int dst, int dst_slot, hipStream_t s);
 template <typename T> hipError_t launch_port_finish(const BatchDev<T>& b, int W, hipStream_t s);

@@ -16,6 +16,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "llg_internal.hpp"
 
 namespace llg {
@@ -35,10 +37,18 @@ template <typename C> __device__ __forceinline__ C cmul_mi(C a) { return cmk<C>(
 // ---------------------------------------------------------------------------
 // LDS Stockham FFT
 // ---------------------------------------------------------------------------
-// Signal b occupies buf[(b >> ln0) * s1 + (b & (2^ln0 - 1)) * s0 + e * es], e in [0, L).
+// LDS arrays of complex values are padded by one element per 16 (lp maps the
+// logical index to the stored one).  The passes write with strides of R or
+// R*Ns elements; without the pad those land in one bank group, with it the
+// 64 lanes of a wave spread over all banks.
+__device__ __forceinline__ int lp(int a) { return a + (a >> 4); }
+
+// Signal b occupies logical positions (b >> ln0) * s1 + (b & (2^ln0 - 1)) * s0 + e * es, e in [0, L).
+// Work items are ordered with the low ln0 bits of the signal index fastest,
+// then the butterfly index, so adjacent lanes touch adjacent elements both for
+// contiguous signals (ln0 = 0, es = 1) and for signals interleaved with s0 = 1.
 struct SigMap {
     int ln0, s1, s0, es;
-    __device__ __forceinline__ int off(int b) const { return (b >> ln0) * s1 + (b & ((1 << ln0) - 1)) * s0; }
 };
 
 // cos / sin of 2 pi m / 16, m = 0..15 (exact constants)
@@ -106,15 +116,16 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
     const int lnbf = lL - LR;
     const int nbf = 1 << lnbf;
     const int total = nsig << lnbf;
+    const int lmask = (1 << sm.ln0) - 1;
     C v[IPT][R];
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
         if (it < total) {
-            const int b = it >> lnbf, j = it & (nbf - 1);
-            const C* s = buf + sm.off(b);
+            const int j = (it >> sm.ln0) & (nbf - 1);
+            const int o = (it >> (sm.ln0 + lnbf)) * sm.s1 + (it & lmask) * sm.s0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = s[(j + (r << lnbf)) * sm.es];
+            for (int r = 0; r < R; ++r) v[q][r] = buf[lp(o + (j + (r << lnbf)) * sm.es)];
         }
     }
     __syncthreads();
@@ -123,7 +134,8 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
         if (it < total) {
-            const int b = it >> lnbf, j = it & (nbf - 1);
+            const int j = (it >> sm.ln0) & (nbf - 1);
+            const int o = (it >> (sm.ln0 + lnbf)) * sm.s1 + (it & lmask) * sm.s0;
             const int jm = j & ((1 << lNs) - 1);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
@@ -132,10 +144,9 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
                 v[q][r] = cmul(v[q][r], w);
             }
             dft_small<C, INV, R>(v[q]);
-            C* d = buf + sm.off(b);
             const int base = ((j - jm) << LR) + jm;
 #pragma unroll
-            for (int r = 0; r < R; ++r) d[(base + (r << lNs)) * sm.es] = v[q][r];
+            for (int r = 0; r < R; ++r) buf[lp(o + (base + (r << lNs)) * sm.es)] = v[q][r];
         }
     }
     __syncthreads();
@@ -158,10 +169,14 @@ __device__ __forceinline__ void fft_lds(C* buf, const SigMap sm, int L, int nsig
                 continue;
             }
         }
-        if (rem >= 3) {
-            fft_pass<C, INV, 8, MAXREG>(buf, sm, lL, lNs, nsig, tw);
-            lNs += 3;
-        } else if (rem == 2) {
+        if constexpr (MAXREG >= 8) {
+            if (rem >= 3) {
+                fft_pass<C, INV, 8, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+                lNs += 3;
+                continue;
+            }
+        }
+        if (rem >= 2) {
             fft_pass<C, INV, 4, MAXREG>(buf, sm, lL, lNs, nsig, tw);
             lNs += 2;
         } else {
@@ -266,9 +281,9 @@ __device__ __forceinline__ void unpack_rows_to_lds(const KParams<T>& p, const cp
             ax = cconj(ax); ay = cconj(ay); az = cconj(az);
             bx = cconj(bx); by = cconj(by); bz = cconj(bz);
         }
-        Z[k] = cadd(ax, cmul_i(ay));
-        Z[Px + k] = cadd(bx, cmul_i(by));
-        Z[2 * Px + k] = cadd(az, cmul_i(bz));
+        Z[lp(k)] = cadd(ax, cmul_i(ay));
+        Z[lp(Px + k)] = cadd(bx, cmul_i(by));
+        Z[lp(2 * Px + k)] = cadd(az, cmul_i(bz));
     }
 }
 
@@ -284,8 +299,8 @@ __device__ __forceinline__ void pack_lds_to_rows(const KParams<T>& p, cplx<T>* _
         C out[6];
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const C a = Z[s * Px + k];
-            const C b = cconj(Z[s * Px + kn]);
+            const C a = Z[lp(s * Px + k)];
+            const C b = cconj(Z[lp(s * Px + kn)]);
             const C sum = cadd(a, b), dif = csub(a, b);
             out[2 * s] = cmk<C>(h * sum.x, h * sum.y);       // spectrum of the real part
             out[2 * s + 1] = cmk<C>(h * dif.y, -h * dif.x);  // spectrum of the imaginary part
@@ -304,7 +319,7 @@ __device__ __forceinline__ void pack_lds_to_rows(const KParams<T>& p, cplx<T>* _
 
 // ---------------------------------------------------------------------------
 // shared-memory layout of the local (row-pair) kernels
-//   Z  [3 * Px] complex  three packed row signals (demag only)
+//   Z  [3 * Px] complex  three packed row signals (demag only; padded, see lp)
 //   Tw [Px]     complex  x twiddles (demag only)
 //   R  [4][NV][nx] real  rows r0-1 .. r0+2 of NV staged node values
 // Staging the two own rows and their two y-neighbour rows lets every x and y
@@ -322,13 +337,139 @@ template <typename T>
 __device__ __forceinline__ LocalSmem<T> local_smem(unsigned char* raw, int Px, bool demag) {
     LocalSmem<T> L;
     L.Z = reinterpret_cast<cplx<T>*>(raw);
-    L.Tw = L.Z + (demag ? 3 * Px : 0);
+    L.Tw = L.Z + (demag ? lds_pad(3 * Px) : 0);
     L.R = reinterpret_cast<T*>(L.Tw + (demag ? Px : 0));
     return L;
 }
 
 // Stage rows r0-1 .. r0+2 of NV arrays src[v] (component-major vectors use
 // stride N) into R; rows outside the grid are left unset (never read).
+// ---------------------------------------------------------------------------
+// batched staging of global data into LDS
+// ---------------------------------------------------------------------------
+// Up to three independent copy streams (element e of stream k: value ldk(e),
+// stored by stk(e, value)) advance in chunks of U_k elements per thread; all
+// loads of a chunk, across the streams, are issued before the first of them
+// is waited on, so a block pays about one memory latency per chunk instead
+// of one per loop iteration.
+template <typename V, int U>
+struct Regs {
+    V v[U];
+};
+
+template <int UA, int UB, int UC, typename VA, typename VB, typename VC, class LA, class SA, class LB, class SB, class LC,
+          class SC>
+__device__ __forceinline__ void gather3(int na, LA&& la, SA&& sa, int nb, LB&& lb, SB&& sb, int nc, LC&& lc, SC&& sc) {
+    const int bd = blockDim.x;
+    int ea = threadIdx.x, eb = threadIdx.x, ec = threadIdx.x;
+    while (ea < na || eb < nb || ec < nc) {
+        Regs<VA, UA> ra;
+        Regs<VB, UB> rb;
+        Regs<VC, UC> rc;
+#pragma unroll
+        for (int u = 0; u < UA; ++u)
+            if (ea + u * bd < na) ra.v[u] = la(ea + u * bd);
+#pragma unroll
+        for (int u = 0; u < UB; ++u)
+            if (eb + u * bd < nb) rb.v[u] = lb(eb + u * bd);
+#pragma unroll
+        for (int u = 0; u < UC; ++u)
+            if (ec + u * bd < nc) rc.v[u] = lc(ec + u * bd);
+#pragma unroll
+        for (int u = 0; u < UA; ++u)
+            if (ea + u * bd < na) sa(ea + u * bd, ra.v[u]);
+#pragma unroll
+        for (int u = 0; u < UB; ++u)
+            if (eb + u * bd < nb) sb(eb + u * bd, rb.v[u]);
+#pragma unroll
+        for (int u = 0; u < UC; ++u)
+            if (ec + u * bd < nc) sc(ec + u * bd, rc.v[u]);
+        ea += UA * bd;
+        eb += UB * bd;
+        ec += UC * bd;
+    }
+}
+
+// Inputs of a row-pair block, staged together:
+//   rows  r0-1 .. r0+2 of NV node arrays src[v] (component comp[v]) into R,
+//         rows outside the grid left unset (never read);
+//   the packed spectrum of rows r0, r0+1 (inverse-FFT input) into Z;
+//   the x twiddles into Tw.
+template <typename T, int NV>
+__device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v1, bool rows, int nvu,
+                                             const T* const (&src)[NV], const int (&comp)[NV], T* R,
+                                             const cplx<T>* __restrict__ S, cplx<T>* Z,
+                                             const cplx<T>* __restrict__ tw, cplx<T>* Tw) {
+    using C = cplx<T>;
+    struct Node {
+        T v[4][NV];  // rows r0-1 .. r0+2 at one x
+    };
+    struct Bin {
+        C a[3], b[3];
+    };
+    const int nx = p.nx, Px = p.Px, Kx = p.Kx, N = p.N, nrows = p.nrows;
+    const size_t cs = (size_t)nrows * Kx;
+    const int nrow_el = rows ? nx : 0;
+    const int nspec = S ? Px : 0;
+    const int ntw = tw ? Px : 0;
+    auto lrow = [&](int x) {
+        Node n;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = r0 - 1 + q;
+            if (r >= 0 && r < nrows) {
+                const int i = r * nx + x;
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (v < nvu) n.v[q][v] = src[v][comp[v] * N + i];
+            }
+        }
+        return n;
+    };
+    auto srow = [&](int x, const Node& n) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = r0 - 1 + q;
+            if (r >= 0 && r < nrows) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    if (v < nvu) R[(q * nvu + v) * nx + x] = n.v[q][v];
+            }
+        }
+    };
+    auto lspec = [&](int k) {
+        Bin b;
+        const int kk = k > Px / 2 ? Px - k : k;
+        const C* s0 = S + (size_t)r0 * Kx + kk;
+        b.a[0] = s0[0];
+        b.a[1] = s0[cs];
+        b.a[2] = s0[2 * cs];
+        if (v1) {
+            b.b[0] = s0[Kx];
+            b.b[1] = s0[Kx + cs];
+            b.b[2] = s0[Kx + 2 * cs];
+        } else {
+            b.b[0] = b.b[1] = b.b[2] = cmk<C>(0, 0);
+        }
+        return b;
+    };
+    auto sspec = [&](int k, Bin b) {
+        if (k > Px / 2) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                b.a[c] = cconj(b.a[c]);
+                b.b[c] = cconj(b.b[c]);
+            }
+        }
+        Z[lp(k)] = cadd(b.a[0], cmul_i(b.a[1]));
+        Z[lp(Px + k)] = cadd(b.b[0], cmul_i(b.b[1]));
+        Z[lp(2 * Px + k)] = cadd(b.a[2], cmul_i(b.b[2]));
+    };
+    auto ltw = [&](int k) { return tw[k]; };
+    auto stw = [&](int k, C w) { Tw[k] = w; };
+    gather3<1, 1, 1, Node, Bin, C>(nrow_el, lrow, srow, nspec, lspec, sspec, ntw, ltw, stw);
+}
+
 template <typename T, int NV>
 __device__ __forceinline__ void stage_rows(const KParams<T>& p, int r0, const T* const (&src)[NV], const int (&comp)[NV],
                                            T* R) {
@@ -409,7 +550,7 @@ __device__ __forceinline__ StageBwdArgs<T> resolve_bwd(const KParams<T>& p, cons
 // forward local kernel: inverse x-FFT (demag) + local field + LL RHS + RK4
 // stage update + forward x-FFT of the next stage's magnetisation
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int MR>
 __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const FwdL L) {
     using C = cplx<T>;
     constexpr int NV = 4;  // m_x, m_y, m_z, psi
@@ -427,16 +568,11 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     T* R = LS.R;
     const int r0 = 2 * wk.y;
     const bool v1 = r0 + 1 < p.nrows;
-    constexpr int MR = MaxReg<T>::v;
     const SigMap sm{0, Px, 0, 1};
 
-    {
-        const T* const src[NV] = {a.ys, a.ys, a.ys, a.psi};
-        const int comp[NV] = {0, 1, 2, 0};
-        stage_rows<T, NV>(p, r0, src, comp, R);
-    }
     // the accumulator and the step-start state of the first column this thread
-    // updates are loaded now, so their latency overlaps the inverse FFT
+    // updates are requested first, so their latency overlaps the staging and
+    // the inverse FFT
     V3<T> pre_acc[2], pre_mn[2];
     const bool need_acc = a.stage >= 1 && a.stage <= 3, need_mn = a.stage == 1 || a.stage == 2;
     if ((int)threadIdx.x < nx) {
@@ -448,9 +584,12 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             if (need_mn) pre_mn[rr] = ld3(a.mn, N, i);
         }
     }
-    if (demag_any)
-        for (int k = threadIdx.x; k < Px; k += blockDim.x) LS.Tw[k] = twx[k];
-    if (demag_in) unpack_rows_to_lds(p, a.S, r0, v1, Z);
+    {
+        const T* const src[NV] = {a.ys, a.ys, a.ys, a.psi};
+        const int comp[NV] = {0, 1, 2, 0};
+        stage_inputs<T, NV>(p, r0, v1, true, NV, src, comp, R, demag_in ? a.S : nullptr, Z,
+                            demag_any ? twx : nullptr, LS.Tw);
+    }
     __syncthreads();
     if (demag_in) fft_lds<C, true, MR>(Z, sm, Px, 3, LS.Tw);
 
@@ -474,8 +613,8 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             const T pi = RP(q, x);
             V3<T> B = v3<T>(0, 0, 0);
             if (demag_in) {
-                const C z01 = Z[rr * Px + x];
-                const C z2 = Z[2 * Px + x];
+                const C z01 = Z[lp(rr * Px + x)];
+                const C z2 = Z[lp(2 * Px + x)];
                 B = v3<T>(z01.x, z01.y, rr == 0 ? z2.x : z2.y);
             }
             if (p.terms & 1) {
@@ -541,9 +680,9 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             out[rr][2] = pi * yn.z;
         }
         if (a.do_fwd) {
-            Z[x] = cmk<C>(out[0][0], out[0][1]);
-            Z[Px + x] = cmk<C>(out[1][0], out[1][1]);
-            Z[2 * Px + x] = cmk<C>(out[0][2], out[1][2]);
+            Z[lp(x)] = cmk<C>(out[0][0], out[0][1]);
+            Z[lp(Px + x)] = cmk<C>(out[1][0], out[1][1]);
+            Z[lp(2 * Px + x)] = cmk<C>(out[0][2], out[1][2]);
         }
     }
     if (a.port_part) {
@@ -570,9 +709,9 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     }
     if (a.do_fwd) {
         for (int x = nx + threadIdx.x; x < Px; x += blockDim.x) {
-            Z[x] = cmk<C>(0, 0);
-            Z[Px + x] = cmk<C>(0, 0);
-            Z[2 * Px + x] = cmk<C>(0, 0);
+            Z[lp(x)] = cmk<C>(0, 0);
+            Z[lp(Px + x)] = cmk<C>(0, 0);
+            Z[lp(2 * Px + x)] = cmk<C>(0, 0);
         }
         __syncthreads();
         fft_lds<C, false, MR>(Z, sm, Px, 3, LS.Tw);
@@ -594,10 +733,11 @@ __device__ __forceinline__ V3<T> field_adjoint(const KParams<T>& p, V3<T> ell, V
     return (-gp) * (w + al * cross(w, m));
 }
 
-template <typename T>
+template <typename T, int MR>
 __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const BwdL L) {
     using C = cplx<T>;
-    constexpr int NV = 4;  // u_x, u_y, u_z, psi
+    constexpr int NV = 7;  // u_x, u_y, u_z, psi, m_x, m_y, m_z (stage state y_s)
+    const int nvu = L.stage_m ? 7 : 4;  // without room in LDS, y_s neighbours come from global memory
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
     const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
@@ -612,17 +752,14 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
     T* R = LS.R;
     const int r0 = 2 * wk.y;
     const bool v1 = r0 + 1 < p.nrows;
-    constexpr int MR = MaxReg<T>::v;
     const SigMap sm{0, Px, 0, 1};
 
-    if (!seed && (p.terms & 1)) {
-        const T* const src[NV] = {a.u_cur, a.u_cur, a.u_cur, a.psi};
-        const int comp[NV] = {0, 1, 2, 0};
-        stage_rows<T, NV>(p, r0, src, comp, R);
+    {
+        const T* const src[NV] = {a.u_cur, a.u_cur, a.u_cur, a.psi, a.ys, a.ys, a.ys};
+        const int comp[NV] = {0, 1, 2, 0, 0, 1, 2};
+        stage_inputs<T, NV>(p, r0, v1, !seed && (p.terms & 1), nvu, src, comp, R, demag_in ? a.S : nullptr, Z,
+                            demag_any ? twx : nullptr, LS.Tw);
     }
-    if (demag_any)
-        for (int k = threadIdx.x; k < Px; k += blockDim.x) LS.Tw[k] = twx[k];
-    if (demag_in) unpack_rows_to_lds(p, a.S, r0, v1, Z);
     __syncthreads();
     if (demag_in) fft_lds<C, true, MR>(Z, sm, Px, 3, LS.Tw);
 
@@ -667,28 +804,32 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                     //   mu_i += exw psi_i/s u_j - exw psi_j/s u_i
                     //   g_i  -= exw psi_j/s^2 (u_i + u_j).(m_j - m_i),   s = psi_i + psi_j
                     auto RU = [&](int qq, int xx) {
-                        return v3<T>(R[(qq * NV + 0) * nx + xx], R[(qq * NV + 1) * nx + xx], R[(qq * NV + 2) * nx + xx]);
+                        return v3<T>(R[(qq * nvu + 0) * nx + xx], R[(qq * nvu + 1) * nx + xx], R[(qq * nvu + 2) * nx + xx]);
                     };
-                    auto RP = [&](int qq, int xx) { return R[(qq * NV + 3) * nx + xx]; };
-                    auto nb = [&](V3<T> uj, T pj, int j, T w) {
+                    auto RP = [&](int qq, int xx) { return R[(qq * nvu + 3) * nx + xx]; };
+                    auto RM = [&](int qq, int xx) {
+                        if (nvu < 7) return ld3(a.ys, N, (r0 - 1 + qq) * nx + xx);
+                        return v3<T>(R[(qq * nvu + 4) * nx + xx], R[(qq * nvu + 5) * nx + xx], R[(qq * nvu + 6) * nx + xx]);
+                    };
+                    auto nb = [&](V3<T> uj, T pj, V3<T> mj, T w) {
                         const T s = pi + pj;
                         if (s != (T)0) {
-                            const V3<T> mj = ld3(a.ys, N, j);
                             const T is = (T)1 / s;
                             mu = mu + (w * pi * is) * uj - (w * pj * is) * uk;
                             g -= (double)(w * pj * is * is) * (double)dot(uk + uj, mj - m);
                         }
                     };
-                    if (x > 0) nb(RU(q, x - 1), RP(q, x - 1), i - 1, p.exw[0]);
-                    if (x < nx - 1) nb(RU(q, x + 1), RP(q, x + 1), i + 1, p.exw[0]);
-                    if (iy > 0) nb(RU(q - 1, x), RP(q - 1, x), i - nx, p.exw[1]);
-                    if (iy < p.ny - 1) nb(RU(q + 1, x), RP(q + 1, x), i + nx, p.exw[1]);
-                    if (iz > 0) nb(ld3(a.u_cur, N, i - nx * p.ny), a.psi[i - nx * p.ny], i - nx * p.ny, p.exw[2]);
-                    if (iz < p.nz - 1) nb(ld3(a.u_cur, N, i + nx * p.ny), a.psi[i + nx * p.ny], i + nx * p.ny, p.exw[2]);
+                    if (x > 0) nb(RU(q, x - 1), RP(q, x - 1), RM(q, x - 1), p.exw[0]);
+                    if (x < nx - 1) nb(RU(q, x + 1), RP(q, x + 1), RM(q, x + 1), p.exw[0]);
+                    if (iy > 0) nb(RU(q - 1, x), RP(q - 1, x), RM(q - 1, x), p.exw[1]);
+                    if (iy < p.ny - 1) nb(RU(q + 1, x), RP(q + 1, x), RM(q + 1, x), p.exw[1]);
+                    const int sl = nx * p.ny;
+                    if (iz > 0) nb(ld3(a.u_cur, N, i - sl), a.psi[i - sl], ld3(a.ys, N, i - sl), p.exw[2]);
+                    if (iz < p.nz - 1) nb(ld3(a.u_cur, N, i + sl), a.psi[i + sl], ld3(a.ys, N, i + sl), p.exw[2]);
                 }
                 if (demag_in) {
-                    const C z01 = Z[rr * Px + x];
-                    const C z2 = Z[2 * Px + x];
+                    const C z01 = Z[lp(rr * Px + x)];
+                    const C z2 = Z[lp(2 * Px + x)];
                     const V3<T> cu = v3<T>(z01.x, z01.y, rr == 0 ? z2.x : z2.y);
                     mu = mu + pi * cu;
                     g += (double)dot(m, cu);
@@ -726,16 +867,16 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
             out[rr][2] = un.z;
         }
         if (a.do_fwd) {
-            Z[x] = cmk<C>(out[0][0], out[0][1]);
-            Z[Px + x] = cmk<C>(out[1][0], out[1][1]);
-            Z[2 * Px + x] = cmk<C>(out[0][2], out[1][2]);
+            Z[lp(x)] = cmk<C>(out[0][0], out[0][1]);
+            Z[lp(Px + x)] = cmk<C>(out[1][0], out[1][1]);
+            Z[lp(2 * Px + x)] = cmk<C>(out[0][2], out[1][2]);
         }
     }
     if (a.do_fwd) {
         for (int x = nx + threadIdx.x; x < Px; x += blockDim.x) {
-            Z[x] = cmk<C>(0, 0);
-            Z[Px + x] = cmk<C>(0, 0);
-            Z[2 * Px + x] = cmk<C>(0, 0);
+            Z[lp(x)] = cmk<C>(0, 0);
+            Z[lp(Px + x)] = cmk<C>(0, 0);
+            Z[lp(2 * Px + x)] = cmk<C>(0, 0);
         }
         __syncthreads();
         fft_lds<C, false, MR>(Z, sm, Px, 3, LS.Tw);
@@ -745,14 +886,15 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
 
 // ---------------------------------------------------------------------------
 // column kernel: y (and z) transforms + tensor-spectrum multiply, in place
-// shared memory: Z [c][z < nz][y < Py][tk] complex, Tw [Py] complex,
+// shared memory: Z [c][z < nz][y < Py][tk] complex (padded, see lp), Tw [Py] complex,
 //                Nt [comp][kz <= Pz/2][ky <= Py/2][tk] real
 // ---------------------------------------------------------------------------
-template <typename T, int NZ>
-__global__ void __launch_bounds__(1024) k_col_conv(const BatchArgs<T> ba, int TK, int sid) {
+// Radix-16 passes need more than the 128 registers a 1024-thread block allows,
+// so that variant is limited to 512 threads.
+template <typename T, int NZ, int MR>
+__global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchArgs<T> ba, int TK, int sid) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int MR = MaxReg<T>::v;
     const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
     const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
     const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
@@ -763,28 +905,31 @@ __global__ void __launch_bounds__(1024) k_col_conv(const BatchArgs<T> ba, int TK
     const int Kx = p.Kx, Py = p.Py, Pz = p.Pz, ny = p.ny, nz = p.nz;
     const int plane = Py * TK;
     C* Z = reinterpret_cast<C*>(smem_raw);
-    C* Tw = Z + 3 * nz * plane;
+    C* Tw = Z + lds_pad(3 * nz * plane);
     T* Nt = reinterpret_cast<T*>(Tw + Py);
     const int k0 = wk.y * TK;
     const size_t cs = (size_t)p.nrows * Kx;
-    // load the columns (zero-padded in y), the twiddles and this tile of the tensor spectrum
-    const int nload = 3 * nz * Py * TK;
-    for (int e = threadIdx.x; e < nload; e += blockDim.x) {
-        const int tk = e % TK;
-        int t = e / TK;
-        const int y = t % Py;
-        t /= Py;
-        const int z = t % nz, c = t / nz;
-        C v = cmk<C>(0, 0);
-        if (y < ny && k0 + tk < Kx) v = S[c * cs + (size_t)(z * ny + y) * Kx + k0 + tk];
-        Z[e] = v;
-    }
-    for (int k = threadIdx.x; k < Py; k += blockDim.x) Tw[k] = twy[k];
+    // the columns (zero-padded in y), the tensor-spectrum tile and the
+    // twiddles, in batched chunks; element e = (cz * Py + y) * TK + tk with
+    // cz = c * nz + z, so the row of S is cz * ny + y (c * cs = c * nz * ny * Kx)
+    const int ltk = ilog2_rt(TK), lpy = ilog2_rt(Py);
+    const int ncolel = 3 * nz * Py * TK;
     const int ntile = p.ncomp * p.Kz2 * p.Ky2 * TK;
-    for (int e = threadIdx.x; e < ntile; e += blockDim.x) {
-        const int tk = e % TK, row = e / TK;  // row = (comp * Kz2 + kz) * Ky2 + ky
-        Nt[e] = (k0 + tk < Kx) ? nhat[(size_t)row * Kx + k0 + tk] : (T)0;
-    }
+    auto lcol = [&](int e) {
+        const int tk = e & (TK - 1);
+        const int t = e >> ltk;
+        const int y = t & (Py - 1), cz = t >> lpy;
+        return (y < ny && k0 + tk < Kx) ? S[(size_t)(cz * ny + y) * Kx + k0 + tk] : cmk<C>(0, 0);
+    };
+    auto scol = [&](int e, C v) { Z[lp(e)] = v; };
+    auto ltile = [&](int e) {
+        const int tk = e & (TK - 1), row = e >> ltk;  // row = (comp * Kz2 + kz) * Ky2 + ky
+        return (k0 + tk < Kx) ? nhat[(size_t)row * Kx + k0 + tk] : (T)0;
+    };
+    auto stile = [&](int e, T v) { Nt[e] = v; };
+    auto ltw = [&](int k) { return twy[k]; };
+    auto stw = [&](int k, C w) { Tw[k] = w; };
+    gather3<2, 2, 1, C, T, C>(ncolel, lcol, scol, ntile, ltile, stile, Py, ltw, stw);
     __syncthreads();
     const SigMap smy{ilog2_rt(TK), plane, 1, TK};
     if (Py > 1) fft_lds<C, false, MR>(Z, smy, Py, 3 * nz * TK, Tw);
@@ -801,7 +946,7 @@ __global__ void __launch_bounds__(1024) k_col_conv(const BatchArgs<T> ba, int TK
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int z = 0; z < NZ; ++z)
-                X[c][z] = z < nz ? Z[(c * nz + z) * plane + ky * TK + tk] : cmk<C>(0, 0);
+                X[c][z] = z < nz ? Z[lp((c * nz + z) * plane + ky * TK + tk)] : cmk<C>(0, 0);
         const bool fy = ky > Py / 2;
         const int kyr = fy ? Py - ky : ky;
         C Y[3][NZ];
@@ -848,18 +993,15 @@ __global__ void __launch_bounds__(1024) k_col_conv(const BatchArgs<T> ba, int TK
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int z = 0; z < NZ; ++z)
-                if (z < nz) Z[(c * nz + z) * plane + ky * TK + tk] = Y[c][z];
+                if (z < nz) Z[lp((c * nz + z) * plane + ky * TK + tk)] = Y[c][z];
     }
     __syncthreads();
     if (Py > 1) fft_lds<C, true, MR>(Z, smy, Py, 3 * nz * TK, Tw);
-    const int nstore = 3 * nz * ny * TK;
-    for (int e = threadIdx.x; e < nstore; e += blockDim.x) {
-        const int tk = e % TK;
-        int t = e / TK;
-        const int y = t % ny;
-        t /= ny;
-        const int z = t % nz, c = t / nz;
-        if (k0 + tk < Kx) S[c * cs + (size_t)(z * ny + y) * Kx + k0 + tk] = Z[((c * nz + z) * Py + y) * TK + tk];
+    for (int e = threadIdx.x; e < ncolel; e += blockDim.x) {
+        const int tk = e & (TK - 1);
+        const int t = e >> ltk;
+        const int y = t & (Py - 1), cz = t >> lpy;
+        if (y < ny && k0 + tk < Kx) S[(size_t)(cz * ny + y) * Kx + k0 + tk] = Z[lp(e)];
     }
 }
 
@@ -942,6 +1084,15 @@ __global__ void k_zero(const KParams<T>* __restrict__ ptab, const InstTab* __res
     if (i < n) role<double>(itab[inst], sel)[i] = 0.0;
 }
 
+// role[e] = v for e < mult * N of every instance
+template <typename T>
+__global__ void k_fill(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, int sel, int mult, T v) {
+    const int inst = blockIdx.y;
+    const size_t n = (size_t)mult * ptab[inst].N;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) role<T>(itab[inst], sel)[i] = v;
+}
+
 template <typename T>
 __global__ void k_copy(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, int src, int src_slot,
                        int dst, int dst_slot) {
@@ -1021,8 +1172,8 @@ __global__ void __launch_bounds__(512) k_energy(const BatchArgs<T> ba, double t,
             const T pi = psi[i];
             V3<T> Bd = v3<T>(0, 0, 0), Bex = v3<T>(0, 0, 0);
             if (demag) {
-                const C z01 = Z[rr * Px + x];
-                const C z2 = Z[2 * Px + x];
+                const C z01 = Z[lp(rr * Px + x)];
+                const C z2 = Z[lp(2 * Px + x)];
                 Bd = v3<T>(z01.x, z01.y, rr == 0 ? z2.x : z2.y);
             }
             double gp = 0.0;
@@ -1141,31 +1292,65 @@ static BatchArgs<T> bargs(const BatchDev<T>& b, const int2* work) {
     a.t0 = b.t0;
     return a;
 }
+// Variants by largest FFT radix (4, 8, or 16 in float): the launchers pick
+// the one the batch's launch configuration names.
+template <typename T, int MR>
+static void stage_fwd_r(const BatchDev<T>& b, const FwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL((k_stage_fwd<T, MR>), dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.loc_lds, s, e0, e1, 0,
+                          bargs(b, b.work_loc), L);
+}
+template <typename T, int MR>
+static void stage_bwd_r(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL((k_stage_bwd<T, MR>), dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.loc_lds, s, e0, e1, 0,
+                          bargs(b, b.work_loc), L);
+}
+template <typename T, int NZ, int MR>
+static void col_r(const BatchDev<T>& b, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL((k_col_conv<T, NZ, MR>), dim3(b.ncol), dim3(b.col_threads), (uint32_t)b.col_lds, s, e0, e1, 0,
+                          bargs(b, b.work_col), b.col_tk, spec);
+}
+template <typename T, int NZ>
+static void col_nz(const BatchDev<T>& b, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (b.col_radix == 4)
+        col_r<T, NZ, 4>(b, spec, s, e0, e1);
+    else if (b.col_radix == 8 || sizeof(T) == 8)
+        col_r<T, NZ, 8>(b, spec, s, e0, e1);
+    else
+        col_r<T, NZ, MaxReg<T>::v>(b, spec, s, e0, e1);
+}
+
 template <typename T>
 hipError_t launch_stage_fwd(const BatchDev<T>& b, const FwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL(k_stage_fwd<T>, dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.loc_lds, s, e0, e1, 0,
-                          bargs(b, b.work_loc), L);
+    if (b.loc_radix == 4)
+        stage_fwd_r<T, 4>(b, L, s, e0, e1);
+    else if (b.loc_radix == 8 || sizeof(T) == 8)
+        stage_fwd_r<T, 8>(b, L, s, e0, e1);
+    else
+        stage_fwd_r<T, MaxReg<T>::v>(b, L, s, e0, e1);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL(k_stage_bwd<T>, dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.loc_lds, s, e0, e1, 0,
-                          bargs(b, b.work_loc), L);
+    BwdL Lm = L;
+    Lm.stage_m = b.loc_nv >= 7;
+    if (b.loc_radix == 4)
+        stage_bwd_r<T, 4>(b, Lm, s, e0, e1);
+    else if (b.loc_radix == 8 || sizeof(T) == 8)
+        stage_bwd_r<T, 8>(b, Lm, s, e0, e1);
+    else
+        stage_bwd_r<T, MaxReg<T>::v>(b, Lm, s, e0, e1);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    const dim3 g(b.ncol), t(b.col_threads);
-    const BatchArgs<T> a = bargs(b, b.work_col);
-    const uint32_t lds = (uint32_t)b.col_lds;
     if (max_nz == 1)
-        hipExtLaunchKernelGGL((k_col_conv<T, 1>), g, t, lds, s, e0, e1, 0, a, b.col_tk, spec);
+        col_nz<T, 1>(b, spec, s, e0, e1);
     else if (max_nz == 2)
-        hipExtLaunchKernelGGL((k_col_conv<T, 2>), g, t, lds, s, e0, e1, 0, a, b.col_tk, spec);
+        col_nz<T, 2>(b, spec, s, e0, e1);
     else if (max_nz <= 4)
-        hipExtLaunchKernelGGL((k_col_conv<T, 4>), g, t, lds, s, e0, e1, 0, a, b.col_tk, spec);
+        col_nz<T, 4>(b, spec, s, e0, e1);
     else
-        hipExtLaunchKernelGGL((k_col_conv<T, 8>), g, t, lds, s, e0, e1, 0, a, b.col_tk, spec);
+        col_nz<T, 8>(b, spec, s, e0, e1);
     return hipGetLastError();
 }
 template <typename T>
@@ -1200,6 +1385,11 @@ hipError_t launch_zero(const BatchDev<T>& b, int sel, int what, hipStream_t s) {
     return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_fill(const BatchDev<T>& b, int sel, int mult, double v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<T>, elem_grid(b, mult * (b.max_n3 / 3)), dim3(256), 0, s, b.ptab, b.itab, sel, mult, (T)v);
+    return hipGetLastError();
+}
+template <typename T>
 hipError_t launch_copy(const BatchDev<T>& b, int src, int src_slot, int dst, int dst_slot, hipStream_t s) {
     hipLaunchKernelGGL(k_copy<T>, elem_grid(b, b.max_n3), dim3(256), 0, s, b.ptab, b.itab, src, src_slot, dst, dst_slot);
     return hipGetLastError();
@@ -1226,20 +1416,40 @@ hipError_t launch_energy_finish(const BatchDev<T>& b, double MsV, double lam, do
     return hipGetLastError();
 }
 
+// The dynamic-LDS limit is a per-kernel attribute shared by every handle of
+// the process: it only ever grows, so a handle never lowers another's limit.
 template <typename T>
 hipError_t set_lds_limits(size_t bytes) {
+    static std::mutex mu;
+    static size_t current = 65536;
+    std::lock_guard<std::mutex> lock(mu);
+    if (bytes <= current) return hipSuccess;
     hipError_t e = hipSuccess;
     const int v = (int)bytes;
 #define LLG_ATTR(K) \
     if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void*>(K), hipFuncAttributeMaxDynamicSharedMemorySize, v);
-    LLG_ATTR(k_stage_fwd<T>)
-    LLG_ATTR(k_stage_bwd<T>)
-    LLG_ATTR((k_col_conv<T, 1>))
-    LLG_ATTR((k_col_conv<T, 2>))
-    LLG_ATTR((k_col_conv<T, 4>))
-    LLG_ATTR((k_col_conv<T, 8>))
+    constexpr int RT = MaxReg<T>::v;
+    LLG_ATTR((k_stage_fwd<T, 4>))
+    LLG_ATTR((k_stage_fwd<T, 8>))
+    LLG_ATTR((k_stage_fwd<T, RT>))
+    LLG_ATTR((k_stage_bwd<T, 4>))
+    LLG_ATTR((k_stage_bwd<T, 8>))
+    LLG_ATTR((k_stage_bwd<T, RT>))
+    LLG_ATTR((k_col_conv<T, 1, 4>))
+    LLG_ATTR((k_col_conv<T, 2, 4>))
+    LLG_ATTR((k_col_conv<T, 4, 4>))
+    LLG_ATTR((k_col_conv<T, 8, 4>))
+    LLG_ATTR((k_col_conv<T, 1, 8>))
+    LLG_ATTR((k_col_conv<T, 2, 8>))
+    LLG_ATTR((k_col_conv<T, 4, 8>))
+    LLG_ATTR((k_col_conv<T, 8, 8>))
+    LLG_ATTR((k_col_conv<T, 1, RT>))
+    LLG_ATTR((k_col_conv<T, 2, RT>))
+    LLG_ATTR((k_col_conv<T, 4, RT>))
+    LLG_ATTR((k_col_conv<T, 8, RT>))
     LLG_ATTR(k_energy<T>)
 #undef LLG_ATTR
+    if (e == hipSuccess) current = bytes;
     return e;
 }
 
@@ -1252,6 +1462,7 @@ hipError_t set_lds_limits(size_t bytes) {
     template hipError_t launch_adj_init<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                     \
     template hipError_t launch_psi_grad_out<T>(const BatchDev<T>&, int, hipStream_t);                               \
     template hipError_t launch_zero<T>(const BatchDev<T>&, int, int, hipStream_t);                                  \
+    template hipError_t launch_fill<T>(const BatchDev<T>&, int, int, double, hipStream_t);                         \
     template hipError_t launch_copy<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                        \
     template hipError_t launch_port_finish<T>(const BatchDev<T>&, int, hipStream_t);                                \
     template hipError_t launch_energy<T>(const BatchDev<T>&, double, const T*, double, T*, double*, hipStream_t);   \

@@ -233,75 +233,130 @@ int upload_tables(llg_handle* h, Instance& I) {
     return LLG_OK;
 }
 
-// Launch geometry of the batch: the most demanding instance sets block size and LDS.
-int choose_launch(llg_handle* h) {
-    const int maxreg = h->dtype == LLG_F32 ? 16 : 8;
-    const size_t csz = 2 * h->tsz;
+// ---------------------------------------------------------------------------
+// launch geometry: one configuration for the whole batch (the most demanding
+// instance sets the minimum block sizes and the LDS); every valid
+// configuration computes identical bits (same FFT passes per signal, same
+// per-node arithmetic), only the tiling of the work over blocks changes
+// ---------------------------------------------------------------------------
+struct LaunchCfg {
+    int tk = 1;       // column-kernel tile: x-bins per block
+    int col_thr = 64;
     int loc_thr = 64;
-    size_t loc_lds = 0;
-    for (auto& I : h->inst) {
-        const int nx = I.prob.nx;
-        int thr = (3 * I.Px + maxreg - 1) / maxreg;
-        thr = std::max(thr, std::min(nx, 512));
-        thr = std::max(64, round_up(thr, 64));
-        if (thr > 512) return fail(LLG_ESHAPE, "x extent too large for the row kernels (nx = " + std::to_string(nx) + ")");
-        loc_thr = std::max(loc_thr, thr);
-        const size_t lds = (h->demag ? (size_t)4 * I.Px * csz : 0) + (size_t)16 * nx * h->tsz;
-        if (lds > 163840) return fail(LLG_ESHAPE, "row kernels need more than 160 KiB of LDS");
-        loc_lds = std::max(loc_lds, lds);
-    }
-    // column tile width: one value for the batch, as wide as keeps >= 256 blocks
-    auto lds_of = [&](const Instance& I, int tk) {
-        const int Ky2 = I.Py / 2 + 1, Kz2 = I.Pz / 2 + 1;
-        return (size_t)3 * I.prob.nz * I.Py * tk * csz + (size_t)I.Py * csz + (size_t)I.ncomp * Kz2 * Ky2 * tk * h->tsz;
-    };
-    auto fits = [&](int tk) {
-        for (auto& I : h->inst)
-            if (lds_of(I, tk) > 163840 || 3 * I.prob.nz * I.Py * tk > maxreg * 1024) return false;
-        return true;
-    };
+    int nv = 4;       // node values per staged row in the backward row kernel (4: u, psi; 7: also y_s)
+    int col_r = 16;   // largest FFT radix of the column kernel (4, 8, 16; 16 in float only)
+    int loc_r = 16;   // largest FFT radix of the row kernels
+};
+
+int maxreg_of(const llg_handle* h) { return h->dtype == LLG_F32 ? 16 : 8; }
+bool radix_ok(const llg_handle* h, int r) { return r == 4 || r == 8 || (r == 16 && h->dtype == LLG_F32); }
+
+// fewest threads the row kernels need (FFT register budget of radix r), at least 64
+int loc_min_threads(const llg_handle* h, int r) {
+    int thr = 64;
+    for (auto& I : h->inst) thr = std::max(thr, round_up((3 * I.Px + r - 1) / r, 64));
+    return thr;
+}
+
+// LDS of the row kernels with nv node values per staged row (4 rows)
+size_t loc_lds_bytes(const llg_handle* h, int nv) {
+    size_t lds = 0;
+    for (auto& I : h->inst)
+        lds = std::max(lds, (h->demag ? (size_t)(lds_pad(3 * I.Px) + I.Px) * 2 * h->tsz : 0) +
+                                (size_t)4 * nv * I.prob.nx * h->tsz);
+    return lds;
+}
+
+
+size_t col_lds_bytes(const llg_handle* h, const Instance& I, int tk) {
+    const size_t csz = 2 * h->tsz;
+    const int Ky2 = I.Py / 2 + 1, Kz2 = I.Pz / 2 + 1;
+    return (size_t)lds_pad(3 * I.prob.nz * I.Py * tk) * csz + (size_t)I.Py * csz +
+           (size_t)I.ncomp * Kz2 * Ky2 * tk * h->tsz;
+}
+
+int col_min_threads(const llg_handle* h, int tk, int r) {
+    int thr = 64;
+    for (auto& I : h->inst) thr = std::max(thr, round_up((3 * I.prob.nz * I.Py * tk + r - 1) / r, 64));
+    return thr;
+}
+
+// block-size limit of the column kernel variant with largest radix r
+int col_max_threads(int r) { return r >= 16 ? 512 : 1024; }
+
+bool col_fits(const llg_handle* h, int tk, int r) {
+    for (auto& I : h->inst)
+        if (col_lds_bytes(h, I, tk) > 163840) return false;
+    return col_min_threads(h, tk, r) <= col_max_threads(r);
+}
+
+int check_cfg(const llg_handle* h, const LaunchCfg& c) {
+    if (!radix_ok(h, c.col_r) || !radix_ok(h, c.loc_r))
+        return fail(LLG_EINVAL, "FFT radix must be 4, 8 or (float only) 16");
+    if (c.tk != 1 && c.tk != 2 && c.tk != 4 && c.tk != 8 && c.tk != 16)
+        return fail(LLG_EINVAL, "column tile must be 1, 2, 4, 8 or 16");
+    if (!col_fits(h, c.tk, c.col_r)) return fail(LLG_ESHAPE, "column tile " + std::to_string(c.tk) + " does not fit");
+    const int cmin = col_min_threads(h, c.tk, c.col_r), lmin = loc_min_threads(h, c.loc_r);
+    const int cmax = col_max_threads(c.col_r);
+    if (c.col_thr % 64 || c.col_thr < cmin || c.col_thr > cmax)
+        return fail(LLG_EINVAL, "column threads must be a multiple of 64 in [" + std::to_string(cmin) + ", " +
+                                    std::to_string(cmax) + "]");
+    if (c.loc_thr % 64 || c.loc_thr < lmin || c.loc_thr > 512)
+        return fail(LLG_EINVAL, "row threads must be a multiple of 64 in [" + std::to_string(lmin) + ", 512]");
+    if (c.nv != 4 && c.nv != 7) return fail(LLG_EINVAL, "staged row values must be 4 or 7");
+    if (loc_lds_bytes(h, c.nv) > 163840) return fail(LLG_ESHAPE, "staged rows do not fit 160 KiB of LDS");
+    return LLG_OK;
+}
+
+// The rule used at creation: row blocks as wide as the widest row (<= 512),
+// column tiles as wide as keeps >= 256 blocks.
+int default_cfg(const llg_handle* h, LaunchCfg& c) {
+    const int r = maxreg_of(h);
+    // column radix: the largest whose block fits the tallest column
+    int cr = r;
+    while (cr > 4 && !col_fits(h, 1, cr)) cr /= 2;
+    int lt = loc_min_threads(h, r);
+    for (auto& I : h->inst) lt = std::max(lt, round_up(std::min(I.prob.nx, 512), 64));
+    if (loc_min_threads(h, r) > 512)
+        return fail(LLG_ESHAPE, "x extent too large for the row kernels");
+    if (loc_lds_bytes(h, 4) > 163840) return fail(LLG_ESHAPE, "row kernels need more than 160 KiB of LDS");
     auto blocks_of = [&](int tk) {
         long long b = 0;
         for (auto& I : h->inst) b += (I.Kx + tk - 1) / tk;
         return b;
     };
     int tk = 8;
-    while (tk > 1 && (blocks_of(tk) < 256 || !fits(tk))) tk /= 2;
-    if (!fits(tk)) return fail(LLG_ESHAPE, "y/z extent too large for the column FFT");
-    int col_thr = 64;
+    while (tk > 1 && (blocks_of(tk) < 256 || !col_fits(h, tk, cr))) tk /= 2;
+    if (!col_fits(h, tk, cr)) return fail(LLG_ESHAPE, "y/z extent too large for the column FFT");
+    int ct = col_min_threads(h, tk, cr);
+    for (auto& I : h->inst)
+        ct = std::max(ct, std::min(col_max_threads(cr), round_up(std::min(I.Py * tk, 256), 64)));
+    c.tk = tk;
+    c.col_thr = ct;
+    c.loc_thr = lt;
+    c.nv = 4;
+    c.col_r = cr;
+    c.loc_r = r;
+    return LLG_OK;
+}
+
+// Make c the batch's launch configuration: column work list, block sizes, LDS limits.
+int apply_cfg(llg_handle* h, const LaunchCfg& c) {
+    std::vector<int2> wc;
+    for (int i = 0; i < (int)h->inst.size(); ++i)
+        for (int k = 0; k < (h->inst[i].Kx + c.tk - 1) / c.tk; ++k) wc.push_back(make_int2(i, k));
+    HIPCHK(hipMemcpy(h->work_col, wc.data(), wc.size() * sizeof(int2), hipMemcpyHostToDevice));
     size_t col_lds = 0;
-    for (auto& I : h->inst) {
-        int thr = (3 * I.prob.nz * I.Py * tk + maxreg - 1) / maxreg;
-        thr = std::max(thr, std::min(I.Py * tk, 256));
-        col_thr = std::max(col_thr, std::min(1024, std::max(64, round_up(thr, 64))));
-        col_lds = std::max(col_lds, lds_of(I, tk));
-    }
-    // work lists
-    std::vector<int2> wl, wc;
-    for (int i = 0; i < (int)h->inst.size(); ++i) {
-        for (int r = 0; r < h->inst[i].nloc; ++r) wl.push_back(make_int2(i, r));
-        for (int c = 0; c < (h->inst[i].Kx + tk - 1) / tk; ++c) wc.push_back(make_int2(i, c));
-    }
-    int rc;
-    void* p;
-    if ((rc = alloc(h, &p, wl.size() * sizeof(int2)))) return rc;
-    h->work_loc = (int2*)p;
-    HIPCHK(hipMemcpy(p, wl.data(), wl.size() * sizeof(int2), hipMemcpyHostToDevice));
-    if ((rc = alloc(h, &p, wc.size() * sizeof(int2)))) return rc;
-    h->work_col = (int2*)p;
-    HIPCHK(hipMemcpy(p, wc.data(), wc.size() * sizeof(int2), hipMemcpyHostToDevice));
-    int max_n3 = 0;
-    for (auto& I : h->inst) max_n3 = std::max(max_n3, 3 * I.N);
+    for (auto& I : h->inst) col_lds = std::max(col_lds, col_lds_bytes(h, I, c.tk));
+    const size_t loc_lds = loc_lds_bytes(h, c.nv);
     auto fill = [&](auto& b) {
-        b.work_loc = h->work_loc;
-        b.work_col = h->work_col;
-        b.nloc = (int)wl.size();
         b.ncol = (int)wc.size();
-        b.ninst = (int)h->inst.size();
-        b.max_n3 = max_n3;
-        b.loc_threads = loc_thr;
-        b.col_threads = col_thr;
-        b.col_tk = tk;
+        b.loc_threads = c.loc_thr;
+        b.col_threads = c.col_thr;
+        b.col_tk = c.tk;
+        b.loc_nv = c.nv;
+        b.col_radix = c.col_r;
+        b.loc_radix = c.loc_r;
         b.loc_lds = loc_lds;
         b.col_lds = col_lds;
     };
@@ -316,6 +371,37 @@ int choose_launch(llg_handle* h) {
         }
     }
     return LLG_OK;
+}
+
+int choose_launch(llg_handle* h) {
+    // work lists: row pairs (fixed) and column tiles (capacity for the narrowest tile)
+    std::vector<int2> wl;
+    size_t ncol_max = 0;
+    for (int i = 0; i < (int)h->inst.size(); ++i) {
+        for (int r = 0; r < h->inst[i].nloc; ++r) wl.push_back(make_int2(i, r));
+        ncol_max += h->inst[i].Kx;
+    }
+    int rc;
+    void* p;
+    if ((rc = alloc(h, &p, wl.size() * sizeof(int2)))) return rc;
+    h->work_loc = (int2*)p;
+    HIPCHK(hipMemcpy(p, wl.data(), wl.size() * sizeof(int2), hipMemcpyHostToDevice));
+    if ((rc = alloc(h, &p, ncol_max * sizeof(int2)))) return rc;
+    h->work_col = (int2*)p;
+    int max_n3 = 0;
+    for (auto& I : h->inst) max_n3 = std::max(max_n3, 3 * I.N);
+    auto fill = [&](auto& b) {
+        b.work_loc = h->work_loc;
+        b.work_col = h->work_col;
+        b.nloc = (int)wl.size();
+        b.ninst = (int)h->inst.size();
+        b.max_n3 = max_n3;
+    };
+    fill(h->bf);
+    fill(h->bd);
+    LaunchCfg c;
+    if ((rc = default_cfg(h, c))) return rc;
+    return apply_cfg(h, c);
 }
 
 int validate_problem(const llg_problem* p) {
@@ -783,6 +869,113 @@ struct Ops {
     }
 };
 
+// Autotuner: time the column kernel over the valid (tile, threads) pairs and
+// the row kernels (one forward and one backward stage) over the valid block
+// sizes, on the handle's own buffers (psi = 1, states zero), and keep the
+// fastest.  Every candidate computes the same bits, so tuning changes speed only.
+template <typename T>
+int autotune_typed(llg_handle* h, hipStream_t s, LaunchCfg& best) {
+    Ops<T> o{h, s};
+    const size_t t = h->tsz;
+    for (auto& I : h->inst) {
+        const size_t n3 = (size_t)3 * I.N * t;
+        for (int id : {B_M, B_ACC, B_YA, B_YB, B_ELL, B_U0, B_U1, B_L0, B_L1})
+            HIPCHK(hipMemsetAsync(I.tab.b[id], 0, n3, s));
+        HIPCHK(hipMemsetAsync(I.tab.b[B_YS], 0, 4 * n3, s));
+        HIPCHK(hipMemsetAsync(I.tab.b[B_BS], 0, 4 * n3, s));
+        HIPCHK(hipMemsetAsync(I.tab.b[B_GPSI], 0, (size_t)I.N * 8, s));
+        if (h->demag) HIPCHK(hipMemsetAsync(I.tab.b[B_S], 0, (size_t)3 * I.nrows * I.Kx * 2 * t, s));
+    }
+    HIPCHK(launch_fill<T>(bdev<T>(h), B_PSI, 1, 1.0, s));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int rc = LLG_OK;
+    auto timed = [&](auto&& body) -> float {
+        for (int k = 0; k < 2 && !rc; ++k) rc = body();
+        if (rc || hipEventRecord(e0, s) != hipSuccess) return 1e30f;
+        for (int k = 0; k < 8 && !rc; ++k) rc = body();
+        float ms = 1e30f;
+        if (rc || hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return 1e30f;
+        return ms;
+    };
+    FwdL Lf = o.fwd_launch(1);
+    Lf.ys = B_YA;
+    Lf.mn = B_M;
+    Lf.acc = B_ACC;
+    Lf.ynext = B_YB;
+    Lf.do_inv = Lf.do_fwd = h->demag;
+    BwdL Lb{};
+    Lb.stage = 1;
+    Lb.ucur = B_U0;
+    Lb.unext = B_U1;
+    Lb.lamp = B_L0;
+    Lb.lacc = B_L1;
+    Lb.do_inv = Lb.do_fwd = h->demag;
+    LaunchCfg cur;
+    if ((rc = default_cfg(h, cur))) return rc;
+    best = cur;
+    if (h->demag) {
+        float tbest = 1e30f;
+        for (int cr : {4, 8, 16}) {
+            if (!radix_ok(h, cr)) continue;
+            for (int tk : {1, 2, 4, 8, 16}) {
+                if (!col_fits(h, tk, cr)) continue;
+                const int cmin = col_min_threads(h, tk, cr);
+                for (int ct : {cmin, 2 * cmin, 4 * cmin}) {
+                    if (ct > col_max_threads(cr)) continue;
+                    LaunchCfg c = cur;
+                    c.tk = tk;
+                    c.col_thr = ct;
+                    c.col_r = cr;
+                    if ((rc = apply_cfg(h, c))) break;
+                    const float ms = timed([&] { return o.col(); });
+                    if (rc) break;
+                    if (ms < tbest) tbest = ms, best = c;
+                }
+                if (rc) break;
+            }
+            if (rc) break;
+        }
+    }
+    if (!rc) {
+        float tbest = 1e30f;
+        LaunchCfg base = best;
+        for (int lr : {4, 8, 16}) {
+            if (!radix_ok(h, lr)) continue;
+            const int lmin = loc_min_threads(h, lr);
+            if (lmin > 512) continue;
+            std::vector<int> cand = {lmin};
+            for (int lt : {128, 256, 512})
+                if (lt > lmin) cand.push_back(lt);
+            for (int lt : cand) {
+                for (int nv : {4, 7}) {
+                    if (loc_lds_bytes(h, nv) > 163840) continue;
+                    LaunchCfg c = base;
+                    c.loc_thr = lt;
+                    c.nv = nv;
+                    c.loc_r = lr;
+                    if ((rc = apply_cfg(h, c))) break;
+                    const float ms = timed([&] {
+                        if (int r = o.fwd(Lf)) return r;
+                        return o.bwd(Lb);
+                    });
+                    if (rc) break;
+                    if (ms < tbest) tbest = ms, best = c;
+                }
+                if (rc) break;
+            }
+            if (rc) break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    return apply_cfg(h, best);
+}
+
 int check_ptr(const void* p, const char* name) {
     if (!p) return fail(LLG_EINVAL, std::string(name) + " is NULL");
     return LLG_OK;
@@ -1140,6 +1333,47 @@ int llg_batch_destroy(llg_batch* b) { return llg_destroy(b); }
 int llg_batch_size(const llg_batch* b, int32_t* n) {
     if (!b || !n) return fail(LLG_EINVAL, "NULL argument");
     *n = (int32_t)b->inst.size();
+    return LLG_OK;
+}
+
+int llg_launch_config(const llg_handle* h, int32_t cfg[6]) {
+    if (!h || !cfg) return fail(LLG_EINVAL, "NULL argument");
+    cfg[0] = h->bf.col_tk;
+    cfg[1] = h->bf.col_threads;
+    cfg[2] = h->bf.loc_threads;
+    cfg[3] = h->bf.loc_nv;
+    cfg[4] = h->bf.col_radix;
+    cfg[5] = h->bf.loc_radix;
+    return LLG_OK;
+}
+
+int llg_set_launch_config(llg_handle* h, const int32_t cfg[6]) {
+    if (!h || !cfg) return fail(LLG_EINVAL, "NULL argument");
+    LaunchCfg c;
+    c.tk = cfg[0];
+    c.col_thr = cfg[1];
+    c.loc_thr = cfg[2];
+    c.nv = cfg[3];
+    c.col_r = cfg[4];
+    c.loc_r = cfg[5];
+    if (int rc = check_cfg(h, c)) return rc;
+    HIPCHK(hipDeviceSynchronize());
+    drop_graphs(h);
+    return apply_cfg(h, c);
+}
+
+int llg_autotune(llg_handle* h, hipStream_t stream) {
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    HIPCHK(hipDeviceSynchronize());
+    drop_graphs(h);
+    const bool prof = h->prof_on;
+    h->prof_on = false;
+    LaunchCfg best;
+    const int rc = h->dtype == LLG_F32 ? autotune_typed<float>(h, stream, best) : autotune_typed<double>(h, stream, best);
+    h->prof_on = prof;
+    h->fwd_valid = false;
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(stream));
     return LLG_OK;
 }
 

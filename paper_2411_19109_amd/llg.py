@@ -23,7 +23,8 @@ LLG_OBJ_NONE, LLG_OBJ_ENERGY_AREA, LLG_OBJ_PORT_MY2 = 0, 1, 2
 
 EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_levelset_to_Ms",
            "llg_levelset_to_Ms_vjp", "llg_field", "llg_forward", "llg_objective", "llg_adjoint",
-           "llg_query_memory", "llg_query_recompute", "llg_set_graphs", "llg_fft_sizes", "llg_profile", "llg_profile_read", "llg_batch_create",
+           "llg_query_memory", "llg_query_recompute", "llg_set_graphs", "llg_launch_config",
+           "llg_set_launch_config", "llg_autotune", "llg_fft_sizes", "llg_profile", "llg_profile_read", "llg_batch_create",
            "llg_batch_destroy", "llg_batch_size", "llg_batch_levelset_to_Ms", "llg_batch_levelset_to_Ms_vjp",
            "llg_batch_forward", "llg_batch_adjoint"]
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
@@ -91,6 +92,9 @@ def lib():
         "llg_fft_sizes": [vp, ctypes.POINTER(ctypes.c_int32)],
         "llg_profile": [vp, ctypes.c_int],
         "llg_set_graphs": [vp, ctypes.c_int],
+        "llg_launch_config": [vp, ctypes.POINTER(i32)],
+        "llg_set_launch_config": [vp, ctypes.POINTER(i32)],
+        "llg_autotune": [vp, vp],
         "llg_batch_create": [ctypes.POINTER(Problem_c), ctypes.POINTER(Masks_c), i32, ctypes.POINTER(vp)],
         "llg_batch_destroy": [vp],
         "llg_batch_size": [vp, ctypes.POINTER(i32)],
@@ -217,6 +221,24 @@ class Solver:
         """Capture forward / adjoint launch sequences in HIP graphs and replay them."""
         check(lib().llg_set_graphs(self.h, int(enable)))
 
+    def launch_config(self):
+        """(column tile, column threads, row threads, staged values per row in the
+        backward kernel, column FFT radix, row FFT radix)."""
+        c = (ctypes.c_int32 * 6)()
+        check(lib().llg_launch_config(self.h, c))
+        return tuple(c)
+
+    def set_launch_config(self, tk, col_threads, row_threads, nv=4, col_radix=None, row_radix=None):
+        cur = self.launch_config()
+        c = (ctypes.c_int32 * 6)(tk, col_threads, row_threads, nv, col_radix or cur[4], row_radix or cur[5])
+        check(lib().llg_set_launch_config(self.h, c))
+
+    def autotune(self):
+        """Time the valid launch configurations and keep the fastest (drops the forward record)."""
+        import torch
+        check(lib().llg_autotune(self.h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        return self.launch_config()
+
     def profile_read(self, kind, reset=True):
         """(device ms, launches, algorithmic bytes) summed over profiled launches of one kernel class."""
         ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
@@ -340,6 +362,24 @@ class Batch:
     def set_graphs(self, enable: bool):
         """Capture forward / adjoint launch sequences in HIP graphs and replay them."""
         check(lib().llg_set_graphs(self.h, int(enable)))
+
+    def launch_config(self):
+        """(column tile, column threads, row threads, staged values per row in the
+        backward kernel, column FFT radix, row FFT radix)."""
+        c = (ctypes.c_int32 * 6)()
+        check(lib().llg_launch_config(self.h, c))
+        return tuple(c)
+
+    def set_launch_config(self, tk, col_threads, row_threads, nv=4, col_radix=None, row_radix=None):
+        cur = self.launch_config()
+        c = (ctypes.c_int32 * 6)(tk, col_threads, row_threads, nv, col_radix or cur[4], row_radix or cur[5])
+        check(lib().llg_set_launch_config(self.h, c))
+
+    def autotune(self):
+        """Time the valid launch configurations and keep the fastest (drops the forward record)."""
+        import torch
+        check(lib().llg_autotune(self.h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        return self.launch_config()
 
     def profile_read(self, kind, reset=True):
         ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()

@@ -11,11 +11,13 @@ from paper_2411_19109_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def run_batch(ws, dtype, n_steps, **kw):
+def run_batch(ws, dtype, n_steps, tune=False, **kw):
     import torch
     from paper_2411_19109_amd import llg
     b = llg.Batch([w.problem for w in ws], dtype=dtype, max_steps=n_steps,
                   masks=[dict(antenna=w.antenna, port1=w.port1, port2=w.port2, design=w.design) for w in ws], **kw)
+    if tune:
+        b.autotune()
     phis = [to_dev(w.phi, dtype) for w in ws]
     psis = b.levelset_to_psi(phis, ws[0].heaviside_a, [to_dev(w.psi_fixed, dtype) for w in ws])
     obj = llg.make_objective(wl.OBJ_PORT_MY2, n_start=ws[0].obj_n_start)
@@ -62,11 +64,9 @@ def test_batch_equals_single_instances_bitwise(dtype):
         assert abs(bo[i]["J"] - so["J"]) <= 1e-12 * abs(so["J"]) + 1e-300
 
 
-def test_batch_instance_matches_oracle():
-    """Two ragged instances with the port windows on and just after the antenna
-    strip, so that J is set by the driven precession (well above rounding)."""
-    n = 20
-    ws = ragged_set(n)[:2]
+def antenna_ports(ws):
+    """Port windows on and just after the antenna strip, so that J is set by the
+    driven precession (well above rounding) even for a few steps."""
     for w in ws:
         ant = w.antenna[0]
         cols = np.nonzero(ant.any(axis=0))[0]
@@ -78,6 +78,12 @@ def test_batch_instance_matches_oracle():
         p1[:, rows[0]:rows[-1] + 1, cols[0]:cols[-1] + 1] = 1
         p2[:, rows[0]:rows[-1] + 1, cols[-1] + 2:cols[-1] + 4] = 1
         w.port1, w.port2 = p1, p2
+    return ws
+
+
+def test_batch_instance_matches_oracle():
+    n = 20
+    ws = antenna_ports(ragged_set(n)[:2])
     say("batch vs oracle (f64)")
     bo = run_batch(ws, "f64", n)
     for i, w in enumerate(ws):

@@ -1,0 +1,83 @@
+"""Launch configurations and the autotuner: for a given FFT radix every valid
+tiling of the column and row kernels gives the same bits (the passes of a
+signal and the per-node arithmetic do not depend on the tiling); another radix
+changes only the rounding order of the transforms; invalid configurations are
+rejected on the host; the autotuner picks a valid one."""
+import numpy as np
+import pytest
+
+from _helpers import gpu_gradient, gpu_solver, say
+from paper_2411_19109_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _same(g, ref):
+    assert g["J"] == ref["J"]
+    for k in ("dpsi", "dm0", "mT"):
+        assert np.array_equal(g[k], ref[k]), k
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_launch_configs_bitwise(dtype):
+    from paper_2411_19109_amd import llg
+    from test_gpu_parity import tiny_workload
+    w = tiny_workload(21, 13, 1, kind=wl.OBJ_PORT_MY2, n_steps=12)
+    s = gpu_solver(w, dtype, max_steps=12)
+    base = s.launch_config()
+    say("default launch config", base, dtype)
+    ref = gpu_gradient(w, dtype, solver=s)
+    tried = 0
+    for tk in (1, 2, 4, 8, 16):
+        for ct in (64, 128, 256):
+            for lt, nv in ((64, 4), (128, 7), (256, 4), (256, 7)):
+                try:
+                    s.set_launch_config(tk, ct, lt, nv)
+                except llg.LLGError:
+                    continue
+                assert s.launch_config()[:4] == (tk, ct, lt, nv)
+                _same(gpu_gradient(w, dtype, solver=s), ref)
+                tried += 1
+    assert tried >= 10
+    # other radices: the same values up to the rounding of the transforms
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    for cr, lr in ((4, 4), (8, 4), (4, 8)):
+        s.set_launch_config(1, 256, 256, 4, cr, lr)
+        g = gpu_gradient(w, dtype, solver=s)
+        assert abs(g["J"] - ref["J"]) <= tol * abs(ref["J"])
+        assert np.abs(g["mT"] - ref["mT"]).max() <= tol
+        assert np.linalg.norm(g["dpsi"] - ref["dpsi"]) <= 50 * tol * np.linalg.norm(ref["dpsi"])
+    if dtype == "f64":
+        with pytest.raises(llg.LLGError):
+            s.set_launch_config(1, 256, 256, 4, 16, 8)
+    with pytest.raises(llg.LLGError):
+        s.set_launch_config(3, 128, 128)
+    with pytest.raises(llg.LLGError):
+        s.set_launch_config(1, 100, 128)
+    with pytest.raises(llg.LLGError):
+        s.set_launch_config(1, 128, 1024)
+    with pytest.raises(llg.LLGError):
+        s.set_launch_config(1, 128, 128, 5)
+    s.close()
+
+
+def test_autotune_keeps_results():
+    from paper_2411_19109_amd import llg
+    from test_gpu_batch import antenna_ports, ragged_set, run_batch
+    n = 10
+    ws = antenna_ports(ragged_set(n))
+    say("autotune on a ragged batch")
+    ref = run_batch(ws, "f32", n)
+    b = llg.Batch([w.problem for w in ws], dtype="f32", max_steps=n,
+                  masks=[dict(antenna=w.antenna, port1=w.port1, port2=w.port2, design=w.design) for w in ws])
+    cfg = b.autotune()
+    say("autotuned", cfg)
+    assert cfg[0] in (1, 2, 4, 8, 16) and cfg[1] % 64 == 0 and cfg[2] % 64 == 0 and cfg[3] in (4, 7)
+    assert cfg[4] in (4, 8, 16) and cfg[5] in (4, 8, 16)
+    b.close()
+    out = run_batch(ws, "f32", n, tune=True)
+    for i in range(len(ws)):
+        # the tuned radices may round the transforms differently: FP32 tolerance
+        assert abs(out[i]["J"] - ref[i]["J"]) <= 1e-4 * abs(ref[i]["J"])
+        assert np.abs(out[i]["mT"] - ref[i]["mT"]).max() <= 1e-5
+        assert np.linalg.norm(out[i]["dpsi"] - ref[i]["dpsi"]) <= 1e-3 * np.linalg.norm(ref[i]["dpsi"])

@@ -215,19 +215,22 @@ int llg_query_recompute(int64_t n_steps, int32_t policy, int32_t ckpt_param, int
 int llg_set_graphs(llg_handle* h, int enable);
 
 /* Launch configuration of a handle's kernels (one for all instances of a
- * batch): cfg[0] = column tile (x-bins per column-kernel block: 1, 2, 4, 8 or
- * 16), cfg[1] = column-kernel threads, cfg[2] = row-kernel threads (multiples
- * of 64), cfg[3] = node values per row the backward row kernel stages in LDS
- * (4: field adjoint and psi; 7: also the stage state), cfg[4] / cfg[5] =
- * largest FFT radix of the column / row kernels (4, 8, or 16 in float; a
+ * batch), 8 ints:
+ *   cfg[0] column tile (x-bins per column-kernel block: 1, 2, 4, 8 or 16),
+ *   cfg[1] column-kernel threads, cfg[2] its largest FFT radix,
+ *   cfg[3] forward row-kernel threads, cfg[4] its largest FFT radix,
+ *   cfg[5] backward row-kernel threads, cfg[6] its largest FFT radix,
+ *   cfg[7] node values per row the backward row kernel stages in LDS
+ *          (4: field adjoint and psi; 7: also the stage state).
+ * Threads are multiples of 64; radices are 4, 8, or 16 (float only): a
  * smaller radix spreads a transform over more lanes, a larger one needs fewer
- * passes).  Configurations differ in speed only, not in the computed values
- * beyond the rounding order of the FFT passes: a given radix gives identical
- * bits for every tiling.  llg_set_launch_config validates (LLG_EINVAL /
- * LLG_ESHAPE when a tile does not fit 160 KiB of LDS or the FFT register
- * budget), synchronises the device and drops cached graphs. */
-int llg_launch_config(const llg_handle* h, int32_t cfg[6]);
-int llg_set_launch_config(llg_handle* h, const int32_t cfg[6]);
+ * passes.  For given radices every tiling computes identical bits; another
+ * radix changes only the rounding order of the transforms.
+ * llg_set_launch_config validates (LLG_EINVAL / LLG_ESHAPE when a tile does
+ * not fit 160 KiB of LDS or the FFT register budget), synchronises the device
+ * and drops cached graphs. */
+int llg_launch_config(const llg_handle* h, int32_t cfg[8]);
+int llg_set_launch_config(llg_handle* h, const int32_t cfg[8]);
 
 /* Autotuner: times the column kernel over every valid (tile, threads) pair
  * and one forward plus one backward row-kernel stage over the valid row block

@@ -177,10 +177,11 @@ struct BatchDev {
     const int2* work_col;  // (instance, column tile)
     int nloc, ncol, ninst;
     int max_n3;            // max 3N over instances (grid of element-wise kernels)
-    int loc_threads, col_threads, col_tk;
-    int loc_nv;            // node values per staged row in the backward row kernel (4 or 7)
-    int col_radix, loc_radix;  // largest FFT radix of the column / row kernels (4, 8 or 16)
-    size_t loc_lds, col_lds;
+    int col_tk, col_threads, col_radix;  // column kernel: x-bins per block, block size, largest FFT radix
+    int loc_threads, loc_radix;          // forward row kernel (and the energy kernel's block size)
+    int bwd_threads, bwd_radix;          // backward row kernel
+    int loc_nv;                          // node values per staged row in the backward row kernel (4 or 7)
+    size_t loc_lds, bwd_lds, col_lds;
     KParams<T> p0;  // instance 0, by value
     InstTab t0;
 };

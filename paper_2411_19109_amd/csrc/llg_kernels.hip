@@ -570,19 +570,17 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     const bool v1 = r0 + 1 < p.nrows;
     const SigMap sm{0, Px, 0, 1};
 
-    // the accumulator and the step-start state of the first column this thread
-    // updates are requested first, so their latency overlaps the staging and
-    // the inverse FFT
-    V3<T> pre_acc[2], pre_mn[2];
+    // Work items are (row, x) pairs of the two rows, item = rr * nx + x, so a
+    // narrow row pair still spreads over twice as many lanes.  The accumulator
+    // and step-start state of this thread's first item are requested first, so
+    // their latency overlaps the staging and the inverse FFT.
+    const int nitem = v1 ? 2 * nx : nx;
+    V3<T> pre_acc = v3<T>(0, 0, 0), pre_mn = v3<T>(0, 0, 0);
     const bool need_acc = a.stage >= 1 && a.stage <= 3, need_mn = a.stage == 1 || a.stage == 2;
-    if ((int)threadIdx.x < nx) {
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
-            const int i = (r0 + rr) * nx + threadIdx.x;
-            if (rr == 1 && !v1) break;
-            if (need_acc) pre_acc[rr] = ld3(a.acc, N, i);
-            if (need_mn) pre_mn[rr] = ld3(a.mn, N, i);
-        }
+    if ((int)threadIdx.x < nitem) {
+        const int i = r0 * nx + threadIdx.x;  // rows r0, r0+1 are contiguous
+        if (need_acc) pre_acc = ld3(a.acc, N, i);
+        if (need_mn) pre_mn = ld3(a.mn, N, i);
     }
     {
         const T* const src[NV] = {a.ys, a.ys, a.ys, a.psi};
@@ -593,17 +591,18 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     __syncthreads();
     if (demag_in) fft_lds<C, true, MR>(Z, sm, Px, 3, LS.Tw);
 
-    const T drv = (T)drive_value(p.f1, p.f2, p.t_switch, a.t);
+    const T drv = ((p.terms & 4) && a.antenna) ? (T)drive_value(p.f1, p.f2, p.t_switch, a.t) : (T)0;
     const T dt = p.dt;
+    const int iy0 = r0 % p.ny, iz0 = r0 / p.ny;
     double s1 = 0.0, s2 = 0.0;
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-        T out[2][3] = {{0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
+    for (int it = threadIdx.x; it < nitem; it += blockDim.x) {
+        {
+            const int rr = it >= nx ? 1 : 0;
+            const int x = it - rr * nx;
             const int r = r0 + rr;
-            if (rr == 1 && !v1) break;
             const int q = rr + 1;
-            const int iy = r % p.ny, iz = r / p.ny;
+            int iy = iy0 + rr, iz = iz0;
+            if (iy == p.ny) iy = 0, iz += 1;
             const int i = r * nx + x;
             auto RM = [&](int qq, int xx) {
                 return v3<T>(R[(qq * NV + 0) * nx + xx], R[(qq * NV + 1) * nx + xx], R[(qq * NV + 2) * nx + xx]);
@@ -649,9 +648,9 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             }
             if (a.ys_store) st3(a.ys_store, N, i, m);
             if (a.Bs_store) st3(a.Bs_store, N, i, B);
-            const bool first = x == (int)threadIdx.x;
-            const V3<T> accv = need_acc ? (first ? pre_acc[rr] : ld3(a.acc, N, i)) : v3<T>(0, 0, 0);
-            const V3<T> mnv = need_mn ? (first ? pre_mn[rr] : ld3(a.mn, N, i)) : v3<T>(0, 0, 0);
+            const bool first = it == (int)threadIdx.x;
+            const V3<T> accv = need_acc ? (first ? pre_acc : ld3(a.acc, N, i)) : v3<T>(0, 0, 0);
+            const V3<T> mnv = need_mn ? (first ? pre_mn : ld3(a.mn, N, i)) : v3<T>(0, 0, 0);
             V3<T> yn;
             if (a.stage == -3) {
                 yn = m;  // prologue: spectrum of psi * m only
@@ -675,14 +674,16 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
                 if (a.port1[i]) s1 += my2;
                 if (a.port2[i]) s2 += my2;
             }
-            out[rr][0] = pi * yn.x;
-            out[rr][1] = pi * yn.y;
-            out[rr][2] = pi * yn.z;
-        }
-        if (a.do_fwd) {
-            Z[lp(x)] = cmk<C>(out[0][0], out[0][1]);
-            Z[lp(Px + x)] = cmk<C>(out[1][0], out[1][1]);
-            Z[lp(2 * Px + x)] = cmk<C>(out[0][2], out[1][2]);
+            if (a.do_fwd) {
+                // packed forward-FFT input: (x, y) of each row, z of row 0 + i z of row 1
+                T* zr = reinterpret_cast<T*>(Z);
+                Z[lp(rr * Px + x)] = cmk<C>(pi * yn.x, pi * yn.y);
+                zr[2 * lp(2 * Px + x) + rr] = pi * yn.z;
+                if (!v1) {
+                    Z[lp(Px + x)] = cmk<C>(0, 0);
+                    zr[2 * lp(2 * Px + x) + 1] = (T)0;
+                }
+            }
         }
     }
     if (a.port_part) {
@@ -768,14 +769,17 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
     const T cl = (a.stage == 1) ? dt / (T)6 : dt / (T)3;
     const T cm = (a.stage == 3) ? dt : dt / (T)2;
 
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-        T out[2][3] = {{0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
+    // work items are (row, x) pairs of the two rows, item = rr * nx + x
+    const int nitem = v1 ? 2 * nx : nx;
+    const int iy0 = r0 % p.ny, iz0 = r0 / p.ny;
+    for (int it = threadIdx.x; it < nitem; it += blockDim.x) {
+        {
+            const int rr = it >= nx ? 1 : 0;
+            const int x = it - rr * nx;
             const int r = r0 + rr;
-            if (rr == 1 && !v1) break;
             const int q = rr + 1;
-            const int iy = r % p.ny, iz = r / p.ny;
+            int iy = iy0 + rr, iz = iz0;
+            if (iy == p.ny) iy = 0, iz += 1;
             const int i = r * nx + x;
             const T pi = a.psi[i];
             V3<T> un = v3<T>(0, 0, 0);
@@ -862,14 +866,15 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                     }
                 }
             }
-            out[rr][0] = un.x;
-            out[rr][1] = un.y;
-            out[rr][2] = un.z;
-        }
-        if (a.do_fwd) {
-            Z[lp(x)] = cmk<C>(out[0][0], out[0][1]);
-            Z[lp(Px + x)] = cmk<C>(out[1][0], out[1][1]);
-            Z[lp(2 * Px + x)] = cmk<C>(out[0][2], out[1][2]);
+            if (a.do_fwd) {
+                T* zr = reinterpret_cast<T*>(Z);
+                Z[lp(rr * Px + x)] = cmk<C>(un.x, un.y);
+                zr[2 * lp(2 * Px + x) + rr] = un.z;
+                if (!v1) {
+                    Z[lp(Px + x)] = cmk<C>(0, 0);
+                    zr[2 * lp(2 * Px + x) + 1] = (T)0;
+                }
+            }
         }
     }
     if (a.do_fwd) {
@@ -1301,7 +1306,7 @@ static void stage_fwd_r(const BatchDev<T>& b, const FwdL& L, hipStream_t s, hipE
 }
 template <typename T, int MR>
 static void stage_bwd_r(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((k_stage_bwd<T, MR>), dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.loc_lds, s, e0, e1, 0,
+    hipExtLaunchKernelGGL((k_stage_bwd<T, MR>), dim3(b.nloc), dim3(b.bwd_threads), (uint32_t)b.bwd_lds, s, e0, e1, 0,
                           bargs(b, b.work_loc), L);
 }
 template <typename T, int NZ, int MR>
@@ -1333,9 +1338,9 @@ template <typename T>
 hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     BwdL Lm = L;
     Lm.stage_m = b.loc_nv >= 7;
-    if (b.loc_radix == 4)
+    if (b.bwd_radix == 4)
         stage_bwd_r<T, 4>(b, Lm, s, e0, e1);
-    else if (b.loc_radix == 8 || sizeof(T) == 8)
+    else if (b.bwd_radix == 8 || sizeof(T) == 8)
         stage_bwd_r<T, 8>(b, Lm, s, e0, e1);
     else
         stage_bwd_r<T, MaxReg<T>::v>(b, Lm, s, e0, e1);

@@ -240,12 +240,14 @@ int upload_tables(llg_handle* h, Instance& I) {
 // per-node arithmetic), only the tiling of the work over blocks changes
 // ---------------------------------------------------------------------------
 struct LaunchCfg {
-    int tk = 1;       // column-kernel tile: x-bins per block
+    int tk = 1;        // column-kernel tile: x-bins per block
     int col_thr = 64;
-    int loc_thr = 64;
-    int nv = 4;       // node values per staged row in the backward row kernel (4: u, psi; 7: also y_s)
-    int col_r = 16;   // largest FFT radix of the column kernel (4, 8, 16; 16 in float only)
-    int loc_r = 16;   // largest FFT radix of the row kernels
+    int col_r = 16;    // largest FFT radix of the column kernel (4, 8, 16; 16 in float only)
+    int fwd_thr = 64;  // forward row kernel
+    int fwd_r = 16;
+    int bwd_thr = 64;  // backward row kernel
+    int bwd_r = 16;
+    int nv = 4;        // node values per staged row in the backward row kernel (4: u, psi; 7: also y_s)
 };
 
 int maxreg_of(const llg_handle* h) { return h->dtype == LLG_F32 ? 16 : 8; }
@@ -291,18 +293,21 @@ bool col_fits(const llg_handle* h, int tk, int r) {
 }
 
 int check_cfg(const llg_handle* h, const LaunchCfg& c) {
-    if (!radix_ok(h, c.col_r) || !radix_ok(h, c.loc_r))
+    if (!radix_ok(h, c.col_r) || !radix_ok(h, c.fwd_r) || !radix_ok(h, c.bwd_r))
         return fail(LLG_EINVAL, "FFT radix must be 4, 8 or (float only) 16");
     if (c.tk != 1 && c.tk != 2 && c.tk != 4 && c.tk != 8 && c.tk != 16)
         return fail(LLG_EINVAL, "column tile must be 1, 2, 4, 8 or 16");
     if (!col_fits(h, c.tk, c.col_r)) return fail(LLG_ESHAPE, "column tile " + std::to_string(c.tk) + " does not fit");
-    const int cmin = col_min_threads(h, c.tk, c.col_r), lmin = loc_min_threads(h, c.loc_r);
+    const int cmin = col_min_threads(h, c.tk, c.col_r);
     const int cmax = col_max_threads(c.col_r);
     if (c.col_thr % 64 || c.col_thr < cmin || c.col_thr > cmax)
         return fail(LLG_EINVAL, "column threads must be a multiple of 64 in [" + std::to_string(cmin) + ", " +
                                     std::to_string(cmax) + "]");
-    if (c.loc_thr % 64 || c.loc_thr < lmin || c.loc_thr > 512)
-        return fail(LLG_EINVAL, "row threads must be a multiple of 64 in [" + std::to_string(lmin) + ", 512]");
+    for (auto tr : {std::make_pair(c.fwd_thr, c.fwd_r), std::make_pair(c.bwd_thr, c.bwd_r)}) {
+        const int lmin = loc_min_threads(h, tr.second);
+        if (tr.first % 64 || tr.first < lmin || tr.first > 512)
+            return fail(LLG_EINVAL, "row threads must be a multiple of 64 in [" + std::to_string(lmin) + ", 512]");
+    }
     if (c.nv != 4 && c.nv != 7) return fail(LLG_EINVAL, "staged row values must be 4 or 7");
     if (loc_lds_bytes(h, c.nv) > 163840) return fail(LLG_ESHAPE, "staged rows do not fit 160 KiB of LDS");
     return LLG_OK;
@@ -333,10 +338,10 @@ int default_cfg(const llg_handle* h, LaunchCfg& c) {
         ct = std::max(ct, std::min(col_max_threads(cr), round_up(std::min(I.Py * tk, 256), 64)));
     c.tk = tk;
     c.col_thr = ct;
-    c.loc_thr = lt;
-    c.nv = 4;
     c.col_r = cr;
-    c.loc_r = r;
+    c.fwd_thr = c.bwd_thr = lt;
+    c.fwd_r = c.bwd_r = r;
+    c.nv = 4;
     return LLG_OK;
 }
 
@@ -348,21 +353,24 @@ int apply_cfg(llg_handle* h, const LaunchCfg& c) {
     HIPCHK(hipMemcpy(h->work_col, wc.data(), wc.size() * sizeof(int2), hipMemcpyHostToDevice));
     size_t col_lds = 0;
     for (auto& I : h->inst) col_lds = std::max(col_lds, col_lds_bytes(h, I, c.tk));
-    const size_t loc_lds = loc_lds_bytes(h, c.nv);
+    const size_t loc_lds = loc_lds_bytes(h, 4), bwd_lds = loc_lds_bytes(h, c.nv);
     auto fill = [&](auto& b) {
         b.ncol = (int)wc.size();
-        b.loc_threads = c.loc_thr;
-        b.col_threads = c.col_thr;
         b.col_tk = c.tk;
-        b.loc_nv = c.nv;
+        b.col_threads = c.col_thr;
         b.col_radix = c.col_r;
-        b.loc_radix = c.loc_r;
+        b.loc_threads = c.fwd_thr;
+        b.loc_radix = c.fwd_r;
+        b.bwd_threads = c.bwd_thr;
+        b.bwd_radix = c.bwd_r;
+        b.loc_nv = c.nv;
         b.loc_lds = loc_lds;
+        b.bwd_lds = bwd_lds;
         b.col_lds = col_lds;
     };
     fill(h->bf);
     fill(h->bd);
-    const size_t need = std::max(loc_lds, col_lds);
+    const size_t need = std::max(std::max(loc_lds, bwd_lds), col_lds);
     if (need > 65536) {
         hipError_t e = h->dtype == LLG_F32 ? set_lds_limits<float>(need) : set_lds_limits<double>(need);
         if (e != hipSuccess) {
@@ -940,9 +948,10 @@ int autotune_typed(llg_handle* h, hipStream_t s, LaunchCfg& best) {
             if (rc) break;
         }
     }
-    if (!rc) {
+    // row kernels: forward (radix, threads), then backward (radix, threads, staged values)
+    for (int pass = 0; pass < 2 && !rc; ++pass) {
         float tbest = 1e30f;
-        LaunchCfg base = best;
+        const LaunchCfg base = best;
         for (int lr : {4, 8, 16}) {
             if (!radix_ok(h, lr)) continue;
             const int lmin = loc_min_threads(h, lr);
@@ -952,16 +961,19 @@ int autotune_typed(llg_handle* h, hipStream_t s, LaunchCfg& best) {
                 if (lt > lmin) cand.push_back(lt);
             for (int lt : cand) {
                 for (int nv : {4, 7}) {
+                    if (pass == 0 && nv == 7) continue;
                     if (loc_lds_bytes(h, nv) > 163840) continue;
                     LaunchCfg c = base;
-                    c.loc_thr = lt;
-                    c.nv = nv;
-                    c.loc_r = lr;
+                    if (pass == 0) {
+                        c.fwd_thr = lt;
+                        c.fwd_r = lr;
+                    } else {
+                        c.bwd_thr = lt;
+                        c.bwd_r = lr;
+                        c.nv = nv;
+                    }
                     if ((rc = apply_cfg(h, c))) break;
-                    const float ms = timed([&] {
-                        if (int r = o.fwd(Lf)) return r;
-                        return o.bwd(Lb);
-                    });
+                    const float ms = timed([&] { return pass == 0 ? o.fwd(Lf) : o.bwd(Lb); });
                     if (rc) break;
                     if (ms < tbest) tbest = ms, best = c;
                 }
@@ -1336,26 +1348,30 @@ int llg_batch_size(const llg_batch* b, int32_t* n) {
     return LLG_OK;
 }
 
-int llg_launch_config(const llg_handle* h, int32_t cfg[6]) {
+int llg_launch_config(const llg_handle* h, int32_t cfg[8]) {
     if (!h || !cfg) return fail(LLG_EINVAL, "NULL argument");
     cfg[0] = h->bf.col_tk;
     cfg[1] = h->bf.col_threads;
-    cfg[2] = h->bf.loc_threads;
-    cfg[3] = h->bf.loc_nv;
-    cfg[4] = h->bf.col_radix;
-    cfg[5] = h->bf.loc_radix;
+    cfg[2] = h->bf.col_radix;
+    cfg[3] = h->bf.loc_threads;
+    cfg[4] = h->bf.loc_radix;
+    cfg[5] = h->bf.bwd_threads;
+    cfg[6] = h->bf.bwd_radix;
+    cfg[7] = h->bf.loc_nv;
     return LLG_OK;
 }
 
-int llg_set_launch_config(llg_handle* h, const int32_t cfg[6]) {
+int llg_set_launch_config(llg_handle* h, const int32_t cfg[8]) {
     if (!h || !cfg) return fail(LLG_EINVAL, "NULL argument");
     LaunchCfg c;
     c.tk = cfg[0];
     c.col_thr = cfg[1];
-    c.loc_thr = cfg[2];
-    c.nv = cfg[3];
-    c.col_r = cfg[4];
-    c.loc_r = cfg[5];
+    c.col_r = cfg[2];
+    c.fwd_thr = cfg[3];
+    c.fwd_r = cfg[4];
+    c.bwd_thr = cfg[5];
+    c.bwd_r = cfg[6];
+    c.nv = cfg[7];
     if (int rc = check_cfg(h, c)) return rc;
     HIPCHK(hipDeviceSynchronize());
     drop_graphs(h);

@@ -222,15 +222,15 @@ class Solver:
         check(lib().llg_set_graphs(self.h, int(enable)))
 
     def launch_config(self):
-        """(column tile, column threads, row threads, staged values per row in the
-        backward kernel, column FFT radix, row FFT radix)."""
-        c = (ctypes.c_int32 * 6)()
+        """(column tile, column threads, column radix, forward row threads, forward radix,
+        backward row threads, backward radix, staged values per row in the backward kernel)."""
+        c = (ctypes.c_int32 * 8)()
         check(lib().llg_launch_config(self.h, c))
         return tuple(c)
 
-    def set_launch_config(self, tk, col_threads, row_threads, nv=4, col_radix=None, row_radix=None):
-        cur = self.launch_config()
-        c = (ctypes.c_int32 * 6)(tk, col_threads, row_threads, nv, col_radix or cur[4], row_radix or cur[5])
+    def set_launch_config(self, *cfg):
+        """Eight values in the order of launch_config()."""
+        c = (ctypes.c_int32 * 8)(*cfg)
         check(lib().llg_set_launch_config(self.h, c))
 
     def autotune(self):
@@ -364,15 +364,15 @@ class Batch:
         check(lib().llg_set_graphs(self.h, int(enable)))
 
     def launch_config(self):
-        """(column tile, column threads, row threads, staged values per row in the
-        backward kernel, column FFT radix, row FFT radix)."""
-        c = (ctypes.c_int32 * 6)()
+        """(column tile, column threads, column radix, forward row threads, forward radix,
+        backward row threads, backward radix, staged values per row in the backward kernel)."""
+        c = (ctypes.c_int32 * 8)()
         check(lib().llg_launch_config(self.h, c))
         return tuple(c)
 
-    def set_launch_config(self, tk, col_threads, row_threads, nv=4, col_radix=None, row_radix=None):
-        cur = self.launch_config()
-        c = (ctypes.c_int32 * 6)(tk, col_threads, row_threads, nv, col_radix or cur[4], row_radix or cur[5])
+    def set_launch_config(self, *cfg):
+        """Eight values in the order of launch_config()."""
+        c = (ctypes.c_int32 * 8)(*cfg)
         check(lib().llg_set_launch_config(self.h, c))
 
     def autotune(self):

@@ -26,38 +26,36 @@ def test_launch_configs_bitwise(dtype):
     s = gpu_solver(w, dtype, max_steps=12)
     base = s.launch_config()
     say("default launch config", base, dtype)
+    cr, fr, br = base[2], base[4], base[6]
     ref = gpu_gradient(w, dtype, solver=s)
     tried = 0
     for tk in (1, 2, 4, 8, 16):
         for ct in (64, 128, 256):
-            for lt, nv in ((64, 4), (128, 7), (256, 4), (256, 7)):
+            for ft, bt, nv in ((64, 128, 4), (128, 64, 7), (256, 256, 4), (192, 320, 7)):
+                cfg = (tk, ct, cr, ft, fr, bt, br, nv)
                 try:
-                    s.set_launch_config(tk, ct, lt, nv)
+                    s.set_launch_config(*cfg)
                 except llg.LLGError:
                     continue
-                assert s.launch_config()[:4] == (tk, ct, lt, nv)
+                assert s.launch_config() == cfg
                 _same(gpu_gradient(w, dtype, solver=s), ref)
                 tried += 1
     assert tried >= 10
     # other radices: the same values up to the rounding of the transforms
     tol = 1e-12 if dtype == "f64" else 2e-5
-    for cr, lr in ((4, 4), (8, 4), (4, 8)):
-        s.set_launch_config(1, 256, 256, 4, cr, lr)
+    for rc, rf, rb in ((4, 4, 4), (8, 4, 8), (4, 8, 4)):
+        s.set_launch_config(1, 256, rc, 256, rf, 256, rb, 4)
         g = gpu_gradient(w, dtype, solver=s)
         assert abs(g["J"] - ref["J"]) <= tol * abs(ref["J"])
         assert np.abs(g["mT"] - ref["mT"]).max() <= tol
         assert np.linalg.norm(g["dpsi"] - ref["dpsi"]) <= 50 * tol * np.linalg.norm(ref["dpsi"])
+    bad = [(3, 128, cr, 128, fr, 128, br, 4), (1, 100, cr, 128, fr, 128, br, 4), (1, 128, cr, 1024, fr, 128, br, 4),
+           (1, 128, cr, 128, fr, 128, br, 5), (1, 128, 2, 128, fr, 128, br, 4)]
     if dtype == "f64":
+        bad.append((1, 256, 16, 256, 8, 256, 8, 4))
+    for cfg in bad:
         with pytest.raises(llg.LLGError):
-            s.set_launch_config(1, 256, 256, 4, 16, 8)
-    with pytest.raises(llg.LLGError):
-        s.set_launch_config(3, 128, 128)
-    with pytest.raises(llg.LLGError):
-        s.set_launch_config(1, 100, 128)
-    with pytest.raises(llg.LLGError):
-        s.set_launch_config(1, 128, 1024)
-    with pytest.raises(llg.LLGError):
-        s.set_launch_config(1, 128, 128, 5)
+            s.set_launch_config(*cfg)
     s.close()
 
 
@@ -72,8 +70,8 @@ def test_autotune_keeps_results():
                   masks=[dict(antenna=w.antenna, port1=w.port1, port2=w.port2, design=w.design) for w in ws])
     cfg = b.autotune()
     say("autotuned", cfg)
-    assert cfg[0] in (1, 2, 4, 8, 16) and cfg[1] % 64 == 0 and cfg[2] % 64 == 0 and cfg[3] in (4, 7)
-    assert cfg[4] in (4, 8, 16) and cfg[5] in (4, 8, 16)
+    assert cfg[0] in (1, 2, 4, 8, 16) and cfg[1] % 64 == 0 and cfg[3] % 64 == 0 and cfg[5] % 64 == 0
+    assert cfg[2] in (4, 8, 16) and cfg[4] in (4, 8, 16) and cfg[6] in (4, 8, 16) and cfg[7] in (4, 7)
     b.close()
     out = run_batch(ws, "f32", n, tune=True)
     for i in range(len(ws)):

@@ -576,11 +576,17 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     // their latency overlaps the staging and the inverse FFT.
     const int nitem = v1 ? 2 * nx : nx;
     V3<T> pre_acc = v3<T>(0, 0, 0), pre_mn = v3<T>(0, 0, 0);
+    uint8_t pre_ant = 0, pre_p1 = 0, pre_p2 = 0;
     const bool need_acc = a.stage >= 1 && a.stage <= 3, need_mn = a.stage == 1 || a.stage == 2;
     if ((int)threadIdx.x < nitem) {
         const int i = r0 * nx + threadIdx.x;  // rows r0, r0+1 are contiguous
         if (need_acc) pre_acc = ld3(a.acc, N, i);
         if (need_mn) pre_mn = ld3(a.mn, N, i);
+        if (a.antenna) pre_ant = a.antenna[i];
+        if (a.port_part) {
+            pre_p1 = a.port1[i];
+            pre_p2 = a.port2[i];
+        }
     }
     {
         const T* const src[NV] = {a.ys, a.ys, a.ys, a.psi};
@@ -633,7 +639,8 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             }
             if (p.terms & 4) {
                 B = B + v3<T>(p.B0[0], p.B0[1], p.B0[2]);
-                if (a.antenna && a.antenna[i]) B = B + drv * v3<T>(p.brf[0], p.brf[1], p.brf[2]);
+                const bool ant = a.antenna && (it == (int)threadIdx.x ? pre_ant : a.antenna[i]);
+                if (ant) B = B + drv * v3<T>(p.brf[0], p.brf[1], p.brf[2]);
             }
             if (p.terms & 8) {
                 const V3<T> u = v3<T>(p.u[0], p.u[1], p.u[2]);
@@ -671,8 +678,9 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             if (a.ynext) st3(a.ynext, N, i, yn);
             if (a.port_part) {
                 const double my2 = (double)yn.y * (double)yn.y;
-                if (a.port1[i]) s1 += my2;
-                if (a.port2[i]) s2 += my2;
+                const bool first_it = it == (int)threadIdx.x;
+                if (first_it ? pre_p1 : a.port1[i]) s1 += my2;
+                if (first_it ? pre_p2 : a.port2[i]) s2 += my2;
             }
             if (a.do_fwd) {
                 // packed forward-FFT input: (x, y) of each row, z of row 0 + i z of row 1
@@ -734,6 +742,41 @@ __device__ __forceinline__ V3<T> field_adjoint(const KParams<T>& p, V3<T> ell, V
     return (-gp) * (w + al * cross(w, m));
 }
 
+// Per-node inputs of a backward stage, loaded together so that one memory
+// latency covers them all.
+template <typename T>
+struct BwdIn {
+    T pi;
+    V3<T> m, B, v, uk, lam, lacc, yprev;
+    double g0;
+    uint8_t p1, p2;
+};
+
+template <typename T>
+__device__ __forceinline__ BwdIn<T> load_bwd(const StageBwdArgs<T>& a, int N, int i, bool seed) {
+    BwdIn<T> d;
+    const V3<T> z = v3<T>(0, 0, 0);
+    d.m = d.B = d.v = d.uk = d.lacc = d.yprev = z;
+    d.g0 = 0.0;
+    d.p1 = d.p2 = 0;
+    d.pi = a.psi[i];
+    d.lam = ld3(a.lamp, N, i);
+    if (!seed) {
+        d.m = ld3(a.ys, N, i);
+        d.B = ld3(a.Bs, N, i);
+        d.v = ld3(a.ell, N, i);
+        d.uk = ld3(a.u_cur, N, i);
+        d.g0 = a.gpsi[i];
+        if (a.stage < 3) d.lacc = ld3(a.lacc_in, N, i);
+        if (a.stage == 0 && a.port1) {
+            d.p1 = a.port1[i];
+            d.p2 = a.port2[i];
+        }
+    }
+    if (a.y_prev) d.yprev = ld3(a.y_prev, N, i);
+    return d;
+}
+
 template <typename T, int MR>
 __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const BwdL L) {
     using C = cplx<T>;
@@ -754,6 +797,13 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
     const int r0 = 2 * wk.y;
     const bool v1 = r0 + 1 < p.nrows;
     const SigMap sm{0, Px, 0, 1};
+    // work items are (row, x) pairs of the two rows, item = rr * nx + x; the
+    // inputs of this thread's first item are requested before the staging
+    // (in float; the float64 inputs would not fit the registers across the FFT)
+    const int nitem = v1 ? 2 * nx : nx;
+    constexpr bool kPre = sizeof(T) == 4;
+    BwdIn<T> pre;
+    if (kPre && (int)threadIdx.x < nitem) pre = load_bwd(a, N, r0 * nx + threadIdx.x, seed);
 
     {
         const T* const src[NV] = {a.u_cur, a.u_cur, a.u_cur, a.psi, a.ys, a.ys, a.ys};
@@ -769,8 +819,6 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
     const T cl = (a.stage == 1) ? dt / (T)6 : dt / (T)3;
     const T cm = (a.stage == 3) ? dt : dt / (T)2;
 
-    // work items are (row, x) pairs of the two rows, item = rr * nx + x
-    const int nitem = v1 ? 2 * nx : nx;
     const int iy0 = r0 % p.ny, iz0 = r0 / p.ny;
     for (int it = threadIdx.x; it < nitem; it += blockDim.x) {
         {
@@ -781,19 +829,19 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
             int iy = iy0 + rr, iz = iz0;
             if (iy == p.ny) iy = 0, iz += 1;
             const int i = r * nx + x;
-            const T pi = a.psi[i];
+            const BwdIn<T> d = (kPre && it == (int)threadIdx.x) ? pre : load_bwd(a, N, i, seed);
+            const T pi = d.pi;
             V3<T> un = v3<T>(0, 0, 0);
             if (seed) {
-                const V3<T> lam = ld3(a.lamp, N, i);
-                const V3<T> ell = (dt / (T)6) * lam;
+                const V3<T> ell = (dt / (T)6) * d.lam;
                 st3(a.ell, N, i, ell);
-                un = field_adjoint(p, ell, ld3(a.y_prev, N, i), x, iy, iz, pi);
+                un = field_adjoint(p, ell, d.yprev, x, iy, iz, pi);
                 st3(a.u_next, N, i, un);
             } else {
-                const V3<T> m = ld3(a.ys, N, i);
-                const V3<T> B = ld3(a.Bs, N, i);
-                const V3<T> v = ld3(a.ell, N, i);
-                const V3<T> uk = ld3(a.u_cur, N, i);
+                const V3<T> m = d.m;
+                const V3<T> B = d.B;
+                const V3<T> v = d.v;
+                const V3<T> uk = d.uk;
                 V3<T> mu = v3<T>(0, 0, 0);
                 if (pi != (T)0) {
                     const T al = node_alpha(p, x, iy, iz);
@@ -842,26 +890,26 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                     const V3<T> ua = v3<T>(p.u[0], p.u[1], p.u[2]);
                     mu = mu + (p.anis * dot(uk, ua)) * ua;
                 }
-                a.gpsi[i] += g;
-                const V3<T> lsum = (a.stage == 3 ? ld3(a.lamp, N, i) : ld3(a.lacc_in, N, i)) + mu;
+                a.gpsi[i] = d.g0 + g;
+                const V3<T> lsum = (a.stage == 3 ? d.lam : d.lacc) + mu;
                 if (a.stage > 0) {
                     st3(a.lacc_out, N, i, lsum);
-                    const V3<T> ell = cl * ld3(a.lamp, N, i) + cm * mu;
+                    const V3<T> ell = cl * d.lam + cm * mu;
                     st3(a.ell, N, i, ell);
-                    un = field_adjoint(p, ell, ld3(a.y_prev, N, i), x, iy, iz, pi);
+                    un = field_adjoint(p, ell, d.yprev, x, iy, iz, pi);
                     st3(a.u_next, N, i, un);
                 } else {
                     V3<T> lam = lsum;
                     if (a.port1) {
                         // running-cost source dJ/dm_n of the port objective (y component)
-                        const T src = (a.port1[i] ? a.src1 : (T)0) - (a.port2[i] ? a.src2 : (T)0);
+                        const T src = (d.p1 ? a.src1 : (T)0) - (d.p2 ? a.src2 : (T)0);
                         lam.y = lam.y + src * m.y;
                     }
                     st3(a.lacc_out, N, i, lam);
                     if (a.y_prev) {
                         const V3<T> ell = (dt / (T)6) * lam;
                         st3(a.ell, N, i, ell);
-                        un = field_adjoint(p, ell, ld3(a.y_prev, N, i), x, iy, iz, pi);
+                        un = field_adjoint(p, ell, d.yprev, x, iy, iz, pi);
                         st3(a.u_next, N, i, un);
                     }
                 }

@@ -178,6 +178,7 @@ struct BatchDev {
     int nloc, ncol, ninst;
     int max_n3;            // max 3N over instances (grid of element-wise kernels)
     int col_tk, col_threads, col_radix;  // column kernel: x-bins per block, block size, largest FFT radix
+    int col_nt_lds;                      // column kernel stages its tensor-spectrum tile in LDS
     int loc_threads, loc_radix;          // forward row kernel (and the energy kernel's block size)
     int bwd_threads, bwd_radix;          // backward row kernel
     int loc_nv;                          // node values per staged row in the backward row kernel (4 or 7)

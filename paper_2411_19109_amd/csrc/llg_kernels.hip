@@ -945,7 +945,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
 // Radix-16 passes need more than the 128 registers a 1024-thread block allows,
 // so that variant is limited to 512 threads.
 template <typename T, int NZ, int MR>
-__global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchArgs<T> ba, int TK, int sid) {
+__global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchArgs<T> ba, int TK, int sid, int nt_lds) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
@@ -967,7 +967,8 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchA
     // cz = c * nz + z, so the row of S is cz * ny + y (c * cs = c * nz * ny * Kx)
     const int ltk = ilog2_rt(TK), lpy = ilog2_rt(Py);
     const int ncolel = 3 * nz * Py * TK;
-    const int ntile = p.ncomp * p.Kz2 * p.Ky2 * TK;
+    // the tensor-spectrum tile is staged in LDS when it fits, else read from global memory
+    const int ntile = nt_lds ? p.ncomp * p.Kz2 * p.Ky2 * TK : 0;
     auto lcol = [&](int e) {
         const int tk = e & (TK - 1);
         const int t = e >> ltk;
@@ -1021,12 +1022,14 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchA
             const bool fz = kz > Pz / 2;
             const int kzr = fz ? Pz - kz : kz;
             const int base = (kzr * p.Ky2 + kyr) * TK + tk;
-            const T nxx = Nt[base], nyy = Nt[cstr + base], nzz = Nt[2 * cstr + base];
-            const T nxy = fy ? -Nt[3 * cstr + base] : Nt[3 * cstr + base];
+            const size_t gbase = (size_t)(kzr * p.Ky2 + kyr) * Kx + kx, gstr = (size_t)p.Kz2 * p.Ky2 * Kx;
+            auto NT = [&](int comp) -> T { return nt_lds ? Nt[comp * cstr + base] : nhat[comp * gstr + gbase]; };
+            const T nxx = NT(0), nyy = NT(1), nzz = NT(2);
+            const T nxy = fy ? -NT(3) : NT(3);
             T nxz = 0, nyz = 0;
             if (p.ncomp == 6) {
-                nxz = fz ? -Nt[4 * cstr + base] : Nt[4 * cstr + base];
-                nyz = Nt[5 * cstr + base];
+                nxz = fz ? -NT(4) : NT(4);
+                nyz = NT(5);
                 if (fy != fz) nyz = -nyz;
             }
             const C hx = cmk<C>(nxx * h[0].x + nxy * h[1].x + nxz * h[2].x, nxx * h[0].y + nxy * h[1].y + nxz * h[2].y);
@@ -1360,7 +1363,7 @@ static void stage_bwd_r(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipE
 template <typename T, int NZ, int MR>
 static void col_r(const BatchDev<T>& b, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     hipExtLaunchKernelGGL((k_col_conv<T, NZ, MR>), dim3(b.ncol), dim3(b.col_threads), (uint32_t)b.col_lds, s, e0, e1, 0,
-                          bargs(b, b.work_col), b.col_tk, spec);
+                          bargs(b, b.work_col), b.col_tk, spec, b.col_nt_lds);
 }
 template <typename T, int NZ>
 static void col_nz(const BatchDev<T>& b, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {

@@ -270,11 +270,23 @@ size_t loc_lds_bytes(const llg_handle* h, int nv) {
 }
 
 
-size_t col_lds_bytes(const llg_handle* h, const Instance& I, int tk) {
+// column-kernel LDS: padded columns, twiddles, and (nt = true) the tensor-spectrum tile
+size_t col_lds_bytes(const llg_handle* h, const Instance& I, int tk, bool nt) {
     const size_t csz = 2 * h->tsz;
     const int Ky2 = I.Py / 2 + 1, Kz2 = I.Pz / 2 + 1;
     return (size_t)lds_pad(3 * I.prob.nz * I.Py * tk) * csz + (size_t)I.Py * csz +
-           (size_t)I.ncomp * Kz2 * Ky2 * tk * h->tsz;
+           (nt ? (size_t)I.ncomp * Kz2 * Ky2 * tk * h->tsz : 0);
+}
+
+// the tile is staged when every instance's column block then still fits
+bool col_nt_lds(const llg_handle* h, int tk) {
+    for (auto& I : h->inst)
+        if (col_lds_bytes(h, I, tk, true) > 163840) return false;
+    return true;
+}
+
+size_t col_lds_bytes(const llg_handle* h, const Instance& I, int tk) {
+    return col_lds_bytes(h, I, tk, col_nt_lds(h, tk));
 }
 
 int col_min_threads(const llg_handle* h, int tk, int r) {
@@ -370,6 +382,7 @@ int apply_cfg(llg_handle* h, const LaunchCfg& c) {
     };
     fill(h->bf);
     fill(h->bd);
+    h->bf.col_nt_lds = h->bd.col_nt_lds = col_nt_lds(h, c.tk) ? 1 : 0;
     const size_t need = std::max(std::max(loc_lds, bwd_lds), col_lds);
     if (need > 65536) {
         hipError_t e = h->dtype == LLG_F32 ? set_lds_limits<float>(need) : set_lds_limits<double>(need);

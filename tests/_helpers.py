@@ -52,10 +52,14 @@ def oracle_sim(w):
     return omm.Sim(w.problem, antenna=w.antenna)
 
 
-def gpu_solver(w, dtype=None, max_steps=None, **kw):
+def gpu_solver(w, dtype=None, max_steps=None, tune=False, **kw):
+    """A handle for the workload; tune=True runs the autotuner (the benchmark's setup)."""
     from paper_2411_19109_amd import llg
-    return llg.Solver(w.problem, dtype=dtype or w.dtype, max_steps=max_steps or w.n_steps, antenna=w.antenna,
-                      port1=w.port1, port2=w.port2, design=w.design, **kw)
+    s = llg.Solver(w.problem, dtype=dtype or w.dtype, max_steps=max_steps or w.n_steps, antenna=w.antenna,
+                   port1=w.port1, port2=w.port2, design=w.design, **kw)
+    if tune:
+        say("autotuned launch", s.autotune())
+    return s
 
 
 def gpu_objective(w, kind=None):

@@ -1,5 +1,6 @@
-"""Parity at the workloads' full sizes, in the launch configuration the
-benchmark times (one handle per workload, sqrt(N) checkpoints)."""
+"""Parity at the workloads' full sizes (one handle per workload, sqrt(N)
+checkpoints); the FP32 particle gradient runs in the autotuned launch
+configuration the benchmark times."""
 import numpy as np
 import pytest
 
@@ -38,8 +39,8 @@ def test_particle_forward_fp32_2000_steps():
 
 def test_particle_gradient_fp32_vs_oracle():
     w, r = particle_oracle()
-    say("permalloy particle 64x64 fp32 gradient, 2000 steps")
-    g = gpu_gradient(w, "f32")
+    say("permalloy particle 64x64 fp32 gradient, 2000 steps, autotuned launch")
+    g = gpu_gradient(w, "f32", solver=gpu_solver(w, "f32", tune=True))
     e = rel_l2(g["dphi"], r["dphi"])
     say("dJ/dphi rel L2 =", e, "J gpu/oracle", g["J"], r["J"])
     assert abs(g["J"] - r["J"]) <= 1e-4 * abs(r["J"])

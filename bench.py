@@ -44,7 +44,7 @@ def make_workload(name):
 class GradientStep:
     """Device-resident inputs and one gradient evaluation through the C ABI."""
 
-    def __init__(self, w, graphs=True, tune=True):
+    def __init__(self, w, graphs=True, tune=True, launch_file=None):
         import torch
         from paper_2411_19109_amd import llg, workloads as wl
         self.w = w
@@ -53,7 +53,15 @@ class GradientStep:
         self.solver = llg.Solver(w.problem, dtype=w.dtype, max_steps=w.n_steps, antenna=w.antenna, port1=w.port1,
                                  port2=w.port2, design=w.design)
         self.solver.set_graphs(graphs)
-        self.launch = self.solver.autotune() if tune else self.solver.launch_config()
+        if launch_file and os.path.exists(launch_file):
+            # a launch configuration fixed by an earlier run (profiling runs reuse it)
+            self.solver.set_launch_config(*[int(v) for v in open(launch_file).read().split()])
+            self.launch = self.solver.launch_config()
+        else:
+            self.launch = self.solver.autotune() if tune else self.solver.launch_config()
+            if launch_file:
+                with open(launch_file, "w") as fh:
+                    fh.write(" ".join(str(v) for v in self.launch) + "\n")
         self.phi = torch.as_tensor(w.phi.reshape(-1), dtype=self.td, device=dev).contiguous()
         self.psi_fixed = torch.as_tensor(w.psi_fixed.reshape(-1), dtype=self.td, device=dev).contiguous()
         self.m0 = torch.as_tensor(w.m0.reshape(-1), dtype=self.td, device=dev).contiguous()
@@ -155,6 +163,8 @@ def main():
                     help="override the workload's RK4 step count (short profiling runs; not a bench line)")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay forward/adjoint as captured HIP graphs")
     ap.add_argument("--autotune", type=int, default=1, help="1: pick launch tiles with the library's autotuner at setup")
+    ap.add_argument("--launch-file", default=None,
+                    help="read the launch configuration from this file if it exists, else write the chosen one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -179,7 +189,7 @@ def main():
     if args.n_steps > 0:
         w.n_steps = args.n_steps
         w.obj_n_start = min(w.obj_n_start, args.n_steps // 2)
-    step = GradientStep(w, bool(args.graphs), bool(args.autotune))
+    step = GradientStep(w, bool(args.graphs), bool(args.autotune), args.launch_file)
     print(f"[bench] workload {w.name}: {w.problem.nx}x{w.problem.ny}x{w.problem.nz} nodes, {w.n_steps} steps, "
           f"{w.dtype}, launch {step.launch}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -209,8 +219,8 @@ def main():
     dom = max(kinds, key=lambda k: kinds[k]["ms"])
     d = kinds[dom]
     roofline = dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(d["gbs"] / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
-                    avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"]))
+                    frac=round(d["gbs"] / HBM_PEAK_GBS, 5), traffic=measured_traffic(w.name, dom, step.launch),
+                    kernel=dom, avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"]))
     for name, v in kinds.items():
         print(f"[bench] {name}: {v['launches']} launches, avg {v['avg_us']:.2f} us, "
               f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
@@ -242,6 +252,28 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(workload, kernel, launch):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this workload (copy-calibrated), or None when there is
+    none or it was taken on another kernel source or launch configuration."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    from paper_2411_19109_amd import profsum
+    rec = None
+    for line in open(path):
+        if line.startswith("{"):
+            rec = json.loads(line)
+    if not rec or rec.get("kernel_source_sha256") != profsum.kernel_source_hash():
+        return None
+    if rec.get("launch") is not None and list(rec["launch"]) != list(launch):
+        return None
+    for name, v in rec["kernels"].items():
+        if name.split("<")[0] == kernel:
+            return round(v["hbm_bytes"])
+    return None
 
 
 def _kernel_stats(solver):

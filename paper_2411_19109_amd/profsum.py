@@ -2,6 +2,7 @@
 
     python -m paper_2411_19109_amd.profsum stats DIR   # --kernel-trace --stats run
     python -m paper_2411_19109_amd.profsum pmc DIR     # --pmc COUNTER run
+    python -m paper_2411_19109_amd.profsum traffic FETCH_DIR WRITE_DIR [LAUNCH_FILE]  # HBM bytes per dispatch
 
 ``stats`` prints, per kernel, the call count and the average / total device
 time from the *_kernel_stats.csv file.  ``pmc`` prints, per kernel, the number
@@ -48,6 +49,49 @@ def pmc(d: str) -> str:
     return "\n".join(out)
 
 
+def _per_kernel(d: str, counter: str):
+    f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+    agg = collections.defaultdict(list)
+    with open(f) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                agg[_short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return agg
+
+
+def kernel_source_hash() -> str:
+    """sha256 of the kernel source the counters belong to."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "llg_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()
+
+
+def traffic(fetch_dir: str, write_dir: str, launch=None, copy_bytes: int = 1 << 28) -> str:
+    """HBM bytes per dispatch of the solver kernels from a FETCH_SIZE run and a
+    WRITE_SIZE run (KiB per dispatch), each scaled by the factor that maps the
+    same counter on a plain device copy of copy_bytes (the largest copy
+    dispatch of the run) to its true size.  One JSON line."""
+    import json
+    fe, wr = _per_kernel(fetch_dir, "FETCH_SIZE"), _per_kernel(write_dir, "WRITE_SIZE")
+    cal = "__amd_rocclr_copyBuffer"
+    kf = copy_bytes / (max(fe[cal]) * 1024.0)
+    kw = copy_bytes / (max(wr[cal]) * 1024.0)
+    out = {"kernel_source_sha256": kernel_source_hash(), "launch": launch, "copy_bytes": copy_bytes,
+           "fetch_scale": kf, "write_scale": kw, "kernels": {}}
+    for k in sorted(set(fe) & set(wr)):
+        if not k.startswith("k_"):
+            continue
+        f = sum(fe[k]) / len(fe[k]) * 1024.0 * kf
+        w = sum(wr[k]) / len(wr[k]) * 1024.0 * kw
+        out["kernels"][k] = {"dispatches": len(fe[k]), "fetch_bytes": f, "write_bytes": w, "hbm_bytes": f + w}
+    return json.dumps(out)
+
+
 if __name__ == "__main__":
-    mode, d = sys.argv[1], sys.argv[2]
-    print(stats(d) if mode == "stats" else pmc(d))
+    mode = sys.argv[1]
+    if mode == "traffic":
+        launch = [int(v) for v in open(sys.argv[4]).read().split()] if len(sys.argv) > 4 else None
+        print(traffic(sys.argv[2], sys.argv[3], launch))
+    else:
+        d = sys.argv[2]
+        print(stats(d) if mode == "stats" else pmc(d))

@@ -20,6 +20,14 @@ constexpr double kMu0 = 4e-7 * 3.14159265358979323846;
 // Stored size of an LDS array of n complex values padded by one element per 16.
 __host__ __device__ inline int lds_pad(int n) { return n + (n >> 4) + 1; }
 
+// Spectra are stored in x-bin tiles of 128 bytes (16 float or 8 double
+// complex bins): S[((c * ktiles + t) * nrows + row) * TW + o] for bin kx =
+// t * TW + o, and the real tensor spectrum nhat[(t * NR + q) * TW + o] with
+// q = (comp * Kz2 + kz) * Ky2 + ky, NR = ncomp * Kz2 * Ky2.  A column tile then
+// reads whole 128-byte lines, and a row reads or writes one line per tile.
+template <typename T> constexpr int spec_tile() { return 128 / (2 * (int)sizeof(T)); }
+inline int spec_tile_of(int tsz) { return 128 / (2 * tsz); }
+
 template <typename T> struct Cx;
 template <> struct Cx<float> { using type = float2; };
 template <> struct Cx<double> { using type = double2; };
@@ -38,12 +46,12 @@ enum BufId : int {
     B_ACC,      // RK accumulator (3N)
     B_YA,       // stage state (3N)
     B_YB,       // stage state (3N)
-    B_S,        // x-spectrum rows (3 * nrows * Kx complex)
+    B_S,        // x-spectrum (3 * ktiles * nrows * TW complex, tiled in x)
     B_S2,       // second x-spectrum (segment recomputation on the second stream)
     B_TWX,      // twiddles (Px), (Py), (Pz)
     B_TWY,
     B_TWZ,
-    B_NHAT,     // tensor spectrum
+    B_NHAT,     // tensor spectrum (ktiles * ncomp * Kz2 * Ky2 * TW real, tiled in x)
     B_SNAP,     // checkpoint snapshots (nsnap * 3N)
     B_YS,       // stage states of recomputed steps (slots * 4 * 3N)
     B_BS,       // fields of those stage states (slots * 4 * 3N)
@@ -71,6 +79,7 @@ template <typename T>
 struct KParams {
     int nx, ny, nz, N, nrows;      // nodes; rows = ny*nz lines along x
     int Px, Kx, Py, Pz, Ky2, Kz2;  // padded FFT sizes; Kx = Px/2+1; Ky2 = Py/2+1; Kz2 = Pz/2+1
+    int ktiles;                    // x-bin tiles of the stored spectra, ceil(Kx / TW)
     int ncomp;                     // stored tensor-spectrum components (4 in 2D, 6 in 3D)
     int terms;
     int nloc;                      // row-pair blocks of this instance
@@ -174,7 +183,7 @@ struct BatchDev {
     const KParams<T>* ptab;
     const InstTab* itab;
     const int2* work_loc;  // (instance, row pair)
-    const int2* work_col;  // (instance, column tile)
+    const int2* work_col;  // (instance, first x-bin of the column tile), XCD-grouped
     int nloc, ncol, ninst;
     int max_n3;            // max 3N over instances (grid of element-wise kernels)
     int col_tk, col_threads, col_radix;  // column kernel: x-bins per block, block size, largest FFT radix

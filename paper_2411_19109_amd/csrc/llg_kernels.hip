@@ -2,8 +2,9 @@
 //
 // Data layout (all in HBM, component-major SoA, x fastest):
 //   vector fields  v[c*N + (iz*ny + iy)*nx + ix]
-//   x-spectrum     S[(c*nrows + row)*Kx + kx], row = iz*ny + iy, kx in [0, Px/2]
-//   tensor spectrum nhat[((comp*Kz2 + kz)*Ky2 + ky)*Kx + kx]  (real)
+//   x-spectrum     S[((c*ktiles + t)*nrows + row)*TW + o], row = iz*ny + iy, bin kx = t*TW + o in [0, Px/2]
+//   tensor spectrum nhat[(t*NR + (comp*Kz2 + kz)*Ky2 + ky)*TW + o]  (real), NR = ncomp*Kz2*Ky2
+//   (TW = 128-byte tile of complex bins: 16 in float, 8 in double)
 //
 // Demag field B_d = -mu0 Ms N * (psi m) is a linear convolution computed with
 // zero padding: a real-to-complex FFT along x of each grid row (fused into the
@@ -264,18 +265,19 @@ template <typename T>
 __device__ __forceinline__ void unpack_rows_to_lds(const KParams<T>& p, const cplx<T>* __restrict__ S, int r0, bool v1,
                                                    cplx<T>* Z) {
     using C = cplx<T>;
-    const int Px = p.Px, Kx = p.Kx;
-    const size_t cs = (size_t)p.nrows * Kx;
+    constexpr int TW = spec_tile<T>();
+    const int Px = p.Px;
+    const size_t cs = (size_t)p.ktiles * p.nrows * TW;
     for (int k = threadIdx.x; k < Px; k += blockDim.x) {
         const bool cj = k > Px / 2;
         const int kk = cj ? Px - k : k;
-        const C* s0 = S + (size_t)r0 * Kx + kk;
+        const C* s0 = S + ((size_t)(kk / TW) * p.nrows + r0) * TW + (kk % TW);
         C ax = s0[0], ay = s0[cs], az = s0[2 * cs];
         C bx = cmk<C>(0, 0), by = bx, bz = bx;
         if (v1) {
-            bx = s0[Kx];
-            by = s0[Kx + cs];
-            bz = s0[Kx + 2 * cs];
+            bx = s0[TW];
+            by = s0[TW + cs];
+            bz = s0[TW + 2 * cs];
         }
         if (cj) {
             ax = cconj(ax); ay = cconj(ay); az = cconj(az);
@@ -291,8 +293,9 @@ template <typename T>
 __device__ __forceinline__ void pack_lds_to_rows(const KParams<T>& p, cplx<T>* __restrict__ S, int r0, bool v1,
                                                  const cplx<T>* Z) {
     using C = cplx<T>;
+    constexpr int TW = spec_tile<T>();
     const int Px = p.Px, Kx = p.Kx;
-    const size_t cs = (size_t)p.nrows * Kx;
+    const size_t cs = (size_t)p.ktiles * p.nrows * TW;
     const T h = (T)0.5;
     for (int k = threadIdx.x; k < Kx; k += blockDim.x) {
         const int kn = (Px - k) & (Px - 1);
@@ -305,14 +308,14 @@ __device__ __forceinline__ void pack_lds_to_rows(const KParams<T>& p, cplx<T>* _
             out[2 * s] = cmk<C>(h * sum.x, h * sum.y);       // spectrum of the real part
             out[2 * s + 1] = cmk<C>(h * dif.y, -h * dif.x);  // spectrum of the imaginary part
         }
-        C* d = S + (size_t)r0 * Kx + k;
+        C* d = S + ((size_t)(k / TW) * p.nrows + r0) * TW + (k % TW);
         d[0] = out[0];
         d[cs] = out[1];
         d[2 * cs] = out[4];
         if (v1) {
-            d[Kx] = out[2];
-            d[Kx + cs] = out[3];
-            d[Kx + 2 * cs] = out[5];
+            d[TW] = out[2];
+            d[TW + cs] = out[3];
+            d[TW + 2 * cs] = out[5];
         }
     }
 }
@@ -407,8 +410,9 @@ __device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v
     struct Bin {
         C a[3], b[3];
     };
-    const int nx = p.nx, Px = p.Px, Kx = p.Kx, N = p.N, nrows = p.nrows;
-    const size_t cs = (size_t)nrows * Kx;
+    constexpr int TW = spec_tile<T>();
+    const int nx = p.nx, Px = p.Px, N = p.N, nrows = p.nrows;
+    const size_t cs = (size_t)p.ktiles * nrows * TW;
     const int nrow_el = rows ? nx : 0;
     const int nspec = S ? Px : 0;
     const int ntw = tw ? Px : 0;
@@ -440,14 +444,14 @@ __device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v
     auto lspec = [&](int k) {
         Bin b;
         const int kk = k > Px / 2 ? Px - k : k;
-        const C* s0 = S + (size_t)r0 * Kx + kk;
+        const C* s0 = S + ((size_t)(kk / TW) * nrows + r0) * TW + (kk % TW);
         b.a[0] = s0[0];
         b.a[1] = s0[cs];
         b.a[2] = s0[2 * cs];
         if (v1) {
-            b.b[0] = s0[Kx];
-            b.b[1] = s0[Kx + cs];
-            b.b[2] = s0[Kx + 2 * cs];
+            b.b[0] = s0[TW];
+            b.b[1] = s0[TW + cs];
+            b.b[2] = s0[TW + 2 * cs];
         } else {
             b.b[0] = b.b[1] = b.b[2] = cmk<C>(0, 0);
         }
@@ -948,7 +952,8 @@ template <typename T, int NZ, int MR>
 __global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchArgs<T> ba, int TK, int sid, int nt_lds) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
+    const int2 wk = ba.work[blockIdx.x];  // (instance, first bin); XCD-grouped order, also for one instance
+    if (wk.y >= (1 << 30)) return;      // empty item that keeps the grouping stride
     const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
     const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
     C* __restrict__ S = role<C>(tb, sid);
@@ -960,8 +965,13 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchA
     C* Z = reinterpret_cast<C*>(smem_raw);
     C* Tw = Z + lds_pad(3 * nz * plane);
     T* Nt = reinterpret_cast<T*>(Tw + Py);
-    const int k0 = wk.y * TK;
-    const size_t cs = (size_t)p.nrows * Kx;
+    constexpr int TW = spec_tile<T>();
+    const int k0 = wk.y;  // first x-bin of the tile (TK <= TW bins inside one spectrum tile)
+    const int kt = k0 / TW, ko = k0 % TW;
+    const size_t cs = (size_t)p.ktiles * p.nrows * TW;
+    const C* __restrict__ Sk = S + (size_t)kt * p.nrows * TW + ko;  // bin k0 of row 0, component 0
+    const int NR = p.ncomp * p.Kz2 * p.Ky2;
+    const T* __restrict__ Nk = nhat + (size_t)kt * NR * TW + ko;
     // the columns (zero-padded in y), the tensor-spectrum tile and the
     // twiddles, in batched chunks; element e = (cz * Py + y) * TK + tk with
     // cz = c * nz + z, so the row of S is cz * ny + y (c * cs = c * nz * ny * Kx)
@@ -969,16 +979,21 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchA
     const int ncolel = 3 * nz * Py * TK;
     // the tensor-spectrum tile is staged in LDS when it fits, else read from global memory
     const int ntile = nt_lds ? p.ncomp * p.Kz2 * p.Ky2 * TK : 0;
+    // row of S for plane cz = c * nz + z and y: component c at c * cs, row z * ny + y
+    auto srow = [&](int cz, int y) {
+        const int c = (cz >= nz) + (cz >= 2 * nz);
+        return (size_t)c * cs + (size_t)((cz - c * nz) * ny + y) * TW;
+    };
     auto lcol = [&](int e) {
         const int tk = e & (TK - 1);
         const int t = e >> ltk;
         const int y = t & (Py - 1), cz = t >> lpy;
-        return (y < ny && k0 + tk < Kx) ? S[(size_t)(cz * ny + y) * Kx + k0 + tk] : cmk<C>(0, 0);
+        return (y < ny && k0 + tk < Kx) ? Sk[srow(cz, y) + tk] : cmk<C>(0, 0);
     };
     auto scol = [&](int e, C v) { Z[lp(e)] = v; };
     auto ltile = [&](int e) {
-        const int tk = e & (TK - 1), row = e >> ltk;  // row = (comp * Kz2 + kz) * Ky2 + ky
-        return (k0 + tk < Kx) ? nhat[(size_t)row * Kx + k0 + tk] : (T)0;
+        const int tk = e & (TK - 1), q = e >> ltk;  // q = (comp * Kz2 + kz) * Ky2 + ky
+        return (k0 + tk < Kx) ? Nk[(size_t)q * TW + tk] : (T)0;
     };
     auto stile = [&](int e, T v) { Nt[e] = v; };
     auto ltw = [&](int k) { return twy[k]; };
@@ -1022,8 +1037,8 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchA
             const bool fz = kz > Pz / 2;
             const int kzr = fz ? Pz - kz : kz;
             const int base = (kzr * p.Ky2 + kyr) * TK + tk;
-            const size_t gbase = (size_t)(kzr * p.Ky2 + kyr) * Kx + kx, gstr = (size_t)p.Kz2 * p.Ky2 * Kx;
-            auto NT = [&](int comp) -> T { return nt_lds ? Nt[comp * cstr + base] : nhat[comp * gstr + gbase]; };
+            const size_t gbase = (size_t)(kzr * p.Ky2 + kyr) * TW + tk, gstr = (size_t)p.Kz2 * p.Ky2 * TW;
+            auto NT = [&](int comp) -> T { return nt_lds ? Nt[comp * cstr + base] : Nk[comp * gstr + gbase]; };
             const T nxx = NT(0), nyy = NT(1), nzz = NT(2);
             const T nxy = fy ? -NT(3) : NT(3);
             T nxz = 0, nyz = 0;
@@ -1057,7 +1072,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchA
         const int tk = e & (TK - 1);
         const int t = e >> ltk;
         const int y = t & (Py - 1), cz = t >> lpy;
-        if (y < ny && k0 + tk < Kx) S[(size_t)(cz * ny + y) * Kx + k0 + tk] = Z[lp(e)];
+        if (y < ny && k0 + tk < Kx) S[srow(cz, y) + (size_t)kt * p.nrows * TW + ko + tk] = Z[lp(e)];
     }
 }
 

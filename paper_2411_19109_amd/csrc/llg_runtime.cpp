@@ -64,6 +64,7 @@ struct DevBuf {
 struct Instance {
     llg_problem prob{};
     int N = 0, nrows = 0, Px = 1, Py = 1, Pz = 1, Kx = 1, ncomp = 4;
+    int ktiles = 1;  // x-bin tiles of the stored spectra
     int nloc = 0;
     long long n_p1 = 0, n_p2 = 0;
     bool has_ant = false, has_design = false;
@@ -172,6 +173,7 @@ void fill_params(Instance& I) {
     p.Pz = I.Pz;
     p.Ky2 = I.Py / 2 + 1;
     p.Kz2 = I.Pz / 2 + 1;
+    p.ktiles = I.ktiles;
     p.ncomp = I.ncomp;
     p.terms = q.terms;
     p.nloc = I.nloc;
@@ -225,8 +227,13 @@ int upload_tables(llg_handle* h, Instance& I) {
         const double scale = -kMu0 * q.Ms / ((double)I.Px * I.Py * I.Pz);
         build_tensor_spectrum(q.nx, q.ny, q.nz, q.dx, q.dy, q.dz, I.Px, I.Py, I.Pz, scale, spec, nc);
         I.ncomp = nc;
-        std::vector<T> st(spec.size());
-        for (size_t i = 0; i < spec.size(); ++i) st[i] = (T)spec[i];
+        // into 128-byte x-bin tiles: [(t * NR + q) * TW + o], q = (comp * Kz2 + kz) * Ky2 + ky
+        const int TW = spec_tile<T>();
+        const size_t NR = spec.size() / I.Kx;
+        std::vector<T> st((size_t)I.ktiles * NR * TW, (T)0);
+        for (size_t q = 0; q < NR; ++q)
+            for (int kx = 0; kx < I.Kx; ++kx)
+                st[((size_t)(kx / TW) * NR + q) * TW + kx % TW] = (T)spec[q * I.Kx + kx];
         if ((rc = alloc(h, &I.tab.b[B_NHAT], sizeof(T) * st.size()))) return rc;
         HIPCHK(hipMemcpy(I.tab.b[B_NHAT], st.data(), sizeof(T) * st.size(), hipMemcpyHostToDevice));
     }
@@ -309,6 +316,7 @@ int check_cfg(const llg_handle* h, const LaunchCfg& c) {
         return fail(LLG_EINVAL, "FFT radix must be 4, 8 or (float only) 16");
     if (c.tk != 1 && c.tk != 2 && c.tk != 4 && c.tk != 8 && c.tk != 16)
         return fail(LLG_EINVAL, "column tile must be 1, 2, 4, 8 or 16");
+    if (c.tk > spec_tile_of((int)h->tsz)) return fail(LLG_EINVAL, "column tile wider than a spectrum tile (8 in double)");
     if (!col_fits(h, c.tk, c.col_r)) return fail(LLG_ESHAPE, "column tile " + std::to_string(c.tk) + " does not fit");
     const int cmin = col_min_threads(h, c.tk, c.col_r);
     const int cmax = col_max_threads(c.col_r);
@@ -342,7 +350,7 @@ int default_cfg(const llg_handle* h, LaunchCfg& c) {
         for (auto& I : h->inst) b += (I.Kx + tk - 1) / tk;
         return b;
     };
-    int tk = 8;
+    int tk = std::min(8, spec_tile_of((int)h->tsz));
     while (tk > 1 && (blocks_of(tk) < 256 || !col_fits(h, tk, cr))) tk /= 2;
     if (!col_fits(h, tk, cr)) return fail(LLG_ESHAPE, "y/z extent too large for the column FFT");
     int ct = col_min_threads(h, tk, cr);
@@ -358,10 +366,35 @@ int default_cfg(const llg_handle* h, LaunchCfg& c) {
 }
 
 // Make c the batch's launch configuration: column work list, block sizes, LDS limits.
-int apply_cfg(llg_handle* h, const LaunchCfg& c) {
-    std::vector<int2> wc;
+// Column work list: one item per (instance, tile of tk bins).  The tk-bin tiles
+// of one 128-byte spectrum tile read the same cache lines, so they are placed
+// 8 items apart: thread blocks are dealt round-robin to the 8 XCDs, and this
+// keeps a spectrum tile's blocks on one XCD (one L2) and close in time.
+std::vector<int2> column_work(const llg_handle* h, int tk) {
+    const int TW = spec_tile_of((int)h->tsz);
+    const int nsub = TW / tk;
+    std::vector<int2> tiles;  // (instance, spectrum tile)
     for (int i = 0; i < (int)h->inst.size(); ++i)
-        for (int k = 0; k < (h->inst[i].Kx + c.tk - 1) / c.tk; ++k) wc.push_back(make_int2(i, k));
+        for (int t = 0; t < h->inst[i].ktiles; ++t) tiles.push_back(make_int2(i, t));
+    // items past an instance's last bin stay in place as empty blocks (k0 = kNoBin)
+    // so that every group keeps the stride of 8
+    constexpr int kNoBin = 1 << 30;
+    std::vector<int2> wc;
+    for (size_t g = 0; g < tiles.size(); g += 8) {
+        const size_t ng = std::min<size_t>(8, tiles.size() - g);
+        const size_t stride = nsub > 1 ? 8 : ng;
+        for (int sub = 0; sub < nsub; ++sub)
+            for (size_t j = 0; j < stride; ++j) {
+                const int2 tt = tiles[g + std::min(j, ng - 1)];
+                const int k0 = tt.y * TW + sub * tk;
+                wc.push_back(make_int2(tt.x, j < ng && k0 < h->inst[tt.x].Kx ? k0 : kNoBin));
+            }
+    }
+    return wc;
+}
+
+int apply_cfg(llg_handle* h, const LaunchCfg& c) {
+    const std::vector<int2> wc = column_work(h, c.tk);
     HIPCHK(hipMemcpy(h->work_col, wc.data(), wc.size() * sizeof(int2), hipMemcpyHostToDevice));
     size_t col_lds = 0;
     for (auto& I : h->inst) col_lds = std::max(col_lds, col_lds_bytes(h, I, c.tk));
@@ -400,8 +433,9 @@ int choose_launch(llg_handle* h) {
     size_t ncol_max = 0;
     for (int i = 0; i < (int)h->inst.size(); ++i) {
         for (int r = 0; r < h->inst[i].nloc; ++r) wl.push_back(make_int2(i, r));
-        ncol_max += h->inst[i].Kx;
+        ncol_max += (size_t)h->inst[i].ktiles * spec_tile_of((int)h->tsz);
     }
+    ncol_max += (size_t)8 * spec_tile_of((int)h->tsz);  // empty items of the last group
     int rc;
     void* p;
     if ((rc = alloc(h, &p, wl.size() * sizeof(int2)))) return rc;
@@ -943,7 +977,7 @@ int autotune_typed(llg_handle* h, hipStream_t s, LaunchCfg& best) {
         for (int cr : {4, 8, 16}) {
             if (!radix_ok(h, cr)) continue;
             for (int tk : {1, 2, 4, 8, 16}) {
-                if (!col_fits(h, tk, cr)) continue;
+                if (tk > spec_tile_of((int)h->tsz) || !col_fits(h, tk, cr)) continue;
                 const int cmin = col_min_threads(h, tk, cr);
                 for (int ct : {cmin, 2 * cmin, 4 * cmin}) {
                     if (ct > col_max_threads(cr)) continue;
@@ -1061,6 +1095,7 @@ int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_ha
         I.Py = padded(I.prob.ny);
         I.Pz = padded(I.prob.nz);
         I.Kx = I.Px / 2 + 1;
+        I.ktiles = (I.Kx + spec_tile_of((int)h->tsz) - 1) / spec_tile_of((int)h->tsz);
         I.ncomp = I.prob.nz > 1 ? 6 : 4;
         I.nloc = (I.nrows + 1) / 2;
         h->max_nz = std::max(h->max_nz, I.prob.nz);
@@ -1094,8 +1129,8 @@ int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_ha
         }
         const std::pair<int, size_t> sizes[] = {
             {B_PSI, N * t}, {B_PHI, N * t}, {B_PSIF, N * t}, {B_M, N3b}, {B_ACC, N3b}, {B_YA, N3b}, {B_YB, N3b},
-            {B_S, h->demag ? (size_t)3 * I.nrows * I.Kx * 2 * t : 0},
-            {B_S2, h->demag && h->halves > 1 ? (size_t)3 * I.nrows * I.Kx * 2 * t : 0},
+            {B_S, h->demag ? (size_t)3 * I.nrows * I.ktiles * spec_tile_of((int)t) * 2 * t : 0},
+            {B_S2, h->demag && h->halves > 1 ? (size_t)3 * I.nrows * I.ktiles * spec_tile_of((int)t) * 2 * t : 0},
             {B_SNAP, (size_t)h->nsnap * N3b}, {B_YS, (size_t)(h->K * h->halves) * 4 * N3b},
             {B_BS, (size_t)(h->K * h->halves) * 4 * N3b}, {B_ELL, N3b}, {B_U0, N3b}, {B_U1, N3b},
             {B_L0, N3b}, {B_L1, N3b}, {B_GPSI, N * 8}, {B_DJDM, N3b}, {B_DPSIE, N * 8}, {B_DPSI, N * 8},

@@ -972,33 +972,90 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchA
     const C* __restrict__ Sk = S + (size_t)kt * p.nrows * TW + ko;  // bin k0 of row 0, component 0
     const int NR = p.ncomp * p.Kz2 * p.Ky2;
     const T* __restrict__ Nk = nhat + (size_t)kt * NR * TW + ko;
-    // the columns (zero-padded in y), the tensor-spectrum tile and the
-    // twiddles, in batched chunks; element e = (cz * Py + y) * TK + tk with
-    // cz = c * nz + z, so the row of S is cz * ny + y (c * cs = c * nz * ny * Kx)
-    const int ltk = ilog2_rt(TK), lpy = ilog2_rt(Py);
-    const int ncolel = 3 * nz * Py * TK;
-    // the tensor-spectrum tile is staged in LDS when it fits, else read from global memory
-    const int ntile = nt_lds ? p.ncomp * p.Kz2 * p.Ky2 * TK : 0;
+    // The columns (zero-padded in y), the tensor-spectrum tile and the
+    // twiddles, in batched chunks of 16-byte loads: the TK bins of a tile row
+    // are contiguous in memory (a unit holds 2 float bins or 1 double bin; a
+    // lone float bin is one 8-byte unit).  Bins past Kx inside a spectrum tile
+    // are zero in memory and never stored back.
+    constexpr int CPU = sizeof(T) == 4 ? 2 : 1;  // complex bins per 16-byte unit
+    const int lpy = ilog2_rt(Py);
+    const int lnu = TK > CPU ? ilog2_rt(TK / CPU) : 0;  // log2 units per row
+    const int ucnt = TK < CPU ? TK : CPU;                // bins per unit
+    const int ncolu = (3 * nz * Py) << lnu;
     // row of S for plane cz = c * nz + z and y: component c at c * cs, row z * ny + y
     auto srow = [&](int cz, int y) {
         const int c = (cz >= nz) + (cz >= 2 * nz);
         return (size_t)c * cs + (size_t)((cz - c * nz) * ny + y) * TW;
     };
+    struct Unit {
+        C c[CPU];
+    };
     auto lcol = [&](int e) {
-        const int tk = e & (TK - 1);
-        const int t = e >> ltk;
-        const int y = t & (Py - 1), cz = t >> lpy;
-        return (y < ny && k0 + tk < Kx) ? Sk[srow(cz, y) + tk] : cmk<C>(0, 0);
+        Unit u;
+        const int uo = (e & ((1 << lnu) - 1)) * CPU;
+        const int row = e >> lnu;
+        const int y = row & (Py - 1), cz = row >> lpy;
+#pragma unroll
+        for (int k = 0; k < CPU; ++k) u.c[k] = cmk<C>(0, 0);
+        if (y < ny) {
+            const C* src = Sk + srow(cz, y) + uo;
+            if constexpr (CPU == 2) {
+                if (ucnt == 2) {
+                    const float4 q = *reinterpret_cast<const float4*>(src);
+                    u.c[0] = cmk<C>(q.x, q.y);
+                    u.c[1] = cmk<C>(q.z, q.w);
+                } else {
+                    u.c[0] = src[0];
+                }
+            } else {
+                u.c[0] = src[0];
+            }
+        }
+        return u;
     };
-    auto scol = [&](int e, C v) { Z[lp(e)] = v; };
+    auto scol = [&](int e, const Unit& u) {
+        const int uo = (e & ((1 << lnu) - 1)) * CPU;
+        const int row = e >> lnu;
+        const int base = row * TK + uo;  // (cz * Py + y) * TK + bin
+#pragma unroll
+        for (int k = 0; k < CPU; ++k)
+            if (k < ucnt) Z[lp(base + k)] = u.c[k];
+    };
+    // tensor-spectrum tile: TK reals per row q = (comp * Kz2 + kz) * Ky2 + ky, 16-byte units
+    constexpr int RPU = 16 / sizeof(T);  // reals per unit
+    const int lnr = TK > RPU ? ilog2_rt(TK / RPU) : 0;
+    const int rcnt = TK < RPU ? TK : RPU;
+    const int ntu = nt_lds ? (p.ncomp * p.Kz2 * p.Ky2) << lnr : 0;
+    struct RUnit {
+        T r[RPU];
+    };
     auto ltile = [&](int e) {
-        const int tk = e & (TK - 1), q = e >> ltk;  // q = (comp * Kz2 + kz) * Ky2 + ky
-        return (k0 + tk < Kx) ? Nk[(size_t)q * TW + tk] : (T)0;
+        RUnit u;
+        const int ro = (e & ((1 << lnr) - 1)) * RPU, q = e >> lnr;
+        const T* src = Nk + (size_t)q * TW + ro;
+        if (rcnt == RPU) {
+            if constexpr (sizeof(T) == 4) {
+                const float4 v = *reinterpret_cast<const float4*>(src);
+                u.r[0] = v.x, u.r[1] = v.y, u.r[2] = v.z, u.r[3] = v.w;
+            } else {
+                const double2 v = *reinterpret_cast<const double2*>(src);
+                u.r[0] = v.x, u.r[1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RPU; ++k) u.r[k] = k < rcnt ? src[k] : (T)0;
+        }
+        return u;
     };
-    auto stile = [&](int e, T v) { Nt[e] = v; };
+    auto stile = [&](int e, const RUnit& u) {
+        const int ro = (e & ((1 << lnr) - 1)) * RPU, q = e >> lnr;
+#pragma unroll
+        for (int k = 0; k < RPU; ++k)
+            if (k < rcnt) Nt[q * TK + ro + k] = u.r[k];
+    };
     auto ltw = [&](int k) { return twy[k]; };
     auto stw = [&](int k, C w) { Tw[k] = w; };
-    gather3<2, 2, 1, C, T, C>(ncolel, lcol, scol, ntile, ltile, stile, Py, ltw, stw);
+    gather3<4, 4, 1, Unit, RUnit, C>(ncolu, lcol, scol, ntu, ltile, stile, Py, ltw, stw);
     __syncthreads();
     const SigMap smy{ilog2_rt(TK), plane, 1, TK};
     if (Py > 1) fft_lds<C, false, MR>(Z, smy, Py, 3 * nz * TK, Tw);
@@ -1068,11 +1125,14 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchA
     }
     __syncthreads();
     if (Py > 1) fft_lds<C, true, MR>(Z, smy, Py, 3 * nz * TK, Tw);
+    const int ltk = ilog2_rt(TK);
+    const int ncolel = 3 * nz * Py * TK;
+    C* __restrict__ Sw = S + (size_t)kt * p.nrows * TW + ko;
     for (int e = threadIdx.x; e < ncolel; e += blockDim.x) {
         const int tk = e & (TK - 1);
         const int t = e >> ltk;
         const int y = t & (Py - 1), cz = t >> lpy;
-        if (y < ny && k0 + tk < Kx) S[srow(cz, y) + (size_t)kt * p.nrows * TW + ko + tk] = Z[lp(e)];
+        if (y < ny && k0 + tk < Kx) Sw[srow(cz, y) + tk] = Z[lp(e)];
     }
 }
 

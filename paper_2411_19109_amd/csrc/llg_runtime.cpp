@@ -1137,6 +1137,11 @@ int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_ha
             {B_DPHI, N * 8}, {B_PPART, (size_t)I.nloc * 2 * 8}, {B_EPART, (size_t)I.nloc * 5 * 8}, {B_SCAL, 8 * 8}};
         for (auto& sz : sizes)
             if ((rc = alloc(h, &I.tab.b[sz.first], sz.second))) return bail(rc);
+        // spectrum bins past Kx inside the last x-bin tile are read by the column
+        // kernel's vector loads and never written: keep them zero
+        for (int id : {B_S, B_S2})
+            if (I.tab.b[id] && hipMemset(I.tab.b[id], 0, (size_t)3 * I.nrows * I.ktiles * spec_tile_of((int)t) * 2 * t) != hipSuccess)
+                return bail(fail(LLG_EHIP, "spectrum clear failed"));
         if (h->dtype == LLG_F32) {
             fill_params<float>(I);
             rc = upload_tables<float>(h, I);

@@ -314,18 +314,20 @@ def run_sweep(args):
               f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
     dom = max(kinds, key=lambda k: kinds[k]["ms"])
     d = kinds[dom]
-    plain, nodes_p = sweep_plain(n, max(1, args.sweep_plain), bool(args.graphs), bool(args.autotune))
-    for p in plain:  # first call of each instance captures its graphs
-        p()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for p in plain:
-        p()
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
     rate_b = step.nodes * n / tb
-    rate_p = nodes_p * n / tp
-    print(f"[bench] plain: {tp * 1e3:.1f} ms for {len(plain)} sequential instances", file=sys.stderr, flush=True)
+    rate_p, tp, plain = None, None, []
+    if args.sweep_plain > 0:
+        plain, nodes_p = sweep_plain(n, args.sweep_plain, bool(args.graphs), bool(args.autotune))
+        for p in plain:  # first call of each instance captures its graphs
+            p()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p in plain:
+            p()
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        rate_p = nodes_p * n / tp
+        print(f"[bench] plain: {tp * 1e3:.1f} ms for {len(plain)} sequential instances", file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
         "value": rate_b,
@@ -341,7 +343,7 @@ def run_sweep(args):
         "data": "synthetic",
         "config": {"workload": f"yig_demux_sweep_64x_prefix{n}", "instances": len(step.ws), "nodes": step.nodes,
                    "rk4_steps": n, "plain_cell_steps_per_s": rate_p, "plain_instances_timed": len(plain),
-                   "batched_over_plain": rate_b / rate_p, "hip_graphs": bool(args.graphs),
+                   "batched_over_plain": rate_b / rate_p if rate_p else None, "hip_graphs": bool(args.graphs),
                    "launch": list(step.launch)},
         "roofline": dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
                          frac=round(d["gbs"] / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,

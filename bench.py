@@ -85,7 +85,7 @@ class SweepStep:
     """The batched sweep: 32 seeded designs x 2 drive frequencies on ragged grids,
     one gradient evaluation of every instance with one launch sequence."""
 
-    def __init__(self, n_steps, graphs=True, tune=True):
+    def __init__(self, n_steps, graphs=True, tune=True, launch_file=None):
         import torch
         from paper_2411_19109_amd import llg, workloads as wl
         self.ws = wl.yig_demux_sweep(n_steps=n_steps)
@@ -98,7 +98,14 @@ class SweepStep:
                                masks=[dict(antenna=w.antenna, port1=w.port1, port2=w.port2, design=w.design)
                                       for w in self.ws])
         self.batch.set_graphs(graphs)
-        self.launch = self.batch.autotune() if tune else self.batch.launch_config()
+        if launch_file and os.path.exists(launch_file):
+            self.batch.set_launch_config(*[int(v) for v in open(launch_file).read().split()])
+            self.launch = self.batch.launch_config()
+        else:
+            self.launch = self.batch.autotune() if tune else self.batch.launch_config()
+            if launch_file:
+                with open(launch_file, "w") as fh:
+                    fh.write(" ".join(str(v) for v in self.launch) + "\n")
         self.phi = [t(w.phi) for w in self.ws]
         self.psif = [t(w.psi_fixed) for w in self.ws]
         self.m0 = [t(w.m0) for w in self.ws]
@@ -292,7 +299,7 @@ def run_sweep(args):
     import torch
     from paper_2411_19109_amd import llg
     n = args.sweep_steps
-    step = SweepStep(n, bool(args.graphs), bool(args.autotune))
+    step = SweepStep(n, bool(args.graphs), bool(args.autotune), args.launch_file)
     print(f"[bench] sweep: {len(step.ws)} instances, {step.nodes} nodes, {n} steps, launch {step.launch}",
           file=sys.stderr, flush=True)
     for i in range(args.warmup):

@@ -5,7 +5,7 @@ n RK4 steps of the LLG equation with checkpoints, the objective, the
 checkpointed discrete adjoint back to t0, and the chain rule to dJ/dphi.
 Inputs are resident in device memory before the timed region starts.
 
-  python bench.py [--steps K] [--warmup W] [--workload particle|waveguide|demux]
+  python bench.py [--steps K] [--warmup W] [--workload particle|waveguide|demux|sweep|probe]
 
 Prints ONE JSON line.  The metric is LLG cell-steps per second of the forward
 + adjoint run: nodes * RK4 steps / wall time of one gradient evaluation.
@@ -192,6 +192,8 @@ def main():
         del src, dst
     if args.workload == "sweep":
         return run_sweep(args)
+    if args.workload == "probe":
+        return run_probe(args)
     w = make_workload(args.workload)
     if args.n_steps > 0:
         w.n_steps = args.n_steps
@@ -355,6 +357,64 @@ def run_sweep(args):
         "roofline": dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
                          frac=round(d["gbs"] / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
                          avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"])),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_probe(args):
+    """HBM-scale measurement of the fused step: a batch of 4 YIG films of
+    1024x1024 nodes (FP32 state, spectra and stage buffers ~0.5 GB, beyond the
+    256 MB last-level cache), forward RK4 steps only; the roofline object is the
+    forward row kernel (fields + LL RHS + RK4 stage + row FFTs)."""
+    import torch
+    from paper_2411_19109_amd import llg, workloads as wl
+    n = args.n_steps or 20
+    ws = [wl.yig_film_probe(seed=5 + k, n_steps=n) for k in range(4)]
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=torch.float32, device=dev)
+    b = llg.Batch([w.problem for w in ws], dtype="f32", max_steps=n)
+    launch = b.autotune() if args.autotune else b.launch_config()
+    psis = [t(w.psi_fixed) for w in ws]
+    m0 = [t(w.m0) for w in ws]
+    nodes = sum(w.problem.n for w in ws)
+    print(f"[bench] probe: {len(ws)} x {ws[0].problem.nx}x{ws[0].problem.ny}, {nodes} nodes, {n} steps, "
+          f"launch {launch}", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        b.forward(psis, m0, n, want_m=False)
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        b.forward(psis, m0, n, want_m=False)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    b.profile(True)
+    b.forward(psis, m0, n, want_m=False)
+    torch.cuda.synchronize()
+    b.profile(False)
+    kinds = _kernel_stats(b)
+    for name, v in kinds.items():
+        print(f"[bench] probe {name}: {v['launches']} launches, avg {v['avg_us']:.2f} us, "
+              f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
+    d = kinds["k_stage_fwd"]
+    out = {
+        "metric": "LLG cell-steps/s forward",
+        "value": nodes * n / sec,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "yig_film_probe_4x1024x1024_forward", "nodes": nodes, "rk4_steps": n,
+                   "launch": list(launch)},
+        "roofline": dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(d["gbs"] / HBM_PEAK_GBS, 5), traffic=None, kernel="k_stage_fwd",
+                         avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"])),
+        "kernels": {k: dict(avg_us=round(v["avg_us"], 2), gbs=round(v["gbs"], 1)) for k, v in kinds.items()},
     }
     print(json.dumps(out), flush=True)
 

@@ -222,9 +222,23 @@ int upload_tables(llg_handle* h, Instance& I) {
     if ((rc = twiddles(I.Pz, B_TWZ))) return rc;
     if (h->demag) {
         const llg_problem& q = I.prob;
+        const double scale = -kMu0 * q.Ms / ((double)I.Px * I.Py * I.Pz);
+        // instances with the same grid, cells and Ms (e.g. one design at several
+        // frequencies) share one device copy of the tensor spectrum
+        const std::vector<double> key = {(double)q.nx, (double)q.ny, (double)q.nz, q.dx, q.dy, q.dz, scale};
+        for (const Instance& J : h->inst) {
+            if (&J == &I || !J.tab.b[B_NHAT]) continue;
+            const llg_problem& r = J.prob;
+            const double sj = -kMu0 * r.Ms / ((double)J.Px * J.Py * J.Pz);
+            const std::vector<double> kj = {(double)r.nx, (double)r.ny, (double)r.nz, r.dx, r.dy, r.dz, sj};
+            if (kj == key) {
+                I.tab.b[B_NHAT] = J.tab.b[B_NHAT];
+                I.ncomp = J.ncomp;
+                return LLG_OK;
+            }
+        }
         std::vector<double> spec;
         int nc = 4;
-        const double scale = -kMu0 * q.Ms / ((double)I.Px * I.Py * I.Pz);
         build_tensor_spectrum(q.nx, q.ny, q.nz, q.dx, q.dy, q.dz, I.Px, I.Py, I.Pz, scale, spec, nc);
         I.ncomp = nc;
         // into 128-byte x-bin tiles: [(t * NR + q) * TW + o], q = (comp * Kz2 + kz) * Ky2 + ky

@@ -194,6 +194,26 @@ def yig_waveguide_plain(seed: int = 0, n_steps: int = 500) -> Workload:
                     psi_fixed=ones, antenna=zeros8, port1=zeros8, port2=zeros8, m0=m0)
 
 
+def yig_film_probe(seed: int = 5, nx: int = 1024, ny: int = 1024, n_steps: int = 20) -> Workload:
+    """HBM-scale probe of the fused step: a 1024x1024x1 YIG film (5x5x10 nm^3
+    cells), the waveguide physics (exchange + demag + 0.2 T bias along x), m0
+    along x with a seeded N(0, 1e-3) transverse perturbation, FP32."""
+    rng = np.random.default_rng(seed)
+    p = Problem(nx=nx, ny=ny, nz=1, dx=5e-9, dy=5e-9, dz=10e-9, Ms=1.4e5, A=3.5e-12,
+                alpha0=1e-3, alpha_max=1e-3, B0=(0.2, 0.0, 0.0),
+                terms=TERM_EXCH | TERM_DEMAG | TERM_ZEEMAN, dt=1e-13)
+    sh = p.shape
+    m0 = np.zeros((3,) + sh)
+    m0[0] = 1.0
+    m0[1] = rng.normal(0.0, 1e-3, sh)
+    m0[2] = rng.normal(0.0, 1e-3, sh)
+    m0 = _normalise(m0)
+    zeros8 = np.zeros(sh, np.uint8)
+    return Workload(name=f"yig_film_probe_{nx}x{ny}", problem=p, n_steps=n_steps, dtype="f32",
+                    heaviside_a=50.0, phi=np.zeros(sh), extrude_z=False, design=zeros8,
+                    psi_fixed=np.ones(sh), antenna=zeros8, port1=zeros8, port2=zeros8, m0=m0)
+
+
 def permalloy_particle(seed: int = 1, n_steps: int = 2000, nx: int = 64, ny: int = 64) -> Workload:
     """64x64x1 nodes, 2 nm cubes, permalloy-like (Ms = 8e5 A/m, A = 1.3e-11 J/m,
     alpha = 0.5), no applied field.  phi = seeded sum of 4 Gaussians (sigma = 8

@@ -87,6 +87,44 @@ def test_effective_field_and_rhs(dtype, shape):
     assert rel_max(to_np(rhs), fref.reshape(-1)) <= tol
 
 
+# widest rows: 1024 nodes in float (2048-point row FFTs), 512 in double (its
+# radix-8 passes need 3 * Px / 8 <= 512 threads); columns up to 1024 nodes
+EXTREME_SHAPES = {"f32": [(1024, 3, 1), (3, 1024, 1), (257, 3, 1), (4, 129, 2), (5, 4, 8)],
+                  "f64": [(512, 3, 1), (3, 1024, 1), (257, 3, 1), (4, 129, 2), (5, 4, 8)]}
+
+
+@pytest.mark.parametrize("dtype,shape", [(d, s) for d in ("f64", "f32") for s in EXTREME_SHAPES[d]])
+def test_field_at_extreme_extents(dtype, shape):
+    """The largest row and column transforms, extents just past a power of two
+    (257 -> 1024-point rows, 129 -> 512-point columns) and the deepest z stack
+    (8 layers -> 16-point z transform), in the default and the autotuned launch
+    configuration."""
+    nx, ny, nz = shape
+    w = tiny_workload(nx, ny, nz)
+    say("field extreme", dtype, shape)
+    psi = oracle_psi(w)
+    sim = oracle_sim(w)
+    t = 1.7e-11
+    Bref = sim.field(w.m0, psi, t)
+    fref = sim.rhs_from_field(w.m0, Bref, psi)
+    tol = 1e-12 if dtype == "f64" else 2e-6
+    for tune in (False, True):
+        s = gpu_solver(w, dtype, tune=tune)
+        B, rhs = s.field(to_dev(psi, dtype), to_dev(w.m0, dtype), t, want_rhs=True)
+        assert rel_max(to_np(B), Bref.reshape(-1)) <= tol, tune
+        assert rel_max(to_np(rhs), fref.reshape(-1)) <= tol, tune
+        s.close()
+
+
+def test_extents_beyond_the_kernels_are_rejected():
+    from paper_2411_19109_amd import llg
+    for dtype, shape in [("f32", (1025, 2, 1)), ("f32", (2, 1025, 1)), ("f64", (513, 2, 1)), ("f64", (2, 1025, 1))]:
+        w = tiny_workload(*shape)
+        with pytest.raises(llg.LLGError) as e:
+            gpu_solver(w, dtype)
+        assert e.value.code == llg.LLG_ESHAPE
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(13, 9, 1), (1, 1, 1), (33, 1, 1), (9, 4, 3)])
 def test_forward_steps(dtype, shape):

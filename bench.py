@@ -373,7 +373,11 @@ def run_probe(args):
     dev = torch.device("cuda:0")
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=torch.float32, device=dev)
     b = llg.Batch([w.problem for w in ws], dtype="f32", max_steps=n)
-    launch = b.autotune() if args.autotune else b.launch_config()
+    if args.launch_file and os.path.exists(args.launch_file):
+        b.set_launch_config(*[int(v) for v in open(args.launch_file).read().split()])
+        launch = b.launch_config()
+    else:
+        launch = b.autotune() if args.autotune else b.launch_config()
     psis = [t(w.psi_fixed) for w in ws]
     m0 = [t(w.m0) for w in ws]
     nodes = sum(w.problem.n for w in ws)

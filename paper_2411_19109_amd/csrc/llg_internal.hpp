@@ -204,6 +204,8 @@ template <typename T>
 hipError_t launch_stage_bwd(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T>
 hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+template <typename T>
+int col_conv_vgprs(int max_nz, int radix);
 template <typename T> hipError_t launch_levelset(const BatchDev<T>& b, double a, int extrude, hipStream_t s);
 template <typename T> hipError_t launch_levelset_vjp(const BatchDev<T>& b, double a, int extrude, hipStream_t s);
 template <typename T>

@@ -1484,6 +1484,29 @@ hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, int spec, hipStream
         col_nz<T, 8>(b, spec, s, e0, e1);
     return hipGetLastError();
 }
+// Registers per lane of the column-kernel variant a launch with these
+// parameters would run (0 if the runtime cannot say).
+template <typename T>
+int col_conv_vgprs(int max_nz, int radix) {
+    const void* f;
+    constexpr int RT = MaxReg<T>::v;
+    const int r = radix == 4 ? 4 : (radix == 8 || sizeof(T) == 8) ? 8 : RT;
+    const int z = max_nz == 1 ? 1 : max_nz == 2 ? 2 : max_nz <= 4 ? 4 : 8;
+#define LLG_PICK(Z)                                                                                   \
+    if (z == Z)                                                                                       \
+        f = r == 4 ? reinterpret_cast<const void*>(k_col_conv<T, Z, 4>)                               \
+                   : r == 8 ? reinterpret_cast<const void*>(k_col_conv<T, Z, 8>)                      \
+                            : reinterpret_cast<const void*>(k_col_conv<T, Z, RT>);
+    LLG_PICK(1) else LLG_PICK(2) else LLG_PICK(4) else LLG_PICK(8)
+#undef LLG_PICK
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, f) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return at.numRegs;
+}
+
 template <typename T>
 static dim3 elem_grid(const BatchDev<T>& b, int per_inst) {
     return dim3((unsigned)((per_inst + 255) / 256), (unsigned)b.ninst);
@@ -1588,6 +1611,7 @@ hipError_t set_lds_limits(size_t bytes) {
     template hipError_t launch_stage_fwd<T>(const BatchDev<T>&, const FwdL&, hipStream_t, hipEvent_t, hipEvent_t);  \
     template hipError_t launch_stage_bwd<T>(const BatchDev<T>&, const BwdL&, hipStream_t, hipEvent_t, hipEvent_t);  \
     template hipError_t launch_col_conv<T>(const BatchDev<T>&, int, int, hipStream_t, hipEvent_t, hipEvent_t);      \
+    template int col_conv_vgprs<T>(int, int);                                                                       \
     template hipError_t launch_levelset<T>(const BatchDev<T>&, double, int, hipStream_t);                           \
     template hipError_t launch_levelset_vjp<T>(const BatchDev<T>&, double, int, hipStream_t);                       \
     template hipError_t launch_adj_init<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                     \

@@ -407,11 +407,31 @@ std::vector<int2> column_work(const llg_handle* h, int tk) {
     return wc;
 }
 
+// The tensor-spectrum tile is staged in LDS only where that costs no resident
+// column block per CU: blocks per CU are the lesser of the LDS bound and the
+// register bound (512 registers per SIMD lane, 4 SIMDs); without the tile the
+// kernel reads the tensor from memory in the multiply.
+bool col_stage_tile(const llg_handle* h, const LaunchCfg& c) {
+    if (!col_nt_lds(h, c.tk)) return false;
+    size_t with = 0, without = 0;
+    for (auto& I : h->inst) {
+        with = std::max(with, col_lds_bytes(h, I, c.tk, true));
+        without = std::max(without, col_lds_bytes(h, I, c.tk, false));
+    }
+    const int regs = h->dtype == LLG_F32 ? col_conv_vgprs<float>(h->max_nz, c.col_r)
+                                         : col_conv_vgprs<double>(h->max_nz, c.col_r);
+    const int waves_simd = regs > 0 ? std::min(8, 512 / round_up(regs, 8)) : 8;
+    const int by_regs = std::max(1, 4 * waves_simd / (c.col_thr / 64));
+    auto by_lds = [](size_t b) { return (int)(163840 / std::max<size_t>(b, 1)); };
+    return std::min(by_lds(with), by_regs) >= std::min(by_lds(without), by_regs);
+}
+
 int apply_cfg(llg_handle* h, const LaunchCfg& c) {
     const std::vector<int2> wc = column_work(h, c.tk);
     HIPCHK(hipMemcpy(h->work_col, wc.data(), wc.size() * sizeof(int2), hipMemcpyHostToDevice));
+    const bool stage_tile = col_stage_tile(h, c);
     size_t col_lds = 0;
-    for (auto& I : h->inst) col_lds = std::max(col_lds, col_lds_bytes(h, I, c.tk));
+    for (auto& I : h->inst) col_lds = std::max(col_lds, col_lds_bytes(h, I, c.tk, stage_tile));
     const size_t loc_lds = loc_lds_bytes(h, 4), bwd_lds = loc_lds_bytes(h, c.nv);
     auto fill = [&](auto& b) {
         b.ncol = (int)wc.size();
@@ -429,7 +449,7 @@ int apply_cfg(llg_handle* h, const LaunchCfg& c) {
     };
     fill(h->bf);
     fill(h->bd);
-    h->bf.col_nt_lds = h->bd.col_nt_lds = col_nt_lds(h, c.tk) ? 1 : 0;
+    h->bf.col_nt_lds = h->bd.col_nt_lds = stage_tile ? 1 : 0;
     const size_t need = std::max(std::max(loc_lds, bwd_lds), col_lds);
     if (need > 65536) {
         hipError_t e = h->dtype == LLG_F32 ? set_lds_limits<float>(need) : set_lds_limits<double>(need);

@@ -194,6 +194,7 @@ class Solver:
         h = ctypes.c_void_p()
         check(lib().llg_create(ctypes.byref(self._pc), ctypes.byref(self._mk), ctypes.byref(h)))
         self.h = h
+        self._fwd_gen = 0  # counts the forward records (forward, autotune) on this handle
         del keep
 
     def close(self):
@@ -237,6 +238,7 @@ class Solver:
         """Time the valid launch configurations and keep the fastest (drops the forward record)."""
         import torch
         check(lib().llg_autotune(self.h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        self._fwd_gen += 1
         return self.launch_config()
 
     def profile_read(self, kind, reset=True):
@@ -282,6 +284,7 @@ class Solver:
         self._t(m0, 3 * self.N)
         m_out = torch.empty_like(m0) if m_out is None else m_out
         J = torch.zeros(1, dtype=torch.float64, device=m0.device)
+        self._fwd_gen += 1
         check(lib().llg_forward(self.h, _ptr(psi), _ptr(m0), float(t0), int(n_steps),
                                 ctypes.byref(obj) if obj is not None else None, _ptr(m_out), _ptr(J), _stream()))
         return m_out, J

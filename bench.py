@@ -50,9 +50,13 @@ class GradientStep:
         self.w = w
         self.td = torch.float64 if w.dtype == "f64" else torch.float32
         dev = torch.device("cuda:0")
+        t0 = time.perf_counter()
         self.solver = llg.Solver(w.problem, dtype=w.dtype, max_steps=w.n_steps, antenna=w.antenna, port1=w.port1,
                                  port2=w.port2, design=w.design)
+        torch.cuda.synchronize()
+        self.t_create = time.perf_counter() - t0  # handle, Newell spectrum, device buffers
         self.solver.set_graphs(graphs)
+        t0 = time.perf_counter()
         if launch_file and os.path.exists(launch_file):
             # a launch configuration fixed by an earlier run (profiling runs reuse it)
             self.solver.set_launch_config(*[int(v) for v in open(launch_file).read().split()])
@@ -62,6 +66,8 @@ class GradientStep:
             if launch_file:
                 with open(launch_file, "w") as fh:
                     fh.write(" ".join(str(v) for v in self.launch) + "\n")
+        torch.cuda.synchronize()
+        self.t_tune = time.perf_counter() - t0
         self.phi = torch.as_tensor(w.phi.reshape(-1), dtype=self.td, device=dev).contiguous()
         self.psi_fixed = torch.as_tensor(w.psi_fixed.reshape(-1), dtype=self.td, device=dev).contiguous()
         self.m0 = torch.as_tensor(w.m0.reshape(-1), dtype=self.td, device=dev).contiguous()
@@ -206,13 +212,18 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
+    ev[0].record()
     for i in range(args.steps):
         J, g = step()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sec = (t1 - t0) / args.steps
-    print(f"[bench] timed {args.steps} steps: {sec * 1e3:.2f} ms per gradient", file=sys.stderr, flush=True)
+    per_step = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+    print(f"[bench] timed {args.steps} steps: {sec * 1e3:.2f} ms per gradient (median {np.median(per_step):.2f} ms)",
+          file=sys.stderr, flush=True)
 
     # per-kernel device time over one more gradient with event bracketing
     s = step.solver
@@ -255,7 +266,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nodes": [w.problem.nx, w.problem.ny, w.problem.nz],
                    "rk4_steps": w.n_steps, "checkpoint": "sqrt", "grad_ms": round(sec * 1e3, 3),
+                   "grad_ms_median": round(float(np.median(per_step)), 3),
                    "hip_graphs": bool(args.graphs), "launch": list(step.launch),
+                   "setup_s": {"create": round(step.t_create, 3), "launch_tuning": round(step.t_tune, 3)},
                    "objective_J": float(J.item())},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -391,6 +391,9 @@ def run_probe(args):
         launch = b.launch_config()
     else:
         launch = b.autotune() if args.autotune else b.launch_config()
+        if args.launch_file:
+            with open(args.launch_file, "w") as fh:
+                fh.write(" ".join(str(v) for v in launch) + "\n")
     psis = [t(w.psi_fixed) for w in ws]
     m0 = [t(w.m0) for w in ws]
     nodes = sum(w.problem.n for w in ws)

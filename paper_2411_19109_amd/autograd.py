@@ -12,10 +12,15 @@ or, with the float64 chain from psi to phi kept inside the library,
 
     J = LevelSetLLG.apply(phi, m0, solver, obj, n_steps, a, psi_fixed, True)
 
-Marshalling only: forward and backward call the C ABI (``llg.Solver``), every
-step runs in the HIP library.  The adjoint walks the checkpoints of the last
-forward on the handle, so a backward after another forward on the same handle
-raises instead of returning a gradient of the wrong trajectory.
+and, for a batch of designs integrated together (one launch per stage for all),
+
+    Js = BatchLevelSetLLG.apply(batch, obj, n_steps, a, psi_fixed_list, True, m0_list, *phis)
+
+Marshalling only: forward and backward call the C ABI (``llg.Solver``,
+``llg.Batch``), every step runs in the HIP library.  The adjoint walks the
+checkpoints of the last forward on the handle, so a backward after another
+forward on the same handle raises instead of returning a gradient of the wrong
+trajectory.
 """
 from __future__ import annotations
 
@@ -124,3 +129,32 @@ class LevelSetLLG(torch.autograd.Function):
         dpsi, dm0 = s.adjoint(ctx.psi, ctx.obj, dJdm_T=ctx.dJdm, dJdpsi_expl=ctx.dJdpsi_e, want_dm0=True)
         dphi = s.levelset_vjp(phi.detach(), dpsi, ctx.a, ctx.extrude)
         return ((gJ * dphi).to(phi.dtype), (gJ * dm0).to(dm0.dtype), None, None, None, None, None, None, None)
+
+
+class BatchLevelSetLLG(torch.autograd.Function):
+    """J_i(phi_i) for every instance of an ``llg.Batch`` (port objective): one
+    forward and one adjoint launch sequence serve all instances.  Returns the
+    vector of J_i; the backward scales instance i's dJ_i/dphi_i by the incoming
+    gradient's entry i."""
+
+    @staticmethod
+    def forward(ctx, batch, obj, n_steps, a, psi_fixed, extrude_z, m0s, *phis):
+        if obj is None or obj.kind != llg.LLG_OBJ_PORT_MY2:
+            raise llg.LLGError(llg.LLG_ENOTSUP, "batched objectives are running (port) costs")
+        phis_d = [p.detach() for p in phis]
+        psis = batch.levelset_to_psi(phis_d, a, psi_fixed, extrude_z)
+        _, J = batch.forward(psis, [m.detach() for m in m0s], n_steps, obj=obj, want_m=False)
+        ctx.batch, ctx.gen, ctx.obj, ctx.a, ctx.extrude, ctx.psis = batch, batch._fwd_gen, obj, a, extrude_z, psis
+        ctx.save_for_backward(*phis)
+        return J
+
+    @staticmethod
+    def backward(ctx, gJ):
+        if ctx.batch._fwd_gen != ctx.gen:
+            raise llg.LLGError(llg.LLG_ESTATE, "the batch ran another forward since this graph was built: "
+                                               "the adjoint would walk the wrong trajectory")
+        phis = ctx.saved_tensors
+        b = ctx.batch
+        dpsis = b.adjoint(ctx.psis, ctx.obj)
+        dphis = b.levelset_vjp([p.detach() for p in phis], dpsis, ctx.a, ctx.extrude)
+        return (None,) * 7 + tuple((gJ[i] * d).to(p.dtype) for i, (d, p) in enumerate(zip(dphis, phis)))

@@ -474,21 +474,6 @@ __device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v
     gather3<1, 1, 1, Node, Bin, C>(nrow_el, lrow, srow, nspec, lspec, sspec, ntw, ltw, stw);
 }
 
-template <typename T, int NV>
-__device__ __forceinline__ void stage_rows(const KParams<T>& p, int r0, const T* const (&src)[NV], const int (&comp)[NV],
-                                           T* R) {
-    const int nx = p.nx;
-    for (int e = threadIdx.x; e < 4 * nx; e += blockDim.x) {
-        const int q = e / nx, x = e - q * nx;
-        const int r = r0 - 1 + q;
-        if (r < 0 || r >= p.nrows) continue;
-        const int i = r * nx + x;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) R[(q * NV + v) * nx + x] = src[v][comp[v] * p.N + i];
-    }
-}
-
-
 // ---------------------------------------------------------------------------
 // batch addressing: thread block -> (instance, unit), role -> buffer
 // ---------------------------------------------------------------------------

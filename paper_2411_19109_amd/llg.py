@@ -346,6 +346,7 @@ class Batch:
         h = ctypes.c_void_p()
         check(lib().llg_batch_create(pcs, mks, self.n, ctypes.byref(h)))
         self.h = h
+        self._fwd_gen = 0  # counts the forward records (forward, autotune) on this batch
         del keep
 
     def close(self):
@@ -382,6 +383,7 @@ class Batch:
         """Time the valid launch configurations and keep the fastest (drops the forward record)."""
         import torch
         check(lib().llg_autotune(self.h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        self._fwd_gen += 1
         return self.launch_config()
 
     def profile_read(self, kind, reset=True):
@@ -408,6 +410,7 @@ class Batch:
         dev = psis[0].device
         m_out = [torch.empty(3 * n, dtype=self.tdtype, device=dev) for n in self.N] if want_m else None
         J = torch.zeros(self.n, dtype=torch.float64, device=dev)
+        self._fwd_gen += 1
         check(lib().llg_batch_forward(self.h, _parr(psis), _parr(m0s), float(t0), int(n_steps),
                                       ctypes.byref(obj) if obj is not None else None,
                                       _parr(m_out) if m_out is not None else None, ctypes.c_void_p(J.data_ptr()),

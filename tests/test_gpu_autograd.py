@@ -2,8 +2,9 @@
 objective chain differentiated by J.backward() gives the same bits as the
 explicit call sequence, matches the oracle's gradient, scales with the
 incoming gradient, and a gradient of <w, m_T> through IntegrateLLG matches
-central differences of the FP64 path; a backward after another forward on the
-handle is refused."""
+central differences of the FP64 path; the batched function gives every
+instance the gradient of the explicit batch call sequence, scaled per instance;
+a backward after another forward on the handle is refused."""
 import numpy as np
 import pytest
 
@@ -112,3 +113,29 @@ def test_backward_after_another_forward_is_refused():
         J.backward()
     torch.cuda.synchronize()
     s.close()
+
+
+def test_batch_levelset_llg_equals_batch_call_sequence():
+    import torch
+    from paper_2411_19109_amd import llg
+    from paper_2411_19109_amd.autograd import BatchLevelSetLLG
+    from test_gpu_batch import antenna_ports, ragged_set, run_batch
+    n = 10
+    ws = antenna_ports(ragged_set(n))
+    say("autograd batch of", len(ws), "ragged instances, f32")
+    ref = run_batch(ws, "f32", n)
+    b = llg.Batch([w.problem for w in ws], dtype="f32", max_steps=n,
+                  masks=[dict(antenna=w.antenna, port1=w.port1, port2=w.port2, design=w.design) for w in ws])
+    obj = llg.make_objective(wl.OBJ_PORT_MY2, n_start=ws[0].obj_n_start)
+    phis = [to_dev(w.phi, "f32").requires_grad_() for w in ws]
+    Js = BatchLevelSetLLG.apply(b, obj, n, ws[0].heaviside_a, [to_dev(w.psi_fixed, "f32") for w in ws], True,
+                                [to_dev(w.m0, "f32") for w in ws], *phis)
+    wts = torch.tensor([1.0, -0.5, 2.0, 0.25][:len(ws)], dtype=torch.float64, device=Js.device)
+    (wts * Js).sum().backward()
+    torch.cuda.synchronize()
+    for i, w in enumerate(ws):
+        assert float(Js[i]) == ref[i]["J"]
+        # the explicit sequence's float64 dJ/dphi, scaled and rounded to phi's dtype
+        want = (float(wts[i]) * ref[i]["dphi"]).astype(np.float32).astype(np.float64)
+        assert np.array_equal(to_np(phis[i].grad), want), i
+    b.close()

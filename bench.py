@@ -5,7 +5,7 @@ n RK4 steps of the LLG equation with checkpoints, the objective, the
 checkpointed discrete adjoint back to t0, and the chain rule to dJ/dphi.
 Inputs are resident in device memory before the timed region starts.
 
-  python bench.py [--steps K] [--warmup W] [--workload particle|waveguide|demux|sweep|probe]
+  python bench.py [--steps K] [--warmup W] [--workload particle|waveguide|demux|device3d|sweep|probe]
 
 Prints ONE JSON line.  The metric is LLG cell-steps per second of the forward
 + adjoint run: nodes * RK4 steps / wall time of one gradient evaluation.
@@ -38,6 +38,8 @@ def make_workload(name):
         return w
     if name == "demux":
         return wl.yig_demux()
+    if name == "device3d":
+        return wl.yig_device_3d()
     raise SystemExit(f"unknown workload {name}")
 
 

@@ -88,6 +88,11 @@ class GradientStep:
         dJdpsi = s.adjoint(psi, self.obj, dJdm_T=dJdm, dJdpsi_expl=dJdpsi_e)
         return J, s.levelset_vjp(self.phi, dJdpsi, w.heaviside_a, extrude_z=True)
 
+    def forward_only(self):
+        s, w = self.solver, self.w
+        psi = s.levelset_to_psi(self.phi, w.heaviside_a, self.psi_fixed, extrude_z=True)
+        return s.forward(psi, self.m0, w.n_steps, obj=self.obj)
+
 
 class SweepStep:
     """The batched sweep: 32 seeded designs x 2 drive frequencies on ragged grids,
@@ -227,6 +232,18 @@ def main():
     print(f"[bench] timed {args.steps} steps: {sec * 1e3:.2f} ms per gradient (median {np.median(per_step):.2f} ms)",
           file=sys.stderr, flush=True)
 
+    # forward alone (level set + RK4 steps with checkpoints), for the forward throughput
+    fwd_ms = []
+    for _ in range(2):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step.forward_only()
+        e1.record()
+        torch.cuda.synchronize()
+        fwd_ms.append(e0.elapsed_time(e1))
+    fwd_ms = min(fwd_ms)
+    print(f"[bench] forward alone: {fwd_ms:.2f} ms", file=sys.stderr, flush=True)
+
     # per-kernel device time over one more gradient with event bracketing
     s = step.solver
     s.profile(True)
@@ -269,6 +286,7 @@ def main():
         "config": {"workload": w.name, "nodes": [w.problem.nx, w.problem.ny, w.problem.nz],
                    "rk4_steps": w.n_steps, "checkpoint": "sqrt", "grad_ms": round(sec * 1e3, 3),
                    "grad_ms_median": round(float(np.median(per_step)), 3),
+                   "forward_ms": round(fwd_ms, 3), "forward_cell_steps_per_s": N * w.n_steps / (fwd_ms * 1e-3),
                    "hip_graphs": bool(args.graphs), "launch": list(step.launch),
                    "setup_s": {"create": round(step.t_create, 3), "launch_tuning": round(step.t_tune, 3)},
                    "objective_J": float(J.item())},

@@ -934,7 +934,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
 // Radix-16 passes need more than the 128 registers a 1024-thread block allows,
 // so that variant is limited to 512 threads.
 template <typename T, int NZ, int MR>
-__global__ void __launch_bounds__(MR >= 16 ? 512 : 1024) k_col_conv(const BatchArgs<T> ba, int TK, int sid, int nt_lds) {
+__global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col_conv(const BatchArgs<T> ba, int TK, int sid, int nt_lds) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 wk = ba.work[blockIdx.x];  // (instance, first bin); XCD-grouped order, also for one instance

@@ -316,13 +316,16 @@ int col_min_threads(const llg_handle* h, int tk, int r) {
     return thr;
 }
 
-// block-size limit of the column kernel variant with largest radix r
-int col_max_threads(int r) { return r >= 16 ? 512 : 1024; }
+// block-size limit of the column kernel variant with largest radix r (its
+// launch bound): radix 16 keeps its butterflies in registers at 512 threads;
+// below, up to 4 planes in z fit the registers of 768 threads without spills,
+// and 5 to 8 planes need up to 1024 threads for 512-point columns
+int col_max_threads(const llg_handle* h, int r) { return r >= 16 ? 512 : h->max_nz > 4 ? 1024 : 768; }
 
 bool col_fits(const llg_handle* h, int tk, int r) {
     for (auto& I : h->inst)
         if (col_lds_bytes(h, I, tk) > 163840) return false;
-    return col_min_threads(h, tk, r) <= col_max_threads(r);
+    return col_min_threads(h, tk, r) <= col_max_threads(h, r);
 }
 
 int check_cfg(const llg_handle* h, const LaunchCfg& c) {
@@ -333,7 +336,7 @@ int check_cfg(const llg_handle* h, const LaunchCfg& c) {
     if (c.tk > spec_tile_of((int)h->tsz)) return fail(LLG_EINVAL, "column tile wider than a spectrum tile (8 in double)");
     if (!col_fits(h, c.tk, c.col_r)) return fail(LLG_ESHAPE, "column tile " + std::to_string(c.tk) + " does not fit");
     const int cmin = col_min_threads(h, c.tk, c.col_r);
-    const int cmax = col_max_threads(c.col_r);
+    const int cmax = col_max_threads(h, c.col_r);
     if (c.col_thr % 64 || c.col_thr < cmin || c.col_thr > cmax)
         return fail(LLG_EINVAL, "column threads must be a multiple of 64 in [" + std::to_string(cmin) + ", " +
                                     std::to_string(cmax) + "]");
@@ -369,7 +372,7 @@ int default_cfg(const llg_handle* h, LaunchCfg& c) {
     if (!col_fits(h, tk, cr)) return fail(LLG_ESHAPE, "y/z extent too large for the column FFT");
     int ct = col_min_threads(h, tk, cr);
     for (auto& I : h->inst)
-        ct = std::max(ct, std::min(col_max_threads(cr), round_up(std::min(I.Py * tk, 256), 64)));
+        ct = std::max(ct, std::min(col_max_threads(h, cr), round_up(std::min(I.Py * tk, 256), 64)));
     c.tk = tk;
     c.col_thr = ct;
     c.col_r = cr;
@@ -1014,7 +1017,7 @@ int autotune_typed(llg_handle* h, hipStream_t s, LaunchCfg& best) {
                 if (tk > spec_tile_of((int)h->tsz) || !col_fits(h, tk, cr)) continue;
                 const int cmin = col_min_threads(h, tk, cr);
                 for (int ct : {cmin, 2 * cmin, 4 * cmin}) {
-                    if (ct > col_max_threads(cr)) continue;
+                    if (ct > col_max_threads(h, cr)) continue;
                     LaunchCfg c = cur;
                     c.tk = tk;
                     c.col_thr = ct;

@@ -172,9 +172,7 @@ struct BatchArgs {
     const KParams<T>* ptab;
     const InstTab* itab;
     const int2* work;
-    int single;
-    KParams<T> p0;
-    InstTab t0;
+    int single;  // one instance: block b works on unit b, no work list
 };
 
 // Device-side description of a batch.
@@ -192,8 +190,6 @@ struct BatchDev {
     int bwd_threads, bwd_radix;          // backward row kernel
     int loc_nv;                          // node values per staged row in the backward row kernel (4 or 7)
     size_t loc_lds, bwd_lds, col_lds;
-    KParams<T> p0;  // instance 0, by value
-    InstTab t0;
 };
 
 // The three per-stage kernels take an optional event pair that the runtime

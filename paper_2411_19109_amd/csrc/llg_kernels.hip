@@ -204,13 +204,44 @@ template <typename T> __device__ __forceinline__ V3<T> cross(V3<T> a, V3<T> b) {
 }
 template <typename T> __device__ __forceinline__ T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
+// The buffers behind the tables and launch descriptors are device global
+// memory.  Accessing them through global-space pointers gives global rather
+// than flat memory instructions: a scalar base with a 32-bit offset, and loads
+// whose completion the LDS waits do not have to drain.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* glb(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+// complex values and 16-byte units move as plain vectors (the HIP vector
+// classes do not bind to global-space references)
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+using vec4 = T __attribute__((ext_vector_type(4)));
+template <typename C>
+__device__ __forceinline__ C gld(const C* p) {
+    using T = decltype(C().x);
+    const vec2<T> v = *(const __attribute__((address_space(1))) vec2<T>*)p;
+    return cmk<C>(v.x, v.y);
+}
+template <typename C>
+__device__ __forceinline__ void gst(C* p, C c) {
+    using T = decltype(C().x);
+    vec2<T> v;
+    v.x = c.x;
+    v.y = c.y;
+    *(__attribute__((address_space(1))) vec2<T>*)p = v;
+}
+
 template <typename T> __device__ __forceinline__ V3<T> ld3(const T* __restrict__ v, int N, int i) {
-    return v3(v[i], v[N + i], v[2 * N + i]);
+    const auto g = glb(v);
+    return v3(g[i], g[N + i], g[2 * N + i]);
 }
 template <typename T> __device__ __forceinline__ void st3(T* __restrict__ v, int N, int i, V3<T> a) {
-    v[i] = a.x;
-    v[N + i] = a.y;
-    v[2 * N + i] = a.z;
+    const auto g = glb(v);
+    g[i] = a.x;
+    g[N + i] = a.y;
+    g[2 * N + i] = a.z;
 }
 
 // Damping of node (ix, iy, iz): linear ramp over ramp_cells nodes from each ramped face.
@@ -272,12 +303,12 @@ __device__ __forceinline__ void unpack_rows_to_lds(const KParams<T>& p, const cp
         const bool cj = k > Px / 2;
         const int kk = cj ? Px - k : k;
         const C* s0 = S + ((size_t)(kk / TW) * p.nrows + r0) * TW + (kk % TW);
-        C ax = s0[0], ay = s0[cs], az = s0[2 * cs];
+        C ax = gld(s0), ay = gld(s0 + cs), az = gld(s0 + 2 * cs);
         C bx = cmk<C>(0, 0), by = bx, bz = bx;
         if (v1) {
-            bx = s0[TW];
-            by = s0[TW + cs];
-            bz = s0[TW + 2 * cs];
+            bx = gld(s0 + TW);
+            by = gld(s0 + TW + cs);
+            bz = gld(s0 + TW + 2 * cs);
         }
         if (cj) {
             ax = cconj(ax); ay = cconj(ay); az = cconj(az);
@@ -309,13 +340,13 @@ __device__ __forceinline__ void pack_lds_to_rows(const KParams<T>& p, cplx<T>* _
             out[2 * s + 1] = cmk<C>(h * dif.y, -h * dif.x);  // spectrum of the imaginary part
         }
         C* d = S + ((size_t)(k / TW) * p.nrows + r0) * TW + (k % TW);
-        d[0] = out[0];
-        d[cs] = out[1];
-        d[2 * cs] = out[4];
+        gst(d, out[0]);
+        gst(d + cs, out[1]);
+        gst(d + 2 * cs, out[4]);
         if (v1) {
-            d[TW] = out[2];
-            d[TW + cs] = out[3];
-            d[TW + 2 * cs] = out[5];
+            gst(d + TW, out[2]);
+            gst(d + TW + cs, out[3]);
+            gst(d + TW + 2 * cs, out[5]);
         }
     }
 }
@@ -425,7 +456,7 @@ __device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v
                 const int i = r * nx + x;
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
-                    if (v < nvu) n.v[q][v] = src[v][comp[v] * N + i];
+                    if (v < nvu) n.v[q][v] = glb(src[v])[comp[v] * N + i];
             }
         }
         return n;
@@ -445,13 +476,13 @@ __device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v
         Bin b;
         const int kk = k > Px / 2 ? Px - k : k;
         const C* s0 = S + ((size_t)(kk / TW) * nrows + r0) * TW + (kk % TW);
-        b.a[0] = s0[0];
-        b.a[1] = s0[cs];
-        b.a[2] = s0[2 * cs];
+        b.a[0] = gld(s0);
+        b.a[1] = gld(s0 + cs);
+        b.a[2] = gld(s0 + 2 * cs);
         if (v1) {
-            b.b[0] = s0[TW];
-            b.b[1] = s0[TW + cs];
-            b.b[2] = s0[TW + 2 * cs];
+            b.b[0] = gld(s0 + TW);
+            b.b[1] = gld(s0 + TW + cs);
+            b.b[2] = gld(s0 + TW + 2 * cs);
         } else {
             b.b[0] = b.b[1] = b.b[2] = cmk<C>(0, 0);
         }
@@ -469,7 +500,7 @@ __device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v
         Z[lp(Px + k)] = cadd(b.b[0], cmul_i(b.b[1]));
         Z[lp(2 * Px + k)] = cadd(b.a[2], cmul_i(b.b[2]));
     };
-    auto ltw = [&](int k) { return tw[k]; };
+    auto ltw = [&](int k) { return gld(tw + k); };
     auto stw = [&](int k, C w) { Tw[k] = w; };
     gather3<1, 1, 1, Node, Bin, C>(nrow_el, lrow, srow, nspec, lspec, sspec, ntw, ltw, stw);
 }
@@ -546,8 +577,8 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[2][512 / 64];
     const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
-    const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
-    const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
+    const KParams<T> p = ba.ptab[wk.x];
+    const InstTab& tb = ba.itab[wk.x];
     const StageFwdArgs<T> a = resolve_fwd<T>(p, tb, L);
     const cplx<T>* __restrict__ twx = role<cplx<T>>(tb, B_TWX);
     const int Px = p.Px, nx = p.nx, N = p.N;
@@ -571,10 +602,10 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
         const int i = r0 * nx + threadIdx.x;  // rows r0, r0+1 are contiguous
         if (need_acc) pre_acc = ld3(a.acc, N, i);
         if (need_mn) pre_mn = ld3(a.mn, N, i);
-        if (a.antenna) pre_ant = a.antenna[i];
+        if (a.antenna) pre_ant = glb(a.antenna)[i];
         if (a.port_part) {
-            pre_p1 = a.port1[i];
-            pre_p2 = a.port2[i];
+            pre_p1 = glb(a.port1)[i];
+            pre_p2 = glb(a.port2)[i];
         }
     }
     {
@@ -622,13 +653,13 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
                 if (x < nx - 1) add(RM(q, x + 1), RP(q, x + 1), p.exw[0]);
                 if (iy > 0) add(RM(q - 1, x), RP(q - 1, x), p.exw[1]);
                 if (iy < p.ny - 1) add(RM(q + 1, x), RP(q + 1, x), p.exw[1]);
-                if (iz > 0) add(ld3(a.ys, N, i - nx * p.ny), a.psi[i - nx * p.ny], p.exw[2]);
-                if (iz < p.nz - 1) add(ld3(a.ys, N, i + nx * p.ny), a.psi[i + nx * p.ny], p.exw[2]);
+                if (iz > 0) add(ld3(a.ys, N, i - nx * p.ny), glb(a.psi)[i - nx * p.ny], p.exw[2]);
+                if (iz < p.nz - 1) add(ld3(a.ys, N, i + nx * p.ny), glb(a.psi)[i + nx * p.ny], p.exw[2]);
                 B = B + Be;
             }
             if (p.terms & 4) {
                 B = B + v3<T>(p.B0[0], p.B0[1], p.B0[2]);
-                const bool ant = a.antenna && (it == (int)threadIdx.x ? pre_ant : a.antenna[i]);
+                const bool ant = a.antenna && (it == (int)threadIdx.x ? pre_ant : glb(a.antenna)[i]);
                 if (ant) B = B + drv * v3<T>(p.brf[0], p.brf[1], p.brf[2]);
             }
             if (p.terms & 8) {
@@ -668,8 +699,8 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             if (a.port_part) {
                 const double my2 = (double)yn.y * (double)yn.y;
                 const bool first_it = it == (int)threadIdx.x;
-                if (first_it ? pre_p1 : a.port1[i]) s1 += my2;
-                if (first_it ? pre_p2 : a.port2[i]) s2 += my2;
+                if (first_it ? pre_p1 : glb(a.port1)[i]) s1 += my2;
+                if (first_it ? pre_p2 : glb(a.port2)[i]) s2 += my2;
             }
             if (a.do_fwd) {
                 // packed forward-FFT input: (x, y) of each row, z of row 0 + i z of row 1
@@ -701,8 +732,8 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
                 t1 += red[0][k];
                 t2 += red[1][k];
             }
-            a.port_part[2 * wk.y] += t1;
-            a.port_part[2 * wk.y + 1] += t2;
+            glb(a.port_part)[2 * wk.y] += t1;
+            glb(a.port_part)[2 * wk.y + 1] += t2;
         }
     }
     if (a.do_fwd) {
@@ -748,18 +779,18 @@ __device__ __forceinline__ BwdIn<T> load_bwd(const StageBwdArgs<T>& a, int N, in
     d.m = d.B = d.v = d.uk = d.lacc = d.yprev = z;
     d.g0 = 0.0;
     d.p1 = d.p2 = 0;
-    d.pi = a.psi[i];
+    d.pi = glb(a.psi)[i];
     d.lam = ld3(a.lamp, N, i);
     if (!seed) {
         d.m = ld3(a.ys, N, i);
         d.B = ld3(a.Bs, N, i);
         d.v = ld3(a.ell, N, i);
         d.uk = ld3(a.u_cur, N, i);
-        d.g0 = a.gpsi[i];
+        d.g0 = glb(a.gpsi)[i];
         if (a.stage < 3) d.lacc = ld3(a.lacc_in, N, i);
         if (a.stage == 0 && a.port1) {
-            d.p1 = a.port1[i];
-            d.p2 = a.port2[i];
+            d.p1 = glb(a.port1)[i];
+            d.p2 = glb(a.port2)[i];
         }
     }
     if (a.y_prev) d.yprev = ld3(a.y_prev, N, i);
@@ -773,8 +804,8 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
     const int nvu = L.stage_m ? 7 : 4;  // without room in LDS, y_s neighbours come from global memory
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
-    const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
-    const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
+    const KParams<T> p = ba.ptab[wk.x];
+    const InstTab& tb = ba.itab[wk.x];
     const StageBwdArgs<T> a = resolve_bwd<T>(p, tb, L);
     const cplx<T>* __restrict__ twx = role<cplx<T>>(tb, B_TWX);
     const int Px = p.Px, nx = p.nx, N = p.N;
@@ -865,8 +896,8 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                     if (iy > 0) nb(RU(q - 1, x), RP(q - 1, x), RM(q - 1, x), p.exw[1]);
                     if (iy < p.ny - 1) nb(RU(q + 1, x), RP(q + 1, x), RM(q + 1, x), p.exw[1]);
                     const int sl = nx * p.ny;
-                    if (iz > 0) nb(ld3(a.u_cur, N, i - sl), a.psi[i - sl], ld3(a.ys, N, i - sl), p.exw[2]);
-                    if (iz < p.nz - 1) nb(ld3(a.u_cur, N, i + sl), a.psi[i + sl], ld3(a.ys, N, i + sl), p.exw[2]);
+                    if (iz > 0) nb(ld3(a.u_cur, N, i - sl), glb(a.psi)[i - sl], ld3(a.ys, N, i - sl), p.exw[2]);
+                    if (iz < p.nz - 1) nb(ld3(a.u_cur, N, i + sl), glb(a.psi)[i + sl], ld3(a.ys, N, i + sl), p.exw[2]);
                 }
                 if (demag_in) {
                     const C z01 = Z[lp(rr * Px + x)];
@@ -879,7 +910,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                     const V3<T> ua = v3<T>(p.u[0], p.u[1], p.u[2]);
                     mu = mu + (p.anis * dot(uk, ua)) * ua;
                 }
-                a.gpsi[i] = d.g0 + g;
+                glb(a.gpsi)[i] = d.g0 + g;
                 const V3<T> lsum = (a.stage == 3 ? d.lam : d.lacc) + mu;
                 if (a.stage > 0) {
                     st3(a.lacc_out, N, i, lsum);
@@ -939,8 +970,8 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 wk = ba.work[blockIdx.x];  // (instance, first bin); XCD-grouped order, also for one instance
     if (wk.y >= (1 << 30)) return;      // empty item that keeps the grouping stride
-    const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
-    const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
+    const KParams<T> p = ba.ptab[wk.x];
+    const InstTab& tb = ba.itab[wk.x];
     C* __restrict__ S = role<C>(tb, sid);
     const T* __restrict__ nhat = role<T>(tb, B_NHAT);
     const C* __restrict__ twy = role<C>(tb, B_TWY);
@@ -986,14 +1017,14 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
             const C* src = Sk + srow(cz, y) + uo;
             if constexpr (CPU == 2) {
                 if (ucnt == 2) {
-                    const float4 q = *reinterpret_cast<const float4*>(src);
+                    const vec4<float> q = *(const __attribute__((address_space(1))) vec4<float>*)src;
                     u.c[0] = cmk<C>(q.x, q.y);
                     u.c[1] = cmk<C>(q.z, q.w);
                 } else {
-                    u.c[0] = src[0];
+                    u.c[0] = gld(src);
                 }
             } else {
-                u.c[0] = src[0];
+                u.c[0] = gld(src);
             }
         }
         return u;
@@ -1017,13 +1048,13 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
     auto ltile = [&](int e) {
         RUnit u;
         const int ro = (e & ((1 << lnr) - 1)) * RPU, q = e >> lnr;
-        const T* src = Nk + (size_t)q * TW + ro;
+        const auto src = glb(Nk + (size_t)q * TW + ro);
         if (rcnt == RPU) {
             if constexpr (sizeof(T) == 4) {
-                const float4 v = *reinterpret_cast<const float4*>(src);
+                const vec4<float> v = *(const __attribute__((address_space(1))) vec4<float>*)src;
                 u.r[0] = v.x, u.r[1] = v.y, u.r[2] = v.z, u.r[3] = v.w;
             } else {
-                const double2 v = *reinterpret_cast<const double2*>(src);
+                const vec2<double> v = *(const __attribute__((address_space(1))) vec2<double>*)src;
                 u.r[0] = v.x, u.r[1] = v.y;
             }
         } else {
@@ -1038,7 +1069,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
         for (int k = 0; k < RPU; ++k)
             if (k < rcnt) Nt[q * TK + ro + k] = u.r[k];
     };
-    auto ltw = [&](int k) { return twy[k]; };
+    auto ltw = [&](int k) { return gld(twy + k); };
     auto stw = [&](int k, C w) { Tw[k] = w; };
     gather3<4, 4, 1, Unit, RUnit, C>(ncolu, lcol, scol, ntu, ltile, stile, Py, ltw, stw);
     __syncthreads();
@@ -1073,14 +1104,14 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
                 C s = X[c][0];
 #pragma unroll
                 for (int z = 1; z < NZ; ++z)
-                    if (z < nz) s = cadd(s, cmul(X[c][z], twz[(kz * z) & (Pz - 1)]));
+                    if (z < nz) s = cadd(s, cmul(X[c][z], gld(twz + ((kz * z) & (Pz - 1)))));
                 h[c] = s;
             }
             const bool fz = kz > Pz / 2;
             const int kzr = fz ? Pz - kz : kz;
             const int base = (kzr * p.Ky2 + kyr) * TK + tk;
             const size_t gbase = (size_t)(kzr * p.Ky2 + kyr) * TW + tk, gstr = (size_t)p.Kz2 * p.Ky2 * TW;
-            auto NT = [&](int comp) -> T { return nt_lds ? Nt[comp * cstr + base] : Nk[comp * gstr + gbase]; };
+            auto NT = [&](int comp) -> T { return nt_lds ? Nt[comp * cstr + base] : glb(Nk)[comp * gstr + gbase]; };
             const T nxx = NT(0), nyy = NT(1), nzz = NT(2);
             const T nxy = fy ? -NT(3) : NT(3);
             T nxz = 0, nyz = 0;
@@ -1096,7 +1127,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
 #pragma unroll
             for (int z = 0; z < NZ; ++z) {
                 if (z >= nz) break;
-                const C w = cconj(twz[(kz * z) & (Pz - 1)]);
+                const C w = cconj(gld(twz + ((kz * z) & (Pz - 1))));
                 Y[0][z] = cadd(Y[0][z], cmul(hx, w));
                 Y[1][z] = cadd(Y[1][z], cmul(hy, w));
                 Y[2][z] = cadd(Y[2][z], cmul(hz, w));
@@ -1117,7 +1148,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
         const int tk = e & (TK - 1);
         const int t = e >> ltk;
         const int y = t & (Py - 1), cz = t >> lpy;
-        if (y < ny && k0 + tk < Kx) Sw[srow(cz, y) + tk] = Z[lp(e)];
+        if (y < ny && k0 + tk < Kx) gst(Sw + srow(cz, y) + tk, Z[lp(e)]);
     }
 }
 
@@ -1261,8 +1292,8 @@ __global__ void __launch_bounds__(512) k_energy(const BatchArgs<T> ba, double t,
     C* Z = reinterpret_cast<C*>(smem_raw);
     __shared__ double red[5][512 / 64];
     const int2 wk = ba.single ? make_int2(0, (int)blockIdx.x) : ba.work[blockIdx.x];
-    const KParams<T> p = ba.single ? ba.p0 : ba.ptab[wk.x];
-    const InstTab& tb = ba.single ? ba.t0 : ba.itab[wk.x];
+    const KParams<T> p = ba.ptab[wk.x];
+    const InstTab& tb = ba.itab[wk.x];
     const T* __restrict__ psi = role<T>(tb, B_PSI);
     const uint8_t* antenna = p.has_ant ? role<uint8_t>(tb, B_ANT) : nullptr;
     const int r0 = 2 * wk.y;
@@ -1404,8 +1435,6 @@ static BatchArgs<T> bargs(const BatchDev<T>& b, const int2* work) {
     a.itab = b.itab;
     a.work = work;
     a.single = b.ninst == 1;
-    a.p0 = b.p0;
-    a.t0 = b.t0;
     return a;
 }
 // Variants by largest FFT radix (4, 8, or 16 in float): the launchers pick

@@ -1217,9 +1217,6 @@ int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_ha
         h->bf.ptab = (const KParams<float>*)h->ptab;
         h->bd.ptab = (const KParams<double>*)h->ptab;
         h->bf.itab = h->bd.itab = h->itab;
-        h->bf.p0 = h->inst[0].pf;
-        h->bd.p0 = h->inst[0].pd;
-        h->bf.t0 = h->bd.t0 = h->inst[0].tab;
     }
     if (hipDeviceSynchronize() != hipSuccess) return bail(fail(LLG_EHIP, "device sync after create failed"));
     *out = h;

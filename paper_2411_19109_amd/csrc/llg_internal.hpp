@@ -189,7 +189,8 @@ struct BatchDev {
     int loc_threads, loc_radix;          // forward row kernel (and the energy kernel's block size)
     int bwd_threads, bwd_radix;          // backward row kernel
     int loc_nv;                          // node values per staged row in the backward row kernel (4 or 7)
-    size_t loc_lds, bwd_lds, col_lds;
+    int fwd_rows;                        // forward row kernel stages its neighbour rows in LDS
+    size_t loc_lds, fwd_lds, bwd_lds, col_lds;  // loc_lds: rows staged (energy kernel)
 };
 
 // The three per-stage kernels take an optional event pair that the runtime
@@ -202,6 +203,8 @@ template <typename T>
 hipError_t launch_col_conv(const BatchDev<T>& b, int max_nz, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T>
 int col_conv_vgprs(int max_nz, int radix);
+template <typename T>
+int stage_fwd_vgprs(int radix, int staged);
 template <typename T> hipError_t launch_levelset(const BatchDev<T>& b, double a, int extrude, hipStream_t s);
 template <typename T> hipError_t launch_levelset_vjp(const BatchDev<T>& b, double a, int extrude, hipStream_t s);
 template <typename T>

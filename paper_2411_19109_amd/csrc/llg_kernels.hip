@@ -376,8 +376,6 @@ __device__ __forceinline__ LocalSmem<T> local_smem(unsigned char* raw, int Px, b
     return L;
 }
 
-// Stage rows r0-1 .. r0+2 of NV arrays src[v] (component-major vectors use
-// stride N) into R; rows outside the grid are left unset (never read).
 // ---------------------------------------------------------------------------
 // batched staging of global data into LDS
 // ---------------------------------------------------------------------------
@@ -570,7 +568,7 @@ __device__ __forceinline__ StageBwdArgs<T> resolve_bwd(const KParams<T>& p, cons
 // forward local kernel: inverse x-FFT (demag) + local field + LL RHS + RK4
 // stage update + forward x-FFT of the next stage's magnetisation
 // ---------------------------------------------------------------------------
-template <typename T, int MR>
+template <typename T, int MR, bool SR>
 __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const FwdL L) {
     using C = cplx<T>;
     constexpr int NV = 4;  // m_x, m_y, m_z, psi
@@ -608,10 +606,13 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             pre_p2 = glb(a.port2)[i];
         }
     }
+    // the neighbour rows r0-1 .. r0+2 of y_s and psi go through LDS (SR), or,
+    // where that would cost a resident block per CU, are read from memory in place
+    constexpr bool srows = SR;
     {
         const T* const src[NV] = {a.ys, a.ys, a.ys, a.psi};
         const int comp[NV] = {0, 1, 2, 0};
-        stage_inputs<T, NV>(p, r0, v1, true, NV, src, comp, R, demag_in ? a.S : nullptr, Z,
+        stage_inputs<T, NV>(p, r0, v1, srows, NV, src, comp, R, demag_in ? a.S : nullptr, Z,
                             demag_any ? twx : nullptr, LS.Tw);
     }
     __syncthreads();
@@ -631,9 +632,13 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             if (iy == p.ny) iy = 0, iz += 1;
             const int i = r * nx + x;
             auto RM = [&](int qq, int xx) {
-                return v3<T>(R[(qq * NV + 0) * nx + xx], R[(qq * NV + 1) * nx + xx], R[(qq * NV + 2) * nx + xx]);
+                if constexpr (!SR) return ld3(a.ys, N, (r0 - 1 + qq) * nx + xx);
+                else return v3<T>(R[(qq * NV + 0) * nx + xx], R[(qq * NV + 1) * nx + xx], R[(qq * NV + 2) * nx + xx]);
             };
-            auto RP = [&](int qq, int xx) { return R[(qq * NV + 3) * nx + xx]; };
+            auto RP = [&](int qq, int xx) {
+                if constexpr (!SR) return glb(a.psi)[(r0 - 1 + qq) * nx + xx];
+                else return R[(qq * NV + 3) * nx + xx];
+            };
             const V3<T> m = RM(q, x);
             const T pi = RP(q, x);
             V3<T> B = v3<T>(0, 0, 0);
@@ -1441,8 +1446,12 @@ static BatchArgs<T> bargs(const BatchDev<T>& b, const int2* work) {
 // the one the batch's launch configuration names.
 template <typename T, int MR>
 static void stage_fwd_r(const BatchDev<T>& b, const FwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((k_stage_fwd<T, MR>), dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.loc_lds, s, e0, e1, 0,
-                          bargs(b, b.work_loc), L);
+    if (b.fwd_rows)
+        hipExtLaunchKernelGGL((k_stage_fwd<T, MR, true>), dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.fwd_lds, s, e0,
+                              e1, 0, bargs(b, b.work_loc), L);
+    else
+        hipExtLaunchKernelGGL((k_stage_fwd<T, MR, false>), dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.fwd_lds, s,
+                              e0, e1, 0, bargs(b, b.work_loc), L);
 }
 template <typename T, int MR>
 static void stage_bwd_r(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -1513,6 +1522,27 @@ int col_conv_vgprs(int max_nz, int radix) {
                             : reinterpret_cast<const void*>(k_col_conv<T, Z, RT>);
     LLG_PICK(1) else LLG_PICK(2) else LLG_PICK(4) else LLG_PICK(8)
 #undef LLG_PICK
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, f) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return at.numRegs;
+}
+
+template <typename T>
+int stage_fwd_vgprs(int radix, int staged) {
+    constexpr int RT = MaxReg<T>::v;
+    const int r = radix == 4 ? 4 : (radix == 8 || sizeof(T) == 8) ? 8 : RT;
+    const void* f;
+    if (staged)
+        f = r == 4 ? reinterpret_cast<const void*>(k_stage_fwd<T, 4, true>)
+            : r == 8 ? reinterpret_cast<const void*>(k_stage_fwd<T, 8, true>)
+                     : reinterpret_cast<const void*>(k_stage_fwd<T, RT, true>);
+    else
+        f = r == 4 ? reinterpret_cast<const void*>(k_stage_fwd<T, 4, false>)
+            : r == 8 ? reinterpret_cast<const void*>(k_stage_fwd<T, 8, false>)
+                     : reinterpret_cast<const void*>(k_stage_fwd<T, RT, false>);
     hipFuncAttributes at;
     if (hipFuncGetAttributes(&at, f) != hipSuccess) {
         (void)hipGetLastError();
@@ -1597,9 +1627,12 @@ hipError_t set_lds_limits(size_t bytes) {
 #define LLG_ATTR(K) \
     if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void*>(K), hipFuncAttributeMaxDynamicSharedMemorySize, v);
     constexpr int RT = MaxReg<T>::v;
-    LLG_ATTR((k_stage_fwd<T, 4>))
-    LLG_ATTR((k_stage_fwd<T, 8>))
-    LLG_ATTR((k_stage_fwd<T, RT>))
+    LLG_ATTR((k_stage_fwd<T, 4, true>))
+    LLG_ATTR((k_stage_fwd<T, 8, true>))
+    LLG_ATTR((k_stage_fwd<T, RT, true>))
+    LLG_ATTR((k_stage_fwd<T, 4, false>))
+    LLG_ATTR((k_stage_fwd<T, 8, false>))
+    LLG_ATTR((k_stage_fwd<T, RT, false>))
     LLG_ATTR((k_stage_bwd<T, 4>))
     LLG_ATTR((k_stage_bwd<T, 8>))
     LLG_ATTR((k_stage_bwd<T, RT>))
@@ -1626,6 +1659,7 @@ hipError_t set_lds_limits(size_t bytes) {
     template hipError_t launch_stage_bwd<T>(const BatchDev<T>&, const BwdL&, hipStream_t, hipEvent_t, hipEvent_t);  \
     template hipError_t launch_col_conv<T>(const BatchDev<T>&, int, int, hipStream_t, hipEvent_t, hipEvent_t);      \
     template int col_conv_vgprs<T>(int, int);                                                                       \
+    template int stage_fwd_vgprs<T>(int, int);                                                                           \
     template hipError_t launch_levelset<T>(const BatchDev<T>&, double, int, hipStream_t);                           \
     template hipError_t launch_levelset_vjp<T>(const BatchDev<T>&, double, int, hipStream_t);                       \
     template hipError_t launch_adj_init<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                     \

@@ -410,10 +410,19 @@ std::vector<int2> column_work(const llg_handle* h, int tk) {
     return wc;
 }
 
+// Blocks of `threads` threads that fit one CU at `lds` bytes of LDS and `regs`
+// registers per lane: the lesser of the LDS bound (160 KiB) and the register
+// bound (512 registers per SIMD lane, 4 SIMDs, at most 8 waves per SIMD).
+int resident_blocks(size_t lds, int regs, int threads) {
+    const int waves_simd = regs > 0 ? std::min(8, 512 / round_up(regs, 8)) : 8;
+    const int by_regs = std::max(1, 4 * waves_simd / std::max(1, threads / 64));
+    const int by_lds = (int)(163840 / std::max<size_t>(lds, 1));
+    return std::min(by_lds, by_regs);
+}
+
 // The tensor-spectrum tile is staged in LDS only where that costs no resident
-// column block per CU: blocks per CU are the lesser of the LDS bound and the
-// register bound (512 registers per SIMD lane, 4 SIMDs); without the tile the
-// kernel reads the tensor from memory in the multiply.
+// column block per CU; without the tile the kernel reads the tensor from
+// memory in the multiply.
 bool col_stage_tile(const llg_handle* h, const LaunchCfg& c) {
     if (!col_nt_lds(h, c.tk)) return false;
     size_t with = 0, without = 0;
@@ -423,10 +432,18 @@ bool col_stage_tile(const llg_handle* h, const LaunchCfg& c) {
     }
     const int regs = h->dtype == LLG_F32 ? col_conv_vgprs<float>(h->max_nz, c.col_r)
                                          : col_conv_vgprs<double>(h->max_nz, c.col_r);
-    const int waves_simd = regs > 0 ? std::min(8, 512 / round_up(regs, 8)) : 8;
-    const int by_regs = std::max(1, 4 * waves_simd / (c.col_thr / 64));
-    auto by_lds = [](size_t b) { return (int)(163840 / std::max<size_t>(b, 1)); };
-    return std::min(by_lds(with), by_regs) >= std::min(by_lds(without), by_regs);
+    return resident_blocks(with, regs, c.col_thr) >= resident_blocks(without, regs, c.col_thr);
+}
+
+// Likewise the forward row kernel stages the neighbour rows of y_s and psi in
+// LDS only where that costs no resident block; otherwise it reads them from
+// memory (wide rows: the 2048-point transforms already fill half the LDS).
+bool fwd_stage_rows(const llg_handle* h, const LaunchCfg& c) {
+    auto regs = [&](int staged) {
+        return h->dtype == LLG_F32 ? stage_fwd_vgprs<float>(c.fwd_r, staged) : stage_fwd_vgprs<double>(c.fwd_r, staged);
+    };
+    return resident_blocks(loc_lds_bytes(h, 4), regs(1), c.fwd_thr) >=
+           resident_blocks(loc_lds_bytes(h, 0), regs(0), c.fwd_thr);
 }
 
 int apply_cfg(llg_handle* h, const LaunchCfg& c) {
@@ -435,7 +452,9 @@ int apply_cfg(llg_handle* h, const LaunchCfg& c) {
     const bool stage_tile = col_stage_tile(h, c);
     size_t col_lds = 0;
     for (auto& I : h->inst) col_lds = std::max(col_lds, col_lds_bytes(h, I, c.tk, stage_tile));
-    const size_t loc_lds = loc_lds_bytes(h, 4), bwd_lds = loc_lds_bytes(h, c.nv);
+    const bool frows = fwd_stage_rows(h, c);
+    const size_t loc_lds = loc_lds_bytes(h, 4), fwd_lds = loc_lds_bytes(h, frows ? 4 : 0),
+                 bwd_lds = loc_lds_bytes(h, c.nv);
     auto fill = [&](auto& b) {
         b.ncol = (int)wc.size();
         b.col_tk = c.tk;
@@ -447,6 +466,8 @@ int apply_cfg(llg_handle* h, const LaunchCfg& c) {
         b.bwd_radix = c.bwd_r;
         b.loc_nv = c.nv;
         b.loc_lds = loc_lds;
+        b.fwd_lds = fwd_lds;
+        b.fwd_rows = frows ? 1 : 0;
         b.bwd_lds = bwd_lds;
         b.col_lds = col_lds;
     };

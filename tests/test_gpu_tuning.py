@@ -79,3 +79,21 @@ def test_autotune_keeps_results():
         assert abs(out[i]["J"] - ref[i]["J"]) <= 1e-4 * abs(ref[i]["J"])
         assert np.abs(out[i]["mT"] - ref[i]["mT"]).max() <= 1e-5
         assert np.linalg.norm(out[i]["dpsi"] - ref[i]["dpsi"]) <= 1e-3 * np.linalg.norm(ref[i]["dpsi"])
+
+
+def test_row_staging_choice_is_bitwise_neutral():
+    """A 512-wide grid where the forward row kernel stages its neighbour rows in
+    LDS at 512 threads (LDS and registers then allow two blocks per CU either
+    way) but reads them from memory at 192 threads (four blocks instead of
+    two): both give the same bits."""
+    from test_gpu_parity import tiny_workload
+    w = tiny_workload(512, 3, 1, kind=wl.OBJ_PORT_MY2, n_steps=6)
+    s = gpu_solver(w, "f32", max_steps=6)
+    base = s.launch_config()
+    outs = []
+    for ft in (512, 192):
+        s.set_launch_config(base[0], base[1], base[2], ft, 16, base[5], base[6], base[7])
+        say("launch", s.launch_config())
+        outs.append(gpu_gradient(w, "f32", solver=s))
+    _same(outs[1], outs[0])
+    s.close()

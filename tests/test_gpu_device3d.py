@@ -66,7 +66,7 @@ def test_device3d_small_forward_vs_oracle_fp64():
     mT, _ = s.forward(to_dev(psi, "f64"), to_dev(w.m0, "f64"), n)
     ref = oracle_sim(w).integrate(w.m0, psi, n).reshape(-1)
     got = to_np(mT)
-    mag = np.repeat(psi.reshape(-1) >= 1e-3, 3)
+    mag = np.tile(psi.reshape(-1) >= 1e-3, 3)  # component-major: x of every node, then y, then z
     err = np.abs(got - ref)[mag].max() / np.abs(ref).max()
     say("relative max-norm on magnetic nodes", err)
     assert err <= 1e-10

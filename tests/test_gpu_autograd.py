@@ -139,3 +139,29 @@ def test_batch_levelset_llg_equals_batch_call_sequence():
         want = (float(wts[i]) * ref[i]["dphi"]).astype(np.float32).astype(np.float64)
         assert np.array_equal(to_np(phis[i].grad), want), i
     b.close()
+
+
+def test_readme_usage():
+    """The usage shown in the README: autotuned FP32 solver on the particle
+    workload, J.backward() through LevelSetLLG, against the oracle gradient of
+    the same map (FP32 tolerance)."""
+    import torch
+    from paper_2411_19109_amd import llg
+    from paper_2411_19109_amd.autograd import LevelSetLLG
+    from _helpers import oracle_gradient
+    w = wl.permalloy_particle(n_steps=200)  # a prefix keeps the oracle quick; the calls are the README's
+    s = llg.Solver(w.problem, dtype="f32", max_steps=w.n_steps, design=w.design)
+    s.autotune()
+    obj = llg.make_objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area)
+    dev = torch.device("cuda:0")
+    phi = torch.as_tensor(w.phi.reshape(-1), dtype=torch.float32, device=dev).requires_grad_()
+    m0 = torch.as_tensor(w.m0.reshape(-1), dtype=torch.float32, device=dev)
+    psi_fixed = torch.as_tensor(w.psi_fixed.reshape(-1), dtype=torch.float32, device=dev)
+    J = LevelSetLLG.apply(phi, m0, s, obj, w.n_steps, w.heaviside_a, psi_fixed, True)
+    J.backward()
+    torch.cuda.synchronize()
+    r = oracle_gradient(w)
+    say("README usage: J", float(J), r["J"], "rel L2 dphi", rel_l2(to_np(phi.grad), r["dphi"]))
+    assert abs(float(J) - r["J"]) <= 1e-4 * abs(r["J"])
+    assert rel_l2(to_np(phi.grad), r["dphi"]) <= 1e-3
+    s.close()

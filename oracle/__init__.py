@@ -16,4 +16,6 @@ Modules
   micromag   effective field, LLG right-hand side, RK4, energies
   adjoint    discrete adjoint of the RK4 map, objectives and gradients
   levelset   smoothed Heaviside map phi -> psi and its derivative
+  rbf        RBF cones and their p-norm level set (amplitudes -> phi), its
+             vector-Jacobian product, and the Adam update of the amplitudes
 """

@@ -15,7 +15,9 @@ The paper keeps Phi in [-1, 1] by renormalising it; here that is a division by
 max |Phi| over the design region.  Readings: coordinates are node indices
 (x = ix, y = iy), c in the same units; dphi and the renormalisation factor are
 recomputed from the current amplitudes on every evaluation and held fixed in
-the derivative (the shift and the scale are chosen, not differentiated).
+the derivative (the shift and the scale are chosen, not differentiated); a
+node whose bases are all 0 (the p-norm's kink, possible when one cone is the
+only one that reaches the shift's node) takes the zero subgradient.
 
 The Adam update follows Kingma & Ba (2015), Algorithm 1, bias-corrected.
 """
@@ -71,8 +73,11 @@ def pnorm_levelset_vjp(s, centers, c, p, design, dJdphi, dphi, scale):
     ny, nx = D.shape
     base = cones(s, centers, c, nx, ny)[:, D] + dphi
     S = np.sum(base ** p, axis=0) ** (1.0 / p)
-    w = (base / S[None]) ** (p - 1)
-    return scale * np.sum(w * np.asarray(dJdphi)[D][None], axis=1)
+    # where every base is 0 the p-norm has its kink at the origin: such a node
+    # contributes nothing (the zero subgradient)
+    live = np.real(S) > 0
+    w = (base[:, live] / S[None, live]) ** (p - 1)
+    return scale * np.sum(w * np.asarray(dJdphi)[D][live][None], axis=1)
 
 
 def adam_step(s, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):

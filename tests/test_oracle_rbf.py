@@ -203,3 +203,18 @@ def test_adam_descends_an_ill_conditioned_quadratic():
             lr *= 0.1
         x, m, v = rbf.adam_step(x, A @ x, m, v, t, lr=lr)
     assert np.abs(x).max() < 1e-2
+
+
+def test_vjp_at_the_kink_takes_the_zero_subgradient():
+    """One cone on a design region: the node where it is smallest has the base
+    0 and a p-norm of 0 (a kink); that node adds nothing, and every other node
+    adds scale * dJ/dphi (one base: (b / S)^(p-1) = 1)."""
+    s, ctr, c = np.array([2.0]), (np.array([1.0]), np.array([1.0])), 1.0
+    design = np.ones((5, 7))
+    phi, dphi, scale = rbf.pnorm_levelset(s, ctr, c, 90.0, design)
+    w = np.ones((5, 7))
+    g = rbf.cones(s, ctr, c, 7, 5)[0]
+    kink = g == g.min()
+    assert kink.sum() == 1
+    got = rbf.pnorm_levelset_vjp(s, ctr, c, 90.0, design, w, dphi, scale)
+    assert got[0] == pytest.approx(scale * (w.size - 1), rel=1e-14)

@@ -258,6 +258,49 @@ int llg_profile_read(llg_handle* h, int32_t kind, double* ms, int64_t* launches,
 /* Padded FFT sizes the handle uses (Px, Py, Pz); of the first instance of a batch. */
 int llg_fft_sizes(const llg_handle* h, int32_t* P3);
 
+/* ---- RBF level set and the amplitude update ----------------------------
+ * The level set as a function of RBF amplitudes s (n_rbf of them), handle-free.
+ * Eq. 2: cone g_i(x, y) = s_i - sqrt((x - x_i)^2 + (y - y_i)^2 + c^2), with x, y
+ * node indices (x = ix, y = iy) and c in the same units.  Eq. 3: on the design
+ * region Phi = [sum_i (g_i + dphi)^p]^(1/p) - dphi, dphi = |smallest g_i on the
+ * design region|; then (the paragraph after Eq. 3) Phi is renormalised into
+ * [-1, 1] by dividing by its largest magnitude on the design region when
+ * normalize != 0.  Phi = 0 off the design region.  All pointers are device
+ * pointers; centers holds 2 n_rbf doubles (x_0..x_{n-1}, then y_0..y_{n-1}), s
+ * n_rbf doubles, design nx*ny bytes (row-major, x fastest; non-zero = design).
+ * Outputs are written on `stream`; nothing is allocated.  Results depend only
+ * on the inputs and the sizes (fixed reduction orders).
+ * Errors: LLG_EINVAL (NULL pointer, dtype, p < 1, n_rbf outside 1..131072,
+ * non-finite c), LLG_ESHAPE (nx*ny outside 1..2^30), LLG_EHIP. */
+
+/* Doubles of device workspace that llg_rbf_levelset and llg_rbf_levelset_vjp
+ * need for this size (the caller allocates it; one buffer serves both calls). */
+int llg_rbf_work_len(int32_t nx, int32_t ny, int32_t n_rbf, int64_t* len);
+
+/* Phi (nx*ny, dtype) from s.  pnorm_out (nullable, nx*ny, dtype) receives the
+ * p-norm S = Phi_raw + dphi that the VJP needs.  On return work[0] = dphi and
+ * work[1] = the renormalisation factor (1 / max |Phi_raw|, or 1); the VJP reads
+ * both from the same buffer. */
+int llg_rbf_levelset(int32_t dtype, int32_t nx, int32_t ny, int32_t n_rbf, const double* centers, const double* s,
+                     double c, double p, const uint8_t* design, int normalize, void* phi_out, void* pnorm_out,
+                     double* work, hipStream_t stream);
+
+/* dJ/ds (n_rbf doubles) from dJ/dPhi (nx*ny doubles, as llg_levelset_to_Ms_vjp
+ * writes it):  dJ/ds_i = f sum_x dJ/dPhi(x) ((g_i(x) + dphi) / S(x))^(p - 1)
+ * over design nodes, with dphi, f (work[0], work[1]) and S (pnorm) from the
+ * llg_rbf_levelset call on the same s: the shift and the scale are held fixed. */
+int llg_rbf_levelset_vjp(int32_t dtype, int32_t nx, int32_t ny, int32_t n_rbf, const double* centers,
+                         const double* s, double c, double p, const uint8_t* design, const double* dJdphi,
+                         const void* pnorm, double* work, double* dJds_out, hipStream_t stream);
+
+/* One Adam step on n device doubles, in place (the amplitude update of Eq. 5
+ * with Adam's adaptive moments, Kingma & Ba's Algorithm 1 with bias
+ * correction): m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+ * s -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).  t >= 1 counts
+ * steps; m and v start at zero.  Errors: LLG_EINVAL, LLG_EHIP. */
+int llg_adam_step(int32_t n, double* s, const double* grad, double* m, double* v, int64_t t, double lr, double beta1,
+                  double beta2, double eps, hipStream_t stream);
+
 /* ---- batched execution ------------------------------------------------
  * Many level-set designs and drive frequencies, on grids of different sizes,
  * integrated together (the optimisation sweep of many initial level sets at

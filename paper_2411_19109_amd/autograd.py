@@ -12,6 +12,13 @@ or, with the float64 chain from psi to phi kept inside the library,
 
     J = LevelSetLLG.apply(phi, m0, solver, obj, n_steps, a, psi_fixed, True)
 
+and with the RBF amplitudes s as the design variables (Eqs. 2, 3), closing the
+loop with an Adam step on s,
+
+    phi = RBFLevelSetFn.apply(s, rbf)          # rbf: llg.RBFLevelSet
+    J = LevelSetLLG.apply(phi, m0, solver, obj, n_steps, a, psi_fixed, True)
+    J.backward(); adam.step(s.data, s.grad)    # adam: llg.Adam
+
 and, for a batch of designs integrated together (one launch per stage for all),
 
     Js = BatchLevelSetLLG.apply(batch, obj, n_steps, a, psi_fixed_list, True, m0_list, *phis)
@@ -158,3 +165,22 @@ class BatchLevelSetLLG(torch.autograd.Function):
         dpsis = b.adjoint(ctx.psis, ctx.obj)
         dphis = b.levelset_vjp([p.detach() for p in phis], dpsis, ctx.a, ctx.extrude)
         return (None,) * 7 + tuple((gJ[i] * d).to(p.dtype) for i, (d, p) in enumerate(zip(dphis, phis)))
+
+
+class RBFLevelSetFn(torch.autograd.Function):
+    """phi(s): the renormalised p-norm of the RBF cones (Eqs. 2, 3), float64
+    amplitudes in, phi in the RBF map's precision out.  Backward: dJ/ds with
+    the shift and the renormalisation factor held at their forward values."""
+
+    @staticmethod
+    def forward(ctx, s, rbf):
+        phi, pnorm, work = rbf.levelset(s.detach())
+        ctx.rbf, ctx.pnorm, ctx.work = rbf, pnorm, work
+        ctx.save_for_backward(s)
+        return phi
+
+    @staticmethod
+    def backward(ctx, g_phi):
+        (s,) = ctx.saved_tensors
+        ds = ctx.rbf.vjp(s.detach(), g_phi.to(torch.float64).contiguous(), ctx.pnorm, ctx.work)
+        return ds, None

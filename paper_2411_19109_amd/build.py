@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libllg.so")
 
-SOURCES = ["llg_kernels.hip", "llg_runtime.cpp", "llg_schedule.cpp", "newell_host.cpp"]
+SOURCES = ["llg_kernels.hip", "llg_rbf.hip", "llg_runtime.cpp", "llg_schedule.cpp", "newell_host.cpp"]
 ARCH = os.environ.get("LLG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]

@@ -223,6 +223,9 @@ hipError_t launch_energy_finish(const BatchDev<T>& b, double MsV, double lam, do
                                 double* en, double* dJdpsi, hipStream_t s);
 template <typename T> hipError_t set_lds_limits(size_t bytes);
 
+// Records msg as the text llg_last_error() returns on this thread; returns code.
+int set_error(int code, const char* msg);
+
 // Host side: tensor spectrum (float64) in the kernel layout, scaled by -mu0 Ms / (Px Py Pz).
 void build_tensor_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, int Px, int Py, int Pz,
                            double scale, std::vector<double>& out, int& ncomp);

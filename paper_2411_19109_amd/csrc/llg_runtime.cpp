@@ -1396,6 +1396,8 @@ int b_adjoint(llg_handle* h, const void* const* psi, const void* const* dJdm_T, 
 
 }  // namespace
 
+int llg::set_error(int code, const char* msg) { return fail(code, msg); }
+
 extern "C" {
 
 const char* llg_last_error(void) { return g_err.c_str(); }

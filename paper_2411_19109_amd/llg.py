@@ -26,7 +26,8 @@ EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_le
            "llg_query_memory", "llg_query_recompute", "llg_set_graphs", "llg_launch_config",
            "llg_set_launch_config", "llg_autotune", "llg_fft_sizes", "llg_profile", "llg_profile_read", "llg_batch_create",
            "llg_batch_destroy", "llg_batch_size", "llg_batch_levelset_to_Ms", "llg_batch_levelset_to_Ms_vjp",
-           "llg_batch_forward", "llg_batch_adjoint"]
+           "llg_batch_forward", "llg_batch_adjoint", "llg_rbf_work_len", "llg_rbf_levelset", "llg_rbf_levelset_vjp",
+           "llg_adam_step"]
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
 KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col_conv", KIND_STAGE_BWD: "k_stage_bwd"}
 
@@ -103,6 +104,10 @@ def lib():
         "llg_batch_forward": [vp, vp, vp, dbl, i64, ctypes.POINTER(Objective_c), vp, vp, vp],
         "llg_batch_adjoint": [vp, vp, vp, vp, ctypes.POINTER(Objective_c), vp, vp, vp],
         "llg_profile_read": [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
+        "llg_rbf_work_len": [i32, i32, i32, ctypes.POINTER(i64)],
+        "llg_rbf_levelset": [i32, i32, i32, i32, vp, vp, dbl, dbl, vp, ctypes.c_int, vp, vp, vp, vp],
+        "llg_rbf_levelset_vjp": [i32, i32, i32, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp, vp],
+        "llg_adam_step": [i32, vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -427,3 +432,95 @@ class Batch:
                                       ctypes.byref(obj) if obj is not None else None, _parr(g),
                                       _parr(dm0) if dm0 is not None else None, _stream()))
         return (g, dm0) if want_dm0 else g
+
+
+class RBFLevelSet:
+    """Level set from RBF amplitudes (Eqs. 2, 3 and the renormalisation after
+    Eq. 3) on an nx x ny node grid: fixed centres (node units), c, p and design
+    mask; the amplitudes s are the argument of each call (wraps
+    llg_rbf_levelset / llg_rbf_levelset_vjp)."""
+
+    def __init__(self, centers_x, centers_y, c, p, design, dtype="f32", normalize=True, device="cuda"):
+        import torch
+        D = np.asarray(design)
+        if D.ndim != 2:
+            raise ValueError("design must be a 2D (ny, nx) mask")
+        self.ny, self.nx = D.shape
+        xc = np.asarray(centers_x, np.float64).reshape(-1)
+        yc = np.asarray(centers_y, np.float64).reshape(-1)
+        if xc.shape != yc.shape or xc.size < 1:
+            raise ValueError("centers_x and centers_y must have the same length >= 1")
+        self.n = xc.size
+        self.c, self.p, self.normalize = float(c), float(p), bool(normalize)
+        self.dtype = LLG_F64 if dtype in ("f64", "float64", LLG_F64) else LLG_F32
+        self.tdtype = torch.float64 if self.dtype == LLG_F64 else torch.float32
+        self.device = torch.device(device)
+        self.centers = torch.as_tensor(np.concatenate([xc, yc]), dtype=torch.float64, device=self.device)
+        self.design = torch.as_tensor(np.ascontiguousarray(D != 0).astype(np.uint8).reshape(-1), device=self.device)
+        v = ctypes.c_int64(0)
+        check(lib().llg_rbf_work_len(self.nx, self.ny, self.n, ctypes.byref(v)))
+        self.work_len = v.value
+
+    def _s(self, s):
+        import torch
+        if s.dtype != torch.float64 or not s.is_cuda or not s.is_contiguous() or s.numel() != self.n:
+            raise ValueError(f"expected a contiguous cuda tensor of {self.n} float64 amplitudes")
+        return s
+
+    def new_work(self):
+        import torch
+        return torch.empty(self.work_len, dtype=torch.float64, device=self.device)
+
+    def levelset(self, s, want_pnorm=True, work=None):
+        """(phi, pnorm, work): phi (nx*ny), the p-norm S for the VJP, and the
+        workspace whose first two entries hold dphi and the scale."""
+        import torch
+        self._s(s)
+        N = self.nx * self.ny
+        phi = torch.empty(N, dtype=self.tdtype, device=self.device)
+        pn = torch.empty(N, dtype=self.tdtype, device=self.device) if want_pnorm else None
+        work = self.new_work() if work is None else work
+        check(lib().llg_rbf_levelset(self.dtype, self.nx, self.ny, self.n, _ptr(self.centers), _ptr(s), self.c, self.p,
+                                     _ptr(self.design), int(self.normalize), _ptr(phi), _ptr(pn), _ptr(work),
+                                     _stream()))
+        return phi, pn, work
+
+    def vjp(self, s, dJdphi, pnorm, work):
+        """dJ/ds (float64, n) from dJ/dphi (float64, nx*ny) and the pnorm and
+        work of the levelset() call on the same s."""
+        import torch
+        self._s(s)
+        if dJdphi.dtype != torch.float64 or dJdphi.numel() != self.nx * self.ny or not dJdphi.is_contiguous():
+            raise ValueError("dJdphi must be a contiguous float64 tensor of nx*ny entries")
+        if pnorm is None or pnorm.dtype != self.tdtype or pnorm.numel() != self.nx * self.ny:
+            raise ValueError("pnorm must be the p-norm returned by levelset() for this s")
+        if work is None or work.numel() != self.work_len:
+            raise ValueError("work must be the workspace of the levelset() call")
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        check(lib().llg_rbf_levelset_vjp(self.dtype, self.nx, self.ny, self.n, _ptr(self.centers), _ptr(s), self.c,
+                                         self.p, _ptr(self.design), _ptr(dJdphi), _ptr(pnorm), _ptr(work), _ptr(out),
+                                         _stream()))
+        return out
+
+
+class Adam:
+    """Adam moments of a float64 parameter vector on the device; step() updates
+    it in place (wraps llg_adam_step)."""
+
+    def __init__(self, n, lr, betas=(0.9, 0.999), eps=1e-8, device="cuda"):
+        import torch
+        self.lr, self.b1, self.b2, self.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
+        self.m = torch.zeros(n, dtype=torch.float64, device=device)
+        self.v = torch.zeros(n, dtype=torch.float64, device=device)
+        self.t = 0
+        self.n = n
+
+    def step(self, s, grad, lr=None):
+        import torch
+        for x in (s, grad):
+            if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != self.n:
+                raise ValueError(f"expected contiguous cuda float64 tensors of {self.n} entries")
+        self.t += 1
+        check(lib().llg_adam_step(self.n, _ptr(s), _ptr(grad), _ptr(self.m), _ptr(self.v), self.t,
+                                  self.lr if lr is None else float(lr), self.b1, self.b2, self.eps, _stream()))
+        return s

@@ -169,6 +169,31 @@ def random_design_phi(rng: np.random.Generator, ny: int, nx: int, box, sigma: fl
     return phi
 
 
+def rbf_layout(box, n_side: int = 20, holes: int = 4, seed: int = 0, p: float = 90.0):
+    """RBF parameterisation of a square design region box = (x0, y0, D) (nodes):
+    n_side x n_side centres evenly spaced over it (the paper's 20 x 20 array),
+    shape constant c = centre spacing h, and initial amplitudes forming a
+    holes x holes grid of holes (the paper's 4 x 4 initial design): s = 1.5 h
+    (material everywhere: the worst point between four centres still has a
+    positive cone) except -1.5 h for centres within 2 h of a hole centre, plus a
+    seeded U(-0.05, 0.05) h jitter.  holes = 0 gives a jittered uniform start."""
+    x0, y0, D = box
+    h = D / n_side
+    k = (np.arange(n_side) + 0.5) * h
+    XC, YC = np.meshgrid(x0 - 0.5 + k, y0 - 0.5 + k, indexing="xy")
+    xc, yc = XC.reshape(-1), YC.reshape(-1)
+    s = np.full(xc.size, 1.5 * h)
+    if holes > 0:
+        hc = (np.arange(holes) + 0.5) * D / holes
+        for hy in hc:
+            for hx in hc:
+                near = np.hypot(xc - (x0 - 0.5 + hx), yc - (y0 - 0.5 + hy)) <= 2.0 * h
+                s[near] = -1.5 * h
+    rng = np.random.default_rng(seed)
+    s += rng.uniform(-0.05, 0.05, s.size) * h
+    return dict(xc=xc, yc=yc, c=h, p=p, s=s)
+
+
 # ----------------------------------------------------------------------------
 # The five workloads
 # ----------------------------------------------------------------------------

@@ -139,3 +139,32 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(llg, "LIB_PATH", os.path.join(ROOT, "no_such_libllg.so"))
     with pytest.raises(RuntimeError, match="not built"):
         llg.lib()
+
+
+def test_rbf_work_len_and_host_side_rejections():
+    L = llg.lib()
+    v = ctypes.c_int64(0)
+    assert L.llg_rbf_work_len(64, 64, 400, ctypes.byref(v)) == llg.LLG_OK
+    assert v.value > 2 + 400
+    assert L.llg_rbf_work_len(0, 64, 400, ctypes.byref(v)) == llg.LLG_ESHAPE
+    assert L.llg_rbf_work_len(64, 64, 0, ctypes.byref(v)) == llg.LLG_EINVAL
+    assert L.llg_rbf_work_len(64, 64, 400, None) == llg.LLG_EINVAL
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails its host checks first
+    args = dict(dtype=llg.LLG_F32, nx=8, ny=8, n=4, c=1.0, p=90.0)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return L.llg_rbf_levelset(a["dtype"], a["nx"], a["ny"], a["n"], fake, fake, a["c"], a["p"], fake, 1,
+                                  kw.get("phi", fake), None, fake, None)
+    assert call(dtype=5) == llg.LLG_EINVAL
+    assert call(p=0.5) == llg.LLG_EINVAL
+    assert call(p=float("nan")) == llg.LLG_EINVAL
+    assert call(c=float("inf")) == llg.LLG_EINVAL
+    assert call(nx=-1) == llg.LLG_ESHAPE
+    assert call(phi=None) == llg.LLG_EINVAL
+    assert "NULL" in L.llg_last_error().decode()
+    assert L.llg_rbf_levelset_vjp(llg.LLG_F64, 8, 8, 4, fake, fake, 1.0, 90.0, fake, fake, None, fake, fake,
+                                  None) == llg.LLG_EINVAL
+    assert L.llg_adam_step(4, fake, fake, fake, fake, 0, 1e-2, 0.9, 0.999, 1e-8, None) == llg.LLG_EINVAL
+    assert L.llg_adam_step(4, fake, fake, fake, fake, 1, 1e-2, 1.0, 0.999, 1e-8, None) == llg.LLG_EINVAL
+    assert L.llg_adam_step(4, None, fake, fake, fake, 1, 1e-2, 0.9, 0.999, 1e-8, None) == llg.LLG_EINVAL

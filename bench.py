@@ -5,7 +5,7 @@ n RK4 steps of the LLG equation with checkpoints, the objective, the
 checkpointed discrete adjoint back to t0, and the chain rule to dJ/dphi.
 Inputs are resident in device memory before the timed region starts.
 
-  python bench.py [--steps K] [--warmup W] [--workload particle|waveguide|demux|device3d|sweep|probe]
+  python bench.py [--steps K] [--warmup W] [--workload particle|waveguide|demux|device3d|sweep|probe|rbf]
 
 Prints ONE JSON line.  The metric is LLG cell-steps per second of the forward
 + adjoint run: nodes * RK4 steps / wall time of one gradient evaluation.
@@ -209,6 +209,8 @@ def main():
         return run_sweep(args)
     if args.workload == "probe":
         return run_probe(args)
+    if args.workload == "rbf":
+        return run_rbf(args)
     w = make_workload(args.workload)
     if args.n_steps > 0:
         w.n_steps = args.n_steps
@@ -301,7 +303,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def measured_traffic(workload, kernel, launch):
+def measured_traffic(workload, kernel, launch, source="llg_kernels.hip"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary of this workload (copy-calibrated), or None when there is
     none or it was taken on another kernel source or launch configuration."""
@@ -313,7 +315,7 @@ def measured_traffic(workload, kernel, launch):
     for line in open(path):
         if line.startswith("{"):
             rec = json.loads(line)
-    if not rec or rec.get("kernel_source_sha256") != profsum.kernel_source_hash():
+    if not rec or rec.get("kernel_source_sha256") != profsum.kernel_source_hash(source):
         return None
     if rec.get("launch") is not None and list(rec["launch"]) != list(launch):
         return None
@@ -464,6 +466,172 @@ def run_probe(args):
         "config": {"workload": name, "nodes": nodes, "rk4_steps": n, "launch": list(launch)},
         "roofline": roofline,
         "kernels": {k: dict(avg_us=round(v["avg_us"], 2), gbs=round(v["gbs"], 1)) for k, v in kinds.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+# VALU issue rate of the chip: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
+# (one non-packed VALU instruction per lane per clock).  Transcendental
+# instructions (sqrt, log2, exp2) issue at half that rate on CDNA 4, so one
+# counts as two issue slots.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# Arithmetic per node-RBF pair of each kernel (plain VALU ops, transcendentals):
+# cones: 2 sub, 2 fma, sub, min, max + sqrt; p-norm: 2 sub, 2 fma, sub, max, mul,
+# mul, add + sqrt, log2, exp2; VJP: 2 sub, 2 fma, sub, max, fma, fma + sqrt,
+# log2, exp2.  Per-node work (loads, coordinates, the node's own log2) is not
+# counted: the bound is the pair arithmetic alone.
+RBF_PAIR_OPS = {"k_rbf_cones": (7, 1), "k_rbf_pnorm": (9, 3), "k_rbf_vjp": (8, 3)}
+
+
+def rbf_pair_peak(kernel):
+    plain, trans = RBF_PAIR_OPS[kernel]
+    return VALU_LANE_OPS / (plain + 2 * trans)
+
+
+def rbf_step_factory(nx, ny, n_side, dtype="f32", seed=7):
+    """One design update of the RBF stage on an nx x ny design region: phi from
+    s, dJ/ds from a fixed dJ/dphi, an Adam step on s."""
+    import torch
+    from paper_2411_19109_amd import llg, workloads as wl
+    D = min(nx, ny)
+    lay = wl.rbf_layout((0, 0, D), n_side=n_side, holes=4, seed=seed)
+    if nx != ny:   # stretch the square array over the whole rectangle
+        lay["xc"] = lay["xc"] * (nx / D)
+        lay["yc"] = lay["yc"] * (ny / D)
+    design = np.ones((ny, nx), np.uint8)
+    m = llg.RBFLevelSet(lay["xc"], lay["yc"], lay["c"], lay["p"], design, dtype=dtype)
+    s = torch.as_tensor(lay["s"], dtype=torch.float64, device="cuda")
+    g = torch.as_tensor(np.random.default_rng(seed).standard_normal(nx * ny), dtype=torch.float64, device="cuda")
+    opt = llg.Adam(s.numel(), lr=1e-3)
+    work = m.new_work()
+
+    def step():
+        phi, pn, _ = m.levelset(s, work=work)
+        ds = m.vjp(s, g, pn, work)
+        opt.step(s, ds)
+        return phi, ds
+    return step, lay, m
+
+
+def rbf_cpu_baseline(budget_s=15.0):
+    """The oracle's level set and VJP on a band of rows of the same 1024-wide
+    film with the same 400 RBFs, sized to about budget_s of host time."""
+    from oracle import rbf as orbf
+    from paper_2411_19109_amd import workloads as wl
+    lay = wl.rbf_layout((0, 0, 1024), n_side=20, holes=4, seed=7)
+    ctr = (lay["xc"], lay["yc"])
+
+    def run(rows):
+        design = np.ones((rows, 1024))
+        t0 = time.perf_counter()
+        phi, dphi, sc = orbf.pnorm_levelset(lay["s"], ctr, lay["c"], lay["p"], design)
+        orbf.pnorm_levelset_vjp(lay["s"], ctr, lay["c"], lay["p"], design, np.ones_like(phi), dphi, sc)
+        return time.perf_counter() - t0
+    rows = 2
+    dt = run(rows)
+    rows = int(max(2, min(1024, rows * budget_s / max(dt, 1e-3))))
+    dt = run(rows)
+    pairs = rows * 1024 * lay["xc"].size
+    return dict(value=pairs / dt, unit="pairs/s", cores=1, kind="oracle",
+                sample=f"float64 NumPy oracle, level set + VJP of {rows} rows x 1024 nodes x {lay['xc'].size} RBFs "
+                       f"({dt:.1f} s, one host thread)")
+
+
+def run_rbf(args):
+    """The RBF stage of the design loop (Eqs. 2, 3, renormalisation, VJP, Adam)
+    at scale: a 1024x1024-node design region with the paper's 20x20 RBF array
+    (FP32), plus the paper's own sizes (the particle's 64x64 mesh and the
+    demultiplexer's 256x96 grid with its 60x60 design square) timed per update."""
+    import torch
+    from paper_2411_19109_amd import llg
+    nx = ny = 1024
+    step, lay, m = rbf_step_factory(nx, ny, 20)
+    n = lay["xc"].size
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    pairs = nx * ny * n
+    print(f"[bench] rbf {nx}x{ny}, {n} RBFs: {sec * 1e6:.1f} us per update "
+          f"(events {e0.elapsed_time(e1) / args.steps * 1e3:.1f} us)", file=sys.stderr, flush=True)
+
+    # the paper's sizes, one update each (launch-bound at these sizes)
+    small = {}
+    from paper_2411_19109_amd import workloads as wl
+    for name, (sx, sy, box) in {"particle_64x64": (64, 64, (0, 0, 64)),
+                                 "demux_256x96": (256, 96, wl.yig_demux(n_steps=10).extra["box"])}.items():
+        sl = wl.rbf_layout(box, n_side=20, holes=4, seed=1)
+        d2 = np.zeros((sy, sx), np.uint8)
+        d2[box[1]:box[1] + box[2], box[0]:box[0] + box[2]] = 1
+        sm = llg.RBFLevelSet(sl["xc"], sl["yc"], sl["c"], sl["p"], d2, dtype="f32")
+        ss = torch.as_tensor(sl["s"], dtype=torch.float64, device="cuda")
+        gg = torch.ones(sx * sy, dtype=torch.float64, device="cuda")
+        opt = llg.Adam(ss.numel(), lr=1e-3)
+        wk = sm.new_work()
+
+        def upd():
+            phi, pn, _ = sm.levelset(ss, work=wk)
+            opt.step(ss, sm.vjp(ss, gg, pn, wk))
+        for _ in range(3):
+            upd()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(50):
+            upd()
+        torch.cuda.synchronize()
+        small[name] = round((time.perf_counter() - t0) / 50 * 1e6, 1)
+        print(f"[bench] rbf {name}: {small[name]} us per update", file=sys.stderr, flush=True)
+
+    roofline, kinds = None, {}
+    if not args.no_kernel_events:
+        llg.rbf_profile(True)
+        step()
+        torch.cuda.synchronize()
+        llg.rbf_profile(False)
+        for k, kn in llg.RBF_KIND_NAMES.items():
+            ms, nl, pr = llg.rbf_profile_read(k)
+            if nl:
+                rate = pr / (ms * 1e-3)
+                peak = rbf_pair_peak(kn)
+                kinds[kn] = dict(avg_us=round(1e3 * ms / nl, 2), gpairs=round(rate / 1e9, 1),
+                                 peak_gpairs=round(peak / 1e9, 1), frac=round(rate / peak, 4))
+                print(f"[bench] {kn}: {nl} launches, avg {1e3 * ms / nl:.1f} us, {rate / 1e9:.1f} Gpairs/s "
+                      f"({rate / peak:.3f} of the ALU bound {peak / 1e9:.0f})", file=sys.stderr, flush=True)
+        dom = max(kinds, key=lambda k: kinds[k]["avg_us"])
+        d = kinds[dom]
+        roofline = dict(bound="alu", achieved=d["gpairs"], peak=d["peak_gpairs"], unit="Gpairs/s", frac=d["frac"],
+                        traffic=measured_traffic(f"rbf_levelset_film_{nx}x{ny}_{n}rbf", dom, None, "llg_rbf.hip"),
+                        kernel=dom, avg_launch_us=d["avg_us"], pairs_per_launch=pairs,
+                        ops_per_pair=dict(zip(("plain", "transcendental"), RBF_PAIR_OPS[dom])))
+    cpu = None
+    if not args.no_cpu:
+        cpu = rbf_cpu_baseline(args.cpu_budget)
+        print(f"[bench] cpu baseline: {cpu['sample']}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "RBF level set + VJP + Adam: node-RBF pairs/s",
+        "value": pairs / sec,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"rbf_levelset_film_{nx}x{ny}_{n}rbf", "nodes": nx * ny, "n_rbf": n, "p": lay["p"],
+                   "update_us": round(sec * 1e6, 1), "paper_sizes_us_per_update": small},
+        "roofline": roofline,
+        "kernels": kinds,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

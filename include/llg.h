@@ -293,6 +293,18 @@ int llg_rbf_levelset_vjp(int32_t dtype, int32_t nx, int32_t ny, int32_t n_rbf, c
                          const double* s, double c, double p, const uint8_t* design, const double* dJdphi,
                          const void* pnorm, double* work, double* dJds_out, hipStream_t stream);
 
+/* Device time of the RBF pair kernels (process-wide, all streams): with
+ * profiling on, every launch of the kinds below carries a start/end event
+ * pair bound to its dispatch; llg_rbf_profile_read synchronises on the
+ * recorded events and returns the summed milliseconds, the launch count and
+ * the node-RBF pairs (nx*ny*n_rbf per launch) of a kind since the last reset. */
+#define LLG_RBF_KIND_CONES 0 /* pass 1: largest cone per node, smallest cone per block */
+#define LLG_RBF_KIND_PNORM 1 /* pass 2: max-scaled p-norm per node                    */
+#define LLG_RBF_KIND_VJP 2   /* dJ/ds partial sums over node chunks                   */
+#define LLG_RBF_KIND_COUNT 3
+int llg_rbf_profile(int enable);
+int llg_rbf_profile_read(int32_t kind, double* ms, int64_t* launches, double* pairs, int reset);
+
 /* One Adam step on n device doubles, in place (the amplitude update of Eq. 5
  * with Adam's adaptive moments, Kingma & Ba's Algorithm 1 with bias
  * correction): m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;

@@ -23,8 +23,10 @@
 //
 // Backward (dphi and the scale held fixed): dJ/ds_i = scale * sum_x dJ/dPhi(x)
 // ((g_i(x) + dphi) / S(x))^(p - 1).  Blocks tile (node chunk) x (group of RB
-// RBFs held in registers); each writes per-chunk partial sums, which a second
+// RBFs held in registers); each thread sums its nodes in the map's precision,
+// blocks reduce in float64 and write per-chunk partial sums, which a second
 // kernel adds in chunk order.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -32,6 +34,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
+#include <vector>
 
 #include "llg.h"
 #include "llg_internal.hpp"
@@ -40,24 +44,31 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kChunk = 1024;  // RBFs staged in LDS per pass
-constexpr int kRB = 4;        // RBFs per block of the backward kernel
+constexpr int kRB = 8;        // RBFs per block of the backward kernel
 constexpr int kMinBlocks = 1024;
 
 template <typename T> struct RbfL { T x, y, s, pad; };
 
-__device__ inline float vsqrt(float v) { return __builtin_sqrtf(v); }
+// FP32: the hardware square root, base-2 logarithm and exponential (about 1
+// ulp each).  Their arguments here are normal (sqrt sees d^2 + c^2 >= c^2 > 0)
+// or harmlessly flushed: a ratio below 2^-126 enters as 0, whose power is 0
+// (its true value, raised to p, is far below a sum that is at least 1).  FP64:
+// the correctly rounded library functions.
+__device__ inline float vsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ inline double vsqrt(double v) { return __builtin_sqrt(v); }
-__device__ inline float vlog2(float v) { return log2f(v); }
+__device__ inline float vlog2(float v) { return __builtin_amdgcn_logf(v); }
 __device__ inline double vlog2(double v) { return log2(v); }
-__device__ inline float vexp2(float v) { return exp2f(v); }
+__device__ inline float vexp2(float v) { return __builtin_amdgcn_exp2f(v); }
 __device__ inline double vexp2(double v) { return exp2(v); }
+__device__ inline float vrcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ inline double vrcp(double v) { return 1.0 / v; }
 
-// Eq. 2 at node (x, y).  One function for every pass, so that all passes see
-// the same cone values.
+// Eq. 2 at node (x, y): r.s - sqrt(dx^2 + dy^2 + c^2).  The p-norm passes
+// stage r.s = s_i + dphi, so that the same call gives the base g_i + dphi.
 template <typename T>
 __device__ inline T cone(T x, T y, const RbfL<T>& r, T c2) {
     const T dx = x - r.x, dy = y - r.y;
-    return r.s - vsqrt(dx * dx + dy * dy + c2);
+    return r.s - vsqrt(fma(dx, dx, fma(dy, dy, c2)));
 }
 
 struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
@@ -79,9 +90,9 @@ __device__ double block_reduce(double v, Op op, double* sh) {
 
 template <typename T>
 __device__ inline void stage_rbfs(RbfL<T>* R, const double* __restrict__ ctr, const double* __restrict__ s, int n,
-                                  int b0, int m) {
+                                  int b0, int m, T shift) {
     for (int i = threadIdx.x; i < m; i += kThreads)
-        R[i] = RbfL<T>{(T)ctr[b0 + i], (T)ctr[n + b0 + i], (T)s[b0 + i], T(0)};
+        R[i] = RbfL<T>{(T)ctr[b0 + i], (T)ctr[n + b0 + i], (T)s[b0 + i] + shift, T(0)};
 }
 
 template <typename T, int TPN>
@@ -99,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_rbf_cones(int nx, int nnode, int n
     for (int b0 = 0; b0 < n; b0 += kChunk) {
         const int m = min(kChunk, n - b0);
         __syncthreads();
-        stage_rbfs(R, ctr, s, n, b0, m);
+        stage_rbfs(R, ctr, s, n, b0, m, T(0));
         __syncthreads();
         if (act) {
             for (int i = sub; i < m; i += TPN) {
@@ -137,11 +148,11 @@ __global__ __launch_bounds__(kThreads) void k_rbf_pnorm(int nx, int nnode, int n
     for (int b0 = 0; b0 < n; b0 += kChunk) {
         const int m = min(kChunk, n - b0);
         __syncthreads();
-        stage_rbfs(R, ctr, s, n, b0, m);
+        stage_rbfs(R, ctr, s, n, b0, m, dphi);
         __syncthreads();
         if (act) {
             for (int i = sub; i < m; i += TPN) {
-                const T b = fmax(cone(x, y, R[i], c2) + dphi, T(0));
+                const T b = fmax(cone(x, y, R[i], c2), T(0));
                 acc += vexp2(p * vlog2(b * inv));
             }
         }
@@ -185,7 +196,8 @@ __global__ __launch_bounds__(kThreads) void k_rbf_scale(int nnode, const uint8_t
     phi[i] = design[i] ? (T)((double)phi[i] * scal[1]) : T(0);
 }
 
-template <typename T>
+// UNIT: p = 1, where every power (b/S)^(p-1) is 1 (also for b = 0).
+template <typename T, bool UNIT>
 __global__ __launch_bounds__(kThreads) void k_rbf_vjp(int nx, int nnode, int n, const double* __restrict__ ctr,
                                                       const double* __restrict__ s, T c2, T pm1,
                                                       const uint8_t* __restrict__ design,
@@ -194,29 +206,64 @@ __global__ __launch_bounds__(kThreads) void k_rbf_vjp(int nx, int nnode, int n, 
                                                       double* __restrict__ part) {
     __shared__ double red[kThreads / 64];
     const int i0 = blockIdx.y * kRB;
+    const T dphi = (T)scal[0];
     RbfL<T> r[kRB];
     for (int k = 0; k < kRB; ++k) {
         const int i = min(i0 + k, n - 1);
-        r[k] = RbfL<T>{(T)ctr[i], (T)ctr[n + i], (T)s[i], T(0)};
+        r[k] = RbfL<T>{(T)ctr[i], (T)ctr[n + i], (T)s[i] + dphi, T(0)};
     }
-    const T dphi = (T)scal[0];
-    double acc[kRB];
-    for (int k = 0; k < kRB; ++k) acc[k] = 0.0;
-    const int beg = blockIdx.x * chunk, end = min(beg + chunk, nnode);
-    for (int node = beg + (int)threadIdx.x; node < end; node += kThreads) {
-        const T Sx = S[node];
-        if (!design[node] || !(Sx > T(0))) continue;
-        const double w = dJdphi[node];
-        const T inv = T(1) / Sx;
-        const T x = (T)(node % nx), y = (T)(node / nx);
-        for (int k = 0; k < kRB; ++k) {
-            const T b = fmax(cone(x, y, r[k], c2) + dphi, T(0)) * inv;
-            const T t = b > T(0) ? vexp2(pm1 * vlog2(b)) : (pm1 == T(0) ? T(1) : T(0));
-            acc[k] += w * (double)t;
+    T acc[kRB];
+    for (int k = 0; k < kRB; ++k) acc[k] = T(0);
+    const int beg = blockIdx.x * chunk, end = min(beg + chunk, nnode);  // beg < nnode: chunks cover the grid
+    // node coordinates advance by kThreads nodes per iteration: qy rows and qx columns
+    const int qy = kThreads / nx, qx = kThreads - qy * nx;
+    int node = beg + (int)threadIdx.x;
+    int iy = node / nx, ix = node - iy * nx;
+    // A node's inputs are loaded one node ahead, unconditionally (the index is
+    // clamped into the chunk), into two alternating register sets (the loop is
+    // unrolled by two), so that no copy waits on a load in flight and the load
+    // latency overlaps the previous node's arithmetic.
+    const int last = max(end - 1, beg);
+    auto visit = [&](T Sv, double wv, uint8_t dv) {
+        if (dv && Sv > T(0)) {
+            const T w = (T)wv;
+            if (UNIT) {
+                for (int k = 0; k < kRB; ++k) acc[k] += w;
+            } else {
+                // (b / S)^(p-1) = 2^((p-1) log2 b - (p-1) log2 S); b = 0 gives 2^-inf = 0
+                const T lS = pm1 * vlog2(Sv);
+                const T x = (T)ix, y = (T)iy;
+                for (int k = 0; k < kRB; ++k) {
+                    const T b = fmax(cone(x, y, r[k], c2), T(0));
+                    acc[k] = fma(w, vexp2(fma(pm1, vlog2(b), -lS)), acc[k]);
+                }
+            }
         }
+        ix += qx;
+        iy += qy;
+        if (ix >= nx) {
+            ix -= nx;
+            ++iy;
+        }
+    };
+    int c = min(node, last);
+    T S0 = S[c];
+    double w0 = dJdphi[c];
+    uint8_t d0 = design[c];
+    for (; node < end; node += 2 * kThreads) {
+        c = min(node + kThreads, last);
+        const T S1 = S[c];
+        const double w1 = dJdphi[c];
+        const uint8_t d1 = design[c];
+        visit(S0, w0, d0);
+        c = min(node + 2 * kThreads, last);
+        S0 = S[c];
+        w0 = dJdphi[c];
+        d0 = design[c];
+        if (node + kThreads < end) visit(S1, w1, d1);
     }
     for (int k = 0; k < kRB; ++k) {
-        const double v = block_reduce(acc[k], OpSum(), red);
+        const double v = block_reduce((double)acc[k], OpSum(), red);
         if (threadIdx.x == 0 && i0 + k < n) part[(size_t)blockIdx.x * n + i0 + k] = v;
     }
 }
@@ -261,7 +308,9 @@ Plan plan_of(long long nnode, int n) {
     while (P.tpn < 16 && (nnode * P.tpn + kThreads - 1) / kThreads < kMinBlocks) P.tpn *= 2;
     P.nb = (int)((nnode * P.tpn + kThreads - 1) / kThreads);
     P.ngrp = (n + kRB - 1) / kRB;
-    long long want = std::max(1, (kMinBlocks + P.ngrp - 1) / P.ngrp);
+    // one round of resident blocks (8 blocks of 4 waves per CU): the backward
+    // blocks are equal in size, so a second, partial round would only add a tail
+    long long want = std::max(1, (2 * kMinBlocks) / P.ngrp);
     long long chunk = (nnode + want - 1) / want;
     chunk = (chunk + kThreads - 1) / kThreads * kThreads;
     P.chunk = (int)chunk;
@@ -291,14 +340,68 @@ int hip_status(const char* what) {
     return LLG_OK;
 }
 
+// Optional per-kernel device time of the three pair kernels (process-wide):
+// when on, each of their launches carries a start/end event pair bound to the
+// dispatch itself.
+struct RbfProf {
+    struct Rec { int kind; double pairs; hipEvent_t a, b; };
+    std::mutex mu;
+    bool on = false;
+    std::vector<Rec> recs;
+    double ms[LLG_RBF_KIND_COUNT] = {0};
+    double pairs[LLG_RBF_KIND_COUNT] = {0};
+    int64_t n[LLG_RBF_KIND_COUNT] = {0};
+};
+RbfProf& prof() {
+    static RbfProf p;
+    return p;
+}
+
+// Events for one launch of `kind` covering `pairs` node-RBF pairs (null when off).
+void prof_events(int kind, double pairs, hipEvent_t* a, hipEvent_t* b) {
+    *a = *b = nullptr;
+    RbfProf& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    if (!P.on) return;
+    if (hipEventCreate(a) != hipSuccess) { *a = nullptr; return; }
+    if (hipEventCreate(b) != hipSuccess) { (void)hipEventDestroy(*a); *a = *b = nullptr; return; }
+    P.recs.push_back({kind, pairs, *a, *b});
+}
+
+int prof_drain() {
+    RbfProf& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    int rc = LLG_OK;
+    for (auto& r : P.recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            rc = llg::set_error(LLG_EHIP, "rbf profile: event timing failed");
+        } else {
+            P.ms[r.kind] += ms;
+            P.pairs[r.kind] += r.pairs;
+            P.n[r.kind] += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    P.recs.clear();
+    return rc;
+}
+
 template <typename T, int TPN>
 void launch_fwd_passes(const Plan& P, int nx, int nnode, int n, const double* ctr, const double* s, T c2, T p,
                        const uint8_t* design, T* phi, T* S_out, double* work, hipStream_t st) {
     double* part_min = work + 2;
     double* part_max = work + 2 + P.nb;
-    k_rbf_cones<T, TPN><<<P.nb, kThreads, 0, st>>>(nx, nnode, n, ctr, s, c2, design, phi, part_min);
+    const double pairs = (double)nnode * n;
+    hipEvent_t a, b;
+    prof_events(LLG_RBF_KIND_CONES, pairs, &a, &b);
+    hipExtLaunchKernelGGL((k_rbf_cones<T, TPN>), dim3(P.nb), dim3(kThreads), 0, st, a, b, 0, nx, nnode, n, ctr, s, c2,
+                          design, phi, part_min);
     k_rbf_finish<<<1, kThreads, 0, st>>>(part_min, P.nb, 0, 0, work);
-    k_rbf_pnorm<T, TPN><<<P.nb, kThreads, 0, st>>>(nx, nnode, n, ctr, s, c2, p, design, work, phi, S_out, part_max);
+    prof_events(LLG_RBF_KIND_PNORM, pairs, &a, &b);
+    hipExtLaunchKernelGGL((k_rbf_pnorm<T, TPN>), dim3(P.nb), dim3(kThreads), 0, st, a, b, 0, nx, nnode, n, ctr, s, c2,
+                          p, design, (const double*)work, phi, S_out, part_max);
 }
 
 template <typename T>
@@ -321,8 +424,14 @@ template <typename T>
 int rbf_backward(const Plan& P, int nx, int nnode, int n, const double* ctr, const double* s, double c, double p,
                  const uint8_t* design, const double* dJdphi, const T* S, const double* work, double* part,
                  double* dJds, hipStream_t st) {
-    k_rbf_vjp<T><<<dim3(P.nchunk, P.ngrp), kThreads, 0, st>>>(nx, nnode, n, ctr, s, (T)(c * c), (T)(p - 1.0), design,
-                                                              dJdphi, S, work, P.chunk, part);
+    hipEvent_t a, b;
+    prof_events(LLG_RBF_KIND_VJP, (double)nnode * n, &a, &b);
+    if (p == 1.0)
+        hipExtLaunchKernelGGL((k_rbf_vjp<T, true>), dim3(P.nchunk, P.ngrp), dim3(kThreads), 0, st, a, b, 0, nx, nnode, n,
+                              ctr, s, (T)(c * c), T(0), design, dJdphi, S, work, P.chunk, part);
+    else
+        hipExtLaunchKernelGGL((k_rbf_vjp<T, false>), dim3(P.nchunk, P.ngrp), dim3(kThreads), 0, st, a, b, 0, nx, nnode,
+                              n, ctr, s, (T)(c * c), (T)(p - 1.0), design, dJdphi, S, work, P.chunk, part);
     k_rbf_vjp_finish<<<(n + kThreads - 1) / kThreads, kThreads, 0, st>>>(n, P.nchunk, part, work, dJds);
     return hip_status("rbf level set VJP launch");
 }
@@ -369,6 +478,30 @@ int llg_rbf_levelset_vjp(int32_t dtype, int32_t nx, int32_t ny, int32_t n_rbf, c
                                    part, dJds_out, stream);
     return rbf_backward<double>(P, nx, nnode, n_rbf, centers, s, c, p, design, dJdphi, (const double*)pnorm, work,
                                 part, dJds_out, stream);
+}
+
+int llg_rbf_profile(int enable) {
+    if (int rc = prof_drain()) return rc;
+    RbfProf& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    P.on = enable != 0;
+    return LLG_OK;
+}
+
+int llg_rbf_profile_read(int32_t kind, double* ms, int64_t* launches, double* pairs, int reset) {
+    if (kind < 0 || kind >= LLG_RBF_KIND_COUNT) return llg::set_error(LLG_EINVAL, "rbf profile: bad kind");
+    if (int rc = prof_drain()) return rc;
+    RbfProf& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    if (ms) *ms = P.ms[kind];
+    if (launches) *launches = P.n[kind];
+    if (pairs) *pairs = P.pairs[kind];
+    if (reset) {
+        P.ms[kind] = 0;
+        P.n[kind] = 0;
+        P.pairs[kind] = 0;
+    }
+    return LLG_OK;
 }
 
 int llg_adam_step(int32_t n, double* s, const double* grad, double* m, double* v, int64_t t, double lr, double beta1,

@@ -27,7 +27,8 @@ EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_le
            "llg_set_launch_config", "llg_autotune", "llg_fft_sizes", "llg_profile", "llg_profile_read", "llg_batch_create",
            "llg_batch_destroy", "llg_batch_size", "llg_batch_levelset_to_Ms", "llg_batch_levelset_to_Ms_vjp",
            "llg_batch_forward", "llg_batch_adjoint", "llg_rbf_work_len", "llg_rbf_levelset", "llg_rbf_levelset_vjp",
-           "llg_adam_step"]
+           "llg_adam_step", "llg_rbf_profile", "llg_rbf_profile_read"]
+RBF_KIND_NAMES = {0: "k_rbf_cones", 1: "k_rbf_pnorm", 2: "k_rbf_vjp"}
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
 KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col_conv", KIND_STAGE_BWD: "k_stage_bwd"}
 
@@ -108,6 +109,8 @@ def lib():
         "llg_rbf_levelset": [i32, i32, i32, i32, vp, vp, dbl, dbl, vp, ctypes.c_int, vp, vp, vp, vp],
         "llg_rbf_levelset_vjp": [i32, i32, i32, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp, vp],
         "llg_adam_step": [i32, vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, vp],
+        "llg_rbf_profile": [ctypes.c_int],
+        "llg_rbf_profile_read": [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -501,6 +504,17 @@ class RBFLevelSet:
                                          self.p, _ptr(self.design), _ptr(dJdphi), _ptr(pnorm), _ptr(work), _ptr(out),
                                          _stream()))
         return out
+
+
+def rbf_profile(enable: bool):
+    check(lib().llg_rbf_profile(int(enable)))
+
+
+def rbf_profile_read(kind, reset=True):
+    """(ms, launches, pairs) of one RBF pair kernel since the last reset."""
+    ms, n, pr = ctypes.c_double(0), ctypes.c_int64(0), ctypes.c_double(0)
+    check(lib().llg_rbf_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(pr), int(reset)))
+    return ms.value, n.value, pr.value
 
 
 class Adam:

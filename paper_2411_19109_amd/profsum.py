@@ -2,7 +2,7 @@
 
     python -m paper_2411_19109_amd.profsum stats DIR   # --kernel-trace --stats run
     python -m paper_2411_19109_amd.profsum pmc DIR     # --pmc COUNTER run
-    python -m paper_2411_19109_amd.profsum traffic FETCH_DIR WRITE_DIR [LAUNCH_FILE]  # HBM bytes per dispatch
+    python -m paper_2411_19109_amd.profsum traffic FETCH_DIR WRITE_DIR [LAUNCH_FILE|-] [SOURCE]  # HBM bytes per dispatch
 
 ``stats`` prints, per kernel, the call count and the average / total device
 time from the *_kernel_stats.csv file.  ``pmc`` prints, per kernel, the number
@@ -59,14 +59,15 @@ def _per_kernel(d: str, counter: str):
     return agg
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(source: str = "llg_kernels.hip") -> str:
     """sha256 of the kernel source the counters belong to."""
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "llg_kernels.hip")
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", source)
     return hashlib.sha256(open(src, "rb").read()).hexdigest()
 
 
-def traffic(fetch_dir: str, write_dir: str, launch=None, copy_bytes: int = 1 << 28) -> str:
+def traffic(fetch_dir: str, write_dir: str, launch=None, copy_bytes: int = 1 << 28,
+            source: str = "llg_kernels.hip") -> str:
     """HBM bytes per dispatch of the solver kernels from a FETCH_SIZE run and a
     WRITE_SIZE run (KiB per dispatch), each scaled by the factor that maps the
     same counter on a plain device copy of copy_bytes (the largest copy
@@ -76,7 +77,8 @@ def traffic(fetch_dir: str, write_dir: str, launch=None, copy_bytes: int = 1 << 
     cal = "__amd_rocclr_copyBuffer"
     kf = copy_bytes / (max(fe[cal]) * 1024.0)
     kw = copy_bytes / (max(wr[cal]) * 1024.0)
-    out = {"kernel_source_sha256": kernel_source_hash(), "launch": launch, "copy_bytes": copy_bytes,
+    out = {"kernel_source_sha256": kernel_source_hash(source), "source": source, "launch": launch,
+           "copy_bytes": copy_bytes,
            "fetch_scale": kf, "write_scale": kw, "kernels": {}}
     for k in sorted(set(fe) & set(wr)):
         if not k.startswith("k_"):
@@ -90,8 +92,10 @@ def traffic(fetch_dir: str, write_dir: str, launch=None, copy_bytes: int = 1 << 
 if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "traffic":
-        launch = [int(v) for v in open(sys.argv[4]).read().split()] if len(sys.argv) > 4 else None
-        print(traffic(sys.argv[2], sys.argv[3], launch))
+        # traffic FETCH_DIR WRITE_DIR [LAUNCH_FILE or -] [KERNEL_SOURCE]
+        lf = sys.argv[4] if len(sys.argv) > 4 else "-"
+        launch = [int(v) for v in open(lf).read().split()] if lf != "-" else None
+        print(traffic(sys.argv[2], sys.argv[3], launch, source=sys.argv[5] if len(sys.argv) > 5 else "llg_kernels.hip"))
     else:
         d = sys.argv[2]
         print(stats(d) if mode == "stats" else pmc(d))

@@ -58,6 +58,7 @@ def run_pair(lay, design, dtype, normalize=True, seed=0):
 
 def check(r, dtype):
     D = r["D"]
+    say("  phi max err", np.abs(r["phi"] - r["ophi"]).max(), "dJ/ds rel L2", rel_l2(r["ds"], r["ods"]))
     assert np.all(r["phi"][~D] == 0)
     if dtype == "f64":
         assert rel_max(r["phi"], r["ophi"]) <= TOL_PHI["f64"]

@@ -187,6 +187,8 @@ def main():
                     help="read the launch configuration from this file if it exists, else write the chosen one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--rbf-paper-sizes", type=int, default=1,
+                    help="rbf workload: 1 also times one update at the paper's grid sizes (0 for counter runs)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="skip the per-kernel event timing pass (counter runs need only the dispatches)")
     args = ap.parse_args()
@@ -565,8 +567,9 @@ def run_rbf(args):
     # the paper's sizes, one update each (launch-bound at these sizes)
     small = {}
     from paper_2411_19109_amd import workloads as wl
-    for name, (sx, sy, box) in {"particle_64x64": (64, 64, (0, 0, 64)),
-                                 "demux_256x96": (256, 96, wl.yig_demux(n_steps=10).extra["box"])}.items():
+    sizes = {"particle_64x64": (64, 64, (0, 0, 64)),
+             "demux_256x96": (256, 96, wl.yig_demux(n_steps=10).extra["box"])} if args.rbf_paper_sizes else {}
+    for name, (sx, sy, box) in sizes.items():
         sl = wl.rbf_layout(box, n_side=20, holes=4, seed=1)
         d2 = np.zeros((sy, sx), np.uint8)
         d2[box[1]:box[1] + box[2], box[0]:box[0] + box[2]] = 1

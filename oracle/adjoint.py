@@ -31,15 +31,18 @@ import numpy as np
 
 from .micromag import MU0, TERM_ANIS, TERM_DEMAG, TERM_EXCH, cross, dot
 
-OBJ_NONE, OBJ_ENERGY_AREA, OBJ_PORT_MY2 = 0, 1, 2
+OBJ_NONE, OBJ_ENERGY_AREA, OBJ_PORT_MY2, OBJ_PORT_SPECTRAL = 0, 1, 2, 3
 
 
 class Objective:
-    """kind: OBJ_ENERGY_AREA -> J = (E_ex + E_d)(m_T)/E_ref + lam (mean psi - area)^2
-             OBJ_PORT_MY2    -> J = 1/|W| sum_{n in W} [mean_P1 m_y^2 - mean_P2 m_y^2],
-                                W = {n : n_start < n <= n_steps}."""
+    """kind: OBJ_ENERGY_AREA    -> J = (E_ex + E_d)(m_T)/E_ref + lam (mean psi - area)^2
+             OBJ_PORT_MY2       -> J = 1/|W| sum_{n in W} [mean_P1 m_y^2 - mean_P2 m_y^2],
+                                   W = {n : n_start < n <= n_steps}
+             OBJ_PORT_SPECTRAL  -> J = sum_q coef[0, q] |X_1(f_q)| + coef[1, q] |X_2(f_q)|
+                                   (Eq. 10 with its frequency windows; see spectral_value)."""
 
-    def __init__(self, kind, E_ref=1.0, lam=1.0, area=0.4, n_start=0, port1=None, port2=None):
+    def __init__(self, kind, E_ref=1.0, lam=1.0, area=0.4, n_start=0, port1=None, port2=None, freqs=None,
+                 coef=None):
         self.kind = kind
         self.E_ref = E_ref
         self.lam = lam
@@ -47,6 +50,8 @@ class Objective:
         self.n_start = n_start
         self.port1 = None if port1 is None else np.asarray(port1, float)
         self.port2 = None if port2 is None else np.asarray(port2, float)
+        self.freqs = None if freqs is None else np.asarray(freqs, float)
+        self.coef = None if coef is None else np.asarray(coef, float).reshape(2, -1)
 
 
 # -- objective values and their explicit derivatives --------------------------
@@ -94,6 +99,57 @@ def port_source(m, obj, n_window):
     return g
 
 
+# -- spectral port objective (Eq. 10) ------------------------------------------
+#
+# Eq. 10 compares, at the two outputs, sums of the magnitudes of the Fourier
+# transform of the magnetisation oscillation over frequency windows around f1
+# and f2.  Readings: the oscillation recorded at output j is the port-mean m_y
+# of the states m_n of the window W = {n_start < n <= n_steps}, at t_n = t0 +
+# n dt; its transform at frequency f is the plain (rectangular-window) DFT
+# X_j(f) = 1/|W| sum_{n in W} x_j(n) exp(-2 pi i f t_n), evaluated at the
+# sample frequencies f_q of the windows; J = sum_q c_1q |X_1(f_q)| + c_2q |X_2(f_q)|,
+# where Eq. 10 takes c = +1 / -1 on the output that should / should not carry
+# a window's frequency.  Real and imaginary parts are kept as separate sums, so
+# that complex-step perturbations of the series pass through |X| analytically.
+
+def port_series(traj, obj, n_steps):
+    """x_j(n), n in W: the port-mean m_y of each output (shape (2, |W|))."""
+    win = range(obj.n_start + 1, n_steps + 1)
+    w1, w2 = obj.port1 / obj.port1.sum(), obj.port2 / obj.port2.sum()
+    return np.array([[(traj[n][1] * w1).sum() for n in win], [(traj[n][1] * w2).sum() for n in win]])
+
+
+def spectral_parts(x, times, freqs):
+    """(C, S): C_jq = 1/|W| sum_n x_j(n) cos(2 pi f_q t_n), S likewise with sin;
+    X_j(f_q) = C_jq - i S_jq."""
+    th = 2 * np.pi * np.outer(freqs, times)          # (K, |W|)
+    W = len(times)
+    return x @ np.cos(th).T / W, x @ np.sin(th).T / W
+
+
+def spectral_value(x, times, obj):
+    C, S = spectral_parts(x, times, obj.freqs)
+    return (obj.coef * np.sqrt(C * C + S * S)).sum()
+
+
+def spectral_sources(x, times, obj):
+    """dJ/dx_j(n) (shape (2, |W|)): d|X| = (C dC + S dS) / |X|, dC/dx(n) = cos/|W|, dS/dx(n) = sin/|W|."""
+    C, S = spectral_parts(x, times, obj.freqs)
+    A = np.sqrt(C * C + S * S)
+    th = 2 * np.pi * np.outer(obj.freqs, times)
+    W = len(times)
+    wc = obj.coef * C / A
+    ws = obj.coef * S / A
+    return (wc @ np.cos(th) + ws @ np.sin(th)) / W
+
+
+def spectral_source_field(g, m, obj):
+    """dJ/dm_n of one window state from the series sources g = (g_1(n), g_2(n))."""
+    out = np.zeros(m.shape, dtype=np.result_type(m, g))
+    out[1] = g[0] * obj.port1 / obj.port1.sum() + g[1] * obj.port2 / obj.port2.sum()
+    return out
+
+
 # -- transpose of one right-hand-side evaluation -------------------------------
 
 def rhs_vjp(sim, m, B, psi, v):
@@ -135,19 +191,25 @@ def rhs_vjp(sim, m, B, psi, v):
 
 # -- forward + objective + adjoint ---------------------------------------------
 
-def objective_value(sim, traj, psi, obj, n_steps):
+def window_times(sim, obj, n_steps, t0=0.0):
+    return t0 + np.arange(obj.n_start + 1, n_steps + 1) * sim.p.dt
+
+
+def objective_value(sim, traj, psi, obj, n_steps, t0=0.0):
     if obj.kind == OBJ_ENERGY_AREA:
         return energy_area_value(sim, traj[-1], psi, obj)
     if obj.kind == OBJ_PORT_MY2:
         win = range(obj.n_start + 1, n_steps + 1)
         return sum(port_value(traj[n], obj) for n in win) / len(win)
+    if obj.kind == OBJ_PORT_SPECTRAL:
+        return spectral_value(port_series(traj, obj, n_steps), window_times(sim, obj, n_steps, t0), obj)
     return 0.0
 
 
 def forward_objective(sim, m0, psi, n_steps, obj, t0=0.0):
     """J of the discrete forward map (stores the whole trajectory)."""
     m, traj = sim.integrate(m0, psi, n_steps, t0=t0, keep=True)
-    return objective_value(sim, traj, psi, obj, n_steps), traj
+    return objective_value(sim, traj, psi, obj, n_steps, t0), traj
 
 
 def gradient(sim, m0, psi, n_steps, obj, t0=0.0):
@@ -163,6 +225,10 @@ def gradient(sim, m0, psi, n_steps, obj, t0=0.0):
         g_psi = g_psi + gp
     if obj.kind == OBJ_PORT_MY2 and n_steps > obj.n_start:
         lam = lam + port_source(traj[n_steps], obj, n_window)
+    spec = obj.kind == OBJ_PORT_SPECTRAL and n_steps > obj.n_start
+    if spec:
+        g_ser = spectral_sources(port_series(traj, obj, n_steps), window_times(sim, obj, n_steps, t0), obj)
+        lam = lam + spectral_source_field(g_ser[:, -1], traj[n_steps], obj)
     for n in range(n_steps - 1, -1, -1):
         t = t0 + n * dt
         _, ys, Bs = sim.rk4_step(traj[n], psi, t)
@@ -178,4 +244,6 @@ def gradient(sim, m0, psi, n_steps, obj, t0=0.0):
         g_psi = g_psi + g1 + g2 + g3 + g4
         if obj.kind == OBJ_PORT_MY2 and obj.n_start < n <= n_steps:
             lam = lam + port_source(traj[n], obj, n_window)
+        if spec and obj.n_start < n:
+            lam = lam + spectral_source_field(g_ser[:, n - obj.n_start - 1], traj[n], obj)
     return J, g_psi, lam

@@ -152,11 +152,15 @@ class Sim:
         return p.alpha0 + (p.alpha_max - p.alpha0) * ramp
 
     def drive(self, t):
-        """Scalar drive waveform sin(phase(t)); the frequency switches from f1 to
-        f2 at t_switch (if t_switch > 0) with a continuous phase."""
+        """Scalar drive waveform.  sin(phase(t)), the frequency switching from f1
+        to f2 at t_switch (if t_switch > 0) with a continuous phase; without a
+        switch and with f2 > 0, the two-tone excitation of the demultiplexer
+        section, sin(2 pi f1 t) + sin(2 pi f2 t)."""
         p = self.p
         if p.t_switch > 0 and t >= p.t_switch:
             ph = 2 * math.pi * (p.f1 * p.t_switch + p.f2 * (t - p.t_switch))
+        elif p.t_switch <= 0 and p.f2 > 0:
+            return math.sin(2 * math.pi * p.f1 * t) + math.sin(2 * math.pi * p.f2 * t)
         else:
             ph = 2 * math.pi * p.f1 * t
         return math.sin(ph)

@@ -82,6 +82,10 @@ extern "C" {
 #define LLG_OBJ_NONE 0
 #define LLG_OBJ_ENERGY_AREA 1 /* J = (E_ex + E_d)(m_T)/E_ref + lambda (mean psi - area)^2            */
 #define LLG_OBJ_PORT_MY2 2    /* J = 1/|W| sum_{n in W} [mean_P1 m_y^2 - mean_P2 m_y^2], W = (n_start, n_steps] */
+/* Eq. 10: J = sum_q coef[q] |X_1(f_q)| + coef[n_freq + q] |X_2(f_q)|, with X_j(f) = 1/|W| sum_{n in W}
+ * x_j(n) exp(-2 pi i f t_n), x_j(n) the mean m_y over port j of the state m_n at t_n = t0 + n dt
+ * (frequency windows around f1 and f2 are sets of sample frequencies f_q with coefficients +-1) */
+#define LLG_OBJ_PORT_SPECTRAL 3
 
 /* ---- problem description --------------------------------------------- */
 typedef struct llg_problem {
@@ -122,7 +126,10 @@ typedef struct llg_objective_spec {
     double E_ref;     /* energy normalisation of LLG_OBJ_ENERGY_AREA, J (> 0)        */
     double lambda;    /* weight of the area penalty                                  */
     double area;      /* target mean psi of the area penalty                         */
-    int64_t n_start;  /* LLG_OBJ_PORT_MY2: steps n with n_start < n <= n_steps count */
+    int64_t n_start;  /* port objectives: steps n with n_start < n <= n_steps count  */
+    int32_t n_freq;   /* LLG_OBJ_PORT_SPECTRAL: number of sample frequencies (1..4096) */
+    const double* freqs;  /* host, n_freq sample frequencies f_q, Hz                */
+    const double* coef;   /* host, 2 n_freq weights: of |X_1(f_q)|, then of |X_2(f_q)| */
 } llg_objective_spec;
 
 typedef struct llg_handle llg_handle;
@@ -168,7 +175,7 @@ int llg_field(llg_handle* h, const void* psi, const void* m, double t, void* B_o
 /* Integrate n_steps classic RK4 steps of the LL form of Eq. 11 from m0 (3N) at
  * time t0 (step n runs from t0 + n dt).  Writes m(t0 + n_steps dt) to m_out
  * (may alias m0).  Records what llg_adjoint needs (psi, t0, n_steps,
- * checkpoints per the handle's policy).  If obj is LLG_OBJ_PORT_MY2 its
+ * checkpoints per the handle's policy).  If obj is a port objective its
  * running cost is accumulated and written to *J_dev (device double) at the
  * end; J_dev may be NULL otherwise.  1 <= n_steps <= max_steps.
  * Errors: LLG_EINVAL, LLG_ENOMEM (checkpoint capacity), LLG_EHIP. */
@@ -179,9 +186,11 @@ int llg_forward(llg_handle* h, const void* psi, const void* m0, double t0, int64
  * *J_dev, dJ/dm to dJdm_out (3N, handle precision) and the explicit dJ/dpsi
  * to dJdpsi_out (N, float64); energies_dev (device double[5]: exchange, demag,
  * Zeeman at t, anisotropy, total; J) receives the energy terms when not NULL.
- * For LLG_OBJ_PORT_MY2 the objective is a running cost: J_dev receives the
- * value accumulated by the last llg_forward, dJdm_out and dJdpsi_out are
- * zeroed (its sources are injected by llg_adjoint). */
+ * For LLG_OBJ_PORT_MY2 and LLG_OBJ_PORT_SPECTRAL the objective is a function of
+ * the trajectory: J_dev receives the value the last llg_forward computed,
+ * dJdm_out and dJdpsi_out are zeroed (its sources are injected by llg_adjoint;
+ * for the spectral objective they are those of the last llg_forward's
+ * frequencies and weights). */
 int llg_objective(llg_handle* h, const llg_objective_spec* obj, const void* psi, const void* m, double t,
                   double* J_dev, void* dJdm_out, double* dJdpsi_out, double* energies_dev, hipStream_t stream);
 

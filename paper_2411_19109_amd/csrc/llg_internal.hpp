@@ -68,6 +68,10 @@ enum BufId : int {
     B_PPART,    // port partial sums (double, 2 per row-pair block)
     B_EPART,    // energy partial sums (double, 5 per row-pair block)
     B_SCAL,     // scalars (double[8]): [0] J, [1] area coefficient
+    B_PSER,     // spectral objective: per-step port partial sums (double, max_steps * nloc * 2)
+    B_SER,      // spectral objective: port-mean m_y series x_1(n), x_2(n) (double, 2 * max_steps)
+    B_PSRC,     // spectral objective: per-step sources dJ/dx_j(n) / |P_j| (double, 2 * max_steps)
+    B_SPC,      // spectral objective: C_1, S_1, C_2, S_2 of each sample frequency (double, 4 * capacity)
     B_COUNT
 };
 struct InstTab {
@@ -102,7 +106,8 @@ struct FwdL {
     double t;             // time of the stage
     int ys, mn, acc, ynext;  // BufId roles (-1 = none)
     int store_j;          // >= 0: copy ys and B(ys) to slot store_j of YS / BS
-    int port;             // accumulate the port running cost (stage 3)
+    int port;             // stage 3: 1 accumulate the port m_y^2 sums, 2 write the port m_y sums of window step pstep
+    int pstep;            // window index of the state this launch produces (port == 2)
     int do_inv, do_fwd;   // inverse x-FFT of S (demag in) / forward x-FFT of psi*ynext into S
     int spec;             // BufId of S (B_S or B_S2)
     void* ext_ys;         // single-instance overrides (field evaluation)
@@ -118,6 +123,8 @@ struct BwdL {
     int ucur, unext, lamp, lacc;  // BufId roles
     int port_src;         // add the port running-cost source at stage 0
     int W;                // port window length (steps)
+    int port_lin;         // spectral objective: the source is the stored per-step scalar (not 2 m_y / (W |P|))
+    int pstep;            // window index of this step's state (port_lin)
     int do_inv, do_fwd;
     int stage_m;          // stage the y_s rows in LDS too (set by the launcher from the batch)
 };
@@ -139,6 +146,7 @@ struct StageFwdArgs {
     const uint8_t* port1;
     const uint8_t* port2;
     double* port_part;
+    int port_lin;         // sum m_y and store (spectral series) instead of accumulating m_y^2
     int do_inv;
     int do_fwd;
 };
@@ -160,7 +168,8 @@ struct StageBwdArgs {
     cplx<T>* S;
     const uint8_t* port1;
     const uint8_t* port2;
-    T src1, src2;
+    T src1, src2;         // port sources (port 2 carries its sign)
+    int src_lin;          // lambda.y += src (spectral) instead of src * m_y
     int do_inv;
     int do_fwd;
 };
@@ -215,6 +224,12 @@ template <typename T> hipError_t launch_fill(const BatchDev<T>& b, int sel, int 
 template <typename T>
 hipError_t launch_copy(const BatchDev<T>& b, int src, int src_slot, int dst, int dst_slot, hipStream_t s);
 template <typename T> hipError_t launch_port_finish(const BatchDev<T>& b, int W, hipStream_t s);
+// Spectral objective after a forward run: series from the per-step partials, DFT
+// parts at the K sample frequencies, J, and the per-step adjoint sources.  fc
+// holds f_q (K), then the weights of |X_1| (K) and of |X_2| (K), on the device.
+template <typename T>
+hipError_t launch_spectral(const BatchDev<T>& b, const double* fc, int K, int W, double t0, int64_t n_start, double dt,
+                           hipStream_t s);
 template <typename T>
 hipError_t launch_energy(const BatchDev<T>& b, double t, const T* m, double scale, T* dJdm, double* dJdpsi,
                          hipStream_t s);

@@ -259,8 +259,12 @@ template <typename T> __device__ __forceinline__ T node_alpha(const KParams<T>& 
     return p.alpha0 + (p.alpha_max - p.alpha0) * ((T)w / (T)p.ramp_cells);
 }
 
+// Drive waveform: sin(2 pi f1 t), switching to f2 at t_switch > 0 with a
+// continuous phase; without a switch and with f2 > 0 the two-tone excitation
+// sin(2 pi f1 t) + sin(2 pi f2 t).
 __device__ __forceinline__ double drive_value(double f1, double f2, double tsw, double t) {
     const double twopi = 6.283185307179586476925286766559;
+    if (tsw <= 0.0 && f2 > 0.0) return sin(twopi * f1 * t) + sin(twopi * f2 * t);
     double ph = (tsw > 0.0 && t >= tsw) ? twopi * (f1 * tsw + f2 * (t - tsw)) : twopi * f1 * t;
     return sin(ph);
 }
@@ -530,7 +534,10 @@ __device__ __forceinline__ StageFwdArgs<T> resolve_fwd(const KParams<T>& p, cons
     const bool port = L.port && (p.n_p1 + p.n_p2) > 0;
     a.port1 = port ? role<uint8_t>(tb, B_P1) : nullptr;
     a.port2 = port ? role<uint8_t>(tb, B_P2) : nullptr;
-    a.port_part = port ? role<double>(tb, B_PPART) : nullptr;
+    a.port_lin = L.port == 2;
+    a.port_part = !port ? nullptr
+                        : (a.port_lin ? role<double>(tb, B_PSER) + (size_t)L.pstep * 2 * p.nloc
+                                      : role<double>(tb, B_PPART));
     a.do_inv = L.do_inv;
     a.do_fwd = L.do_fwd;
     return a;
@@ -557,8 +564,15 @@ __device__ __forceinline__ StageBwdArgs<T> resolve_bwd(const KParams<T>& p, cons
     const bool port = L.port_src && (p.n_p1 + p.n_p2) > 0 && L.W > 0;
     a.port1 = port ? role<uint8_t>(tb, B_P1) : nullptr;
     a.port2 = port ? role<uint8_t>(tb, B_P2) : nullptr;
-    a.src1 = port && p.n_p1 > 0 ? (T)(2.0 / ((double)L.W * p.n_p1)) : (T)0;
-    a.src2 = port && p.n_p2 > 0 ? (T)(2.0 / ((double)L.W * p.n_p2)) : (T)0;
+    a.src_lin = L.port_lin;
+    if (port && L.port_lin) {
+        const double* g = role<double>(tb, B_PSRC) + 2 * (size_t)L.pstep;
+        a.src1 = (T)g[0];
+        a.src2 = (T)g[1];
+    } else {
+        a.src1 = port && p.n_p1 > 0 ? (T)(2.0 / ((double)L.W * p.n_p1)) : (T)0;
+        a.src2 = port && p.n_p2 > 0 ? -(T)(2.0 / ((double)L.W * p.n_p2)) : (T)0;
+    }
     a.do_inv = L.do_inv;
     a.do_fwd = L.do_fwd;
     return a;
@@ -702,10 +716,10 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             }
             if (a.ynext) st3(a.ynext, N, i, yn);
             if (a.port_part) {
-                const double my2 = (double)yn.y * (double)yn.y;
+                const double v = a.port_lin ? (double)yn.y : (double)yn.y * (double)yn.y;
                 const bool first_it = it == (int)threadIdx.x;
-                if (first_it ? pre_p1 : glb(a.port1)[i]) s1 += my2;
-                if (first_it ? pre_p2 : glb(a.port2)[i]) s2 += my2;
+                if (first_it ? pre_p1 : glb(a.port1)[i]) s1 += v;
+                if (first_it ? pre_p2 : glb(a.port2)[i]) s2 += v;
             }
             if (a.do_fwd) {
                 // packed forward-FFT input: (x, y) of each row, z of row 0 + i z of row 1
@@ -737,8 +751,13 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
                 t1 += red[0][k];
                 t2 += red[1][k];
             }
-            glb(a.port_part)[2 * wk.y] += t1;
-            glb(a.port_part)[2 * wk.y + 1] += t2;
+            if (a.port_lin) {
+                glb(a.port_part)[2 * wk.y] = t1;
+                glb(a.port_part)[2 * wk.y + 1] = t2;
+            } else {
+                glb(a.port_part)[2 * wk.y] += t1;
+                glb(a.port_part)[2 * wk.y + 1] += t2;
+            }
         }
     }
     if (a.do_fwd) {
@@ -926,9 +945,9 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                 } else {
                     V3<T> lam = lsum;
                     if (a.port1) {
-                        // running-cost source dJ/dm_n of the port objective (y component)
-                        const T src = (d.p1 ? a.src1 : (T)0) - (d.p2 ? a.src2 : (T)0);
-                        lam.y = lam.y + src * m.y;
+                        // source dJ/dm_n of the port objective (y component)
+                        const T src = (d.p1 ? a.src1 : (T)0) + (d.p2 ? a.src2 : (T)0);
+                        lam.y = lam.y + (a.src_lin ? src : src * m.y);
                     }
                     st3(a.lacc_out, N, i, lam);
                     if (a.y_prev) {
@@ -1207,11 +1226,17 @@ __global__ void k_adj_init(const KParams<T>* __restrict__ ptab, const InstTab* _
     if (i >= p.N) return;
     const int N = p.N;
     V3<T> l = use_djdm ? ld3(role<T>(tb, B_DJDM), N, i) : v3<T>(0, 0, 0);
-    if (port && W > 0 && (p.n_p1 + p.n_p2) > 0) {
+    if (port == 1 && W > 0 && (p.n_p1 + p.n_p2) > 0) {
         const T s1 = p.n_p1 > 0 ? (T)(2.0 / ((double)W * p.n_p1)) : (T)0;
         const T s2 = p.n_p2 > 0 ? (T)(2.0 / ((double)W * p.n_p2)) : (T)0;
         const T src = (role<uint8_t>(tb, B_P1)[i] ? s1 : (T)0) - (role<uint8_t>(tb, B_P2)[i] ? s2 : (T)0);
         l.y = l.y + src * role<T>(tb, B_M)[N + i];
+    }
+    if (port == 2 && W > 0 && (p.n_p1 + p.n_p2) > 0) {
+        // spectral objective: the stored source of the last window state m_N
+        const double* g = role<double>(tb, B_PSRC) + 2 * (size_t)(W - 1);
+        const T src = (role<uint8_t>(tb, B_P1)[i] ? (T)g[0] : (T)0) + (role<uint8_t>(tb, B_P2)[i] ? (T)g[1] : (T)0);
+        l.y = l.y + src;
     }
     st3(role<T>(tb, lam_sel), N, i, l);
 }
@@ -1283,6 +1308,126 @@ __global__ void k_port_finish(const KParams<T>* __restrict__ ptab, const InstTab
         const double i1 = p.n_p1 > 0 ? 1.0 / p.n_p1 : 0.0, i2 = p.n_p2 > 0 ? 1.0 / p.n_p2 : 0.0;
         role<double>(tb, B_SCAL)[0] = W > 0 ? (red[0][0] * i1 - red[1][0] * i2) / W : 0.0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// spectral port objective (Eq. 10) after a forward run
+// ---------------------------------------------------------------------------
+
+// Wave-wide sum in a fixed butterfly order (every lane receives it).
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One 64-lane block per (window step n, instance): x_j(n) = sum over the
+// row-pair blocks of the stored partial sums / |P_j|, in block order.
+template <typename T>
+__global__ __launch_bounds__(64) void k_spec_series(const KParams<T>* __restrict__ ptab,
+                                                    const InstTab* __restrict__ itab) {
+    const int inst = blockIdx.y, n = blockIdx.x;
+    const KParams<T>& p = ptab[inst];
+    const InstTab& tb = itab[inst];
+    const double* part = role<double>(tb, B_PSER) + (size_t)n * 2 * p.nloc;
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = threadIdx.x; b < p.nloc; b += 64) {
+        s1 += part[2 * b];
+        s2 += part[2 * b + 1];
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (threadIdx.x == 0) {
+        double* x = role<double>(tb, B_SER) + 2 * (size_t)n;
+        x[0] = p.n_p1 > 0 ? s1 / p.n_p1 : 0.0;
+        x[1] = p.n_p2 > 0 ? s2 / p.n_p2 : 0.0;
+    }
+}
+
+// t_n of window step n (state m_{n_start + 1 + n})
+__device__ __forceinline__ double window_time(double t0, int64_t n_start, int n, double dt) {
+    return t0 + (double)(n_start + 1 + n) * dt;
+}
+
+// One block per (sample frequency q, instance): C_jq = 1/W sum_n x_j(n)
+// cos(2 pi f_q t_n), S_jq likewise with sin; fixed-order reduction.
+template <typename T>
+__global__ __launch_bounds__(256) void k_spec_dft(const KParams<T>* __restrict__ ptab,
+                                                  const InstTab* __restrict__ itab, const double* __restrict__ fc,
+                                                  int W, double t0, int64_t n_start, double dt) {
+    __shared__ double red[4][4];
+    const int inst = blockIdx.y, q = blockIdx.x;
+    const InstTab& tb = itab[inst];
+    const double* x = role<double>(tb, B_SER);
+    const double w = 6.283185307179586476925286766559 * fc[q];
+    double c1 = 0.0, s1 = 0.0, c2 = 0.0, s2 = 0.0;
+    for (int n = threadIdx.x; n < W; n += 256) {
+        double sn, cn;
+        sincos(w * window_time(t0, n_start, n, dt), &sn, &cn);
+        c1 += x[2 * n] * cn;
+        s1 += x[2 * n] * sn;
+        c2 += x[2 * n + 1] * cn;
+        s2 += x[2 * n + 1] * sn;
+    }
+    c1 = wave_sum(c1);
+    s1 = wave_sum(s1);
+    c2 = wave_sum(c2);
+    s2 = wave_sum(s2);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wv] = c1;
+        red[1][wv] = s1;
+        red[2][wv] = c2;
+        red[3][wv] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        const double v = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+        role<double>(tb, B_SPC)[4 * (size_t)q + k] = v / W;
+    }
+}
+
+// |X| of one (C, S) pair
+__device__ __forceinline__ double spec_mag(double c, double s) { return sqrt(c * c + s * s); }
+
+// One block per instance: J = sum_q c_1q |X_1q| + c_2q |X_2q|, in q order.
+template <typename T>
+__global__ void k_spec_finish(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab,
+                              const double* __restrict__ fc, int K) {
+    const InstTab& tb = itab[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const double* X = role<double>(tb, B_SPC);
+    double J = 0.0;
+    for (int q = 0; q < K; ++q)
+        J += fc[K + q] * spec_mag(X[4 * q], X[4 * q + 1]) + fc[2 * K + q] * spec_mag(X[4 * q + 2], X[4 * q + 3]);
+    role<double>(tb, B_SCAL)[0] = J;
+}
+
+// Per window step n: g_j(n) = sum_q c_jq (C_jq cos + S_jq sin)(2 pi f_q t_n) /
+// (W |X_jq|), divided by |P_j| (the source of each node of port j).  A
+// sample frequency with |X| = 0 (the magnitude's kink) contributes nothing.
+template <typename T>
+__global__ __launch_bounds__(256) void k_spec_src(const KParams<T>* __restrict__ ptab,
+                                                  const InstTab* __restrict__ itab, const double* __restrict__ fc,
+                                                  int K, int W, double t0, int64_t n_start, double dt) {
+    const int inst = blockIdx.y;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= W) return;
+    const KParams<T>& p = ptab[inst];
+    const InstTab& tb = itab[inst];
+    const double* X = role<double>(tb, B_SPC);
+    const double t = window_time(t0, n_start, n, dt);
+    double g1 = 0.0, g2 = 0.0;
+    for (int q = 0; q < K; ++q) {
+        double sn, cn;
+        sincos(6.283185307179586476925286766559 * fc[q] * t, &sn, &cn);
+        const double a1 = spec_mag(X[4 * q], X[4 * q + 1]), a2 = spec_mag(X[4 * q + 2], X[4 * q + 3]);
+        if (a1 > 0.0) g1 += fc[K + q] * (X[4 * q] * cn + X[4 * q + 1] * sn) / a1;
+        if (a2 > 0.0) g2 += fc[2 * K + q] * (X[4 * q + 2] * cn + X[4 * q + 3] * sn) / a2;
+    }
+    double* out = role<double>(tb, B_PSRC) + 2 * (size_t)n;
+    out[0] = p.n_p1 > 0 ? g1 / ((double)W * p.n_p1) : 0.0;
+    out[1] = p.n_p2 > 0 ? g2 / ((double)W * p.n_p2) : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1598,6 +1743,16 @@ hipError_t launch_port_finish(const BatchDev<T>& b, int W, hipStream_t s) {
     return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_spectral(const BatchDev<T>& b, const double* fc, int K, int W, double t0, int64_t n_start, double dt,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_spec_series<T>, dim3(W, b.ninst), dim3(64), 0, s, b.ptab, b.itab);
+    hipLaunchKernelGGL(k_spec_dft<T>, dim3(K, b.ninst), dim3(256), 0, s, b.ptab, b.itab, fc, W, t0, n_start, dt);
+    hipLaunchKernelGGL(k_spec_finish<T>, dim3(b.ninst), dim3(64), 0, s, b.ptab, b.itab, fc, K);
+    hipLaunchKernelGGL(k_spec_src<T>, dim3((W + 255) / 256, b.ninst), dim3(256), 0, s, b.ptab, b.itab, fc, K, W, t0,
+                       n_start, dt);
+    return hipGetLastError();
+}
+template <typename T>
 hipError_t launch_energy(const BatchDev<T>& b, double t, const T* m, double scale, T* dJdm, double* dJdpsi,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_energy<T>, dim3(b.nloc), dim3(b.loc_threads), b.loc_lds, s, bargs(b, b.work_loc), t, m,
@@ -1668,6 +1823,8 @@ hipError_t set_lds_limits(size_t bytes) {
     template hipError_t launch_fill<T>(const BatchDev<T>&, int, int, double, hipStream_t);                         \
     template hipError_t launch_copy<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                        \
     template hipError_t launch_port_finish<T>(const BatchDev<T>&, int, hipStream_t);                                \
+    template hipError_t launch_spectral<T>(const BatchDev<T>&, const double*, int, int, double, int64_t, double,     \
+                                           hipStream_t);                                                            \
     template hipError_t launch_energy<T>(const BatchDev<T>&, double, const T*, double, T*, double*, hipStream_t);   \
     template hipError_t launch_energy_finish<T>(const BatchDev<T>&, double, double, double, double, double*,        \
                                                 double*, double*, hipStream_t);                                     \

@@ -122,6 +122,11 @@ struct llg_handle {
     double prof_ms[LLG_KIND_COUNT] = {0};
     double prof_bytes[LLG_KIND_COUNT] = {0};
     int64_t prof_n[LLG_KIND_COUNT] = {0};
+    // spectral objective: sample frequencies and weights on the device (f, c_1, c_2)
+    double* spec_fc = nullptr;
+    int spec_cap = 0;        // capacity in frequencies of spec_fc and of every instance's B_SPC
+    int spec_k = 0;          // frequencies of the last upload
+    std::vector<double> spec_host;
     // forward record
     bool fwd_valid = false;
     double t0 = 0.0;
@@ -585,6 +590,7 @@ void record_forward(llg_handle* h, double t0, int64_t n, const llg_objective_spe
     h->n_steps = n;
     h->K_used = segment_length(n, h->policy, h->ckpt_param);
     h->last_obj = obj ? *obj : llg_objective_spec{};
+    h->last_obj.freqs = h->last_obj.coef = nullptr;  // the caller's arrays are not kept
 }
 
 // Second stream and events of the overlapped adjoint (created outside any capture).
@@ -664,6 +670,7 @@ struct Ops {
     // adjoint state: ping-pong roles of lambda and u, port window
     int Lc = B_L0, Lo = B_L1, Uc = B_U0, Uo = B_U1;
     bool adj_port = false;
+    bool adj_spec = false;
     int64_t adj_nstart = 0;
     int adj_W = 0;
     const BatchDev<T>& B() const { return bdev<T>(h); }
@@ -751,7 +758,8 @@ struct Ops {
     }
 
     // one RK4 step from B_M (spectrum of psi*m already in S); optional stage store
-    int step(double t, bool last, int store_j, bool port) {
+    // port: 0 none, 1 accumulate the m_y^2 sums, 2 store the m_y sums of window step pstep
+    int step(double t, bool last, int store_j, int port, int pstep = -1) {
         const double dt = h->inst[0].prob.dt;
         const double cs[4] = {0.0, 0.5, 0.5, 1.0};
         const int y_in[4] = {B_M, B_YA, B_YB, B_YA};
@@ -765,7 +773,8 @@ struct Ops {
             L.acc = B_ACC;
             L.ynext = y_out[st];
             L.store_j = store_j;
-            L.port = st == 3 && port;
+            L.port = st == 3 ? port : 0;
+            L.pstep = pstep;
             L.do_inv = h->demag;
             L.do_fwd = h->demag && !(last && st == 3);
             if (int rc = fwd(L)) return rc;
@@ -774,9 +783,12 @@ struct Ops {
     }
 
     int forward(double t0, int64_t n, const llg_objective_spec* obj) {
-        const bool port = obj && obj->kind == LLG_OBJ_PORT_MY2;
+        const bool spec = obj && obj->kind == LLG_OBJ_PORT_SPECTRAL;
+        const bool port = obj && (obj->kind == LLG_OBJ_PORT_MY2 || spec);
         const double dt = h->inst[0].prob.dt;
-        auto in_win = [&](int64_t k) { return port && (k + 1) > obj->n_start; };
+        // port mode of step k (which produces m_{k+1}) and its window index
+        auto in_win = [&](int64_t k) { return port && (k + 1) > obj->n_start ? (spec ? 2 : 1) : 0; };
+        auto wstep = [&](int64_t k) { return port ? (int)(k - obj->n_start) : -1; };
         const int64_t K = segment_length(n, h->policy, h->ckpt_param);
         if (h->policy == LLG_CKPT_BINOMIAL) {
             if (binomial_slots(n, h->ckpt_param) > h->nsnap)
@@ -784,7 +796,7 @@ struct Ops {
         } else if ((n + K - 1) / K > h->nsnap || K > h->K) {
             return fail(LLG_ENOMEM, "checkpoint store too small for n_steps (raise max_steps at create)");
         }
-        if (port)
+        if (port && !spec)
             if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_PPART, 1, s); })) return rc;
         if (int rc = prologue()) return rc;
         int64_t k = 0;
@@ -798,7 +810,7 @@ struct Ops {
                 if (q.op == P_ADV) {
                     if (q.a != k) return fail(LLG_ESTATE, "internal error: checkpoint schedule");
                     for (; k < q.b; ++k)
-                        if (int rc = step(t0 + (double)k * dt, k == n - 1, -1, in_win(k))) return rc;
+                        if (int rc = step(t0 + (double)k * dt, k == n - 1, -1, in_win(k), wstep(k))) return rc;
                 }
                 if (q.op == P_SAVE)
                     if (int rc = copy(B_M, 0, B_SNAP, q.slot)) return rc;
@@ -807,11 +819,18 @@ struct Ops {
         for (; k < n; ++k) {
             if (h->policy != LLG_CKPT_BINOMIAL && k % K == 0)
                 if (int rc = copy(B_M, 0, B_SNAP, (int)(k / K))) return rc;
-            if (int rc = step(t0 + (double)k * dt, k == n - 1, -1, in_win(k))) return rc;
+            if (int rc = step(t0 + (double)k * dt, k == n - 1, -1, in_win(k), wstep(k))) return rc;
         }
         if (port) {
             const int W = (int)(n - obj->n_start);
-            if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_port_finish<T>(B(), W, s); })) return rc;
+            if (spec) {
+                if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) {
+                        return launch_spectral<T>(B(), h->spec_fc, obj->n_freq, W, t0, obj->n_start, dt, s);
+                    }))
+                    return rc;
+            } else if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_port_finish<T>(B(), W, s); })) {
+                return rc;
+            }
         }
         h->fwd_valid = true;
         h->t0 = t0;
@@ -852,7 +871,7 @@ struct Ops {
         const double dt = h->inst[0].prob.dt;
         if (int rc = prologue()) return rc;
         for (int64_t k = n0; k < n1; ++k)
-            if (int rc = step(h->t0 + (double)k * dt, k == n1 - 1, off + (int)(k - n0), false)) return rc;
+            if (int rc = step(h->t0 + (double)k * dt, k == n1 - 1, off + (int)(k - n0), 0)) return rc;
         return LLG_OK;
     }
 
@@ -886,6 +905,8 @@ struct Ops {
                 L.lacc = Lo;
                 L.port_src = st == 0 && adj_port && k > adj_nstart;
                 L.W = adj_W;
+                L.port_lin = adj_spec;
+                L.pstep = (int)(k - adj_nstart - 1);
                 L.do_inv = h->demag;
                 L.do_fwd = h->demag && L.prev_j >= 0;
                 if (int rc = bwd(L)) return rc;
@@ -901,12 +922,14 @@ struct Ops {
         if (!h->fwd_valid) return fail(LLG_ESTATE, "llg_adjoint needs a preceding llg_forward on this handle");
         const int64_t n = h->n_steps, K = h->K_used;
         const double dt = h->inst[0].prob.dt;
-        adj_port = obj && obj->kind == LLG_OBJ_PORT_MY2;
+        adj_spec = obj && obj->kind == LLG_OBJ_PORT_SPECTRAL;
+        adj_port = obj && (obj->kind == LLG_OBJ_PORT_MY2 || adj_spec);
         adj_nstart = adj_port ? obj->n_start : n;
         adj_W = (int)(n - adj_nstart);
         Lc = B_L0, Lo = B_L1, Uc = B_U0, Uo = B_U1;
         // lambda_N = dJ/dm_N (+ port source at N); B_M holds m_N
-        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_adj_init<T>(B(), Lc, use_djdm, adj_port, adj_W, s); }))
+        const int port_mode = adj_port ? (adj_spec ? 2 : 1) : 0;
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_adj_init<T>(B(), Lc, use_djdm, port_mode, adj_W, s); }))
             return rc;
         if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_GPSI, 0, s); })) return rc;
         if (h->policy == LLG_CKPT_BINOMIAL) {
@@ -923,7 +946,7 @@ struct Ops {
                     if (cur != q.a) return fail(LLG_ESTATE, "internal error: checkpoint schedule");
                     if (int rc = prologue()) return rc;
                     for (int64_t k = q.a; k < q.b; ++k)
-                        if (int rc = step(h->t0 + (double)k * dt, k == q.b - 1, -1, false)) return rc;
+                        if (int rc = step(h->t0 + (double)k * dt, k == q.b - 1, -1, 0)) return rc;
                     cur = q.b;
                 } else if (q.op == P_SAVE) {
                     if (int rc = copy(B_M, 0, B_SNAP, q.slot)) return rc;
@@ -1303,6 +1326,71 @@ int b_levelset_vjp(llg_handle* h, const void* const* phi, const double* const* g
     return LLG_OK;
 }
 
+// Validation of an objective for a run of n_steps.
+int check_objective(const llg_objective_spec* obj, int64_t n_steps) {
+    if (!obj) return LLG_OK;
+    if (obj->kind < LLG_OBJ_NONE || obj->kind > LLG_OBJ_PORT_SPECTRAL) return fail(LLG_EINVAL, "unknown objective");
+    const bool port = obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL;
+    if (port && (obj->n_start < 0 || obj->n_start >= n_steps)) return fail(LLG_EINVAL, "n_start must be in [0, n_steps)");
+    if (obj->kind == LLG_OBJ_PORT_SPECTRAL) {
+        if (obj->n_freq < 1 || obj->n_freq > 4096) return fail(LLG_EINVAL, "n_freq must be in [1, 4096]");
+        if (!obj->freqs || !obj->coef) return fail(LLG_EINVAL, "spectral objective needs freqs and coef");
+        for (int q = 0; q < obj->n_freq; ++q)
+            if (!std::isfinite(obj->freqs[q]) || !std::isfinite(obj->coef[q]) ||
+                !std::isfinite(obj->coef[obj->n_freq + q]))
+                return fail(LLG_EINVAL, "freqs and coef must be finite");
+    }
+    return LLG_OK;
+}
+
+// Buffers of the spectral objective (allocated on first use, sized for
+// max_steps) and the upload of its frequencies and weights.  Runs before a
+// launch sequence (outside any graph capture); blocks the host.
+int ensure_spectral(llg_handle* h, const llg_objective_spec* obj) {
+    const int K = obj->n_freq;
+    bool tabs = false;
+    int rc;
+    const size_t steps = (size_t)h->max_steps;
+    for (auto& I : h->inst) {
+        if (!I.tab.b[B_PSER]) {
+            if ((rc = alloc(h, &I.tab.b[B_PSER], steps * 2 * (size_t)I.nloc * 8))) return rc;
+            if ((rc = alloc(h, &I.tab.b[B_SER], steps * 2 * 8))) return rc;
+            if ((rc = alloc(h, &I.tab.b[B_PSRC], steps * 2 * 8))) return rc;
+            tabs = true;
+        }
+    }
+    if (K > h->spec_cap) {
+        const int cap = std::max(K, 64);
+        void* p;
+        if ((rc = alloc(h, &p, (size_t)cap * 3 * 8))) return rc;
+        h->spec_fc = (double*)p;
+        for (auto& I : h->inst)
+            if ((rc = alloc(h, &I.tab.b[B_SPC], (size_t)cap * 4 * 8))) return rc;
+        h->spec_cap = cap;
+        h->spec_host.clear();
+        tabs = true;
+    }
+    if (tabs) {
+        std::vector<InstTab> host(h->inst.size());
+        for (size_t i = 0; i < h->inst.size(); ++i) host[i] = h->inst[i].tab;
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(h->itab, host.data(), sizeof(InstTab) * host.size(), hipMemcpyHostToDevice));
+    }
+    std::vector<double> fc(3 * (size_t)K);
+    for (int q = 0; q < K; ++q) {
+        fc[q] = obj->freqs[q];
+        fc[K + q] = obj->coef[q];
+        fc[2 * K + q] = obj->coef[K + q];
+    }
+    if (fc != h->spec_host) {
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(h->spec_fc, fc.data(), fc.size() * 8, hipMemcpyHostToDevice));
+        h->spec_host = fc;
+    }
+    h->spec_k = K;
+    return LLG_OK;
+}
+
 int b_forward(llg_handle* h, const void* const* psi, const void* const* m0, double t0, int64_t n_steps,
               const llg_objective_spec* obj, void* const* m_out, double* J_dev, hipStream_t s) {
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
@@ -1314,9 +1402,9 @@ int b_forward(llg_handle* h, const void* const* psi, const void* const* m0, doub
     }
     if (n_steps < 1 || n_steps > h->max_steps) return fail(LLG_EINVAL, "n_steps must be in [1, max_steps]");
     if (!std::isfinite(t0)) return fail(LLG_EINVAL, "t0 must be finite");
-    if (obj && (obj->kind < LLG_OBJ_NONE || obj->kind > LLG_OBJ_PORT_MY2)) return fail(LLG_EINVAL, "unknown objective");
-    if (obj && obj->kind == LLG_OBJ_PORT_MY2 && (obj->n_start < 0 || obj->n_start >= n_steps))
-        return fail(LLG_EINVAL, "n_start must be in [0, n_steps)");
+    if (int rc = check_objective(obj, n_steps)) return rc;
+    if (obj && obj->kind == LLG_OBJ_PORT_SPECTRAL)
+        if (int rc = ensure_spectral(h, obj)) return rc;
     h->fwd_valid = false;
     for (int i = 0; i < n; ++i) {
         const size_t N = h->inst[i].N;
@@ -1325,7 +1413,8 @@ int b_forward(llg_handle* h, const void* const* psi, const void* const* m0, doub
     }
     ensure_plan(h, n_steps);
     const std::vector<double> key = {0.0, (double)n_steps, t0, obj ? (double)obj->kind : -1.0,
-                                     obj ? (double)obj->n_start : -1.0};
+                                     obj ? (double)obj->n_start : -1.0,
+                                     obj && obj->kind == LLG_OBJ_PORT_SPECTRAL ? (double)obj->n_freq : 0.0};
     int res = 0;
     int rc = run_sequence(h, s, key, &res, [&](hipStream_t st, int* r) {
         *r = 0;
@@ -1337,7 +1426,7 @@ int b_forward(llg_handle* h, const void* const* psi, const void* const* m0, doub
     for (int i = 0; i < n; ++i) {
         if (m_out && m_out[i])
             if ((rc = get(h, i, B_M, m_out[i], 3 * (size_t)h->inst[i].N * h->tsz, s))) return rc;
-        if (J_dev && obj && obj->kind == LLG_OBJ_PORT_MY2)
+        if (J_dev && obj && (obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL))
             if ((rc = get(h, i, B_SCAL, J_dev + i, sizeof(double), s))) return rc;
     }
     return LLG_OK;
@@ -1353,8 +1442,13 @@ int b_adjoint(llg_handle* h, const void* const* psi, const void* const* dJdm_T, 
         if (int rc = check_ptr(dJdpsi_out[i], "dJdpsi_out")) return rc;
     }
     if (!h->fwd_valid) return fail(LLG_ESTATE, "llg_adjoint needs a preceding llg_forward on this handle");
-    if (obj && obj->kind == LLG_OBJ_PORT_MY2 && (obj->n_start < 0 || obj->n_start >= h->n_steps))
+    if (obj && (obj->kind < LLG_OBJ_NONE || obj->kind > LLG_OBJ_PORT_SPECTRAL)) return fail(LLG_EINVAL, "unknown objective");
+    if (obj && (obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL) &&
+        (obj->n_start < 0 || obj->n_start >= h->n_steps))
         return fail(LLG_EINVAL, "n_start must be in [0, n_steps)");
+    if (obj && obj->kind == LLG_OBJ_PORT_SPECTRAL &&
+        (h->last_obj.kind != LLG_OBJ_PORT_SPECTRAL || h->last_obj.n_start != obj->n_start))
+        return fail(LLG_ESTATE, "the spectral sources come from the last forward: run it with the same objective");
     bool use_djdm = dJdm_T != nullptr, use_expl = expl != nullptr;
     for (int i = 0; i < n; ++i) {
         if (use_djdm && !dJdm_T[i]) use_djdm = false;
@@ -1580,10 +1674,10 @@ int llg_objective(llg_handle* h, const llg_objective_spec* obj, const void* psi,
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
     if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
     if ((rc = check_ptr(obj, "obj"))) return rc;
-    if (obj->kind != LLG_OBJ_ENERGY_AREA && obj->kind != LLG_OBJ_PORT_MY2)
-        return fail(LLG_EINVAL, "objective kind must be ENERGY_AREA or PORT_MY2");
+    if (obj->kind != LLG_OBJ_ENERGY_AREA && obj->kind != LLG_OBJ_PORT_MY2 && obj->kind != LLG_OBJ_PORT_SPECTRAL)
+        return fail(LLG_EINVAL, "objective kind must be ENERGY_AREA, PORT_MY2 or PORT_SPECTRAL");
     const size_t N = h->inst[0].N;
-    if (obj->kind == LLG_OBJ_PORT_MY2) {
+    if (obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL) {
         if (!h->fwd_valid) return fail(LLG_ESTATE, "port objective needs a preceding llg_forward");
         if (J_dev && (rc = get(h, 0, B_SCAL, J_dev, sizeof(double), stream))) return rc;
         if (dJdm_out) HIPCHK(hipMemsetAsync(dJdm_out, 0, 3 * N * h->tsz, stream));

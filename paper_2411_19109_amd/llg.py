@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libllg.so")
 LLG_OK, LLG_EINVAL, LLG_ESHAPE, LLG_ENOMEM, LLG_EHIP, LLG_ENONFINITE, LLG_ENOTSUP, LLG_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 LLG_F32, LLG_F64 = 0, 1
 LLG_CKPT_SQRT, LLG_CKPT_ALL, LLG_CKPT_BINOMIAL = 0, 1, 2
-LLG_OBJ_NONE, LLG_OBJ_ENERGY_AREA, LLG_OBJ_PORT_MY2 = 0, 1, 2
+LLG_OBJ_NONE, LLG_OBJ_ENERGY_AREA, LLG_OBJ_PORT_MY2, LLG_OBJ_PORT_SPECTRAL = 0, 1, 2, 3
 
 EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_levelset_to_Ms",
            "llg_levelset_to_Ms_vjp", "llg_field", "llg_forward", "llg_objective", "llg_adjoint",
@@ -59,7 +59,8 @@ class Masks_c(ctypes.Structure):
 
 class Objective_c(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("E_ref", ctypes.c_double), ("lambda_", ctypes.c_double),
-                ("area", ctypes.c_double), ("n_start", ctypes.c_int64)]
+                ("area", ctypes.c_double), ("n_start", ctypes.c_int64), ("n_freq", ctypes.c_int32),
+                ("freqs", ctypes.POINTER(ctypes.c_double)), ("coef", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -147,10 +148,34 @@ def make_problem(prob, dtype="f32", max_steps=1, ckpt_policy=LLG_CKPT_SQRT, ckpt
     return c
 
 
-def make_objective(kind=LLG_OBJ_NONE, E_ref=1.0, lam=1.0, area=0.4, n_start=0) -> Objective_c:
+def make_objective(kind=LLG_OBJ_NONE, E_ref=1.0, lam=1.0, area=0.4, n_start=0, freqs=None, coef=None) -> Objective_c:
+    """Objective_c; for LLG_OBJ_PORT_SPECTRAL, freqs (K sample frequencies, Hz)
+    and coef (2 x K weights of |X_1(f_q)| and |X_2(f_q)|).  The object keeps its
+    arrays alive."""
     o = Objective_c()
     o.kind, o.E_ref, o.lambda_, o.area, o.n_start = kind, E_ref, lam, area, n_start
+    if freqs is not None:
+        f = np.ascontiguousarray(np.asarray(freqs, np.float64).reshape(-1))
+        c = np.ascontiguousarray(np.asarray(coef, np.float64).reshape(-1))
+        if c.size != 2 * f.size:
+            raise ValueError("coef must hold 2 x len(freqs) weights")
+        o._keep = (f, c)
+        o.n_freq = f.size
+        o.freqs = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o.coef = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return o
+
+
+def demux_windows(f1, f2, half_width, n_per_window):
+    """Sample frequencies and weights of Eq. 10: n_per_window frequencies evenly
+    spread over [f - half_width, f + half_width] around f1 and around f2; port 1
+    is the top output (TO), port 2 the bottom one (BO), and
+    J = (A_TO(f1) - A_BO(f1)) + (A_BO(f2) - A_TO(f2))."""
+    w = np.linspace(-half_width, half_width, n_per_window) if n_per_window > 1 else np.zeros(1)
+    freqs = np.concatenate([f1 + w, f2 + w])
+    one = np.ones(n_per_window)
+    coef = np.stack([np.concatenate([one, -one]), np.concatenate([-one, one])])
+    return freqs, coef
 
 
 def query_memory(prob, n_steps, policy=LLG_CKPT_SQRT, ckpt_param=0, dtype="f32") -> int:

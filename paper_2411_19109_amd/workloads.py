@@ -37,6 +37,7 @@ FACE_XLO, FACE_XHI, FACE_YLO, FACE_YHI, FACE_ZLO, FACE_ZHI = 1, 2, 4, 8, 16, 32
 OBJ_NONE = 0
 OBJ_ENERGY_AREA = 1
 OBJ_PORT_MY2 = 2
+OBJ_PORT_SPECTRAL = 3
 
 
 @dataclasses.dataclass

@@ -5,7 +5,8 @@ n RK4 steps of the LLG equation with checkpoints, the objective, the
 checkpointed discrete adjoint back to t0, and the chain rule to dJ/dphi.
 Inputs are resident in device memory before the timed region starts.
 
-  python bench.py [--steps K] [--warmup W] [--workload particle|waveguide|demux|device3d|sweep|probe|rbf]
+  python bench.py [--steps K] [--warmup W]
+                  [--workload particle|waveguide|demux|demux_spectral|device3d|sweep|probe|rbf]
 
 Prints ONE JSON line.  The metric is LLG cell-steps per second of the forward
 + adjoint run: nodes * RK4 steps / wall time of one gradient evaluation.
@@ -38,6 +39,8 @@ def make_workload(name):
         return w
     if name == "demux":
         return wl.yig_demux()
+    if name == "demux_spectral":
+        return wl.yig_demux_two_tone()
     if name == "device3d":
         return wl.yig_device_3d()
     raise SystemExit(f"unknown workload {name}")
@@ -74,7 +77,7 @@ class GradientStep:
         self.psi_fixed = torch.as_tensor(w.psi_fixed.reshape(-1), dtype=self.td, device=dev).contiguous()
         self.m0 = torch.as_tensor(w.m0.reshape(-1), dtype=self.td, device=dev).contiguous()
         self.obj = llg.make_objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area,
-                                      n_start=w.obj_n_start)
+                                      n_start=w.obj_n_start, freqs=w.extra.get("freqs"), coef=w.extra.get("coef"))
         self.energy = w.objective == wl.OBJ_ENERGY_AREA
 
     def __call__(self):
@@ -155,7 +158,7 @@ def cpu_baseline(w, budget_s=15.0):
     sim = omm.Sim(w.problem, antenna=w.antenna)
     psi = ols.levelset_to_psi(w.phi, w.heaviside_a, w.design, w.psi_fixed)
     obj = oadj.Objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area,
-                         n_start=0, port1=w.port1, port2=w.port2)
+                         n_start=0, port1=w.port1, port2=w.port2, freqs=w.extra.get("freqs"), coef=w.extra.get("coef"))
     n = 10
     t0 = time.perf_counter()
     oadj.gradient(sim, w.m0, psi, n, obj)

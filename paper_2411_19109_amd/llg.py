@@ -166,18 +166,6 @@ def make_objective(kind=LLG_OBJ_NONE, E_ref=1.0, lam=1.0, area=0.4, n_start=0, f
     return o
 
 
-def demux_windows(f1, f2, half_width, n_per_window):
-    """Sample frequencies and weights of Eq. 10: n_per_window frequencies evenly
-    spread over [f - half_width, f + half_width] around f1 and around f2; port 1
-    is the top output (TO), port 2 the bottom one (BO), and
-    J = (A_TO(f1) - A_BO(f1)) + (A_BO(f2) - A_TO(f2))."""
-    w = np.linspace(-half_width, half_width, n_per_window) if n_per_window > 1 else np.zeros(1)
-    freqs = np.concatenate([f1 + w, f2 + w])
-    one = np.ones(n_per_window)
-    coef = np.stack([np.concatenate([one, -one]), np.concatenate([-one, one])])
-    return freqs, coef
-
-
 def query_memory(prob, n_steps, policy=LLG_CKPT_SQRT, ckpt_param=0, dtype="f32") -> int:
     b = ctypes.c_size_t(0)
     check(lib().llg_query_memory(ctypes.byref(make_problem(prob, dtype, max(1, n_steps))), n_steps, policy,

@@ -302,6 +302,35 @@ def yig_demux(seed: int = 2, n_steps: int = 20000, nx: int = 256, ny: int = 96, 
                     extra=dict(box=lay["box"]))
 
 
+def demux_windows(f1: float, f2: float, half_width: float, n_per_window: int):
+    """Sample frequencies and weights of Eq. 10: n_per_window frequencies evenly
+    spread over [f - half_width, f + half_width] around f1 and around f2.  Port 1
+    is the top output (TO), port 2 the bottom one (BO), and
+    J = (A_TO(f1) - A_BO(f1)) + (A_BO(f2) - A_TO(f2)): coef[0] weighs |X_TO|,
+    coef[1] weighs |X_BO|."""
+    w = np.linspace(-half_width, half_width, n_per_window) if n_per_window > 1 else np.zeros(1)
+    freqs = np.concatenate([f1 + w, f2 + w])
+    one = np.ones(n_per_window)
+    coef = np.stack([np.concatenate([one, -one]), np.concatenate([-one, one])])
+    return freqs, coef
+
+
+def yig_demux_two_tone(seed: int = 2, n_steps: int = 20000, f1: float = 2.5e9, f2: float = 3.5e9,
+                       half_width: float = 0.2e9, n_per_window: int = 5, dtype: str = "f32") -> Workload:
+    """The demultiplexer driven by both tones at once (sin 2 pi f1 t + sin 2 pi
+    f2 t on the antenna) with the spectral objective of Eq. 10 over the second
+    half of the run: windows of n_per_window sample frequencies within
+    +-half_width of f1 and f2.  2.5 / 3.5 GHz rather than the paper's 2.6 / 2.8
+    GHz: the 1 ns window of a 20 000-step run resolves 1 GHz."""
+    w = yig_demux(seed=seed, n_steps=n_steps, f=f1, dtype=dtype)
+    w.problem.f2 = f2
+    w.objective = OBJ_PORT_SPECTRAL
+    freqs, coef = demux_windows(f1, f2, half_width, n_per_window)
+    w.extra = dict(w.extra, freqs=freqs, coef=coef)
+    w.name = f"yig_demux_{w.problem.nx}x{w.problem.ny}_spectral_grad"
+    return w
+
+
 def yig_demux_sweep(seed: int = 3, n_designs: int = 32, freqs=(2.5e9, 3.5e9), n_steps: int = 10000) -> List[Workload]:
     """Batched sweep: n_designs independently seeded phi, each on its own grid
     with nx ~ U{128..256}, ny ~ U{64..128}, times the listed drive

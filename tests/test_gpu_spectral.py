@@ -35,8 +35,7 @@ def two_tone_case(n_steps, nx=48, ny=32, seed=21):
 
 
 def windows():
-    from paper_2411_19109_amd import llg
-    return llg.demux_windows(2.5e12, 4.0e12, 0.3e12, 3)
+    return wl.demux_windows(2.5e12, 4.0e12, 0.3e12, 3)
 
 
 def gpu_spectral(w, dtype, n, batch=None, **kw):
@@ -146,11 +145,9 @@ def test_full_length_two_tone_demux_fp32_matches_fp64():
     (both paths are checked against the oracle at short length above)."""
     import torch
     from paper_2411_19109_amd import llg
-    w = wl.yig_demux(n_steps=20000)
-    w.problem.f1, w.problem.f2 = 2.5e9, 3.5e9
+    w = wl.yig_demux_two_tone()
     n = w.n_steps
-    freqs, coef = llg.demux_windows(2.5e9, 3.5e9, 0.2e9, 5)
-    obj = llg.make_objective(wl.OBJ_PORT_SPECTRAL, n_start=n // 2, freqs=freqs, coef=coef)
+    obj = llg.make_objective(wl.OBJ_PORT_SPECTRAL, n_start=w.obj_n_start, freqs=w.extra["freqs"], coef=w.extra["coef"])
     Js = {}
     for dtype in ("f32", "f64"):
         s = llg.Solver(w.problem, dtype=dtype, max_steps=n, antenna=w.antenna, port1=w.port1, port2=w.port2,

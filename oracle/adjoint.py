@@ -31,7 +31,7 @@ import numpy as np
 
 from .micromag import MU0, TERM_ANIS, TERM_DEMAG, TERM_EXCH, cross, dot
 
-OBJ_NONE, OBJ_ENERGY_AREA, OBJ_PORT_MY2, OBJ_PORT_SPECTRAL = 0, 1, 2, 3
+OBJ_NONE, OBJ_ENERGY_AREA, OBJ_PORT_MY2, OBJ_PORT_SPECTRAL, OBJ_MAG_CURVE = 0, 1, 2, 3, 4
 
 
 class Objective:
@@ -39,10 +39,12 @@ class Objective:
              OBJ_PORT_MY2       -> J = 1/|W| sum_{n in W} [mean_P1 m_y^2 - mean_P2 m_y^2],
                                    W = {n : n_start < n <= n_steps}
              OBJ_PORT_SPECTRAL  -> J = sum_q coef[0, q] |X_1(f_q)| + coef[1, q] |X_2(f_q)|
-                                   (Eq. 10 with its frequency windows; see spectral_value)."""
+                                   (Eq. 10 with its frequency windows; see spectral_value)
+             OBJ_MAG_CURVE      -> J = sum_{n in W} weight_n |M_x(n) - target_n|
+                                   (Eq. 8; see curve_value)."""
 
     def __init__(self, kind, E_ref=1.0, lam=1.0, area=0.4, n_start=0, port1=None, port2=None, freqs=None,
-                 coef=None):
+                 coef=None, target=None, weight=None):
         self.kind = kind
         self.E_ref = E_ref
         self.lam = lam
@@ -52,6 +54,8 @@ class Objective:
         self.port2 = None if port2 is None else np.asarray(port2, float)
         self.freqs = None if freqs is None else np.asarray(freqs, float)
         self.coef = None if coef is None else np.asarray(coef, float).reshape(2, -1)
+        self.target = None if target is None else np.asarray(target, float)
+        self.weight = None if weight is None else np.asarray(weight, float)
 
 
 # -- objective values and their explicit derivatives --------------------------
@@ -150,6 +154,35 @@ def spectral_source_field(g, m, obj):
     return out
 
 
+# -- magnetisation-curve objective (Eq. 8) -------------------------------------
+#
+# Eq. 8 sums, over the steps of a run whose applied field ramps linearly from 0
+# to 0.3 Ms, the relative distance between the particle's mean magnetisation
+# M_x and a target curve.  Readings: M_x(n) = 1/N sum_i psi_i m_x,i(n) over all
+# N nodes (the magnetic moment along x in units of Ms times the domain volume;
+# air contributes nothing), for the states m_n of the window W; the weights
+# weight_n = 1 / (M^target_n |W|) and the target are inputs; |.| takes the zero
+# subgradient at 0.  J depends on psi explicitly through M_x.
+
+def _absr(z):
+    """|z| for real z, continued analytically for complex-step perturbations."""
+    return np.where(np.real(z) >= 0, z, -z)
+
+
+def curve_series(traj, psi, obj, n_steps):
+    win = range(obj.n_start + 1, n_steps + 1)
+    return np.array([(psi * traj[n][0]).sum() / psi.size for n in win])
+
+
+def curve_value(M, obj):
+    return (obj.weight * _absr(M - obj.target)).sum()
+
+
+def curve_sources(M, obj):
+    """dJ/dM(n) = weight_n sign(M(n) - target_n) (0 where they are equal)."""
+    return obj.weight * np.sign(np.real(M - obj.target))
+
+
 # -- transpose of one right-hand-side evaluation -------------------------------
 
 def rhs_vjp(sim, m, B, psi, v):
@@ -203,6 +236,8 @@ def objective_value(sim, traj, psi, obj, n_steps, t0=0.0):
         return sum(port_value(traj[n], obj) for n in win) / len(win)
     if obj.kind == OBJ_PORT_SPECTRAL:
         return spectral_value(port_series(traj, obj, n_steps), window_times(sim, obj, n_steps, t0), obj)
+    if obj.kind == OBJ_MAG_CURVE:
+        return curve_value(curve_series(traj, psi, obj, n_steps), obj)
     return 0.0
 
 
@@ -229,6 +264,18 @@ def gradient(sim, m0, psi, n_steps, obj, t0=0.0):
     if spec:
         g_ser = spectral_sources(port_series(traj, obj, n_steps), window_times(sim, obj, n_steps, t0), obj)
         lam = lam + spectral_source_field(g_ser[:, -1], traj[n_steps], obj)
+    curve = obj.kind == OBJ_MAG_CURVE and n_steps > obj.n_start
+    if curve:
+        # dJ/dm_x,i(n) = g_n psi_i / N and dJ/dpsi_i += g_n m_x,i(n) / N
+        g_cur = curve_sources(curve_series(traj, psi, obj, n_steps), obj) / psi.size
+
+        def curve_terms(g, m):
+            gm = np.zeros(m.shape, dtype=np.result_type(m, psi, g))
+            gm[0] = g * psi
+            return gm, g * m[0]
+        gm, gp = curve_terms(g_cur[-1], traj[n_steps])
+        lam = lam + gm
+        g_psi = g_psi + gp
     for n in range(n_steps - 1, -1, -1):
         t = t0 + n * dt
         _, ys, Bs = sim.rk4_step(traj[n], psi, t)
@@ -246,4 +293,8 @@ def gradient(sim, m0, psi, n_steps, obj, t0=0.0):
             lam = lam + port_source(traj[n], obj, n_window)
         if spec and obj.n_start < n:
             lam = lam + spectral_source_field(g_ser[:, n - obj.n_start - 1], traj[n], obj)
+        if curve and obj.n_start < n:
+            gm, gp = curve_terms(g_cur[n - obj.n_start - 1], traj[n])
+            lam = lam + gm
+            g_psi = g_psi + gp
     return J, g_psi, lam

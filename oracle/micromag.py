@@ -155,8 +155,12 @@ class Sim:
         """Scalar drive waveform.  sin(phase(t)), the frequency switching from f1
         to f2 at t_switch (if t_switch > 0) with a continuous phase; without a
         switch and with f2 > 0, the two-tone excitation of the demultiplexer
-        section, sin(2 pi f1 t) + sin(2 pi f2 t)."""
+        section, sin(2 pi f1 t) + sin(2 pi f2 t).  drive_kind 1: the ramp t / t_ramp
+        (with b_rf the field reached at t_ramp)."""
         p = self.p
+        if getattr(p, "drive_kind", 0) == 1:
+            # the linear field ramp of the magnetisation-curve experiment: 0 at t = 0, 1 at t_ramp
+            return t / p.t_ramp
         if p.t_switch > 0 and t >= p.t_switch:
             ph = 2 * math.pi * (p.f1 * p.t_switch + p.f2 * (t - p.t_switch))
         elif p.t_switch <= 0 and p.f2 > 0:

@@ -38,6 +38,7 @@ OBJ_NONE = 0
 OBJ_ENERGY_AREA = 1
 OBJ_PORT_MY2 = 2
 OBJ_PORT_SPECTRAL = 3
+OBJ_MAG_CURVE = 4
 
 
 @dataclasses.dataclass
@@ -65,6 +66,8 @@ class Problem:
     t_switch: float = -1.0      # < 0: no switch
     terms: int = TERM_ALL
     dt: float = 1e-13
+    drive_kind: int = 0         # 0: sine (switch / two tones as above); 1: linear ramp t / t_ramp
+    t_ramp: float = 0.0         # duration of the ramp (drive_kind 1), s
 
     @property
     def n(self) -> int:

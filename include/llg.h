@@ -86,6 +86,9 @@ extern "C" {
  * x_j(n) exp(-2 pi i f t_n), x_j(n) the mean m_y over port j of the state m_n at t_n = t0 + n dt
  * (frequency windows around f1 and f2 are sets of sample frequencies f_q with coefficients +-1) */
 #define LLG_OBJ_PORT_SPECTRAL 3
+/* Eq. 8: J = sum_{n in W} weight[n'] |M_x(n) - target[n']|, n' = n - n_start - 1, with
+ * M_x(n) = 1/N sum_i psi_i m_x,i(n) over all N nodes (explicit in psi as well as in m) */
+#define LLG_OBJ_MAG_CURVE 4
 
 /* ---- problem description --------------------------------------------- */
 typedef struct llg_problem {
@@ -110,7 +113,13 @@ typedef struct llg_problem {
     int32_t ckpt_policy;      /* LLG_CKPT_*                                                 */
     int32_t ckpt_param;       /* SQRT: segment length K (0 = ceil(sqrt(n_steps)));
                                  BINOMIAL: snapshot slots (0 = 32)                            */
+    int32_t drive_kind;       /* LLG_DRIVE_*                                                */
+    double t_ramp;            /* LLG_DRIVE_RAMP: time at which the drive reaches b_rf, s (> 0) */
 } llg_problem;
+
+/* Drive waveforms on the antenna mask */
+#define LLG_DRIVE_SINE 0 /* b_rf sin(2 pi f1 t); f2 at t_switch > 0; with f2 > 0 and no switch both tones summed */
+#define LLG_DRIVE_RAMP 1 /* b_rf t / t_ramp: the linear field ramp of a magnetisation curve (Eq. 8) */
 
 /* Host-side copies of the u8 masks (length N, values 0/1); NULL = all zero.
  * They are copied into the handle by llg_create. */
@@ -130,6 +139,8 @@ typedef struct llg_objective_spec {
     int32_t n_freq;   /* LLG_OBJ_PORT_SPECTRAL: number of sample frequencies (1..4096) */
     const double* freqs;  /* host, n_freq sample frequencies f_q, Hz                */
     const double* coef;   /* host, 2 n_freq weights: of |X_1(f_q)|, then of |X_2(f_q)| */
+    const double* target; /* LLG_OBJ_MAG_CURVE: host, n_steps - n_start target values   */
+    const double* weight; /* LLG_OBJ_MAG_CURVE: host, n_steps - n_start weights          */
 } llg_objective_spec;
 
 typedef struct llg_handle llg_handle;
@@ -186,11 +197,11 @@ int llg_forward(llg_handle* h, const void* psi, const void* m0, double t0, int64
  * *J_dev, dJ/dm to dJdm_out (3N, handle precision) and the explicit dJ/dpsi
  * to dJdpsi_out (N, float64); energies_dev (device double[5]: exchange, demag,
  * Zeeman at t, anisotropy, total; J) receives the energy terms when not NULL.
- * For LLG_OBJ_PORT_MY2 and LLG_OBJ_PORT_SPECTRAL the objective is a function of
+ * For LLG_OBJ_PORT_MY2, LLG_OBJ_PORT_SPECTRAL and LLG_OBJ_MAG_CURVE the objective is a function of
  * the trajectory: J_dev receives the value the last llg_forward computed,
  * dJdm_out and dJdpsi_out are zeroed (its sources are injected by llg_adjoint;
- * for the spectral objective they are those of the last llg_forward's
- * frequencies and weights). */
+ * for the spectral and curve objectives they are those of the last
+ * llg_forward's frequencies, targets and weights). */
 int llg_objective(llg_handle* h, const llg_objective_spec* obj, const void* psi, const void* m, double t,
                   double* J_dev, void* dJdm_out, double* dJdpsi_out, double* energies_dev, hipStream_t stream);
 

@@ -98,6 +98,8 @@ struct KParams {
     T gamma;
     T dt;
     double f1, f2, t_switch;
+    int drive_kind;                // 0 sine, 1 ramp t / t_ramp
+    double t_ramp;
 };
 
 // One forward-stage launch (shared by every instance of the batch).
@@ -106,7 +108,8 @@ struct FwdL {
     double t;             // time of the stage
     int ys, mn, acc, ynext;  // BufId roles (-1 = none)
     int store_j;          // >= 0: copy ys and B(ys) to slot store_j of YS / BS
-    int port;             // stage 3: 1 accumulate the port m_y^2 sums, 2 write the port m_y sums of window step pstep
+    int port;             // stage 3: 1 accumulate the port m_y^2 sums; write, for window step pstep, 2 the port
+                          // m_y sums (spectral objective), 3 the psi m_x sums over all nodes (curve objective)
     int pstep;            // window index of the state this launch produces (port == 2)
     int do_inv, do_fwd;   // inverse x-FFT of S (demag in) / forward x-FFT of psi*ynext into S
     int spec;             // BufId of S (B_S or B_S2)
@@ -123,7 +126,7 @@ struct BwdL {
     int ucur, unext, lamp, lacc;  // BufId roles
     int port_src;         // add the port running-cost source at stage 0
     int W;                // port window length (steps)
-    int port_lin;         // spectral objective: the source is the stored per-step scalar (not 2 m_y / (W |P|))
+    int port_lin;         // 1 spectral, 2 curve objective: the source is the stored per-step scalar
     int pstep;            // window index of this step's state (port_lin)
     int do_inv, do_fwd;
     int stage_m;          // stage the y_s rows in LDS too (set by the launcher from the batch)
@@ -146,7 +149,7 @@ struct StageFwdArgs {
     const uint8_t* port1;
     const uint8_t* port2;
     double* port_part;
-    int port_lin;         // sum m_y and store (spectral series) instead of accumulating m_y^2
+    int port_lin;         // 0 accumulate m_y^2; store 1 the port m_y sums, 2 the psi m_x sums over all nodes
     int do_inv;
     int do_fwd;
 };
@@ -169,7 +172,8 @@ struct StageBwdArgs {
     const uint8_t* port1;
     const uint8_t* port2;
     T src1, src2;         // port sources (port 2 carries its sign)
-    int src_lin;          // lambda.y += src (spectral) instead of src * m_y
+    int src_lin;          // 0 lambda.y += src m_y; 1 lambda.y += src (spectral); 2 lambda.x += src psi and
+                          // dJ/dpsi += src m_x on every node (curve)
     int do_inv;
     int do_fwd;
 };
@@ -227,6 +231,9 @@ template <typename T> hipError_t launch_port_finish(const BatchDev<T>& b, int W,
 // Spectral objective after a forward run: series from the per-step partials, DFT
 // parts at the K sample frequencies, J, and the per-step adjoint sources.  fc
 // holds f_q (K), then the weights of |X_1| (K) and of |X_2| (K), on the device.
+// Curve objective after a forward run: M_x series and per-step sources, then J.
+// tw holds the W targets, then the W weights, on the device.
+template <typename T> hipError_t launch_curve(const BatchDev<T>& b, const double* tw, int W, hipStream_t s);
 template <typename T>
 hipError_t launch_spectral(const BatchDev<T>& b, const double* fc, int K, int W, double t0, int64_t n_start, double dt,
                            hipStream_t s);

@@ -261,9 +261,10 @@ template <typename T> __device__ __forceinline__ T node_alpha(const KParams<T>& 
 
 // Drive waveform: sin(2 pi f1 t), switching to f2 at t_switch > 0 with a
 // continuous phase; without a switch and with f2 > 0 the two-tone excitation
-// sin(2 pi f1 t) + sin(2 pi f2 t).
-__device__ __forceinline__ double drive_value(double f1, double f2, double tsw, double t) {
+// sin(2 pi f1 t) + sin(2 pi f2 t); kind 1: the linear ramp t / t_ramp.
+__device__ __forceinline__ double drive_value(double f1, double f2, double tsw, int kind, double t_ramp, double t) {
     const double twopi = 6.283185307179586476925286766559;
+    if (kind == 1) return t / t_ramp;
     if (tsw <= 0.0 && f2 > 0.0) return sin(twopi * f1 * t) + sin(twopi * f2 * t);
     double ph = (tsw > 0.0 && t >= tsw) ? twopi * (f1 * tsw + f2 * (t - tsw)) : twopi * f1 * t;
     return sin(ph);
@@ -531,10 +532,10 @@ __device__ __forceinline__ StageFwdArgs<T> resolve_fwd(const KParams<T>& p, cons
     a.ys_store = L.store_j >= 0 ? role<T>(tb, B_YS) + ((size_t)L.store_j * 4 + L.stage) * n3 : nullptr;
     a.Bs_store = L.ext_B ? static_cast<T*>(L.ext_B)
                          : (L.store_j >= 0 ? role<T>(tb, B_BS) + ((size_t)L.store_j * 4 + L.stage) * n3 : nullptr);
-    const bool port = L.port && (p.n_p1 + p.n_p2) > 0;
+    const bool port = L.port && (L.port == 3 || (p.n_p1 + p.n_p2) > 0);
     a.port1 = port ? role<uint8_t>(tb, B_P1) : nullptr;
     a.port2 = port ? role<uint8_t>(tb, B_P2) : nullptr;
-    a.port_lin = L.port == 2;
+    a.port_lin = L.port >= 2 ? L.port - 1 : 0;
     a.port_part = !port ? nullptr
                         : (a.port_lin ? role<double>(tb, B_PSER) + (size_t)L.pstep * 2 * p.nloc
                                       : role<double>(tb, B_PPART));
@@ -561,7 +562,7 @@ __device__ __forceinline__ StageBwdArgs<T> resolve_bwd(const KParams<T>& p, cons
     a.y_prev = L.prev_j >= 0 ? role<T>(tb, B_YS) + ((size_t)L.prev_j * 4 + L.prev_st) * n3 : nullptr;
     a.u_next = role<T>(tb, L.unext);
     a.S = role<cplx<T>>(tb, B_S);
-    const bool port = L.port_src && (p.n_p1 + p.n_p2) > 0 && L.W > 0;
+    const bool port = L.port_src && L.W > 0 && (L.port_lin == 2 || (p.n_p1 + p.n_p2) > 0);
     a.port1 = port ? role<uint8_t>(tb, B_P1) : nullptr;
     a.port2 = port ? role<uint8_t>(tb, B_P2) : nullptr;
     a.src_lin = L.port_lin;
@@ -632,7 +633,7 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     __syncthreads();
     if (demag_in) fft_lds<C, true, MR>(Z, sm, Px, 3, LS.Tw);
 
-    const T drv = ((p.terms & 4) && a.antenna) ? (T)drive_value(p.f1, p.f2, p.t_switch, a.t) : (T)0;
+    const T drv = ((p.terms & 4) && a.antenna) ? (T)drive_value(p.f1, p.f2, p.t_switch, p.drive_kind, p.t_ramp, a.t) : (T)0;
     const T dt = p.dt;
     const int iy0 = r0 % p.ny, iz0 = r0 / p.ny;
     double s1 = 0.0, s2 = 0.0;
@@ -716,10 +717,14 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             }
             if (a.ynext) st3(a.ynext, N, i, yn);
             if (a.port_part) {
-                const double v = a.port_lin ? (double)yn.y : (double)yn.y * (double)yn.y;
-                const bool first_it = it == (int)threadIdx.x;
-                if (first_it ? pre_p1 : glb(a.port1)[i]) s1 += v;
-                if (first_it ? pre_p2 : glb(a.port2)[i]) s2 += v;
+                if (a.port_lin == 2) {
+                    s1 += (double)pi * (double)yn.x;  // curve objective: psi m_x over every node
+                } else {
+                    const double v = a.port_lin ? (double)yn.y : (double)yn.y * (double)yn.y;
+                    const bool first_it = it == (int)threadIdx.x;
+                    if (first_it ? pre_p1 : glb(a.port1)[i]) s1 += v;
+                    if (first_it ? pre_p2 : glb(a.port2)[i]) s2 += v;
+                }
             }
             if (a.do_fwd) {
                 // packed forward-FFT input: (x, y) of each row, z of row 0 + i z of row 1
@@ -934,6 +939,8 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                     const V3<T> ua = v3<T>(p.u[0], p.u[1], p.u[2]);
                     mu = mu + (p.anis * dot(uk, ua)) * ua;
                 }
+                // curve objective at stage 0: its explicit psi dependence, dJ/dpsi_i += g_n m_x,i
+                if (a.port1 && a.src_lin == 2) g += (double)a.src1 * (double)m.x;
                 glb(a.gpsi)[i] = d.g0 + g;
                 const V3<T> lsum = (a.stage == 3 ? d.lam : d.lacc) + mu;
                 if (a.stage > 0) {
@@ -944,7 +951,9 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                     st3(a.u_next, N, i, un);
                 } else {
                     V3<T> lam = lsum;
-                    if (a.port1) {
+                    if (a.port1 && a.src_lin == 2) {
+                        lam.x = lam.x + a.src1 * pi;  // curve objective: dJ/dm_x,i = g_n psi_i
+                    } else if (a.port1) {
                         // source dJ/dm_n of the port objective (y component)
                         const T src = (d.p1 ? a.src1 : (T)0) + (d.p2 ? a.src2 : (T)0);
                         lam.y = lam.y + (a.src_lin ? src : src * m.y);
@@ -1232,6 +1241,13 @@ __global__ void k_adj_init(const KParams<T>* __restrict__ ptab, const InstTab* _
         const T src = (role<uint8_t>(tb, B_P1)[i] ? s1 : (T)0) - (role<uint8_t>(tb, B_P2)[i] ? s2 : (T)0);
         l.y = l.y + src * role<T>(tb, B_M)[N + i];
     }
+    if (port == 3 && W > 0) {
+        // curve objective: sources of the last window state m_N (the psi term adds to the cleared dJ/dpsi)
+        const double g = role<double>(tb, B_PSRC)[2 * (size_t)(W - 1)];
+        const T pi = role<T>(tb, B_PSI)[i];
+        l.x = l.x + (T)g * pi;
+        role<double>(tb, B_GPSI)[i] += g * (double)role<T>(tb, B_M)[i];
+    }
     if (port == 2 && W > 0 && (p.n_p1 + p.n_p2) > 0) {
         // spectral objective: the stored source of the last window state m_N
         const double* g = role<double>(tb, B_PSRC) + 2 * (size_t)(W - 1);
@@ -1430,6 +1446,45 @@ __global__ __launch_bounds__(256) void k_spec_src(const KParams<T>* __restrict__
     out[1] = p.n_p2 > 0 ? g2 / ((double)W * p.n_p2) : 0.0;
 }
 
+// Curve objective (Eq. 8): per window step n, M(n) = sum over the row-pair
+// blocks of the stored psi m_x sums / N (block order) and the source
+// g_n = weight_n sign(M(n) - target_n) / N.  grid (ceil(W / 256), instances).
+template <typename T>
+__global__ __launch_bounds__(256) void k_curve_series(const KParams<T>* __restrict__ ptab,
+                                                      const InstTab* __restrict__ itab,
+                                                      const double* __restrict__ tw, int W) {
+    const int inst = blockIdx.y;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= W) return;
+    const KParams<T>& p = ptab[inst];
+    const InstTab& tb = itab[inst];
+    const double* part = role<double>(tb, B_PSER) + (size_t)n * 2 * p.nloc;
+    double s = 0.0;
+    for (int b = 0; b < p.nloc; ++b) s += part[2 * b];
+    const double M = s / p.N;
+    const double d = M - tw[n];
+    role<double>(tb, B_SER)[2 * (size_t)n] = M;
+    double* g = role<double>(tb, B_PSRC) + 2 * (size_t)n;
+    g[0] = tw[W + n] * (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) / p.N;
+    g[1] = 0.0;
+}
+
+// One block per instance: J = sum_n weight_n |M(n) - target_n|, fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_curve_finish(const KParams<T>* __restrict__ ptab,
+                                                      const InstTab* __restrict__ itab,
+                                                      const double* __restrict__ tw, int W) {
+    __shared__ double red[4];
+    const InstTab& tb = itab[blockIdx.x];
+    const double* M = role<double>(tb, B_SER);
+    double s = 0.0;
+    for (int n = threadIdx.x; n < W; n += 256) s += tw[W + n] * fabs(M[2 * n] - tw[n]);
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) role<double>(tb, B_SCAL)[0] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 // ---------------------------------------------------------------------------
 // energy + area objective (single instance): energy terms, dJ/dm and the
 // explicit dJ/dpsi, with per-block partial sums (ex, d, Z, an, psi)
@@ -1456,7 +1511,7 @@ __global__ void __launch_bounds__(512) k_energy(const BatchArgs<T> ba, double t,
         __syncthreads();
         fft_lds<C, true, MR>(Z, SigMap{0, Px, 0, 1}, Px, 3, role<C>(tb, B_TWX));
     }
-    const T drv = (T)drive_value(p.f1, p.f2, p.t_switch, t);
+    const T drv = (T)drive_value(p.f1, p.f2, p.t_switch, p.drive_kind, p.t_ramp, t);
     const int N = p.N, nx = p.nx;
     double e[5] = {0, 0, 0, 0, 0};
     for (int x = threadIdx.x; x < nx; x += blockDim.x) {
@@ -1743,6 +1798,12 @@ hipError_t launch_port_finish(const BatchDev<T>& b, int W, hipStream_t s) {
     return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_curve(const BatchDev<T>& b, const double* tw, int W, hipStream_t s) {
+    hipLaunchKernelGGL(k_curve_series<T>, dim3((W + 255) / 256, b.ninst), dim3(256), 0, s, b.ptab, b.itab, tw, W);
+    hipLaunchKernelGGL(k_curve_finish<T>, dim3(b.ninst), dim3(256), 0, s, b.ptab, b.itab, tw, W);
+    return hipGetLastError();
+}
+template <typename T>
 hipError_t launch_spectral(const BatchDev<T>& b, const double* fc, int K, int W, double t0, int64_t n_start, double dt,
                            hipStream_t s) {
     hipLaunchKernelGGL(k_spec_series<T>, dim3(W, b.ninst), dim3(64), 0, s, b.ptab, b.itab);
@@ -1823,6 +1884,7 @@ hipError_t set_lds_limits(size_t bytes) {
     template hipError_t launch_fill<T>(const BatchDev<T>&, int, int, double, hipStream_t);                         \
     template hipError_t launch_copy<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                        \
     template hipError_t launch_port_finish<T>(const BatchDev<T>&, int, hipStream_t);                                \
+    template hipError_t launch_curve<T>(const BatchDev<T>&, const double*, int, hipStream_t);                      \
     template hipError_t launch_spectral<T>(const BatchDev<T>&, const double*, int, int, double, int64_t, double,     \
                                            hipStream_t);                                                            \
     template hipError_t launch_energy<T>(const BatchDev<T>&, double, const T*, double, T*, double*, hipStream_t);   \

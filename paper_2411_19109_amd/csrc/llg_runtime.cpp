@@ -127,6 +127,9 @@ struct llg_handle {
     int spec_cap = 0;        // capacity in frequencies of spec_fc and of every instance's B_SPC
     int spec_k = 0;          // frequencies of the last upload
     std::vector<double> spec_host;
+    // curve objective: targets and weights of the window steps on the device
+    double* curve_tw = nullptr;
+    std::vector<double> curve_host;
     // forward record
     bool fwd_valid = false;
     double t0 = 0.0;
@@ -204,6 +207,8 @@ void fill_params(Instance& I) {
     p.f1 = q.f1;
     p.f2 = q.f2;
     p.t_switch = q.t_switch;
+    p.drive_kind = q.drive_kind;
+    p.t_ramp = q.t_ramp;
 }
 
 template <typename T>
@@ -539,9 +544,11 @@ int validate_problem(const llg_problem* p) {
     if (p->ckpt_policy != LLG_CKPT_SQRT && p->ckpt_policy != LLG_CKPT_ALL && p->ckpt_policy != LLG_CKPT_BINOMIAL)
         return fail(LLG_EINVAL, "unknown checkpoint policy");
     if (p->ckpt_param < 0) return fail(LLG_EINVAL, "ckpt_param must be >= 0");
-    const double* vals[] = {&p->A, &p->K, &p->f1, &p->f2, &p->t_switch};
+    const double* vals[] = {&p->A, &p->K, &p->f1, &p->f2, &p->t_switch, &p->t_ramp};
     for (auto v : vals)
         if (!std::isfinite(*v)) return fail(LLG_EINVAL, "non-finite parameter");
+    if (p->drive_kind != LLG_DRIVE_SINE && p->drive_kind != LLG_DRIVE_RAMP) return fail(LLG_EINVAL, "unknown drive kind");
+    if (p->drive_kind == LLG_DRIVE_RAMP && !(p->t_ramp > 0)) return fail(LLG_EINVAL, "t_ramp must be > 0");
     return LLG_OK;
 }
 
@@ -591,6 +598,7 @@ void record_forward(llg_handle* h, double t0, int64_t n, const llg_objective_spe
     h->K_used = segment_length(n, h->policy, h->ckpt_param);
     h->last_obj = obj ? *obj : llg_objective_spec{};
     h->last_obj.freqs = h->last_obj.coef = nullptr;  // the caller's arrays are not kept
+    h->last_obj.target = h->last_obj.weight = nullptr;
 }
 
 // Second stream and events of the overlapped adjoint (created outside any capture).
@@ -671,6 +679,7 @@ struct Ops {
     int Lc = B_L0, Lo = B_L1, Uc = B_U0, Uo = B_U1;
     bool adj_port = false;
     bool adj_spec = false;
+    bool adj_curve = false;
     int64_t adj_nstart = 0;
     int adj_W = 0;
     const BatchDev<T>& B() const { return bdev<T>(h); }
@@ -784,10 +793,12 @@ struct Ops {
 
     int forward(double t0, int64_t n, const llg_objective_spec* obj) {
         const bool spec = obj && obj->kind == LLG_OBJ_PORT_SPECTRAL;
-        const bool port = obj && (obj->kind == LLG_OBJ_PORT_MY2 || spec);
+        const bool curve = obj && obj->kind == LLG_OBJ_MAG_CURVE;
+        const bool port = obj && (obj->kind == LLG_OBJ_PORT_MY2 || spec || curve);
         const double dt = h->inst[0].prob.dt;
         // port mode of step k (which produces m_{k+1}) and its window index
-        auto in_win = [&](int64_t k) { return port && (k + 1) > obj->n_start ? (spec ? 2 : 1) : 0; };
+        const int mode = curve ? 3 : (spec ? 2 : 1);
+        auto in_win = [&](int64_t k) { return port && (k + 1) > obj->n_start ? mode : 0; };
         auto wstep = [&](int64_t k) { return port ? (int)(k - obj->n_start) : -1; };
         const int64_t K = segment_length(n, h->policy, h->ckpt_param);
         if (h->policy == LLG_CKPT_BINOMIAL) {
@@ -796,7 +807,7 @@ struct Ops {
         } else if ((n + K - 1) / K > h->nsnap || K > h->K) {
             return fail(LLG_ENOMEM, "checkpoint store too small for n_steps (raise max_steps at create)");
         }
-        if (port && !spec)
+        if (mode == 1 && port)
             if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_PPART, 1, s); })) return rc;
         if (int rc = prologue()) return rc;
         int64_t k = 0;
@@ -823,7 +834,10 @@ struct Ops {
         }
         if (port) {
             const int W = (int)(n - obj->n_start);
-            if (spec) {
+            if (curve) {
+                if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_curve<T>(B(), h->curve_tw, W, s); }))
+                    return rc;
+            } else if (spec) {
                 if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) {
                         return launch_spectral<T>(B(), h->spec_fc, obj->n_freq, W, t0, obj->n_start, dt, s);
                     }))
@@ -905,7 +919,7 @@ struct Ops {
                 L.lacc = Lo;
                 L.port_src = st == 0 && adj_port && k > adj_nstart;
                 L.W = adj_W;
-                L.port_lin = adj_spec;
+                L.port_lin = adj_curve ? 2 : (adj_spec ? 1 : 0);
                 L.pstep = (int)(k - adj_nstart - 1);
                 L.do_inv = h->demag;
                 L.do_fwd = h->demag && L.prev_j >= 0;
@@ -923,15 +937,17 @@ struct Ops {
         const int64_t n = h->n_steps, K = h->K_used;
         const double dt = h->inst[0].prob.dt;
         adj_spec = obj && obj->kind == LLG_OBJ_PORT_SPECTRAL;
-        adj_port = obj && (obj->kind == LLG_OBJ_PORT_MY2 || adj_spec);
+        adj_curve = obj && obj->kind == LLG_OBJ_MAG_CURVE;
+        adj_port = obj && (obj->kind == LLG_OBJ_PORT_MY2 || adj_spec || adj_curve);
         adj_nstart = adj_port ? obj->n_start : n;
         adj_W = (int)(n - adj_nstart);
         Lc = B_L0, Lo = B_L1, Uc = B_U0, Uo = B_U1;
+        // dJ/dpsi starts at zero (the curve objective's terminal term adds to it);
         // lambda_N = dJ/dm_N (+ port source at N); B_M holds m_N
-        const int port_mode = adj_port ? (adj_spec ? 2 : 1) : 0;
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_GPSI, 0, s); })) return rc;
+        const int port_mode = adj_port ? (adj_curve ? 3 : (adj_spec ? 2 : 1)) : 0;
         if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_adj_init<T>(B(), Lc, use_djdm, port_mode, adj_W, s); }))
             return rc;
-        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_GPSI, 0, s); })) return rc;
         if (h->policy == LLG_CKPT_BINOMIAL) {
             // the rest of the binomial schedule, on this stream
             int64_t cur = n;
@@ -1329,8 +1345,8 @@ int b_levelset_vjp(llg_handle* h, const void* const* phi, const double* const* g
 // Validation of an objective for a run of n_steps.
 int check_objective(const llg_objective_spec* obj, int64_t n_steps) {
     if (!obj) return LLG_OK;
-    if (obj->kind < LLG_OBJ_NONE || obj->kind > LLG_OBJ_PORT_SPECTRAL) return fail(LLG_EINVAL, "unknown objective");
-    const bool port = obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL;
+    if (obj->kind < LLG_OBJ_NONE || obj->kind > LLG_OBJ_MAG_CURVE) return fail(LLG_EINVAL, "unknown objective");
+    const bool port = obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL || obj->kind == LLG_OBJ_MAG_CURVE;
     if (port && (obj->n_start < 0 || obj->n_start >= n_steps)) return fail(LLG_EINVAL, "n_start must be in [0, n_steps)");
     if (obj->kind == LLG_OBJ_PORT_SPECTRAL) {
         if (obj->n_freq < 1 || obj->n_freq > 4096) return fail(LLG_EINVAL, "n_freq must be in [1, 4096]");
@@ -1340,15 +1356,20 @@ int check_objective(const llg_objective_spec* obj, int64_t n_steps) {
                 !std::isfinite(obj->coef[obj->n_freq + q]))
                 return fail(LLG_EINVAL, "freqs and coef must be finite");
     }
+    if (obj->kind == LLG_OBJ_MAG_CURVE) {
+        if (!obj->target || !obj->weight) return fail(LLG_EINVAL, "curve objective needs target and weight");
+        for (int64_t k = 0; k < n_steps - obj->n_start; ++k)
+            if (!std::isfinite(obj->target[k]) || !std::isfinite(obj->weight[k]))
+                return fail(LLG_EINVAL, "target and weight must be finite");
+    }
     return LLG_OK;
 }
 
 // Buffers of the spectral objective (allocated on first use, sized for
 // max_steps) and the upload of its frequencies and weights.  Runs before a
 // launch sequence (outside any graph capture); blocks the host.
-int ensure_spectral(llg_handle* h, const llg_objective_spec* obj) {
-    const int K = obj->n_freq;
-    bool tabs = false;
+// Per-step series buffers shared by the spectral and curve objectives.
+int ensure_series(llg_handle* h, bool* tabs) {
     int rc;
     const size_t steps = (size_t)h->max_steps;
     for (auto& I : h->inst) {
@@ -1356,9 +1377,51 @@ int ensure_spectral(llg_handle* h, const llg_objective_spec* obj) {
             if ((rc = alloc(h, &I.tab.b[B_PSER], steps * 2 * (size_t)I.nloc * 8))) return rc;
             if ((rc = alloc(h, &I.tab.b[B_SER], steps * 2 * 8))) return rc;
             if ((rc = alloc(h, &I.tab.b[B_PSRC], steps * 2 * 8))) return rc;
-            tabs = true;
+            *tabs = true;
         }
     }
+    return LLG_OK;
+}
+
+int upload_itab(llg_handle* h) {
+    std::vector<InstTab> host(h->inst.size());
+    for (size_t i = 0; i < h->inst.size(); ++i) host[i] = h->inst[i].tab;
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(h->itab, host.data(), sizeof(InstTab) * host.size(), hipMemcpyHostToDevice));
+    return LLG_OK;
+}
+
+// Curve objective: series buffers and the targets and weights of the window
+// steps on the device (before any launch sequence; blocks the host).
+int ensure_curve(llg_handle* h, const llg_objective_spec* obj, int64_t n_steps) {
+    bool tabs = false;
+    int rc;
+    if ((rc = ensure_series(h, &tabs))) return rc;
+    if (!h->curve_tw) {
+        void* p;
+        if ((rc = alloc(h, &p, (size_t)h->max_steps * 2 * 8))) return rc;
+        h->curve_tw = (double*)p;
+    }
+    if (tabs && (rc = upload_itab(h))) return rc;
+    const int64_t W = n_steps - obj->n_start;
+    std::vector<double> tw(2 * (size_t)W);
+    for (int64_t k = 0; k < W; ++k) {
+        tw[k] = obj->target[k];
+        tw[W + k] = obj->weight[k];
+    }
+    if (tw != h->curve_host) {
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(h->curve_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
+        h->curve_host = tw;
+    }
+    return LLG_OK;
+}
+
+int ensure_spectral(llg_handle* h, const llg_objective_spec* obj) {
+    const int K = obj->n_freq;
+    bool tabs = false;
+    int rc;
+    if ((rc = ensure_series(h, &tabs))) return rc;
     if (K > h->spec_cap) {
         const int cap = std::max(K, 64);
         void* p;
@@ -1370,12 +1433,7 @@ int ensure_spectral(llg_handle* h, const llg_objective_spec* obj) {
         h->spec_host.clear();
         tabs = true;
     }
-    if (tabs) {
-        std::vector<InstTab> host(h->inst.size());
-        for (size_t i = 0; i < h->inst.size(); ++i) host[i] = h->inst[i].tab;
-        HIPCHK(hipDeviceSynchronize());
-        HIPCHK(hipMemcpy(h->itab, host.data(), sizeof(InstTab) * host.size(), hipMemcpyHostToDevice));
-    }
+    if (tabs && (rc = upload_itab(h))) return rc;
     std::vector<double> fc(3 * (size_t)K);
     for (int q = 0; q < K; ++q) {
         fc[q] = obj->freqs[q];
@@ -1405,6 +1463,8 @@ int b_forward(llg_handle* h, const void* const* psi, const void* const* m0, doub
     if (int rc = check_objective(obj, n_steps)) return rc;
     if (obj && obj->kind == LLG_OBJ_PORT_SPECTRAL)
         if (int rc = ensure_spectral(h, obj)) return rc;
+    if (obj && obj->kind == LLG_OBJ_MAG_CURVE)
+        if (int rc = ensure_curve(h, obj, n_steps)) return rc;
     h->fwd_valid = false;
     for (int i = 0; i < n; ++i) {
         const size_t N = h->inst[i].N;
@@ -1426,7 +1486,8 @@ int b_forward(llg_handle* h, const void* const* psi, const void* const* m0, doub
     for (int i = 0; i < n; ++i) {
         if (m_out && m_out[i])
             if ((rc = get(h, i, B_M, m_out[i], 3 * (size_t)h->inst[i].N * h->tsz, s))) return rc;
-        if (J_dev && obj && (obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL))
+        if (J_dev && obj && (obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL ||
+                             obj->kind == LLG_OBJ_MAG_CURVE))
             if ((rc = get(h, i, B_SCAL, J_dev + i, sizeof(double), s))) return rc;
     }
     return LLG_OK;
@@ -1442,13 +1503,13 @@ int b_adjoint(llg_handle* h, const void* const* psi, const void* const* dJdm_T, 
         if (int rc = check_ptr(dJdpsi_out[i], "dJdpsi_out")) return rc;
     }
     if (!h->fwd_valid) return fail(LLG_ESTATE, "llg_adjoint needs a preceding llg_forward on this handle");
-    if (obj && (obj->kind < LLG_OBJ_NONE || obj->kind > LLG_OBJ_PORT_SPECTRAL)) return fail(LLG_EINVAL, "unknown objective");
-    if (obj && (obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL) &&
+    if (obj && (obj->kind < LLG_OBJ_NONE || obj->kind > LLG_OBJ_MAG_CURVE)) return fail(LLG_EINVAL, "unknown objective");
+    if (obj && (obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL || obj->kind == LLG_OBJ_MAG_CURVE) &&
         (obj->n_start < 0 || obj->n_start >= h->n_steps))
         return fail(LLG_EINVAL, "n_start must be in [0, n_steps)");
-    if (obj && obj->kind == LLG_OBJ_PORT_SPECTRAL &&
-        (h->last_obj.kind != LLG_OBJ_PORT_SPECTRAL || h->last_obj.n_start != obj->n_start))
-        return fail(LLG_ESTATE, "the spectral sources come from the last forward: run it with the same objective");
+    if (obj && (obj->kind == LLG_OBJ_PORT_SPECTRAL || obj->kind == LLG_OBJ_MAG_CURVE) &&
+        (h->last_obj.kind != obj->kind || h->last_obj.n_start != obj->n_start))
+        return fail(LLG_ESTATE, "the objective's sources come from the last forward: run it with the same objective");
     bool use_djdm = dJdm_T != nullptr, use_expl = expl != nullptr;
     for (int i = 0; i < n; ++i) {
         if (use_djdm && !dJdm_T[i]) use_djdm = false;
@@ -1674,10 +1735,11 @@ int llg_objective(llg_handle* h, const llg_objective_spec* obj, const void* psi,
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
     if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
     if ((rc = check_ptr(obj, "obj"))) return rc;
-    if (obj->kind != LLG_OBJ_ENERGY_AREA && obj->kind != LLG_OBJ_PORT_MY2 && obj->kind != LLG_OBJ_PORT_SPECTRAL)
-        return fail(LLG_EINVAL, "objective kind must be ENERGY_AREA, PORT_MY2 or PORT_SPECTRAL");
+    if (obj->kind != LLG_OBJ_ENERGY_AREA && obj->kind != LLG_OBJ_PORT_MY2 && obj->kind != LLG_OBJ_PORT_SPECTRAL &&
+        obj->kind != LLG_OBJ_MAG_CURVE)
+        return fail(LLG_EINVAL, "objective kind must be ENERGY_AREA, PORT_MY2, PORT_SPECTRAL or MAG_CURVE");
     const size_t N = h->inst[0].N;
-    if (obj->kind == LLG_OBJ_PORT_MY2 || obj->kind == LLG_OBJ_PORT_SPECTRAL) {
+    if (obj->kind != LLG_OBJ_ENERGY_AREA) {
         if (!h->fwd_valid) return fail(LLG_ESTATE, "port objective needs a preceding llg_forward");
         if (J_dev && (rc = get(h, 0, B_SCAL, J_dev, sizeof(double), stream))) return rc;
         if (dJdm_out) HIPCHK(hipMemsetAsync(dJdm_out, 0, 3 * N * h->tsz, stream));

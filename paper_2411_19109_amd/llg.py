@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libllg.so")
 LLG_OK, LLG_EINVAL, LLG_ESHAPE, LLG_ENOMEM, LLG_EHIP, LLG_ENONFINITE, LLG_ENOTSUP, LLG_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 LLG_F32, LLG_F64 = 0, 1
 LLG_CKPT_SQRT, LLG_CKPT_ALL, LLG_CKPT_BINOMIAL = 0, 1, 2
-LLG_OBJ_NONE, LLG_OBJ_ENERGY_AREA, LLG_OBJ_PORT_MY2, LLG_OBJ_PORT_SPECTRAL = 0, 1, 2, 3
+LLG_OBJ_NONE, LLG_OBJ_ENERGY_AREA, LLG_OBJ_PORT_MY2, LLG_OBJ_PORT_SPECTRAL, LLG_OBJ_MAG_CURVE = 0, 1, 2, 3, 4
+LLG_DRIVE_SINE, LLG_DRIVE_RAMP = 0, 1
 
 EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_levelset_to_Ms",
            "llg_levelset_to_Ms_vjp", "llg_field", "llg_forward", "llg_objective", "llg_adjoint",
@@ -49,7 +50,8 @@ class Problem_c(ctypes.Structure):
                 ("B0", ctypes.c_double * 3), ("b_rf", ctypes.c_double * 3),
                 ("f1", ctypes.c_double), ("f2", ctypes.c_double), ("t_switch", ctypes.c_double),
                 ("terms", ctypes.c_int32), ("dtype", ctypes.c_int32), ("dt", ctypes.c_double),
-                ("max_steps", ctypes.c_int64), ("ckpt_policy", ctypes.c_int32), ("ckpt_param", ctypes.c_int32)]
+                ("max_steps", ctypes.c_int64), ("ckpt_policy", ctypes.c_int32), ("ckpt_param", ctypes.c_int32),
+                ("drive_kind", ctypes.c_int32), ("t_ramp", ctypes.c_double)]
 
 
 class Masks_c(ctypes.Structure):
@@ -60,7 +62,8 @@ class Masks_c(ctypes.Structure):
 class Objective_c(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("E_ref", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("area", ctypes.c_double), ("n_start", ctypes.c_int64), ("n_freq", ctypes.c_int32),
-                ("freqs", ctypes.POINTER(ctypes.c_double)), ("coef", ctypes.POINTER(ctypes.c_double))]
+                ("freqs", ctypes.POINTER(ctypes.c_double)), ("coef", ctypes.POINTER(ctypes.c_double)),
+                ("target", ctypes.POINTER(ctypes.c_double)), ("weight", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -145,15 +148,29 @@ def make_problem(prob, dtype="f32", max_steps=1, ckpt_policy=LLG_CKPT_SQRT, ckpt
     c.max_steps = max_steps
     c.ckpt_policy = ckpt_policy
     c.ckpt_param = ckpt_param
+    c.drive_kind = getattr(prob, "drive_kind", LLG_DRIVE_SINE)
+    c.t_ramp = getattr(prob, "t_ramp", 0.0)
     return c
 
 
-def make_objective(kind=LLG_OBJ_NONE, E_ref=1.0, lam=1.0, area=0.4, n_start=0, freqs=None, coef=None) -> Objective_c:
+def make_objective(kind=LLG_OBJ_NONE, E_ref=1.0, lam=1.0, area=0.4, n_start=0, freqs=None, coef=None, target=None,
+                   weight=None) -> Objective_c:
     """Objective_c; for LLG_OBJ_PORT_SPECTRAL, freqs (K sample frequencies, Hz)
-    and coef (2 x K weights of |X_1(f_q)| and |X_2(f_q)|).  The object keeps its
-    arrays alive."""
+    and coef (2 x K weights of |X_1(f_q)| and |X_2(f_q)|); for LLG_OBJ_MAG_CURVE,
+    target and weight (one value per window step).  The object keeps its arrays
+    alive."""
     o = Objective_c()
     o.kind, o.E_ref, o.lambda_, o.area, o.n_start = kind, E_ref, lam, area, n_start
+    keep = []
+    if target is not None:
+        tg = np.ascontiguousarray(np.asarray(target, np.float64).reshape(-1))
+        wt = np.ascontiguousarray(np.asarray(weight, np.float64).reshape(-1))
+        if wt.size != tg.size:
+            raise ValueError("target and weight must have one value per window step")
+        keep += [tg, wt]
+        o.target = tg.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o.weight = wt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    o._keep_curve = keep
     if freqs is not None:
         f = np.ascontiguousarray(np.asarray(freqs, np.float64).reshape(-1))
         c = np.ascontiguousarray(np.asarray(coef, np.float64).reshape(-1))
@@ -164,6 +181,15 @@ def make_objective(kind=LLG_OBJ_NONE, E_ref=1.0, lam=1.0, area=0.4, n_start=0, f
         o.freqs = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         o.coef = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return o
+
+
+def _check_obj(obj, n_steps):
+    """The curve objective's host arrays are read for n_steps - n_start window
+    steps: refuse shorter ones before the library reads them."""
+    if obj is not None and obj.kind == LLG_OBJ_MAG_CURVE:
+        keep = getattr(obj, "_keep_curve", [])
+        if not keep or keep[0].size != n_steps - obj.n_start:
+            raise ValueError("curve objective: target and weight need n_steps - n_start values")
 
 
 def query_memory(prob, n_steps, policy=LLG_CKPT_SQRT, ckpt_param=0, dtype="f32") -> int:
@@ -303,6 +329,7 @@ class Solver:
         import torch
         self._t(psi, self.N)
         self._t(m0, 3 * self.N)
+        _check_obj(obj, n_steps)
         m_out = torch.empty_like(m0) if m_out is None else m_out
         J = torch.zeros(1, dtype=torch.float64, device=m0.device)
         self._fwd_gen += 1
@@ -429,6 +456,7 @@ class Batch:
     def forward(self, psis, m0s, n_steps, t0=0.0, obj: Optional[Objective_c] = None, want_m=True):
         import torch
         dev = psis[0].device
+        _check_obj(obj, n_steps)
         m_out = [torch.empty(3 * n, dtype=self.tdtype, device=dev) for n in self.N] if want_m else None
         J = torch.zeros(self.n, dtype=torch.float64, device=dev)
         self._fwd_gen += 1

@@ -334,6 +334,39 @@ def yig_demux_two_tone(seed: int = 2, n_steps: int = 20000, f1: float = 2.5e9, f
     return w
 
 
+def sw_particle_curve(seed: int = 6, n_steps: int = 2000, nx: int = 30, ny: int = 30) -> Workload:
+    """The magnetisation-curve task (Eq. 8): 30x30x1 nodes of 3 nm, permalloy
+    (Ms = 800 kA/m, A = 13 pJ/m), alpha = 0.5, the applied field ramped linearly
+    along x from 0 to 0.3 Ms over the run; phi is seeded smooth noise (max |phi| = 1),
+    and extra["rbf"] the 20x20 RBF array over the mesh with 3x3 holes for the
+    design loop.  Target M_x: a seeded smooth
+    monotone curve from 0.1 to 0.6 (synthetic; the paper's target is shown only
+    as a figure); weights 1 / (target |W|), window = the whole run."""
+    rng = np.random.default_rng(seed)
+    dt = 1e-13
+    mu0 = 4e-7 * math.pi
+    p = Problem(nx=nx, ny=ny, nz=1, dx=3e-9, dy=3e-9, dz=3e-9, Ms=8e5, A=1.3e-11, alpha0=0.5, alpha_max=0.5,
+                b_rf=(0.3 * mu0 * 8e5, 0.0, 0.0), drive_kind=1, t_ramp=n_steps * dt,
+                terms=TERM_EXCH | TERM_DEMAG | TERM_ZEEMAN, dt=dt)
+    sh = p.shape
+    lay = rbf_layout((0, 0, min(nx, ny)), n_side=20, holes=3, seed=seed)
+    m0 = np.zeros((3,) + sh)
+    m0[1] = 1.0
+    m0 += rng.normal(0.0, 1e-3, m0.shape)
+    m0 = _normalise(m0)
+    u = np.arange(1, n_steps + 1) / n_steps
+    bend = rng.uniform(0.5, 1.5)
+    target = 0.1 + 0.5 * u ** bend
+    ones8 = np.ones(sh, np.uint8)
+    zeros8 = np.zeros(sh, np.uint8)
+    phi = random_design_phi(rng, ny, nx, (0, 0, min(nx, ny)))
+    w = Workload(name=f"sw_particle_{nx}x{ny}_curve_grad", problem=p, n_steps=n_steps, dtype="f32",
+                 heaviside_a=50.0, phi=phi, extrude_z=True, design=ones8, psi_fixed=np.zeros(sh),
+                 antenna=ones8, port1=zeros8, port2=zeros8, m0=m0, objective=OBJ_MAG_CURVE, obj_n_start=0,
+                 extra=dict(rbf=lay, target=target, weight=1.0 / (target * n_steps)))
+    return w
+
+
 def yig_demux_sweep(seed: int = 3, n_designs: int = 32, freqs=(2.5e9, 3.5e9), n_steps: int = 10000) -> List[Workload]:
     """Batched sweep: n_designs independently seeded phi, each on its own grid
     with nx ~ U{128..256}, ny ~ U{64..128}, times the listed drive

@@ -6,7 +6,7 @@ checkpointed discrete adjoint back to t0, and the chain rule to dJ/dphi.
 Inputs are resident in device memory before the timed region starts.
 
   python bench.py [--steps K] [--warmup W]
-                  [--workload particle|waveguide|demux|demux_spectral|device3d|sweep|probe|rbf]
+                  [--workload particle|particle_curve|waveguide|demux|demux_spectral|device3d|sweep|probe|rbf]
 
 Prints ONE JSON line.  The metric is LLG cell-steps per second of the forward
 + adjoint run: nodes * RK4 steps / wall time of one gradient evaluation.
@@ -41,6 +41,8 @@ def make_workload(name):
         return wl.yig_demux()
     if name == "demux_spectral":
         return wl.yig_demux_two_tone()
+    if name == "particle_curve":
+        return wl.sw_particle_curve()
     if name == "device3d":
         return wl.yig_device_3d()
     raise SystemExit(f"unknown workload {name}")
@@ -77,7 +79,8 @@ class GradientStep:
         self.psi_fixed = torch.as_tensor(w.psi_fixed.reshape(-1), dtype=self.td, device=dev).contiguous()
         self.m0 = torch.as_tensor(w.m0.reshape(-1), dtype=self.td, device=dev).contiguous()
         self.obj = llg.make_objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area,
-                                      n_start=w.obj_n_start, freqs=w.extra.get("freqs"), coef=w.extra.get("coef"))
+                                      n_start=w.obj_n_start, freqs=w.extra.get("freqs"), coef=w.extra.get("coef"),
+                                      target=w.extra.get("target"), weight=w.extra.get("weight"))
         self.energy = w.objective == wl.OBJ_ENERGY_AREA
 
     def __call__(self):
@@ -157,15 +160,19 @@ def cpu_baseline(w, budget_s=15.0):
     from paper_2411_19109_amd import workloads as wl
     sim = omm.Sim(w.problem, antenna=w.antenna)
     psi = ols.levelset_to_psi(w.phi, w.heaviside_a, w.design, w.psi_fixed)
-    obj = oadj.Objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area,
-                         n_start=0, port1=w.port1, port2=w.port2, freqs=w.extra.get("freqs"), coef=w.extra.get("coef"))
+    def obj(n):
+        tg, wt = w.extra.get("target"), w.extra.get("weight")
+        return oadj.Objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area,
+                              n_start=0, port1=w.port1, port2=w.port2, freqs=w.extra.get("freqs"),
+                              coef=w.extra.get("coef"), target=None if tg is None else tg[:n],
+                              weight=None if wt is None else wt[:n])
     n = 10
     t0 = time.perf_counter()
-    oadj.gradient(sim, w.m0, psi, n, obj)
+    oadj.gradient(sim, w.m0, psi, n, obj(n))
     dt = time.perf_counter() - t0
     n = max(10, min(w.n_steps, int(n * budget_s / max(dt, 1e-3))))
     t0 = time.perf_counter()
-    oadj.gradient(sim, w.m0, psi, n, obj)
+    oadj.gradient(sim, w.m0, psi, n, obj(n))
     dt = time.perf_counter() - t0
     return dict(value=w.problem.n * n / dt, unit="cell-steps/s", cores=1, kind="oracle",
                 sample=f"float64 NumPy oracle, forward+adjoint of the first {n} of {w.n_steps} RK4 steps "
@@ -217,7 +224,10 @@ def main():
     if args.workload == "rbf":
         return run_rbf(args)
     w = make_workload(args.workload)
-    if args.n_steps > 0:
+    if args.n_steps > 0 and args.workload == "particle_curve":
+        from paper_2411_19109_amd import workloads as wl
+        w = wl.sw_particle_curve(n_steps=args.n_steps)  # the ramp and the target follow the run length
+    elif args.n_steps > 0:
         w.n_steps = args.n_steps
         w.obj_n_start = min(w.obj_n_start, args.n_steps // 2)
     step = GradientStep(w, bool(args.graphs), bool(args.autotune), args.launch_file)

@@ -14,8 +14,10 @@ Modules
   newell     cell-averaged demagnetisation tensor (Newell closed form near,
              Gauss-Legendre quadrature of the tent-weighted dipole kernel far)
   micromag   effective field, LLG right-hand side, RK4, energies
-  adjoint    discrete adjoint of the RK4 map, objectives and gradients
+  adjoint    discrete adjoint of the RK4 map, objectives (energy + area, port
+             m_y^2, spectral port, magnetisation curve) and gradients
   levelset   smoothed Heaviside map phi -> psi and its derivative
   rbf        RBF cones and their p-norm level set (amplitudes -> phi), its
              vector-Jacobian product, and the Adam update of the amplitudes
+  shape      size and centre-of-mass constraints of the regularised objective
 """

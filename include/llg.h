@@ -214,6 +214,19 @@ int llg_objective(llg_handle* h, const llg_objective_spec* obj, const void* psi,
 int llg_adjoint(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl,
                 const llg_objective_spec* obj, double* dJdpsi_out, void* dJdm0_out, hipStream_t stream);
 
+/* Size and centre-of-mass constraints of the regularised objective (Eq. 9):
+ *   J = xi (S - S_target)^2 + nu (|x_c - x0| + |y_c - y0|),
+ * S = sum_i psi_i / nz (in-plane area in cells), x_c = sum_i psi_i x_i / sum_i psi_i,
+ * y_c likewise (node indices).  psi: device, N entries in the handle's precision.
+ * Writes J to *J_dev (device double) and, if dJdpsi_out (device, N doubles) is
+ * not NULL, dJ/dpsi there, ready to pass as dJdpsi_expl to llg_adjoint (the
+ * constraints depend on psi only).  |.| takes the zero subgradient at 0; with no
+ * material the centre term is 0.  Single-instance handles; uses a small scratch
+ * buffer of the handle (allocated on first use), so calls on one handle and
+ * stream are ordered.  Errors: LLG_EINVAL, LLG_ENOMEM, LLG_EHIP. */
+int llg_shape_penalty(llg_handle* h, const void* psi, double xi, double S_target, double nu, double x0, double y0,
+                      double* J_dev, double* dJdpsi_out, hipStream_t stream);
+
 /* Device bytes the checkpoint store needs for n_steps under a policy
  * (snapshots + recomputed stage states), without allocating anything. */
 int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int32_t ckpt_param, size_t* bytes);

@@ -233,6 +233,11 @@ template <typename T> hipError_t launch_port_finish(const BatchDev<T>& b, int W,
 // holds f_q (K), then the weights of |X_1| (K) and of |X_2| (K), on the device.
 // Curve objective after a forward run: M_x series and per-step sources, then J.
 // tw holds the W targets, then the W weights, on the device.
+// Size and centre constraints (Eq. 9) of psi (nx*ny*nz): J to J[0], dJ/dpsi to g
+// (nullable); work holds 8 + 3 * ceil(N / 256) doubles.
+template <typename T>
+hipError_t launch_shape(const T* psi, int nx, int ny, int nz, double xi, double S_target, double nu, double x0,
+                        double y0, double* work, double* J, double* g, hipStream_t s);
 template <typename T> hipError_t launch_curve(const BatchDev<T>& b, const double* tw, int W, hipStream_t s);
 template <typename T>
 hipError_t launch_spectral(const BatchDev<T>& b, const double* fc, int K, int W, double t0, int64_t n_start, double dt,

@@ -1485,6 +1485,72 @@ __global__ __launch_bounds__(256) void k_curve_finish(const KParams<T>* __restri
     if (threadIdx.x == 0) role<double>(tb, B_SCAL)[0] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// Size and centre-of-mass constraints of the regularised objective (Eq. 9):
+// block sums of psi, psi x and psi y (fixed order), then J and the gradient
+// dJ/dpsi_i = c0 + c1 (x_i - x_c) + c2 (y_i - y_c).
+template <typename T>
+__global__ __launch_bounds__(256) void k_shape_sums(const T* __restrict__ psi, int nx, int ny, int N,
+                                                    double* __restrict__ part) {
+    __shared__ double red[3][4];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double a = 0.0, bx = 0.0, by = 0.0;
+    if (i < N) {
+        const double v = (double)psi[i];
+        a = v;
+        bx = v * (double)(i % nx);
+        by = v * (double)((i / nx) % ny);
+    }
+    a = wave_sum(a);
+    bx = wave_sum(bx);
+    by = wave_sum(by);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = a;
+        red[1][threadIdx.x >> 6] = bx;
+        red[2][threadIdx.x >> 6] = by;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        part[3 * (size_t)blockIdx.x + k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_shape_finish(const double* __restrict__ part, int nb, int nz, double xi,
+                                                      double S_target, double nu, double x0, double y0,
+                                                      double* __restrict__ J, double* __restrict__ coef) {
+    __shared__ double red[3][4];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += 256)
+        for (int k = 0; k < 3; ++k) s[k] += part[3 * (size_t)b + k];
+    for (int k = 0; k < 3; ++k) {
+        const double v = wave_sum(s[k]);
+        if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double tot = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    const double sx = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    const double sy = ((red[2][0] + red[2][1]) + red[2][2]) + red[2][3];
+    const double S = tot / nz;
+    // no material: no centre (the centre constraint and its gradient vanish)
+    const double xc = tot > 0.0 ? sx / tot : x0, yc = tot > 0.0 ? sy / tot : y0;
+    const double dxc = xc - x0, dyc = yc - y0;
+    J[0] = xi * (S - S_target) * (S - S_target) + nu * (fabs(dxc) + fabs(dyc));
+    coef[0] = 2.0 * xi * (S - S_target) / nz;
+    coef[1] = tot > 0.0 ? nu * (dxc > 0.0 ? 1.0 : (dxc < 0.0 ? -1.0 : 0.0)) / tot : 0.0;
+    coef[2] = tot > 0.0 ? nu * (dyc > 0.0 ? 1.0 : (dyc < 0.0 ? -1.0 : 0.0)) / tot : 0.0;
+    coef[3] = xc;
+    coef[4] = yc;
+}
+
+__global__ __launch_bounds__(256) void k_shape_grad(int nx, int ny, int N, const double* __restrict__ coef,
+                                                    double* __restrict__ g) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const double x = (double)(i % nx), y = (double)((i / nx) % ny);
+    g[i] = coef[0] + coef[1] * (x - coef[3]) + coef[2] * (y - coef[4]);
+}
+
 // ---------------------------------------------------------------------------
 // energy + area objective (single instance): energy terms, dJ/dm and the
 // explicit dJ/dpsi, with per-block partial sums (ex, d, Z, an, psi)
@@ -1798,6 +1864,15 @@ hipError_t launch_port_finish(const BatchDev<T>& b, int W, hipStream_t s) {
     return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_shape(const T* psi, int nx, int ny, int nz, double xi, double S_target, double nu, double x0,
+                        double y0, double* work, double* J, double* g, hipStream_t s) {
+    const int N = nx * ny * nz, nb = (N + 255) / 256;
+    hipLaunchKernelGGL(k_shape_sums<T>, dim3(nb), dim3(256), 0, s, psi, nx, ny, N, work + 8);
+    hipLaunchKernelGGL(k_shape_finish, dim3(1), dim3(256), 0, s, work + 8, nb, nz, xi, S_target, nu, x0, y0, J, work);
+    if (g) hipLaunchKernelGGL(k_shape_grad, dim3(nb), dim3(256), 0, s, nx, ny, N, work, g);
+    return hipGetLastError();
+}
+template <typename T>
 hipError_t launch_curve(const BatchDev<T>& b, const double* tw, int W, hipStream_t s) {
     hipLaunchKernelGGL(k_curve_series<T>, dim3((W + 255) / 256, b.ninst), dim3(256), 0, s, b.ptab, b.itab, tw, W);
     hipLaunchKernelGGL(k_curve_finish<T>, dim3(b.ninst), dim3(256), 0, s, b.ptab, b.itab, tw, W);
@@ -1885,6 +1960,8 @@ hipError_t set_lds_limits(size_t bytes) {
     template hipError_t launch_copy<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                        \
     template hipError_t launch_port_finish<T>(const BatchDev<T>&, int, hipStream_t);                                \
     template hipError_t launch_curve<T>(const BatchDev<T>&, const double*, int, hipStream_t);                      \
+    template hipError_t launch_shape<T>(const T*, int, int, int, double, double, double, double, double, double*,  \
+                                        double*, double*, hipStream_t);                                             \
     template hipError_t launch_spectral<T>(const BatchDev<T>&, const double*, int, int, double, int64_t, double,     \
                                            hipStream_t);                                                            \
     template hipError_t launch_energy<T>(const BatchDev<T>&, double, const T*, double, T*, double*, hipStream_t);   \

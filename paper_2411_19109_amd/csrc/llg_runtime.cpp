@@ -129,6 +129,7 @@ struct llg_handle {
     std::vector<double> spec_host;
     // curve objective: targets and weights of the window steps on the device
     double* curve_tw = nullptr;
+    double* shape_work = nullptr;  // size / centre constraints: coefficients and block sums
     std::vector<double> curve_host;
     // forward record
     bool fwd_valid = false;
@@ -1781,6 +1782,31 @@ int llg_batch_adjoint(llg_batch* b, const void* const* psi, const void* const* d
                       const llg_objective_spec* obj, double* const* dJdpsi_out, void* const* dJdm0_out,
                       hipStream_t stream) {
     return b_adjoint(b, psi, dJdm_T, dJdpsi_expl, obj, dJdpsi_out, dJdm0_out, stream);
+}
+
+int llg_shape_penalty(llg_handle* h, const void* psi, double xi, double S_target, double nu, double x0, double y0,
+                      double* J_dev, double* dJdpsi_out, hipStream_t stream) {
+    int rc;
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
+    if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(J_dev, "J_dev"))) return rc;
+    const double vals[] = {xi, S_target, nu, x0, y0};
+    for (double v : vals)
+        if (!std::isfinite(v)) return fail(LLG_EINVAL, "constraint parameters must be finite");
+    const llg_problem& q = h->inst[0].prob;
+    const size_t N = h->inst[0].N;
+    if (!h->shape_work) {
+        void* p;
+        if ((rc = alloc(h, &p, (8 + 3 * ((N + 255) / 256)) * sizeof(double)))) return rc;
+        h->shape_work = (double*)p;
+    }
+    hipError_t e = h->dtype == LLG_F32
+                       ? launch_shape<float>((const float*)psi, q.nx, q.ny, q.nz, xi, S_target, nu, x0, y0,
+                                             h->shape_work, J_dev, dJdpsi_out, stream)
+                       : launch_shape<double>((const double*)psi, q.nx, q.ny, q.nz, xi, S_target, nu, x0, y0,
+                                              h->shape_work, J_dev, dJdpsi_out, stream);
+    if (e != hipSuccess) return fail(LLG_EHIP, std::string("shape constraint launch: ") + hipGetErrorString(e));
+    return LLG_OK;
 }
 
 }  // extern "C"

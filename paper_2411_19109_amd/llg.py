@@ -28,7 +28,7 @@ EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_le
            "llg_set_launch_config", "llg_autotune", "llg_fft_sizes", "llg_profile", "llg_profile_read", "llg_batch_create",
            "llg_batch_destroy", "llg_batch_size", "llg_batch_levelset_to_Ms", "llg_batch_levelset_to_Ms_vjp",
            "llg_batch_forward", "llg_batch_adjoint", "llg_rbf_work_len", "llg_rbf_levelset", "llg_rbf_levelset_vjp",
-           "llg_adam_step", "llg_rbf_profile", "llg_rbf_profile_read"]
+           "llg_adam_step", "llg_rbf_profile", "llg_rbf_profile_read", "llg_shape_penalty"]
 RBF_KIND_NAMES = {0: "k_rbf_cones", 1: "k_rbf_pnorm", 2: "k_rbf_vjp"}
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
 KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col_conv", KIND_STAGE_BWD: "k_stage_bwd"}
@@ -114,6 +114,7 @@ def lib():
         "llg_rbf_levelset_vjp": [i32, i32, i32, i32, vp, vp, dbl, dbl, vp, vp, vp, vp, vp, vp],
         "llg_adam_step": [i32, vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, vp],
         "llg_rbf_profile": [ctypes.c_int],
+        "llg_shape_penalty": [vp, vp, dbl, dbl, dbl, dbl, dbl, vp, vp, vp],
         "llg_rbf_profile_read": [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
     }
     for name, args in sig.items():
@@ -315,6 +316,17 @@ class Solver:
         out = torch.empty(phi.numel(), dtype=torch.float64, device=phi.device)
         check(lib().llg_levelset_to_Ms_vjp(self.h, _ptr(phi), _ptr(dJdpsi), float(a), int(extrude_z), _ptr(out), _stream()))
         return out
+
+    def shape_penalty(self, psi, xi, S_target, nu, x0, y0, want_grad=True):
+        """(J, dJ/dpsi) of the size and centre constraints of Eq. 9 (device
+        tensors; the gradient goes to adjoint(..., dJdpsi_expl=...))."""
+        import torch
+        self._t(psi, self.N)
+        J = torch.zeros(1, dtype=torch.float64, device=psi.device)
+        g = torch.empty(self.N, dtype=torch.float64, device=psi.device) if want_grad else None
+        check(lib().llg_shape_penalty(self.h, _ptr(psi), float(xi), float(S_target), float(nu), float(x0), float(y0),
+                                      _ptr(J), _ptr(g), _stream()))
+        return J, g
 
     def field(self, psi, m, t=0.0, want_rhs=False):
         import torch

@@ -168,3 +168,8 @@ def test_rbf_work_len_and_host_side_rejections():
     assert L.llg_adam_step(4, fake, fake, fake, fake, 0, 1e-2, 0.9, 0.999, 1e-8, None) == llg.LLG_EINVAL
     assert L.llg_adam_step(4, fake, fake, fake, fake, 1, 1e-2, 1.0, 0.999, 1e-8, None) == llg.LLG_EINVAL
     assert L.llg_adam_step(4, None, fake, fake, fake, 1, 1e-2, 0.9, 0.999, 1e-8, None) == llg.LLG_EINVAL
+
+
+def test_shape_penalty_rejects_null_handle():
+    L = llg.lib()
+    assert L.llg_shape_penalty(None, None, 0.05, 30.0, 1.0, 0.0, 0.0, None, None, None) == llg.LLG_EINVAL

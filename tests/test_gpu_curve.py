@@ -156,3 +156,59 @@ def test_particle_curve_design_loop_matches_oracle(dtype):
         assert rel_l2(g_now, dso) <= (1e-8 if dtype == "f64" else 1e-3)
         opt.step(s.data, s.grad)
     solver.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nz", [1, 2])
+def test_shape_constraints_match_oracle(dtype, nz):
+    import torch
+    from oracle import shape as oshape
+    from paper_2411_19109_amd import llg
+    p = wl.Problem(nx=37, ny=29, nz=nz, dx=3e-9, dy=3e-9, dz=3e-9, Ms=8e5, A=1.3e-11, terms=wl.TERM_EXCH)
+    rng = np.random.default_rng(40 + nz)
+    psi = rng.uniform(0.0, 1.0, p.shape) ** 3
+    s = llg.Solver(p, dtype=dtype, max_steps=1)
+    args = (0.05, 120.0, 1.0, 17.0, 11.5)
+    J, g = s.shape_penalty(to_dev(psi, dtype), *args)
+    torch.cuda.synchronize()
+    psi_used = to_np(to_dev(psi, dtype)).reshape(p.shape)   # the values the GPU saw
+    Jo = oshape.penalty(psi_used, *args)
+    go = oshape.penalty_grad(psi_used, *args).reshape(-1)
+    say("shape constraints", dtype, nz, "J", float(J.item()), Jo)
+    assert abs(float(J.item()) - Jo) <= 1e-12 * abs(Jo)
+    assert rel_l2(to_np(g), go) <= 1e-12
+    s.close()
+
+
+def test_regularised_objective_gradient_matches_oracle():
+    """Eq. 9: zeta x the curve term + the size and centre constraints, the
+    constraint gradient passed to the adjoint as its explicit dJ/dpsi."""
+    import torch
+    from oracle import shape as oshape
+    from paper_2411_19109_amd import llg
+    n, zeta = 24, 10.0
+    w = curve_case(n, seed=35)
+    psi_o = ols.levelset_to_psi(w.phi, w.heaviside_a, w.design, w.psi_fixed)
+    # targets near the map's own area and centre, so that no term swamps the others
+    args = (0.05, psi_o.sum() - 2.0, 1.0, 11.0, 9.0)
+    tgt, wt = w.extra["target"], zeta * w.extra["weight"]
+    obj = llg.make_objective(wl.OBJ_MAG_CURVE, n_start=w.obj_n_start, target=tgt, weight=wt)
+    s = llg.Solver(w.problem, dtype="f64", max_steps=n, antenna=w.antenna, design=w.design)
+    phi = to_dev(w.phi, "f64")
+    psi = s.levelset_to_psi(phi, w.heaviside_a, to_dev(w.psi_fixed, "f64"))
+    _, Jc = s.forward(psi, to_dev(w.m0, "f64"), n, obj=obj)
+    Js, gs = s.shape_penalty(psi, *args)
+    dpsi = s.adjoint(psi, obj, dJdpsi_expl=gs)
+    dphi = s.levelset_vjp(phi, dpsi, w.heaviside_a)
+    torch.cuda.synchronize()
+    J = float(Jc.item()) + float(Js.item())
+    sim = omm.Sim(w.problem, antenna=w.antenna)
+    o = oadj.Objective(oadj.OBJ_MAG_CURVE, n_start=w.obj_n_start, target=tgt, weight=wt)
+    Jo, gpsi, _ = oadj.gradient(sim, w.m0, psi_o, n, o)
+    Jo += oshape.penalty(psi_o, *args)
+    gpsi = gpsi + oshape.penalty_grad(psi_o, *args)
+    go = ols.levelset_vjp(w.phi, w.heaviside_a, w.design, gpsi).reshape(-1)
+    say("Eq. 9 J", J, Jo, "(curve", float(Jc.item()), ") dJ/dphi rel L2", rel_l2(to_np(dphi), go))
+    assert abs(J - Jo) <= 1e-10 * abs(Jo)
+    assert rel_l2(to_np(dphi), go) <= 1e-9
+    s.close()

@@ -20,4 +20,6 @@ Modules
   rbf        RBF cones and their p-norm level set (amplitudes -> phi), its
              vector-Jacobian product, and the Adam update of the amplitudes
   shape      size and centre-of-mass constraints of the regularised objective
+  dopri      adaptive Dormand-Prince 5(4) integration and the adjoint of its
+             accepted steps
 """

@@ -227,6 +227,37 @@ int llg_adjoint(llg_handle* h, const void* psi, const void* dJdm_T, const double
 int llg_shape_penalty(llg_handle* h, const void* psi, double xi, double S_target, double nu, double x0, double y0,
                       double* J_dev, double* dJdpsi_out, hipStream_t stream);
 
+/* ---- adaptive integration --------------------------------------------
+ * The Methods integrate adaptively: embedded Dormand-Prince 5(4) steps (fifth
+ * order carried, fourth order for the estimate) from m0 at t0 to exactly t_end,
+ * first trial step h0.  A trial is accepted when max over all nodes and
+ * components of |y5 - y4| / (atol + rtol max(|y_n|, |y5|)) <= 1; the next step
+ * is h min(5, max(0.2, 0.9 err^(-1/5))), without growth right after a
+ * rejection.  Every accepted state is kept (at most max_steps accepted steps,
+ * else LLG_ENOMEM), so that llg_adjoint_adaptive can transpose the accepted
+ * steps with their sizes held fixed.  The controller reads each error norm on
+ * the host (the call blocks per trial step).  Single-instance handles; the
+ * stage store must hold 6 stage states (checkpoint K x halves >= 6, true for
+ * max_steps >= 36).  m_out (nullable, 3N) receives m(t_end); n_accepted /
+ * n_rejected (nullable, host) the step counts.
+ * Errors: LLG_EINVAL, LLG_ENOMEM, LLG_ENOTSUP, LLG_ENONFINITE, LLG_EHIP. */
+int llg_forward_adaptive(llg_handle* h, const void* psi, const void* m0, double t0, double t_end, double h0,
+                         double rtol, double atol, void* m_out, int64_t* n_accepted, int64_t* n_rejected,
+                         hipStream_t stream);
+
+/* Accepted step sizes of the last llg_forward_adaptive (host array of cap >= n_accepted). */
+int llg_adaptive_steps(const llg_handle* h, double* hs_out, int64_t cap);
+
+/* Discrete adjoint of the last adaptive run with its step sizes fixed: from
+ * lambda_N = dJdm_T (3N; NULL = 0), per step kappa_s = h (b_s lambda' + sum_{i>s}
+ * a_is mu_i), mu_s = J_f(Y_s)^T kappa_s (stages recomputed from the kept state),
+ * lambda = lambda' + sum_s mu_s; dJ/dpsi accumulates kappa_s . df/dpsi(Y_s) and
+ * dJdpsi_expl (nullable).  Writes dJ/dpsi (N, float64) and, if not NULL, dJ/dm0
+ * (3N).  A terminal objective is evaluated with llg_objective on m(t_end).
+ * Errors: LLG_ESTATE (no adaptive run), LLG_EINVAL, LLG_EHIP. */
+int llg_adjoint_adaptive(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl,
+                         double* dJdpsi_out, void* dJdm0_out, hipStream_t stream);
+
 /* Device bytes the checkpoint store needs for n_steps under a policy
  * (snapshots + recomputed stage states), without allocating anything. */
 int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int32_t ckpt_param, size_t* bytes);

@@ -128,6 +128,7 @@ struct BwdL {
     int W;                // port window length (steps)
     int port_lin;         // 1 spectral, 2 curve objective: the source is the stored per-step scalar
     int pstep;            // window index of this step's state (port_lin)
+    int seed_unit;        // seed stage: l = lambda' itself (a generic stage transpose) instead of dt/6 lambda'
     int do_inv, do_fwd;
     int stage_m;          // stage the y_s rows in LDS too (set by the launcher from the batch)
 };
@@ -174,6 +175,7 @@ struct StageBwdArgs {
     T src1, src2;         // port sources (port 2 carries its sign)
     int src_lin;          // 0 lambda.y += src m_y; 1 lambda.y += src (spectral); 2 lambda.x += src psi and
                           // dJ/dpsi += src m_x on every node (curve)
+    int seed_unit;
     int do_inv;
     int do_fwd;
 };
@@ -233,6 +235,21 @@ template <typename T> hipError_t launch_port_finish(const BatchDev<T>& b, int W,
 // holds f_q (K), then the weights of |X_1| (K) and of |X_2| (K), on the device.
 // Curve objective after a forward run: M_x series and per-step sources, then J.
 // tw holds the W targets, then the W weights, on the device.
+// Linear combinations of up to 7 device vectors (explicit Runge-Kutta stages):
+// out[e] = (base ? base[e] : 0) + sum_j c[j] src[j][e], e < n, in order j = 0, 1, ...
+template <typename T>
+struct LinTerms {
+    const T* src[7];
+    double c[7];
+    int nt;
+};
+template <typename T> hipError_t launch_lincomb(int n, T* out, const T* base, const LinTerms<T>& t, hipStream_t s);
+// Error norm of an embedded pair: max_e |sum_j c[j] k_j[e]| / (atol + rtol max(|y[e]|, |y5[e]|)) into *out
+// (device double); part holds ceil(n / 256) doubles.
+template <typename T>
+hipError_t launch_err_norm(int n, const T* y, const T* y5, const LinTerms<T>& t, double rtol, double atol,
+                           double* part, double* out, hipStream_t s);
+
 // Size and centre constraints (Eq. 9) of psi (nx*ny*nz): J to J[0], dJ/dpsi to g
 // (nullable); work holds 8 + 3 * ceil(N / 256) doubles.
 template <typename T>

@@ -566,6 +566,7 @@ __device__ __forceinline__ StageBwdArgs<T> resolve_bwd(const KParams<T>& p, cons
     a.port1 = port ? role<uint8_t>(tb, B_P1) : nullptr;
     a.port2 = port ? role<uint8_t>(tb, B_P2) : nullptr;
     a.src_lin = L.port_lin;
+    a.seed_unit = L.seed_unit;
     if (port && L.port_lin) {
         const double* g = role<double>(tb, B_PSRC) + 2 * (size_t)L.pstep;
         a.src1 = (T)g[0];
@@ -882,7 +883,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
             const T pi = d.pi;
             V3<T> un = v3<T>(0, 0, 0);
             if (seed) {
-                const V3<T> ell = (dt / (T)6) * d.lam;
+                const V3<T> ell = a.seed_unit ? d.lam : (dt / (T)6) * d.lam;
                 st3(a.ell, N, i, ell);
                 un = field_adjoint(p, ell, d.yprev, x, iy, iz, pi);
                 st3(a.u_next, N, i, un);
@@ -1485,6 +1486,47 @@ __global__ __launch_bounds__(256) void k_curve_finish(const KParams<T>* __restri
     if (threadIdx.x == 0) role<double>(tb, B_SCAL)[0] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// Explicit Runge-Kutta helpers of the adaptive integrator: stage sums and the
+// max-norm of the embedded error estimate.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lincomb(int n, T* __restrict__ out, const T* __restrict__ base,
+                                                 LinTerms<T> lt) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    T v = base ? base[e] : (T)0;
+    for (int j = 0; j < lt.nt; ++j) v += (T)lt.c[j] * lt.src[j][e];
+    out[e] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_err_norm(int n, const T* __restrict__ y, const T* __restrict__ y5,
+                                                  LinTerms<T> lt, double rtol, double atol,
+                                                  double* __restrict__ part) {
+    __shared__ double red[4];
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    double r = 0.0;
+    if (e < n) {
+        T v = (T)0;
+        for (int j = 0; j < lt.nt; ++j) v += (T)lt.c[j] * lt.src[j][e];
+        const double sc = atol + rtol * fmax(fabs((double)y[e]), fabs((double)y5[e]));
+        r = fabs((double)v) / sc;
+    }
+    for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void k_max_finish(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double red[4];
+    double r = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) r = fmax(r, part[b]);
+    for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
 // Size and centre-of-mass constraints of the regularised objective (Eq. 9):
 // block sums of psi, psi x and psi y (fixed order), then J and the gradient
 // dJ/dpsi_i = c0 + c1 (x_i - x_c) + c2 (y_i - y_c).
@@ -1864,6 +1906,19 @@ hipError_t launch_port_finish(const BatchDev<T>& b, int W, hipStream_t s) {
     return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_lincomb(int n, T* out, const T* base, const LinTerms<T>& lt, hipStream_t s) {
+    hipLaunchKernelGGL(k_lincomb<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, out, base, lt);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_err_norm(int n, const T* y, const T* y5, const LinTerms<T>& lt, double rtol, double atol,
+                           double* part, double* out, hipStream_t s) {
+    const int nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_err_norm<T>, dim3(nb), dim3(256), 0, s, n, y, y5, lt, rtol, atol, part);
+    hipLaunchKernelGGL(k_max_finish, dim3(1), dim3(256), 0, s, part, nb, out);
+    return hipGetLastError();
+}
+template <typename T>
 hipError_t launch_shape(const T* psi, int nx, int ny, int nz, double xi, double S_target, double nu, double x0,
                         double y0, double* work, double* J, double* g, hipStream_t s) {
     const int N = nx * ny * nz, nb = (N + 255) / 256;
@@ -1960,6 +2015,9 @@ hipError_t set_lds_limits(size_t bytes) {
     template hipError_t launch_copy<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                        \
     template hipError_t launch_port_finish<T>(const BatchDev<T>&, int, hipStream_t);                                \
     template hipError_t launch_curve<T>(const BatchDev<T>&, const double*, int, hipStream_t);                      \
+    template hipError_t launch_lincomb<T>(int, T*, const T*, const LinTerms<T>&, hipStream_t);                    \
+    template hipError_t launch_err_norm<T>(int, const T*, const T*, const LinTerms<T>&, double, double, double*,   \
+                                           double*, hipStream_t);                                                   \
     template hipError_t launch_shape<T>(const T*, int, int, int, double, double, double, double, double, double*,  \
                                         double*, double*, hipStream_t);                                             \
     template hipError_t launch_spectral<T>(const BatchDev<T>&, const double*, int, int, double, int64_t, double,     \

@@ -130,6 +130,19 @@ struct llg_handle {
     // curve objective: targets and weights of the window steps on the device
     double* curve_tw = nullptr;
     double* shape_work = nullptr;  // size / centre constraints: coefficients and block sums
+    // adaptive Dormand-Prince run: stage rates, trial state, per-step snapshots,
+    // stage adjoints, error-norm scratch; the accepted steps of the last run
+    struct Dopri {
+        void* k[7] = {};
+        void* y5 = nullptr;
+        void* ystage = nullptr;
+        void* snaps = nullptr;   // (max_steps + 1) states
+        void* mu[6] = {};
+        void* lam = nullptr;
+        double* err = nullptr;   // [0] norm, [8..] block maxima
+        std::vector<double> hs, ts;
+        bool valid = false;
+    } dp;
     std::vector<double> curve_host;
     // forward record
     bool fwd_valid = false;
@@ -866,6 +879,132 @@ struct Ops {
         L.ext_B = Bout;
         L.do_inv = h->demag;
         return fwd(L);
+    }
+
+    // ---- adaptive Dormand-Prince 5(4) (single instance) -------------------
+    static constexpr double kC[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+    static constexpr double kA[7][6] = {{0, 0, 0, 0, 0, 0},
+                                        {1.0 / 5, 0, 0, 0, 0, 0},
+                                        {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+                                        {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+                                        {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+                                        {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+                                        {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+    static constexpr double kB5[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0};
+    static constexpr double kB4[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200,
+                                      187.0 / 2100, 1.0 / 40};
+
+    T* P(void* v) const { return static_cast<T*>(v); }
+    size_t n3() const { return (size_t)3 * h->inst[0].N; }
+    T* slot(int id, int j) const { return static_cast<T*>(h->inst[0].tab.b[id]) + (size_t)j * 4 * n3(); }
+    // stage st of a step from m at (t, hstep): Y = m + hstep sum_j a_st,j k_j, rate k_st = f(Y, t + c_st hstep)
+    int dp_stage(int st, const T* m, double t, double hstep, T* Y, void* Bout) {
+        const auto& D = h->dp;
+        const T* y = m;
+        if (st > 0) {
+            LinTerms<T> lt{};
+            for (int j = 0; j < st; ++j)
+                if (kA[st][j] != 0.0) {
+                    lt.src[lt.nt] = P(D.k[j]);
+                    lt.c[lt.nt] = hstep * kA[st][j];
+                    ++lt.nt;
+                }
+            if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), Y, m, lt, s); }))
+                return rc;
+            y = Y;
+        } else if (Y != m) {
+            HIPCHK(hipMemcpyAsync(Y, m, n3() * sizeof(T), hipMemcpyDeviceToDevice, s));
+            y = Y;
+        }
+        return field(y, t + kC[st] * hstep, Bout, D.k[st]);
+    }
+
+    // Trial step from m: y5 and the error norm (device double at D.err[0]).
+    int dp_trial(const T* m, double t, double hstep, double rtol, double atol) {
+        auto& D = h->dp;
+        for (int st = 0; st < 7; ++st)
+            if (int rc = dp_stage(st, m, t, hstep, P(D.ystage), nullptr)) return rc;
+        LinTerms<T> b5{}, e{};
+        for (int j = 0; j < 7; ++j) {
+            if (kB5[j] != 0.0) {
+                b5.src[b5.nt] = P(D.k[j]);
+                b5.c[b5.nt] = hstep * kB5[j];
+                ++b5.nt;
+            }
+            e.src[e.nt] = P(D.k[j]);
+            e.c[e.nt] = hstep * (kB5[j] - kB4[j]);
+            ++e.nt;
+        }
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), P(D.y5), m, b5, s); }))
+            return rc;
+        return run(-1, 0, [&](hipEvent_t, hipEvent_t) {
+            return launch_err_norm<T>((int)n3(), m, P(D.y5), e, rtol, atol, D.err + 8, D.err, s);
+        });
+    }
+
+    // Discrete adjoint of the accepted steps (sizes fixed), from lambda_N in D.lam.
+    int dp_adjoint(bool use_expl) {
+        auto& D = h->dp;
+        const size_t nb = n3() * sizeof(T);
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_GPSI, 0, s); })) return rc;
+        for (int64_t n = (int64_t)D.hs.size() - 1; n >= 0; --n) {
+            const double hstep = D.hs[n], t = D.ts[n];
+            const T* m = P(D.snaps) + (size_t)n * n3();
+            // recompute the stages this step's transpose needs (the 7th has b = 0 and feeds no stage)
+            for (int st = 0; st < 6; ++st)
+                if (int rc = dp_stage(st, m, t, hstep, slot(B_YS, st), slot(B_BS, st))) return rc;
+            for (int st = 5; st >= 0; --st) {
+                // kappa_s = h (b_s lambda' + sum_{i>s} a_is mu_i) into the role buffer L0
+                LinTerms<T> lt{};
+                lt.src[lt.nt] = P(D.lam);
+                lt.c[lt.nt++] = hstep * kB5[st];
+                for (int i = st + 1; i < 6; ++i)
+                    if (kA[i][st] != 0.0) {
+                        lt.src[lt.nt] = P(D.mu[i]);
+                        lt.c[lt.nt++] = hstep * kA[i][st];
+                    }
+                T* kap = static_cast<T*>(h->inst[0].tab.b[B_L0]);
+                if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), kap, nullptr, lt, s); }))
+                    return rc;
+                // mu_s = J_f(Y_s)^T kappa_s: field adjoint u_s and its spectrum, the column pass, then the transpose
+                BwdL Ls{};
+                Ls.stage = -2;
+                Ls.seed_unit = 1;
+                Ls.j = Ls.prev_j = st;
+                Ls.prev_st = 0;
+                Ls.ucur = -1;
+                Ls.unext = B_U0;
+                Ls.lamp = B_L0;
+                Ls.lacc = -1;
+                Ls.do_fwd = h->demag;
+                if (int rc = bwd(Ls)) return rc;
+                if (int rc = col()) return rc;
+                if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_fill<T>(B(), B_L1, 3, 0.0, s); })) return rc;
+                BwdL Lf{};
+                Lf.stage = 0;
+                Lf.j = st;
+                Lf.prev_j = -1;
+                Lf.prev_st = 3;
+                Lf.ucur = B_U0;
+                Lf.unext = B_U1;
+                Lf.lamp = B_L0;
+                Lf.lacc = B_L1;
+                Lf.do_inv = h->demag;
+                Lf.do_fwd = 0;
+                if (int rc = bwd(Lf)) return rc;
+                HIPCHK(hipMemcpyAsync(D.mu[st], h->inst[0].tab.b[B_L1], nb, hipMemcpyDeviceToDevice, s));
+            }
+            // lambda_n = lambda' + sum_s mu_s
+            LinTerms<T> lt{};
+            for (int st = 0; st < 6; ++st) {
+                lt.src[lt.nt] = P(D.mu[st]);
+                lt.c[lt.nt++] = 1.0;
+            }
+            if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), P(D.ystage), P(D.lam), lt, s); }))
+                return rc;
+            HIPCHK(hipMemcpyAsync(D.lam, D.ystage, nb, hipMemcpyDeviceToDevice, s));
+        }
+        return run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_psi_grad_out<T>(B(), use_expl, s); });
     }
 
     int energy(const llg_objective_spec* obj, const T* m, double t, double* J, T* dJdm, double* dJdpsi, double* en) {
@@ -1782,6 +1921,134 @@ int llg_batch_adjoint(llg_batch* b, const void* const* psi, const void* const* d
                       const llg_objective_spec* obj, double* const* dJdpsi_out, void* const* dJdm0_out,
                       hipStream_t stream) {
     return b_adjoint(b, psi, dJdm_T, dJdpsi_expl, obj, dJdpsi_out, dJdm0_out, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Buffers of the adaptive integrator (first use; sized for max_steps accepted steps).
+int ensure_dopri(llg_handle* h) {
+    auto& D = h->dp;
+    if (D.snaps) return LLG_OK;
+    const size_t nb = (size_t)3 * h->inst[0].N * h->tsz;
+    int rc;
+    for (auto& k : D.k)
+        if ((rc = alloc(h, &k, nb))) return rc;
+    for (auto& m : D.mu)
+        if ((rc = alloc(h, &m, nb))) return rc;
+    if ((rc = alloc(h, &D.y5, nb)) || (rc = alloc(h, &D.ystage, nb)) || (rc = alloc(h, &D.lam, nb))) return rc;
+    if ((rc = alloc(h, &D.snaps, nb * (size_t)(h->max_steps + 1)))) return rc;
+    void* e;
+    if ((rc = alloc(h, &e, (8 + (3 * h->inst[0].N + 255) / 256) * sizeof(double)))) return rc;
+    D.err = (double*)e;
+    return LLG_OK;
+}
+
+template <typename T>
+int forward_adaptive(llg_handle* h, double t0, double t_end, double h0, double rtol, double atol, int64_t* n_rej,
+                     hipStream_t s) {
+    Ops<T> o{h, s};
+    auto& D = h->dp;
+    const size_t n3 = (size_t)3 * h->inst[0].N;
+    double t = t0, hstep = h0;
+    bool ok_last = true;
+    int64_t rejected = 0;
+    T* snaps = static_cast<T*>(D.snaps);
+    while (t < t_end) {
+        if ((int64_t)D.hs.size() >= h->max_steps)
+            return fail(LLG_ENOMEM, "adaptive run needs more accepted steps than max_steps");
+        hstep = std::min(hstep, t_end - t);
+        const T* m = snaps + D.hs.size() * n3;
+        if (int rc = o.dp_trial(m, t, hstep, rtol, atol)) return rc;
+        double err = 0.0;
+        HIPCHK(hipMemcpyAsync(&err, D.err, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!std::isfinite(err)) return fail(LLG_ENONFINITE, "non-finite error estimate");
+        double f = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(err, -0.2)));
+        if (err <= 1.0) {
+            HIPCHK(hipMemcpyAsync(snaps + (D.hs.size() + 1) * n3, D.y5, n3 * sizeof(T), hipMemcpyDeviceToDevice, s));
+            D.ts.push_back(t);
+            D.hs.push_back(hstep);
+            t = t_end - t > hstep ? t + hstep : t_end;
+            if (!ok_last) f = std::min(f, 1.0);
+            hstep *= f;
+            ok_last = true;
+        } else {
+            ++rejected;
+            hstep *= std::min(f, 1.0);
+            ok_last = false;
+            if (!(hstep > 0.0)) return fail(LLG_ENONFINITE, "step size underflow");
+        }
+    }
+    if (n_rej) *n_rej = rejected;
+    return LLG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int llg_forward_adaptive(llg_handle* h, const void* psi, const void* m0, double t0, double t_end, double h0,
+                         double rtol, double atol, void* m_out, int64_t* n_accepted, int64_t* n_rejected,
+                         hipStream_t stream) {
+    int rc;
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
+    if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(m0, "m0"))) return rc;
+    if (!std::isfinite(t0) || !std::isfinite(t_end) || !(t_end > t0)) return fail(LLG_EINVAL, "need t_end > t0");
+    if (!(h0 > 0.0) || !std::isfinite(h0)) return fail(LLG_EINVAL, "h0 must be > 0");
+    if (!(rtol >= 0.0) || !(atol >= 0.0) || !(rtol + atol > 0.0)) return fail(LLG_EINVAL, "need rtol, atol >= 0, not both 0");
+    if (h->K * h->halves < 6) return fail(LLG_ENOTSUP, "adaptive adjoint needs 6 stage slots: raise max_steps");
+    if ((rc = ensure_dopri(h))) return rc;
+    auto& D = h->dp;
+    D.valid = false;
+    D.hs.clear();
+    D.ts.clear();
+    h->fwd_valid = false;
+    const size_t N = h->inst[0].N;
+    if ((rc = put(h, 0, B_PSI, psi, N * h->tsz, stream))) return rc;
+    HIPCHK(hipMemcpyAsync(D.snaps, m0, 3 * N * h->tsz, hipMemcpyDeviceToDevice, stream));
+    rc = h->dtype == LLG_F32 ? forward_adaptive<float>(h, t0, t_end, h0, rtol, atol, n_rejected, stream)
+                             : forward_adaptive<double>(h, t0, t_end, h0, rtol, atol, n_rejected, stream);
+    if (rc) return rc;
+    if (m_out)
+        HIPCHK(hipMemcpyAsync(m_out, static_cast<char*>(D.snaps) + D.hs.size() * 3 * N * h->tsz, 3 * N * h->tsz,
+                              hipMemcpyDeviceToDevice, stream));
+    if (n_accepted) *n_accepted = (int64_t)D.hs.size();
+    D.valid = true;
+    return LLG_OK;
+}
+
+int llg_adaptive_steps(const llg_handle* h, double* hs_out, int64_t cap) {
+    if (!h || !hs_out) return fail(LLG_EINVAL, "NULL argument");
+    if (!h->dp.valid) return fail(LLG_ESTATE, "no adaptive run recorded");
+    if (cap < (int64_t)h->dp.hs.size()) return fail(LLG_EINVAL, "cap smaller than the number of accepted steps");
+    std::copy(h->dp.hs.begin(), h->dp.hs.end(), hs_out);
+    return LLG_OK;
+}
+
+int llg_adjoint_adaptive(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl,
+                         double* dJdpsi_out, void* dJdm0_out, hipStream_t stream) {
+    int rc;
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
+    if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(dJdpsi_out, "dJdpsi_out"))) return rc;
+    if (!h->dp.valid) return fail(LLG_ESTATE, "llg_adjoint_adaptive needs a preceding llg_forward_adaptive");
+    const size_t N = h->inst[0].N, nb = 3 * N * h->tsz;
+    if ((rc = put(h, 0, B_PSI, psi, N * h->tsz, stream))) return rc;
+    if (dJdm_T)
+        HIPCHK(hipMemcpyAsync(h->dp.lam, dJdm_T, nb, hipMemcpyDeviceToDevice, stream));
+    else
+        HIPCHK(hipMemsetAsync(h->dp.lam, 0, nb, stream));
+    if (dJdpsi_expl && (rc = put(h, 0, B_DPSIE, dJdpsi_expl, N * 8, stream))) return rc;
+    h->fwd_valid = false;  // the stage store now holds this run's states
+    rc = h->dtype == LLG_F32 ? Ops<float>{h, stream}.dp_adjoint(dJdpsi_expl != nullptr)
+                             : Ops<double>{h, stream}.dp_adjoint(dJdpsi_expl != nullptr);
+    if (rc) return rc;
+    if ((rc = get(h, 0, B_DPSI, dJdpsi_out, N * 8, stream))) return rc;
+    if (dJdm0_out) HIPCHK(hipMemcpyAsync(dJdm0_out, h->dp.lam, nb, hipMemcpyDeviceToDevice, stream));
+    return LLG_OK;
 }
 
 int llg_shape_penalty(llg_handle* h, const void* psi, double xi, double S_target, double nu, double x0, double y0,

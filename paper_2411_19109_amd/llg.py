@@ -28,7 +28,8 @@ EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_le
            "llg_set_launch_config", "llg_autotune", "llg_fft_sizes", "llg_profile", "llg_profile_read", "llg_batch_create",
            "llg_batch_destroy", "llg_batch_size", "llg_batch_levelset_to_Ms", "llg_batch_levelset_to_Ms_vjp",
            "llg_batch_forward", "llg_batch_adjoint", "llg_rbf_work_len", "llg_rbf_levelset", "llg_rbf_levelset_vjp",
-           "llg_adam_step", "llg_rbf_profile", "llg_rbf_profile_read", "llg_shape_penalty"]
+           "llg_adam_step", "llg_rbf_profile", "llg_rbf_profile_read", "llg_shape_penalty", "llg_forward_adaptive",
+           "llg_adaptive_steps", "llg_adjoint_adaptive"]
 RBF_KIND_NAMES = {0: "k_rbf_cones", 1: "k_rbf_pnorm", 2: "k_rbf_vjp"}
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
 KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col_conv", KIND_STAGE_BWD: "k_stage_bwd"}
@@ -115,6 +116,9 @@ def lib():
         "llg_adam_step": [i32, vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, vp],
         "llg_rbf_profile": [ctypes.c_int],
         "llg_shape_penalty": [vp, vp, dbl, dbl, dbl, dbl, dbl, vp, vp, vp],
+        "llg_forward_adaptive": [vp, vp, vp, dbl, dbl, dbl, dbl, dbl, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp],
+        "llg_adaptive_steps": [vp, ctypes.POINTER(dbl), i64],
+        "llg_adjoint_adaptive": [vp, vp, vp, vp, vp, vp, vp],
         "llg_rbf_profile_read": [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
     }
     for name, args in sig.items():
@@ -316,6 +320,29 @@ class Solver:
         out = torch.empty(phi.numel(), dtype=torch.float64, device=phi.device)
         check(lib().llg_levelset_to_Ms_vjp(self.h, _ptr(phi), _ptr(dJdpsi), float(a), int(extrude_z), _ptr(out), _stream()))
         return out
+
+    def forward_adaptive(self, psi, m0, t_end, h0, rtol, atol, t0=0.0):
+        """Adaptive Dormand-Prince run to t_end: (m(t_end), accepted step sizes
+        (numpy), rejected trials)."""
+        import torch
+        self._t(psi, self.N)
+        self._t(m0, 3 * self.N)
+        m_out = torch.empty_like(m0)
+        na, nr = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._fwd_gen += 1
+        check(lib().llg_forward_adaptive(self.h, _ptr(psi), _ptr(m0), float(t0), float(t_end), float(h0), float(rtol),
+                                         float(atol), _ptr(m_out), ctypes.byref(na), ctypes.byref(nr), _stream()))
+        hs = np.zeros(max(1, na.value))
+        check(lib().llg_adaptive_steps(self.h, hs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hs.size))
+        return m_out, hs[:na.value], nr.value
+
+    def adjoint_adaptive(self, psi, dJdm_T=None, dJdpsi_expl=None, want_dm0=False):
+        import torch
+        dJdpsi = torch.empty(self.N, dtype=torch.float64, device=psi.device)
+        dm0 = torch.empty(3 * self.N, dtype=self.tdtype, device=psi.device) if want_dm0 else None
+        check(lib().llg_adjoint_adaptive(self.h, _ptr(psi), _ptr(dJdm_T), _ptr(dJdpsi_expl), _ptr(dJdpsi), _ptr(dm0),
+                                         _stream()))
+        return (dJdpsi, dm0) if want_dm0 else dJdpsi
 
     def shape_penalty(self, psi, xi, S_target, nu, x0, y0, want_grad=True):
         """(J, dJ/dpsi) of the size and centre constraints of Eq. 9 (device

@@ -6,7 +6,8 @@ checkpointed discrete adjoint back to t0, and the chain rule to dJ/dphi.
 Inputs are resident in device memory before the timed region starts.
 
   python bench.py [--steps K] [--warmup W]
-                  [--workload particle|particle_curve|waveguide|demux|demux_spectral|device3d|sweep|probe|rbf]
+                  [--workload particle|particle_curve|particle_adaptive|waveguide|demux|demux_spectral|device3d|sweep|
+                              probe|rbf]
 
 Prints ONE JSON line.  The metric is LLG cell-steps per second of the forward
 + adjoint run: nodes * RK4 steps / wall time of one gradient evaluation.
@@ -223,6 +224,8 @@ def main():
         return run_probe(args)
     if args.workload == "rbf":
         return run_rbf(args)
+    if args.workload == "particle_adaptive":
+        return run_adaptive(args)
     w = make_workload(args.workload)
     if args.n_steps > 0 and args.workload == "particle_curve":
         from paper_2411_19109_amd import workloads as wl
@@ -479,6 +482,78 @@ def run_probe(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": name, "nodes": nodes, "rk4_steps": n, "launch": list(launch)},
+        "roofline": roofline,
+        "kernels": {k: dict(avg_us=round(v["avg_us"], 2), gbs=round(v["gbs"], 1)) for k, v in kinds.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_adaptive(args):
+    """The particle gradient with adaptive Dormand-Prince steps over the same
+    physical time as the fixed-step run (2000 x 50 fs = 100 ps), FP32, error
+    tolerance 1e-5: adaptive forward, energy objective, adjoint of the
+    accepted steps, chain to dJ/dphi."""
+    import torch
+    from paper_2411_19109_amd import llg, workloads as wl
+    w = wl.permalloy_particle()
+    dev = torch.device("cuda:0")
+    t_end = w.n_steps * w.problem.dt
+    tol = 1e-5
+    s = llg.Solver(w.problem, dtype="f32", max_steps=4 * w.n_steps, design=w.design)
+    launch = s.autotune()
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=torch.float32, device=dev)
+    phi, psif, m0 = t(w.phi), t(w.psi_fixed), t(w.m0)
+    obj = llg.make_objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area)
+
+    def step():
+        psi = s.levelset_to_psi(phi, w.heaviside_a, psif)
+        mT, hs, nrej = s.forward_adaptive(psi, m0, t_end, w.problem.dt, tol, tol)
+        J, dJdm, dJdpsi_e, _ = s.objective(obj, psi, mT)
+        dpsi = s.adjoint_adaptive(psi, dJdm_T=dJdm, dJdpsi_expl=dJdpsi_e)
+        return J, s.levelset_vjp(phi, dpsi, w.heaviside_a), hs, nrej
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        J, g, hs, nrej = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    n_acc = len(hs)
+    print(f"[bench] adaptive particle: {n_acc} accepted, {nrej} rejected steps (h {hs.min():.3e}..{hs.max():.3e} s), "
+          f"{sec * 1e3:.1f} ms per gradient", file=sys.stderr, flush=True)
+    roofline, kinds = None, {}
+    if not args.no_kernel_events:
+        s.profile(True)
+        step()
+        torch.cuda.synchronize()
+        s.profile(False)
+        kinds = _kernel_stats(s)
+        for kn, v in kinds.items():
+            print(f"[bench] adaptive {kn}: {v['launches']} launches, avg {v['avg_us']:.2f} us, "
+                  f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
+        dom = max(kinds, key=lambda k: kinds[k]["ms"])
+        d = kinds[dom]
+        roofline = dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(d["gbs"] / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
+                        avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"]))
+    N = w.problem.n
+    out = {
+        "metric": METRIC,
+        "value": N * n_acc / sec,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "permalloy_particle_64x64_adaptive_grad", "nodes": [w.problem.nx, w.problem.ny, 1],
+                   "t_end_s": t_end, "rtol": tol, "atol": tol, "accepted_steps": n_acc, "rejected_steps": nrej,
+                   "fixed_step_equivalent": w.n_steps, "launch": list(launch), "objective_J": float(J.item())},
         "roofline": roofline,
         "kernels": {k: dict(avg_us=round(v["avg_us"], 2), gbs=round(v["gbs"], 1)) for k, v in kinds.items()},
     }

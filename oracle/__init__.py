@@ -22,4 +22,6 @@ Modules
   shape      size and centre-of-mass constraints of the regularised objective
   dopri      adaptive Dormand-Prince 5(4) integration and the adjoint of its
              accepted steps
+  continuous the continuous adjoint (the adjoint equation integrated backwards
+             on the kept forward states), for comparison with the discrete one
 """

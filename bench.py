@@ -522,6 +522,29 @@ def run_adaptive(args):
     n_acc = len(hs)
     print(f"[bench] adaptive particle: {n_acc} accepted, {nrej} rejected steps (h {hs.min():.3e}..{hs.max():.3e} s), "
           f"{sec * 1e3:.1f} ms per gradient", file=sys.stderr, flush=True)
+    # the continuous adjoint (Eqs. 6-7) of the same run beside the discrete one: time of the backward
+    # pass alone and the relative L2 gap of dJ/dphi.  Two RK4 sub-steps per interval: the adaptive steps of
+    # this stiff run sit at the edge of Dormand-Prince's stability region, beyond RK4's.
+    n_sub = 2
+    psi = s.levelset_to_psi(phi, w.heaviside_a, psif)
+    mT, hs, nrej = s.forward_adaptive(psi, m0, t_end, w.problem.dt, tol, tol)
+    _, dJdm, dJdpsi_e, _ = s.objective(obj, psi, mT)
+    back = {}
+    for key, cont in (("discrete", False), ("continuous", True)):
+        s.adjoint_adaptive(psi, dJdm_T=dJdm, dJdpsi_expl=dJdpsi_e, continuous=cont, n_sub=n_sub)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.steps)):
+            dpsi = s.adjoint_adaptive(psi, dJdm_T=dJdm, dJdpsi_expl=dJdpsi_e, continuous=cont, n_sub=n_sub)
+        torch.cuda.synchronize()
+        back[key] = ((time.perf_counter() - t0) / max(1, args.steps), s.levelset_vjp(phi, dpsi, w.heaviside_a))
+    gd, gc = back["discrete"][1].double(), back["continuous"][1].double()
+    gap = float((gc - gd).norm() / gd.norm())
+    compare = {"discrete_adjoint_ms": round(back["discrete"][0] * 1e3, 2),
+               "continuous_adjoint_ms": round(back["continuous"][0] * 1e3, 2), "continuous_sub_steps": n_sub,
+               "continuous_vs_discrete_rel_l2": gap}
+    print(f"[bench] adaptive backward pass: discrete {compare['discrete_adjoint_ms']} ms, continuous "
+          f"{compare['continuous_adjoint_ms']} ms, dJ/dphi gap {gap:.2e}", file=sys.stderr, flush=True)
     roofline, kinds = None, {}
     if not args.no_kernel_events:
         s.profile(True)
@@ -556,6 +579,7 @@ def run_adaptive(args):
                    "fixed_step_equivalent": w.n_steps, "launch": list(launch), "objective_J": float(J.item())},
         "roofline": roofline,
         "kernels": {k: dict(avg_us=round(v["avg_us"], 2), gbs=round(v["gbs"], 1)) for k, v in kinds.items()},
+        "adjoint_compare": compare,
     }
     print(json.dumps(out), flush=True)
 

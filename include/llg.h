@@ -258,6 +258,21 @@ int llg_adaptive_steps(const llg_handle* h, double* hs_out, int64_t cap);
 int llg_adjoint_adaptive(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl,
                          double* dJdpsi_out, void* dJdm0_out, hipStream_t stream);
 
+/* Continuous adjoint (Eqs. 6-7), for comparison with the discrete one: the
+ * adjoint equation da/dt = -J_f(m)^T a and dJ/dpsi = integral a . df/dpsi are
+ * integrated backwards over every interval of the last llg_forward_adaptive
+ * run, each split into n_sub (1..64) equal classic RK4 steps, with the
+ * Jacobians taken at states of the cubic Hermite interpolant of the kept
+ * states and their rates (not at the forward stage states).  Otherwise the
+ * same arguments and outputs as llg_adjoint_adaptive.  The result differs
+ * from the discrete gradient by the discretisation error of the backward
+ * integration (fourth order in the step).  On stiff runs the adaptive steps
+ * lie at the edge of Dormand-Prince's stability region, beyond RK4's: n_sub = 1
+ * then diverges (non-finite output in FP32) and n_sub = 2 is needed.
+ * LLG_EINVAL for n_sub outside 1..64, LLG_ESTATE without an adaptive run. */
+int llg_adjoint_continuous(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl, int n_sub,
+                           double* dJdpsi_out, void* dJdm0_out, hipStream_t stream);
+
 /* Device bytes the checkpoint store needs for n_steps under a policy
  * (snapshots + recomputed stage states), without allocating anything. */
 int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int32_t ckpt_param, size_t* bytes);

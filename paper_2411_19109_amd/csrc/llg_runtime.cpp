@@ -942,6 +942,126 @@ struct Ops {
         });
     }
 
+    // mu = J_f(Y)^T kappa for the state Y and field B(Y) in stage slot j of YS / BS and kappa in the role
+    // buffer L0: the field adjoint u and its spectrum (seed with a unit scale), the column pass, then the
+    // transpose (stage 0 without a next stage) into L1, copied to mu_out; dJ/dpsi gains kappa . df/dpsi(Y).
+    int stage_transpose(int j, void* mu_out) {
+        BwdL Ls{};
+        Ls.stage = -2;
+        Ls.seed_unit = 1;
+        Ls.j = Ls.prev_j = j;
+        Ls.prev_st = 0;
+        Ls.ucur = -1;
+        Ls.unext = B_U0;
+        Ls.lamp = B_L0;
+        Ls.lacc = -1;
+        Ls.do_fwd = h->demag;
+        if (int rc = bwd(Ls)) return rc;
+        if (int rc = col()) return rc;
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_fill<T>(B(), B_L1, 3, 0.0, s); })) return rc;
+        BwdL Lf{};
+        Lf.stage = 0;
+        Lf.j = j;
+        Lf.prev_j = -1;
+        Lf.prev_st = 3;
+        Lf.ucur = B_U0;
+        Lf.unext = B_U1;
+        Lf.lamp = B_L0;
+        Lf.lacc = B_L1;
+        Lf.do_inv = h->demag;
+        Lf.do_fwd = 0;
+        if (int rc = bwd(Lf)) return rc;
+        HIPCHK(hipMemcpyAsync(mu_out, h->inst[0].tab.b[B_L1], n3() * sizeof(T), hipMemcpyDeviceToDevice, s));
+        return LLG_OK;
+    }
+    int kappa(std::initializer_list<std::pair<double, const void*>> terms) {
+        LinTerms<T> lt{};
+        for (auto& tm : terms) {
+            lt.src[lt.nt] = static_cast<const T*>(tm.second);
+            lt.c[lt.nt++] = tm.first;
+        }
+        T* kap = static_cast<T*>(h->inst[0].tab.b[B_L0]);
+        return run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), kap, nullptr, lt, s); });
+    }
+
+    // Cubic Hermite interpolant of the kept states on [t_n, t_n + h] at t_n + th h into Y:
+    // h00 m_n + h10 h f(m_n) + h01 m_n+1 + h11 h f(m_n+1), with f(m_n) in k[1] and f(m_n+1) in k[0].
+    int hermite(const T* m0, const T* m1, double hstep, double th, T* Y) {
+        const auto& D = h->dp;
+        LinTerms<T> lt{};
+        const double th2 = th * th, th3 = th2 * th;
+        lt.src[0] = m0;
+        lt.c[0] = 2.0 * th3 - 3.0 * th2 + 1.0;
+        lt.src[1] = P(D.k[1]);
+        lt.c[1] = (th3 - 2.0 * th2 + th) * hstep;
+        lt.src[2] = m1;
+        lt.c[2] = 3.0 * th2 - 2.0 * th3;
+        lt.src[3] = P(D.k[0]);
+        lt.c[3] = (th3 - th2) * hstep;
+        lt.nt = 4;
+        return run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), Y, nullptr, lt, s); });
+    }
+
+    // Continuous adjoint (Eqs. 6-7) over the kept states of the last adaptive run: each interval is split into
+    // n_sub classic RK4 steps backwards for the augmented system (a, dJ/dpsi), with the Jacobians at the
+    // sub-step's end, the Hermite state at its midpoint (twice) and its start.  Stage slots of YS / BS:
+    // 0 and 2 alternate as the sub-step's end and start, 1 = midpoint, 3 = m_n.
+    int continuous_adjoint(bool use_expl, int n_sub) {
+        auto& D = h->dp;
+        const size_t nb = n3() * sizeof(T);
+        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_GPSI, 0, s); })) return rc;
+        const int64_t N = (int64_t)D.hs.size();
+        const T* snaps = P(D.snaps);
+        const double tN = D.ts.empty() ? 0.0 : D.ts.back() + D.hs.back();
+        HIPCHK(hipMemcpyAsync(slot(B_YS, 0), snaps + (size_t)N * n3(), nb, hipMemcpyDeviceToDevice, s));
+        if (int rc = field(slot(B_YS, 0), tN, slot(B_BS, 0), D.k[0])) return rc;
+        for (int64_t n = N - 1; n >= 0; --n) {
+            const double hn = D.hs[n], t = D.ts[n], hsub = hn / n_sub;
+            const T* m0 = snaps + (size_t)n * n3();
+            const T* m1 = snaps + (size_t)(n + 1) * n3();
+            HIPCHK(hipMemcpyAsync(slot(B_YS, 3), m0, nb, hipMemcpyDeviceToDevice, s));
+            if (int rc = field(slot(B_YS, 3), t, slot(B_BS, 3), D.k[1])) return rc;
+            int up = 0;
+            for (int k = n_sub - 1; k >= 0; --k) {
+                const double thm = (k + 0.5) / n_sub;
+                if (int rc = hermite(m0, m1, hn, thm, slot(B_YS, 1))) return rc;
+                if (int rc = field(slot(B_YS, 1), t + thm * hn, slot(B_BS, 1), D.k[2])) return rc;
+                int lo = 3;
+                if (k > 0) {
+                    lo = up == 0 ? 2 : 0;
+                    const double thl = (double)k / n_sub;
+                    if (int rc = hermite(m0, m1, hn, thl, slot(B_YS, lo))) return rc;
+                    if (int rc = field(slot(B_YS, lo), t + thl * hn, slot(B_BS, lo), D.k[2])) return rc;
+                }
+                // kappa_s = w_s hsub A_s gives mu_s = w_s hsub G_s: A2 = a + 3 mu1, A3 = a + 1.5 mu2,
+                // A4 = a + 3 mu3, and a <- a + mu1 + mu2 + mu3 + mu4
+                if (int rc = kappa({{hsub / 6.0, D.lam}})) return rc;
+                if (int rc = stage_transpose(up, D.mu[0])) return rc;
+                if (int rc = kappa({{hsub / 3.0, D.lam}, {hsub, D.mu[0]}})) return rc;
+                if (int rc = stage_transpose(1, D.mu[1])) return rc;
+                if (int rc = kappa({{hsub / 3.0, D.lam}, {hsub / 2.0, D.mu[1]}})) return rc;
+                if (int rc = stage_transpose(1, D.mu[2])) return rc;
+                if (int rc = kappa({{hsub / 6.0, D.lam}, {hsub / 2.0, D.mu[2]}})) return rc;
+                if (int rc = stage_transpose(lo, D.mu[3])) return rc;
+                LinTerms<T> lt{};
+                for (int q = 0; q < 4; ++q) {
+                    lt.src[q] = P(D.mu[q]);
+                    lt.c[q] = 1.0;
+                }
+                lt.nt = 4;
+                if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), P(D.ystage), P(D.lam), lt, s); }))
+                    return rc;
+                HIPCHK(hipMemcpyAsync(D.lam, D.ystage, nb, hipMemcpyDeviceToDevice, s));
+                up = lo;
+            }
+            // m_n and its field and rate become the next interval's end
+            HIPCHK(hipMemcpyAsync(slot(B_YS, 0), slot(B_YS, 3), nb, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(slot(B_BS, 0), slot(B_BS, 3), nb, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(D.k[0], D.k[1], nb, hipMemcpyDeviceToDevice, s));
+        }
+        return run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_psi_grad_out<T>(B(), use_expl, s); });
+    }
+
     // Discrete adjoint of the accepted steps (sizes fixed), from lambda_N in D.lam.
     int dp_adjoint(bool use_expl) {
         auto& D = h->dp;
@@ -966,33 +1086,7 @@ struct Ops {
                 T* kap = static_cast<T*>(h->inst[0].tab.b[B_L0]);
                 if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), kap, nullptr, lt, s); }))
                     return rc;
-                // mu_s = J_f(Y_s)^T kappa_s: field adjoint u_s and its spectrum, the column pass, then the transpose
-                BwdL Ls{};
-                Ls.stage = -2;
-                Ls.seed_unit = 1;
-                Ls.j = Ls.prev_j = st;
-                Ls.prev_st = 0;
-                Ls.ucur = -1;
-                Ls.unext = B_U0;
-                Ls.lamp = B_L0;
-                Ls.lacc = -1;
-                Ls.do_fwd = h->demag;
-                if (int rc = bwd(Ls)) return rc;
-                if (int rc = col()) return rc;
-                if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_fill<T>(B(), B_L1, 3, 0.0, s); })) return rc;
-                BwdL Lf{};
-                Lf.stage = 0;
-                Lf.j = st;
-                Lf.prev_j = -1;
-                Lf.prev_st = 3;
-                Lf.ucur = B_U0;
-                Lf.unext = B_U1;
-                Lf.lamp = B_L0;
-                Lf.lacc = B_L1;
-                Lf.do_inv = h->demag;
-                Lf.do_fwd = 0;
-                if (int rc = bwd(Lf)) return rc;
-                HIPCHK(hipMemcpyAsync(D.mu[st], h->inst[0].tab.b[B_L1], nb, hipMemcpyDeviceToDevice, s));
+                if (int rc = stage_transpose(st, D.mu[st])) return rc;
             }
             // lambda_n = lambda' + sum_s mu_s
             LinTerms<T> lt{};
@@ -2028,10 +2122,15 @@ int llg_adaptive_steps(const llg_handle* h, double* hs_out, int64_t cap) {
     return LLG_OK;
 }
 
-int llg_adjoint_adaptive(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl,
-                         double* dJdpsi_out, void* dJdm0_out, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+int adjoint_on_kept_states(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl,
+                           double* dJdpsi_out, void* dJdm0_out, int n_sub, hipStream_t stream) {
     int rc;
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (n_sub < 0 || n_sub > 64) return fail(LLG_EINVAL, "n_sub must be in 1..64");
     if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
     if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(dJdpsi_out, "dJdpsi_out"))) return rc;
     if (!h->dp.valid) return fail(LLG_ESTATE, "llg_adjoint_adaptive needs a preceding llg_forward_adaptive");
@@ -2043,12 +2142,33 @@ int llg_adjoint_adaptive(llg_handle* h, const void* psi, const void* dJdm_T, con
         HIPCHK(hipMemsetAsync(h->dp.lam, 0, nb, stream));
     if (dJdpsi_expl && (rc = put(h, 0, B_DPSIE, dJdpsi_expl, N * 8, stream))) return rc;
     h->fwd_valid = false;  // the stage store now holds this run's states
-    rc = h->dtype == LLG_F32 ? Ops<float>{h, stream}.dp_adjoint(dJdpsi_expl != nullptr)
-                             : Ops<double>{h, stream}.dp_adjoint(dJdpsi_expl != nullptr);
+    const bool ex = dJdpsi_expl != nullptr;
+    if (h->dtype == LLG_F32) {
+        Ops<float> o{h, stream};
+        rc = n_sub ? o.continuous_adjoint(ex, n_sub) : o.dp_adjoint(ex);
+    } else {
+        Ops<double> o{h, stream};
+        rc = n_sub ? o.continuous_adjoint(ex, n_sub) : o.dp_adjoint(ex);
+    }
     if (rc) return rc;
     if ((rc = get(h, 0, B_DPSI, dJdpsi_out, N * 8, stream))) return rc;
     if (dJdm0_out) HIPCHK(hipMemcpyAsync(dJdm0_out, h->dp.lam, nb, hipMemcpyDeviceToDevice, stream));
     return LLG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int llg_adjoint_adaptive(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl,
+                         double* dJdpsi_out, void* dJdm0_out, hipStream_t stream) {
+    return adjoint_on_kept_states(h, psi, dJdm_T, dJdpsi_expl, dJdpsi_out, dJdm0_out, 0, stream);
+}
+
+int llg_adjoint_continuous(llg_handle* h, const void* psi, const void* dJdm_T, const double* dJdpsi_expl, int n_sub,
+                           double* dJdpsi_out, void* dJdm0_out, hipStream_t stream) {
+    if (n_sub < 1) return fail(LLG_EINVAL, "n_sub must be in 1..64");
+    return adjoint_on_kept_states(h, psi, dJdm_T, dJdpsi_expl, dJdpsi_out, dJdm0_out, n_sub, stream);
 }
 
 int llg_shape_penalty(llg_handle* h, const void* psi, double xi, double S_target, double nu, double x0, double y0,

@@ -1,0 +1,139 @@
+"""Continuous adjoint (Eqs. 6-7 integrated backwards) through the C ABI:
+dJ/dphi and dJ/dm0 against the oracle's continuous adjoint on the GPU's own
+accepted steps (FP64 1e-9, FP32 1e-3) with one and two RK4 sub-steps per
+interval, its distance from the discrete adjoint of the same run, that it
+leaves the discrete adjoint's result unchanged, the divergence of one sub-step
+and the stability of two on a stiff adaptive run, and argument checks."""
+import numpy as np
+import pytest
+
+from _helpers import rel_l2, say, to_dev, to_np
+from oracle import adjoint as oadj
+from oracle import continuous as ocont
+from oracle import dopri as odp
+from oracle import levelset as ols
+from oracle import micromag as omm
+from paper_2411_19109_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+T_END, H0 = 4e-12, 2e-13
+
+
+def case(nx=13, ny=9, seed=61):
+    p = wl.Problem(nx=nx, ny=ny, nz=1, dx=3e-9, dy=3e-9, dz=4e-9, Ms=8e5, A=1.3e-11, K=5e4, ku=(0.6, 0.8, 0.0),
+                   alpha0=0.2, alpha_max=0.2, B0=(0.05, 0.02, 0.1), b_rf=(0.0, 0.01, 0.0), f1=5e9,
+                   terms=wl.TERM_ALL, dt=5e-14)
+    rng = np.random.default_rng(seed)
+    sh = p.shape
+    ant = np.zeros(sh, np.uint8)
+    ant[:, :, 1] = 1
+    phi = rng.standard_normal((ny, nx)) * 0.5
+    design = np.ones(sh, np.uint8)
+    psif = np.zeros(sh)
+    m0 = rng.standard_normal((3,) + sh)
+    m0 /= np.sqrt((m0 ** 2).sum(0))
+    return p, ant, phi, design, psif, m0
+
+
+def gpu_run(dtype, tol, n_sub):
+    import torch
+    from paper_2411_19109_amd import llg
+    p, ant, phi, design, psif, m0 = case()
+    s = llg.Solver(p, dtype=dtype, max_steps=400, antenna=ant, design=design)
+    ph = to_dev(phi, dtype)
+    psi = s.levelset_to_psi(ph, 3.0, to_dev(psif, dtype))
+    mT, hs, _ = s.forward_adaptive(psi, to_dev(m0, dtype), T_END, H0, tol, tol)
+    obj = llg.make_objective(wl.OBJ_ENERGY_AREA, E_ref=1e-18, lam=0.7, area=0.4)
+    _, dJdm, dJdpsi_e, _ = s.objective(obj, psi, mT)
+    out = {"hs": np.asarray(hs)}
+    for key, cont in (("disc", False), ("cont", True), ("disc2", False)):
+        dpsi, dm0 = s.adjoint_adaptive(psi, dJdm_T=dJdm, dJdpsi_expl=dJdpsi_e, want_dm0=True, continuous=cont,
+                                       n_sub=n_sub)
+        out[key] = (to_np(s.levelset_vjp(ph, dpsi, 3.0)), to_np(dm0))
+    torch.cuda.synchronize()
+    s.close()
+    return out
+
+
+def oracle_continuous(sim, m0, psi, obj, hs, n_sub):
+    mT, traj = odp.integrate_fixed(sim, m0, psi, 0.0, list(hs), keep=True)
+    ts = [0.0]
+    for h in hs:
+        ts.append(ts[-1] + h)
+    lamT, gT = oadj.energy_area_grad(sim, mT, psi, obj)
+    return ocont.continuous_adjoint(sim, traj, ts, list(hs), psi, lamT, gT, n_sub=n_sub)
+
+
+@pytest.mark.parametrize("dtype,tol,bound", [("f64", 1e-8, 1e-9), ("f32", 1e-5, 1e-3)])
+@pytest.mark.parametrize("n_sub", [1, 2])
+def test_continuous_adjoint_matches_oracle(dtype, tol, bound, n_sub):
+    g = gpu_run(dtype, tol, n_sub)
+    p, ant, phi, design, psif, m0 = case()
+    psi = ols.levelset_to_psi(phi, 3.0, design, psif)
+    obj = oadj.Objective(oadj.OBJ_ENERGY_AREA, E_ref=1e-18, lam=0.7, area=0.4)
+    gpsi, lam0 = oracle_continuous(omm.Sim(p, antenna=ant), m0, psi, obj, g["hs"], n_sub)
+    o_phi, o_m0 = ols.levelset_vjp(phi, 3.0, design, gpsi).reshape(-1), lam0.reshape(-1)
+    c_phi, c_m0 = g["cont"]
+    d_phi, d_m0 = g["disc"]
+    say(f"continuous {dtype} n_sub {n_sub}: {len(g['hs'])} steps; vs oracle dJ/dphi {rel_l2(c_phi, o_phi):.2e} "
+        f"dJ/dm0 {rel_l2(c_m0, o_m0):.2e}; vs discrete {rel_l2(c_phi, d_phi):.2e}")
+    assert rel_l2(c_phi, o_phi) <= bound
+    assert rel_l2(c_m0, o_m0) <= bound
+    # a different discretisation of the same gradient: close to the discrete adjoint, not equal to it
+    assert rel_l2(c_phi, d_phi) <= 1e-2
+    if dtype == "f64":
+        assert rel_l2(c_phi, d_phi) >= 1e-12
+    # the discrete adjoint of the same run is unchanged by the continuous one in between
+    np.testing.assert_array_equal(g["disc2"][0], d_phi)
+    np.testing.assert_array_equal(g["disc2"][1], d_m0)
+
+
+def test_stiff_adaptive_run_needs_two_sub_steps():
+    """Permalloy particle, 12x10 nodes of 2 nm, FP64: on the adaptive run's
+    steps one RK4 step per interval diverges (as in the oracle) and two
+    sub-steps match the oracle and stay close to the discrete adjoint."""
+    import torch
+    from paper_2411_19109_amd import llg
+    w = wl.permalloy_particle(nx=12, ny=10, n_steps=400)
+    p = w.problem
+    s = llg.Solver(p, dtype="f64", max_steps=2000, design=w.design)
+    ph = to_dev(w.phi, "f64")
+    psi = s.levelset_to_psi(ph, w.heaviside_a, to_dev(w.psi_fixed, "f64"))
+    mT, hs, _ = s.forward_adaptive(psi, to_dev(w.m0, "f64"), w.n_steps * p.dt, p.dt, 1e-5, 1e-5)
+    obj = llg.make_objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area)
+    _, dJdm, dJdpsi_e, _ = s.objective(obj, psi, mT)
+    res = {}
+    for key, cont, ns in (("disc", False, 1), ("c1", True, 1), ("c2", True, 2)):
+        dpsi, dm0 = s.adjoint_adaptive(psi, dJdm_T=dJdm, dJdpsi_expl=dJdpsi_e, want_dm0=True, continuous=cont,
+                                       n_sub=ns)
+        res[key] = (to_np(dpsi), to_np(dm0))
+    torch.cuda.synchronize()
+    s.close()
+    sim = omm.Sim(p)
+    psi_o = ols.levelset_to_psi(w.phi, w.heaviside_a, w.design, w.psi_fixed)
+    obj_o = oadj.Objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area)
+    gpsi, lam0 = oracle_continuous(sim, w.m0, psi_o, obj_o, np.asarray(hs), 2)
+    d1 = rel_l2(res["c1"][0], res["disc"][0])
+    say(f"stiff particle: {len(hs)} steps; n_sub 1 vs discrete {d1:.2e}; n_sub 2 vs oracle "
+        f"{rel_l2(res['c2'][0], gpsi.reshape(-1)):.2e}, vs discrete {rel_l2(res['c2'][0], res['disc'][0]):.2e}")
+    assert not np.isfinite(d1) or d1 > 1e3
+    assert rel_l2(res["c2"][0], gpsi.reshape(-1)) <= 1e-9
+    assert rel_l2(res["c2"][1], lam0.reshape(-1)) <= 1e-9
+    assert rel_l2(res["c2"][0], res["disc"][0]) <= 1e-4
+
+
+def test_continuous_adjoint_call_checks():
+    import torch
+    from paper_2411_19109_amd import llg
+    p, ant, phi, design, psif, m0 = case()
+    s = llg.Solver(p, dtype="f64", max_steps=400, antenna=ant, design=design)
+    psi = to_dev(np.ones(p.n), "f64")
+    with pytest.raises(llg.LLGError):
+        s.adjoint_adaptive(psi, continuous=True)   # no adaptive run yet
+    s.forward_adaptive(psi, to_dev(m0, "f64"), 1e-12, 1e-13, 1e-6, 1e-6)
+    for bad in (0, -1, 65):
+        with pytest.raises(llg.LLGError):
+            s.adjoint_adaptive(psi, continuous=True, n_sub=bad)
+    torch.cuda.synchronize()
+    s.close()

@@ -500,7 +500,14 @@ def run_adaptive(args):
     t_end = w.n_steps * w.problem.dt
     tol = 1e-5
     s = llg.Solver(w.problem, dtype="f32", max_steps=4 * w.n_steps, design=w.design)
-    launch = s.autotune()
+    if args.launch_file and os.path.exists(args.launch_file):
+        s.set_launch_config(*[int(v) for v in open(args.launch_file).read().split()])
+        launch = s.launch_config()
+    else:
+        launch = s.autotune()
+        if args.launch_file:
+            with open(args.launch_file, "w") as fh:
+                fh.write(" ".join(str(v) for v in launch) + "\n")
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=torch.float32, device=dev)
     phi, psif, m0 = t(w.phi), t(w.psi_fixed), t(w.m0)
     obj = llg.make_objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area)

@@ -920,9 +920,12 @@ struct Ops {
     }
 
     // Trial step from m: y5 and the error norm (device double at D.err[0]).
-    int dp_trial(const T* m, double t, double hstep, double rtol, double atol) {
+    // The last stage's state equals y5 (its coefficients are the fifth-order weights, summed in the same order
+    // from the same base), and its time is t + h: y5 is formed once and the rate there, k[6], is the next
+    // step's k[0] (first same as last).  With have_k0, k[0] already holds f(m, t) and is not recomputed.
+    int dp_trial(const T* m, double t, double hstep, double rtol, double atol, bool have_k0) {
         auto& D = h->dp;
-        for (int st = 0; st < 7; ++st)
+        for (int st = have_k0 ? 1 : 0; st < 6; ++st)
             if (int rc = dp_stage(st, m, t, hstep, P(D.ystage), nullptr)) return rc;
         LinTerms<T> b5{}, e{};
         for (int j = 0; j < 7; ++j) {
@@ -937,6 +940,7 @@ struct Ops {
         }
         if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), P(D.y5), m, b5, s); }))
             return rc;
+        if (int rc = field(D.y5, t + kC[6] * hstep, nullptr, D.k[6])) return rc;
         return run(-1, 0, [&](hipEvent_t, hipEvent_t) {
             return launch_err_norm<T>((int)n3(), m, P(D.y5), e, rtol, atol, D.err + 8, D.err, s);
         });
@@ -2046,7 +2050,7 @@ int forward_adaptive(llg_handle* h, double t0, double t_end, double h0, double r
     auto& D = h->dp;
     const size_t n3 = (size_t)3 * h->inst[0].N;
     double t = t0, hstep = h0;
-    bool ok_last = true;
+    bool ok_last = true, have_k0 = false;
     int64_t rejected = 0;
     T* snaps = static_cast<T*>(D.snaps);
     while (t < t_end) {
@@ -2054,7 +2058,8 @@ int forward_adaptive(llg_handle* h, double t0, double t_end, double h0, double r
             return fail(LLG_ENOMEM, "adaptive run needs more accepted steps than max_steps");
         hstep = std::min(hstep, t_end - t);
         const T* m = snaps + D.hs.size() * n3;
-        if (int rc = o.dp_trial(m, t, hstep, rtol, atol)) return rc;
+        if (int rc = o.dp_trial(m, t, hstep, rtol, atol, have_k0)) return rc;
+        have_k0 = true;  // a rejection keeps (m, t); an acceptance moves k[6] = f(y5, t + h) into k[0]
         double err = 0.0;
         HIPCHK(hipMemcpyAsync(&err, D.err, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -2065,6 +2070,7 @@ int forward_adaptive(llg_handle* h, double t0, double t_end, double h0, double r
             D.ts.push_back(t);
             D.hs.push_back(hstep);
             t = t_end - t > hstep ? t + hstep : t_end;
+            std::swap(D.k[0], D.k[6]);
             if (!ok_last) f = std::min(f, 1.0);
             hstep *= f;
             ok_last = true;

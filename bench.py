@@ -492,7 +492,9 @@ def run_adaptive(args):
     """The particle gradient with adaptive Dormand-Prince steps over the same
     physical time as the fixed-step run (2000 x 50 fs = 100 ps), FP32, error
     tolerance 1e-5: adaptive forward, energy objective, adjoint of the
-    accepted steps, chain to dJ/dphi."""
+    accepted steps, chain to dJ/dphi.  The forward keeps every accepted
+    step's stages for the adjoint (a 4.3 GB store); the recomputing mode is
+    timed beside it."""
     import torch
     from paper_2411_19109_amd import llg, workloads as wl
     w = wl.permalloy_particle()
@@ -508,6 +510,7 @@ def run_adaptive(args):
         if args.launch_file:
             with open(args.launch_file, "w") as fh:
                 fh.write(" ".join(str(v) for v in launch) + "\n")
+    s.set_keep_stages(True)
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=torch.float32, device=dev)
     phi, psif, m0 = t(w.phi), t(w.psi_fixed), t(w.m0)
     obj = llg.make_objective(w.objective, E_ref=wl.energy_reference(w), lam=w.obj_lambda, area=w.obj_area)
@@ -552,6 +555,20 @@ def run_adaptive(args):
                "continuous_vs_discrete_rel_l2": gap}
     print(f"[bench] adaptive backward pass: discrete {compare['discrete_adjoint_ms']} ms, continuous "
           f"{compare['continuous_adjoint_ms']} ms, dJ/dphi gap {gap:.2e}", file=sys.stderr, flush=True)
+    # the same gradient without the stage store: the adjoint recomputes each step's stages (bitwise the same)
+    s.set_keep_stages(False)
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps)):
+        _, gr, _, _ = step()
+    torch.cuda.synchronize()
+    compare["recomputed_stages_ms_per_gradient"] = round((time.perf_counter() - t0) / max(1, args.steps) * 1e3, 2)
+    compare["recomputed_stages_bitwise_equal"] = bool(torch.equal(gr, g))
+    s.set_keep_stages(True)
+    print(f"[bench] adaptive gradient recomputing the stages: {compare['recomputed_stages_ms_per_gradient']} ms "
+          f"(kept stages: {sec * 1e3:.1f} ms), bitwise equal: {compare['recomputed_stages_bitwise_equal']}",
+          file=sys.stderr, flush=True)
     roofline, kinds = None, {}
     if not args.no_kernel_events:
         s.profile(True)
@@ -583,7 +600,8 @@ def run_adaptive(args):
         "data": "synthetic",
         "config": {"workload": "permalloy_particle_64x64_adaptive_grad", "nodes": [w.problem.nx, w.problem.ny, 1],
                    "t_end_s": t_end, "rtol": tol, "atol": tol, "accepted_steps": n_acc, "rejected_steps": nrej,
-                   "fixed_step_equivalent": w.n_steps, "launch": list(launch), "objective_J": float(J.item())},
+                   "fixed_step_equivalent": w.n_steps, "launch": list(launch), "objective_J": float(J.item()),
+                   "kept_stages": True, "stage_store_bytes": 11 * (4 * w.n_steps + 1) * 3 * w.problem.n * 4},
         "roofline": roofline,
         "kernels": {k: dict(avg_us=round(v["avg_us"], 2), gbs=round(v["gbs"], 1)) for k, v in kinds.items()},
         "adjoint_compare": compare,

@@ -245,12 +245,23 @@ int llg_forward_adaptive(llg_handle* h, const void* psi, const void* m0, double 
                          double rtol, double atol, void* m_out, int64_t* n_accepted, int64_t* n_rejected,
                          hipStream_t stream);
 
+/* With keep != 0, later llg_forward_adaptive runs also keep every accepted
+ * step's stage states and fields (11 state vectors of 3N per step, a device
+ * store of (max_steps + 1) x 11 x 3N elements, allocated by the first such
+ * run), and llg_adjoint_adaptive reads them instead of recomputing six field
+ * evaluations per step.  The results are bitwise the same either way.  With
+ * keep == 0 (the default) runs keep only the accepted states; an allocated
+ * store stays until llg_destroy.  Single-instance handles.
+ * Errors: LLG_EINVAL (NULL handle or a batch); LLG_ENOMEM at the next run. */
+int llg_set_keep_stages(llg_handle* h, int keep);
+
 /* Accepted step sizes of the last llg_forward_adaptive (host array of cap >= n_accepted). */
 int llg_adaptive_steps(const llg_handle* h, double* hs_out, int64_t cap);
 
 /* Discrete adjoint of the last adaptive run with its step sizes fixed: from
  * lambda_N = dJdm_T (3N; NULL = 0), per step kappa_s = h (b_s lambda' + sum_{i>s}
- * a_is mu_i), mu_s = J_f(Y_s)^T kappa_s (stages recomputed from the kept state),
+ * a_is mu_i), mu_s = J_f(Y_s)^T kappa_s (stages recomputed from the kept state,
+ * or read from the stage store, see llg_set_keep_stages),
  * lambda = lambda' + sum_s mu_s; dJ/dpsi accumulates kappa_s . df/dpsi(Y_s) and
  * dJdpsi_expl (nullable).  Writes dJ/dpsi (N, float64) and, if not NULL, dJ/dm0
  * (3N).  A terminal objective is evaluated with llg_objective on m(t_end).

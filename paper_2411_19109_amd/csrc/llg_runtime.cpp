@@ -142,6 +142,11 @@ struct llg_handle {
         double* err = nullptr;   // [0] norm, [8..] block maxima
         std::vector<double> hs, ts;
         bool valid = false;
+        // optional store of every accepted step's stages, 11 state vectors per step n:
+        // B_0, then (Y_s, B_s) for s = 1..5 (Y_0 is the kept state); max_steps + 1 steps
+        void* stages = nullptr;
+        bool keep = false;         // the next adaptive run fills the store
+        bool stages_valid = false;  // the last adaptive run filled it
     } dp;
     std::vector<double> curve_host;
     // forward record
@@ -920,13 +925,22 @@ struct Ops {
     }
 
     // Trial step from m: y5 and the error norm (device double at D.err[0]).
+    // Stage store of step n: the field of stage s (s = 0..5) and the state of stage s (s = 1..5).
+    T* kept_B(int64_t n, int st) const { return P(h->dp.stages) + ((size_t)n * 11 + (st ? 2 * st : 0)) * n3(); }
+    T* kept_Y(int64_t n, int st) const { return P(h->dp.stages) + ((size_t)n * 11 + 2 * st - 1) * n3(); }
+
     // The last stage's state equals y5 (its coefficients are the fifth-order weights, summed in the same order
     // from the same base), and its time is t + h: y5 is formed once and the rate there, k[6], is the next
     // step's k[0] (first same as last).  With have_k0, k[0] already holds f(m, t) and is not recomputed.
-    int dp_trial(const T* m, double t, double hstep, double rtol, double atol, bool have_k0) {
+    // With the stage store, trial step n writes its stage states and fields into slot n (a rejected trial's
+    // are overwritten by the next) and the field at y5 into slot n + 1 as that step's stage-0 field.
+    int dp_trial(int64_t n, const T* m, double t, double hstep, double rtol, double atol, bool have_k0) {
         auto& D = h->dp;
-        for (int st = have_k0 ? 1 : 0; st < 6; ++st)
-            if (int rc = dp_stage(st, m, t, hstep, P(D.ystage), nullptr)) return rc;
+        const bool keep = D.keep;
+        for (int st = have_k0 ? 1 : 0; st < 6; ++st) {
+            T* Y = keep && st > 0 ? kept_Y(n, st) : P(D.ystage);
+            if (int rc = dp_stage(st, m, t, hstep, Y, keep ? kept_B(n, st) : nullptr)) return rc;
+        }
         LinTerms<T> b5{}, e{};
         for (int j = 0; j < 7; ++j) {
             if (kB5[j] != 0.0) {
@@ -940,7 +954,7 @@ struct Ops {
         }
         if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), P(D.y5), m, b5, s); }))
             return rc;
-        if (int rc = field(D.y5, t + kC[6] * hstep, nullptr, D.k[6])) return rc;
+        if (int rc = field(D.y5, t + kC[6] * hstep, keep ? kept_B(n + 1, 0) : nullptr, D.k[6])) return rc;
         return run(-1, 0, [&](hipEvent_t, hipEvent_t) {
             return launch_err_norm<T>((int)n3(), m, P(D.y5), e, rtol, atol, D.err + 8, D.err, s);
         });
@@ -1074,9 +1088,19 @@ struct Ops {
         for (int64_t n = (int64_t)D.hs.size() - 1; n >= 0; --n) {
             const double hstep = D.hs[n], t = D.ts[n];
             const T* m = P(D.snaps) + (size_t)n * n3();
-            // recompute the stages this step's transpose needs (the 7th has b = 0 and feeds no stage)
-            for (int st = 0; st < 6; ++st)
-                if (int rc = dp_stage(st, m, t, hstep, slot(B_YS, st), slot(B_BS, st))) return rc;
+            // the stages this step's transpose needs (the 7th has b = 0 and feeds no stage): from the stage
+            // store when the forward filled it, else recomputed from the kept state (bitwise the same values)
+            if (D.stages_valid) {
+                const size_t nb = n3() * sizeof(T);
+                HIPCHK(hipMemcpyAsync(slot(B_YS, 0), m, nb, hipMemcpyDeviceToDevice, s));
+                for (int st = 0; st < 6; ++st) {
+                    if (st) HIPCHK(hipMemcpyAsync(slot(B_YS, st), kept_Y(n, st), nb, hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(slot(B_BS, st), kept_B(n, st), nb, hipMemcpyDeviceToDevice, s));
+                }
+            } else {
+                for (int st = 0; st < 6; ++st)
+                    if (int rc = dp_stage(st, m, t, hstep, slot(B_YS, st), slot(B_BS, st))) return rc;
+            }
             for (int st = 5; st >= 0; --st) {
                 // kappa_s = h (b_s lambda' + sum_{i>s} a_is mu_i) into the role buffer L0
                 LinTerms<T> lt{};
@@ -2028,6 +2052,10 @@ namespace {
 // Buffers of the adaptive integrator (first use; sized for max_steps accepted steps).
 int ensure_dopri(llg_handle* h) {
     auto& D = h->dp;
+    if (D.keep && !D.stages) {
+        const size_t nb = (size_t)3 * h->inst[0].N * h->tsz;
+        if (int rc = alloc(h, &D.stages, nb * 11 * (size_t)(h->max_steps + 1))) return rc;
+    }
     if (D.snaps) return LLG_OK;
     const size_t nb = (size_t)3 * h->inst[0].N * h->tsz;
     int rc;
@@ -2058,7 +2086,7 @@ int forward_adaptive(llg_handle* h, double t0, double t_end, double h0, double r
             return fail(LLG_ENOMEM, "adaptive run needs more accepted steps than max_steps");
         hstep = std::min(hstep, t_end - t);
         const T* m = snaps + D.hs.size() * n3;
-        if (int rc = o.dp_trial(m, t, hstep, rtol, atol, have_k0)) return rc;
+        if (int rc = o.dp_trial((int64_t)D.hs.size(), m, t, hstep, rtol, atol, have_k0)) return rc;
         have_k0 = true;  // a rejection keeps (m, t); an acceptance moves k[6] = f(y5, t + h) into k[0]
         double err = 0.0;
         HIPCHK(hipMemcpyAsync(&err, D.err, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -2103,6 +2131,7 @@ int llg_forward_adaptive(llg_handle* h, const void* psi, const void* m0, double 
     if ((rc = ensure_dopri(h))) return rc;
     auto& D = h->dp;
     D.valid = false;
+    D.stages_valid = false;
     D.hs.clear();
     D.ts.clear();
     h->fwd_valid = false;
@@ -2117,6 +2146,14 @@ int llg_forward_adaptive(llg_handle* h, const void* psi, const void* m0, double 
                               hipMemcpyDeviceToDevice, stream));
     if (n_accepted) *n_accepted = (int64_t)D.hs.size();
     D.valid = true;
+    D.stages_valid = D.keep;
+    return LLG_OK;
+}
+
+int llg_set_keep_stages(llg_handle* h, int keep) {
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
+    h->dp.keep = keep != 0;
     return LLG_OK;
 }
 

@@ -29,7 +29,8 @@ EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_le
            "llg_batch_destroy", "llg_batch_size", "llg_batch_levelset_to_Ms", "llg_batch_levelset_to_Ms_vjp",
            "llg_batch_forward", "llg_batch_adjoint", "llg_rbf_work_len", "llg_rbf_levelset", "llg_rbf_levelset_vjp",
            "llg_adam_step", "llg_rbf_profile", "llg_rbf_profile_read", "llg_shape_penalty", "llg_forward_adaptive",
-           "llg_adaptive_steps", "llg_adjoint_adaptive", "llg_adjoint_continuous"]
+           "llg_adaptive_steps", "llg_adjoint_adaptive", "llg_adjoint_continuous",
+           "llg_set_keep_stages"]
 RBF_KIND_NAMES = {0: "k_rbf_cones", 1: "k_rbf_pnorm", 2: "k_rbf_vjp"}
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
 KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col_conv", KIND_STAGE_BWD: "k_stage_bwd"}
@@ -120,6 +121,7 @@ def lib():
         "llg_adaptive_steps": [vp, ctypes.POINTER(dbl), i64],
         "llg_adjoint_adaptive": [vp, vp, vp, vp, vp, vp, vp],
         "llg_adjoint_continuous": [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp],
+        "llg_set_keep_stages": [vp, ctypes.c_int],
         "llg_rbf_profile_read": [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
     }
     for name, args in sig.items():
@@ -336,6 +338,11 @@ class Solver:
         hs = np.zeros(max(1, na.value))
         check(lib().llg_adaptive_steps(self.h, hs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), hs.size))
         return m_out, hs[:na.value], nr.value
+
+    def set_keep_stages(self, keep: bool):
+        """Adaptive runs keep every accepted step's stages for the adjoint
+        (more device memory, no recomputation, bitwise-equal results)."""
+        check(lib().llg_set_keep_stages(self.h, int(keep)))
 
     def adjoint_adaptive(self, psi, dJdm_T=None, dJdpsi_expl=None, want_dm0=False, continuous=False, n_sub=1):
         """Adjoint of the last adaptive run: discrete (exact for the accepted

@@ -1,7 +1,8 @@
 """Adaptive Dormand-Prince integration and the adjoint of its accepted steps
 through the C ABI: the accepted step sequence, m(t_end), J and dJ/dphi against
 the oracle's adaptive run (FP64 1e-10 / 1e-9), FP32 against the oracle replay
-of the GPU's own steps, rejected trials, and call-order checks."""
+of the GPU's own steps, rejected trials, call-order checks, and bitwise-equal
+results with the optional stage store."""
 import numpy as np
 import pytest
 
@@ -106,3 +107,37 @@ def test_adaptive_call_checks():
     torch.cuda.synchronize()
     small.close()
     s.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-7), ("f32", 1e-4)])
+def test_kept_stages_give_bitwise_the_same_gradient(dtype, tol):
+    """With the stage store the adjoint reads the forward's stage states and
+    fields instead of recomputing them: the same accepted steps, m(t_end),
+    dJ/dpsi and dJ/dm0, bit for bit (runs with rejected trials included); the
+    store stays valid for the run that filled it."""
+    import torch
+    from paper_2411_19109_amd import llg
+    p, ant, phi, design, psif, m0 = case()
+    out = {}
+    for keep in (False, True):
+        s = llg.Solver(p, dtype=dtype, max_steps=400, antenna=ant, design=design)
+        s.set_keep_stages(keep)
+        ph = to_dev(phi, dtype)
+        psi = s.levelset_to_psi(ph, 3.0, to_dev(psif, dtype))
+        # an oversized first step (1 ps) is rejected, so rejected trials write into the store too
+        mT, hs, nrej = s.forward_adaptive(psi, to_dev(m0, dtype), 3e-12, 1e-12, tol, tol)
+        obj = llg.make_objective(wl.OBJ_ENERGY_AREA, E_ref=1e-18, lam=0.7, area=0.4)
+        _, dJdm, dJdpsi_e, _ = s.objective(obj, psi, mT)
+        dpsi, dm0 = s.adjoint_adaptive(psi, dJdm_T=dJdm, dJdpsi_expl=dJdpsi_e, want_dm0=True)
+        if keep:
+            s.set_keep_stages(False)   # the store of the last run is still read
+            dpsi2, dm02 = s.adjoint_adaptive(psi, dJdm_T=dJdm, dJdpsi_expl=dJdpsi_e, want_dm0=True)
+            np.testing.assert_array_equal(to_np(dpsi2), to_np(dpsi))
+            np.testing.assert_array_equal(to_np(dm02), to_np(dm0))
+        torch.cuda.synchronize()
+        out[keep] = (np.asarray(hs), nrej, to_np(mT), to_np(dpsi), to_np(dm0))
+        s.close()
+    say(f"kept stages {dtype}: {len(out[True][0])} steps, {out[True][1]} rejected")
+    assert out[True][1] >= 1
+    for a, b in zip(out[False], out[True]):
+        np.testing.assert_array_equal(a, b)

@@ -131,6 +131,11 @@ struct BwdL {
     int seed_unit;        // seed stage: l = lambda' itself (a generic stage transpose) instead of dt/6 lambda'
     int do_inv, do_fwd;
     int stage_m;          // stage the y_s rows in LDS too (set by the launcher from the batch)
+    // single-instance transposes on states held elsewhere (nullptr: the role buffers above): the stage state
+    // (also y_prev when prev_j >= 0), its field, and the accumulator written without reading one (lacc unused)
+    void* ext_ys;
+    void* ext_B;
+    void* ext_lacc;
 };
 
 // Resolved per-instance arguments (built inside the kernels).

@@ -551,15 +551,17 @@ __device__ __forceinline__ StageBwdArgs<T> resolve_bwd(const KParams<T>& p, cons
     const int st = L.stage < 0 ? 0 : L.stage;
     a.stage = L.stage;
     a.psi = role<T>(tb, B_PSI);
-    a.ys = role<T>(tb, B_YS) + ((size_t)L.j * 4 + st) * n3;
-    a.Bs = role<T>(tb, B_BS) + ((size_t)L.j * 4 + st) * n3;
+    a.ys = L.ext_ys ? static_cast<const T*>(L.ext_ys) : role<T>(tb, B_YS) + ((size_t)L.j * 4 + st) * n3;
+    a.Bs = L.ext_B ? static_cast<const T*>(L.ext_B) : role<T>(tb, B_BS) + ((size_t)L.j * 4 + st) * n3;
     a.u_cur = role<T>(tb, L.ucur);
     a.ell = role<T>(tb, B_ELL);
     a.lamp = role<T>(tb, L.lamp);
-    a.lacc_in = role<T>(tb, L.lacc);
-    a.lacc_out = role<T>(tb, L.lacc);
+    a.lacc_in = L.ext_lacc ? nullptr : role<T>(tb, L.lacc);
+    a.lacc_out = L.ext_lacc ? static_cast<T*>(L.ext_lacc) : role<T>(tb, L.lacc);
     a.gpsi = role<double>(tb, B_GPSI);
-    a.y_prev = L.prev_j >= 0 ? role<T>(tb, B_YS) + ((size_t)L.prev_j * 4 + L.prev_st) * n3 : nullptr;
+    a.y_prev = L.prev_j < 0 ? nullptr
+               : L.ext_ys ? static_cast<const T*>(L.ext_ys)
+                          : role<T>(tb, B_YS) + ((size_t)L.prev_j * 4 + L.prev_st) * n3;
     a.u_next = role<T>(tb, L.unext);
     a.S = role<cplx<T>>(tb, B_S);
     const bool port = L.port_src && L.W > 0 && (L.port_lin == 2 || (p.n_p1 + p.n_p2) > 0);
@@ -817,7 +819,7 @@ __device__ __forceinline__ BwdIn<T> load_bwd(const StageBwdArgs<T>& a, int N, in
         d.v = ld3(a.ell, N, i);
         d.uk = ld3(a.u_cur, N, i);
         d.g0 = glb(a.gpsi)[i];
-        if (a.stage < 3) d.lacc = ld3(a.lacc_in, N, i);
+        if (a.stage < 3 && a.lacc_in) d.lacc = ld3(a.lacc_in, N, i);
         if (a.stage == 0 && a.port1) {
             d.p1 = glb(a.port1)[i];
             d.p2 = glb(a.port2)[i];

@@ -742,7 +742,7 @@ struct Ops {
         if (L.stage < 0) {
             b = n * 13 * t + h->sumSpec;
         } else {
-            b = n * (16 * t + 16) + (L.stage == 3 ? 0 : n * 3 * t);
+            b = n * (16 * t + 16) + (L.stage == 3 || L.ext_lacc ? 0 : n * 3 * t);
             if (L.prev_j >= 0) b += n * 9 * t;
             if (L.do_inv) b += h->sumSpec;
             if (L.do_fwd) b += h->sumSpec;
@@ -960,37 +960,38 @@ struct Ops {
         });
     }
 
-    // mu = J_f(Y)^T kappa for the state Y and field B(Y) in stage slot j of YS / BS and kappa in the role
-    // buffer L0: the field adjoint u and its spectrum (seed with a unit scale), the column pass, then the
-    // transpose (stage 0 without a next stage) into L1, copied to mu_out; dJ/dpsi gains kappa . df/dpsi(Y).
-    int stage_transpose(int j, void* mu_out) {
+    // mu = J_f(Y)^T kappa for the state Y with field Bf = B(Y) and kappa in the role buffer L0: the field
+    // adjoint u and its spectrum (seed with a unit scale), the column pass, then the transpose (stage 0 without
+    // a next stage), written to mu_out; dJ/dpsi gains kappa . df/dpsi(Y).  Y and Bf are read where they are.
+    int stage_transpose(const T* Y, const T* Bf, void* mu_out) {
         BwdL Ls{};
         Ls.stage = -2;
         Ls.seed_unit = 1;
-        Ls.j = Ls.prev_j = j;
+        Ls.j = Ls.prev_j = 0;
         Ls.prev_st = 0;
         Ls.ucur = -1;
         Ls.unext = B_U0;
         Ls.lamp = B_L0;
         Ls.lacc = -1;
         Ls.do_fwd = h->demag;
+        Ls.ext_ys = const_cast<T*>(Y);
         if (int rc = bwd(Ls)) return rc;
         if (int rc = col()) return rc;
-        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_fill<T>(B(), B_L1, 3, 0.0, s); })) return rc;
         BwdL Lf{};
         Lf.stage = 0;
-        Lf.j = j;
+        Lf.j = 0;
         Lf.prev_j = -1;
         Lf.prev_st = 3;
         Lf.ucur = B_U0;
         Lf.unext = B_U1;
         Lf.lamp = B_L0;
-        Lf.lacc = B_L1;
+        Lf.lacc = -1;
         Lf.do_inv = h->demag;
         Lf.do_fwd = 0;
-        if (int rc = bwd(Lf)) return rc;
-        HIPCHK(hipMemcpyAsync(mu_out, h->inst[0].tab.b[B_L1], n3() * sizeof(T), hipMemcpyDeviceToDevice, s));
-        return LLG_OK;
+        Lf.ext_ys = const_cast<T*>(Y);
+        Lf.ext_B = const_cast<T*>(Bf);
+        Lf.ext_lacc = mu_out;
+        return bwd(Lf);
     }
     int kappa(std::initializer_list<std::pair<double, const void*>> terms) {
         LinTerms<T> lt{};
@@ -1054,13 +1055,13 @@ struct Ops {
                 // kappa_s = w_s hsub A_s gives mu_s = w_s hsub G_s: A2 = a + 3 mu1, A3 = a + 1.5 mu2,
                 // A4 = a + 3 mu3, and a <- a + mu1 + mu2 + mu3 + mu4
                 if (int rc = kappa({{hsub / 6.0, D.lam}})) return rc;
-                if (int rc = stage_transpose(up, D.mu[0])) return rc;
+                if (int rc = stage_transpose(slot(B_YS, up), slot(B_BS, up), D.mu[0])) return rc;
                 if (int rc = kappa({{hsub / 3.0, D.lam}, {hsub, D.mu[0]}})) return rc;
-                if (int rc = stage_transpose(1, D.mu[1])) return rc;
+                if (int rc = stage_transpose(slot(B_YS, 1), slot(B_BS, 1), D.mu[1])) return rc;
                 if (int rc = kappa({{hsub / 3.0, D.lam}, {hsub / 2.0, D.mu[1]}})) return rc;
-                if (int rc = stage_transpose(1, D.mu[2])) return rc;
+                if (int rc = stage_transpose(slot(B_YS, 1), slot(B_BS, 1), D.mu[2])) return rc;
                 if (int rc = kappa({{hsub / 6.0, D.lam}, {hsub / 2.0, D.mu[2]}})) return rc;
-                if (int rc = stage_transpose(lo, D.mu[3])) return rc;
+                if (int rc = stage_transpose(slot(B_YS, lo), slot(B_BS, lo), D.mu[3])) return rc;
                 LinTerms<T> lt{};
                 for (int q = 0; q < 4; ++q) {
                     lt.src[q] = P(D.mu[q]);
@@ -1088,18 +1089,21 @@ struct Ops {
         for (int64_t n = (int64_t)D.hs.size() - 1; n >= 0; --n) {
             const double hstep = D.hs[n], t = D.ts[n];
             const T* m = P(D.snaps) + (size_t)n * n3();
-            // the stages this step's transpose needs (the 7th has b = 0 and feeds no stage): from the stage
+            // the stages this step's transpose needs (the 7th has b = 0 and feeds no stage): read in the stage
             // store when the forward filled it, else recomputed from the kept state (bitwise the same values)
+            const T* Ys[6];
+            const T* Bs[6];
             if (D.stages_valid) {
-                const size_t nb = n3() * sizeof(T);
-                HIPCHK(hipMemcpyAsync(slot(B_YS, 0), m, nb, hipMemcpyDeviceToDevice, s));
                 for (int st = 0; st < 6; ++st) {
-                    if (st) HIPCHK(hipMemcpyAsync(slot(B_YS, st), kept_Y(n, st), nb, hipMemcpyDeviceToDevice, s));
-                    HIPCHK(hipMemcpyAsync(slot(B_BS, st), kept_B(n, st), nb, hipMemcpyDeviceToDevice, s));
+                    Ys[st] = st ? kept_Y(n, st) : m;
+                    Bs[st] = kept_B(n, st);
                 }
             } else {
-                for (int st = 0; st < 6; ++st)
+                for (int st = 0; st < 6; ++st) {
                     if (int rc = dp_stage(st, m, t, hstep, slot(B_YS, st), slot(B_BS, st))) return rc;
+                    Ys[st] = slot(B_YS, st);
+                    Bs[st] = slot(B_BS, st);
+                }
             }
             for (int st = 5; st >= 0; --st) {
                 // kappa_s = h (b_s lambda' + sum_{i>s} a_is mu_i) into the role buffer L0
@@ -1114,7 +1118,7 @@ struct Ops {
                 T* kap = static_cast<T*>(h->inst[0].tab.b[B_L0]);
                 if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), kap, nullptr, lt, s); }))
                     return rc;
-                if (int rc = stage_transpose(st, D.mu[st])) return rc;
+                if (int rc = stage_transpose(Ys[st], Bs[st], D.mu[st])) return rc;
             }
             // lambda_n = lambda' + sum_s mu_s
             LinTerms<T> lt{};

@@ -116,6 +116,15 @@ struct FwdL {
     void* ext_ys;         // single-instance overrides (field evaluation)
     void* ext_ynext;
     void* ext_B;
+    // single-instance stage sum of a field evaluation (stage -1): the launch also forms
+    // Y' = lin_base + sum_j lin_c[j] lin_src[j] + lin_cf f, f the rate it computes (added last, each term one
+    // fused multiply-add in this order), stores Y' at lin_out and, with do_fwd, transforms psi * Y'
+    const void* lin_base;
+    const void* lin_src[6];
+    double lin_c[6];
+    double lin_cf;
+    int lin_nt;
+    void* lin_out;
 };
 
 // One backward-stage launch.

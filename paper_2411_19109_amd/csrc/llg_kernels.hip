@@ -586,7 +586,7 @@ __device__ __forceinline__ StageBwdArgs<T> resolve_bwd(const KParams<T>& p, cons
 // forward local kernel: inverse x-FFT (demag) + local field + LL RHS + RK4
 // stage update + forward x-FFT of the next stage's magnetisation
 // ---------------------------------------------------------------------------
-template <typename T, int MR, bool SR>
+template <typename T, int MR, bool SR, bool LIN = false>
 __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const FwdL L) {
     using C = cplx<T>;
     constexpr int NV = 4;  // m_x, m_y, m_z, psi
@@ -719,6 +719,21 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
                 yn = accv + (dt / (T)6) * f;
             }
             if (a.ynext) st3(a.ynext, N, i, yn);
+            if constexpr (LIN) {
+                // next stage state of an embedded Runge-Kutta step: the same fused multiply-adds, in the same
+                // order, as the stage-sum kernel, so that both give the same bits
+                const auto g = [&](const void* q) { return ld3(static_cast<const T*>(q), N, i); };
+                V3<T> y = g(L.lin_base);
+                for (int j = 0; j < L.lin_nt; ++j) {
+                    const V3<T> sj = g(L.lin_src[j]);
+                    const T c = (T)L.lin_c[j];
+                    y = v3<T>(fma(c, sj.x, y.x), fma(c, sj.y, y.y), fma(c, sj.z, y.z));
+                }
+                const T cf = (T)L.lin_cf;
+                y = v3<T>(fma(cf, yn.x, y.x), fma(cf, yn.y, y.y), fma(cf, yn.z, y.z));
+                st3(static_cast<T*>(L.lin_out), N, i, y);
+                yn = y;  // the transform below takes psi * Y'
+            }
             if (a.port_part) {
                 if (a.port_lin == 2) {
                     s1 += (double)pi * (double)yn.x;  // curve objective: psi m_x over every node
@@ -1496,7 +1511,7 @@ __global__ __launch_bounds__(256) void k_lincomb(int n, T* __restrict__ out, con
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
     T v = base ? base[e] : (T)0;
-    for (int j = 0; j < lt.nt; ++j) v += (T)lt.c[j] * lt.src[j][e];
+    for (int j = 0; j < lt.nt; ++j) v = fma((T)lt.c[j], lt.src[j][e], v);
     out[e] = v;
 }
 
@@ -1756,6 +1771,15 @@ static BatchArgs<T> bargs(const BatchDev<T>& b, const int2* work) {
 // the one the batch's launch configuration names.
 template <typename T, int MR>
 static void stage_fwd_r(const BatchDev<T>& b, const FwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (L.lin_out) {
+        if (b.fwd_rows)
+            hipExtLaunchKernelGGL((k_stage_fwd<T, MR, true, true>), dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.fwd_lds,
+                                  s, e0, e1, 0, bargs(b, b.work_loc), L);
+        else
+            hipExtLaunchKernelGGL((k_stage_fwd<T, MR, false, true>), dim3(b.nloc), dim3(b.loc_threads),
+                                  (uint32_t)b.fwd_lds, s, e0, e1, 0, bargs(b, b.work_loc), L);
+        return;
+    }
     if (b.fwd_rows)
         hipExtLaunchKernelGGL((k_stage_fwd<T, MR, true>), dim3(b.nloc), dim3(b.loc_threads), (uint32_t)b.fwd_lds, s, e0,
                               e1, 0, bargs(b, b.work_loc), L);
@@ -1981,6 +2005,12 @@ hipError_t set_lds_limits(size_t bytes) {
     LLG_ATTR((k_stage_fwd<T, 4, false>))
     LLG_ATTR((k_stage_fwd<T, 8, false>))
     LLG_ATTR((k_stage_fwd<T, RT, false>))
+    LLG_ATTR((k_stage_fwd<T, 4, true, true>))
+    LLG_ATTR((k_stage_fwd<T, 8, true, true>))
+    LLG_ATTR((k_stage_fwd<T, RT, true, true>))
+    LLG_ATTR((k_stage_fwd<T, 4, false, true>))
+    LLG_ATTR((k_stage_fwd<T, 8, false, true>))
+    LLG_ATTR((k_stage_fwd<T, RT, false, true>))
     LLG_ATTR((k_stage_bwd<T, 4>))
     LLG_ATTR((k_stage_bwd<T, 8>))
     LLG_ATTR((k_stage_bwd<T, RT>))

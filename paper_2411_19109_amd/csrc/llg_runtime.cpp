@@ -136,6 +136,7 @@ struct llg_handle {
         void* k[7] = {};
         void* y5 = nullptr;
         void* ystage = nullptr;
+        void* ystage2 = nullptr;  // stage states alternate between the two while one is read
         void* snaps = nullptr;   // (max_steps + 1) states
         void* mu[6] = {};
         void* lam = nullptr;
@@ -929,32 +930,69 @@ struct Ops {
     T* kept_B(int64_t n, int st) const { return P(h->dp.stages) + ((size_t)n * 11 + (st ? 2 * st : 0)) * n3(); }
     T* kept_Y(int64_t n, int st) const { return P(h->dp.stages) + ((size_t)n * 11 + 2 * st - 1) * n3(); }
 
-    // The last stage's state equals y5 (its coefficients are the fifth-order weights, summed in the same order
-    // from the same base), and its time is t + h: y5 is formed once and the rate there, k[6], is the next
-    // step's k[0] (first same as last).  With have_k0, k[0] already holds f(m, t) and is not recomputed.
-    // With the stage store, trial step n writes its stage states and fields into slot n (a rejected trial's
-    // are overwritten by the next) and the field at y5 into slot n + 1 as that step's stage-0 field.
+    // One trial step.  Stage s's field evaluation also forms stage s + 1's state (the stage-sum variant of the
+    // forward kernel: the rate it computes enters last, after the earlier rates, in the order and with the fused
+    // multiply-adds of the stage-sum kernel) and transforms it for the next column pass, so that a stage costs
+    // two launches.  The last stage's state is y5 itself (its coefficients are the fifth-order weights) and its
+    // time is t + h: the rate there, k[6], is the next step's k[0] (first same as last).  With have_k0, k[0]
+    // already holds f(m, t).  With the stage store, trial step n writes its stage states and fields into slot n
+    // (a rejected trial's are overwritten by the next) and the field at y5 into slot n + 1 as that step's
+    // stage-0 field.
     int dp_trial(int64_t n, const T* m, double t, double hstep, double rtol, double atol, bool have_k0) {
         auto& D = h->dp;
         const bool keep = D.keep;
-        for (int st = have_k0 ? 1 : 0; st < 6; ++st) {
-            T* Y = keep && st > 0 ? kept_Y(n, st) : P(D.ystage);
-            if (int rc = dp_stage(st, m, t, hstep, Y, keep ? kept_B(n, st) : nullptr)) return rc;
+        if (!have_k0)
+            if (int rc = dp_stage(0, m, t, hstep, P(D.ystage), keep ? kept_B(n, 0) : nullptr)) return rc;
+        T* Y = keep ? kept_Y(n, 1) : P(D.ystage);
+        {
+            LinTerms<T> lt{};
+            lt.src[0] = P(D.k[0]);
+            lt.c[0] = hstep * kA[1][0];
+            lt.nt = 1;
+            if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), Y, m, lt, s); }))
+                return rc;
         }
-        LinTerms<T> b5{}, e{};
+        if (int rc = prologue(Y)) return rc;
+        for (int st = 1; st < 6; ++st) {
+            T* Yn = st == 5 ? P(D.y5) : keep ? kept_Y(n, st + 1) : (Y == P(D.ystage) ? P(D.ystage2) : P(D.ystage));
+            if (int rc = col()) return rc;
+            FwdL L = fwd_launch(-1);
+            L.t = t + kC[st] * hstep;
+            L.ys = B_M;
+            L.ext_ys = Y;
+            L.ext_ynext = D.k[st];
+            L.ext_B = keep ? kept_B(n, st) : nullptr;
+            L.do_inv = h->demag;
+            L.do_fwd = h->demag;
+            L.lin_base = m;
+            for (int j = 0; j < st; ++j)
+                if (kA[st + 1][j] != 0.0) {
+                    L.lin_src[L.lin_nt] = D.k[j];
+                    L.lin_c[L.lin_nt++] = hstep * kA[st + 1][j];
+                }
+            L.lin_cf = hstep * kA[st + 1][st];
+            L.lin_out = Yn;
+            if (int rc = fwd(L)) return rc;
+            Y = Yn;
+        }
+        {
+            // the rate at y5 (its spectrum is in S)
+            if (int rc = col()) return rc;
+            FwdL L = fwd_launch(-1);
+            L.t = t + kC[6] * hstep;
+            L.ys = B_M;
+            L.ext_ys = D.y5;
+            L.ext_ynext = D.k[6];
+            L.ext_B = keep ? kept_B(n + 1, 0) : nullptr;
+            L.do_inv = h->demag;
+            if (int rc = fwd(L)) return rc;
+        }
+        LinTerms<T> e{};
         for (int j = 0; j < 7; ++j) {
-            if (kB5[j] != 0.0) {
-                b5.src[b5.nt] = P(D.k[j]);
-                b5.c[b5.nt] = hstep * kB5[j];
-                ++b5.nt;
-            }
             e.src[e.nt] = P(D.k[j]);
             e.c[e.nt] = hstep * (kB5[j] - kB4[j]);
             ++e.nt;
         }
-        if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), P(D.y5), m, b5, s); }))
-            return rc;
-        if (int rc = field(D.y5, t + kC[6] * hstep, keep ? kept_B(n + 1, 0) : nullptr, D.k[6])) return rc;
         return run(-1, 0, [&](hipEvent_t, hipEvent_t) {
             return launch_err_norm<T>((int)n3(), m, P(D.y5), e, rtol, atol, D.err + 8, D.err, s);
         });
@@ -2067,7 +2105,9 @@ int ensure_dopri(llg_handle* h) {
         if ((rc = alloc(h, &k, nb))) return rc;
     for (auto& m : D.mu)
         if ((rc = alloc(h, &m, nb))) return rc;
-    if ((rc = alloc(h, &D.y5, nb)) || (rc = alloc(h, &D.ystage, nb)) || (rc = alloc(h, &D.lam, nb))) return rc;
+    if ((rc = alloc(h, &D.y5, nb)) || (rc = alloc(h, &D.ystage, nb)) || (rc = alloc(h, &D.ystage2, nb)) ||
+        (rc = alloc(h, &D.lam, nb)))
+        return rc;
     if ((rc = alloc(h, &D.snaps, nb * (size_t)(h->max_steps + 1)))) return rc;
     void* e;
     if ((rc = alloc(h, &e, (8 + (3 * h->inst[0].N + 255) / 256) * sizeof(double)))) return rc;

@@ -16,10 +16,10 @@ from paper_2411_19109_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def case(nx=12, ny=9, seed=51):
+def case(nx=12, ny=9, seed=51, terms=wl.TERM_ALL):
     p = wl.Problem(nx=nx, ny=ny, nz=1, dx=3e-9, dy=3e-9, dz=4e-9, Ms=8e5, A=1.3e-11, K=5e4, ku=(0.6, 0.8, 0.0),
                    alpha0=0.2, alpha_max=0.2, B0=(0.05, 0.02, 0.1), b_rf=(0.0, 0.01, 0.0), f1=5e9,
-                   terms=wl.TERM_ALL, dt=5e-14)
+                   terms=terms, dt=5e-14)
     rng = np.random.default_rng(seed)
     sh = p.shape
     ant = np.zeros(sh, np.uint8)
@@ -32,10 +32,10 @@ def case(nx=12, ny=9, seed=51):
     return p, ant, phi, design, psif, m0
 
 
-def gpu_run(dtype, t_end, h0, tol, seed=51):
+def gpu_run(dtype, t_end, h0, tol, seed=51, terms=wl.TERM_ALL):
     import torch
     from paper_2411_19109_amd import llg
-    p, ant, phi, design, psif, m0 = case(seed=seed)
+    p, ant, phi, design, psif, m0 = case(seed=seed, terms=terms)
     s = llg.Solver(p, dtype=dtype, max_steps=400, antenna=ant, design=design)
     ph = to_dev(phi, dtype)
     psi = s.levelset_to_psi(ph, 3.0, to_dev(psif, dtype))
@@ -50,8 +50,8 @@ def gpu_run(dtype, t_end, h0, tol, seed=51):
     return out
 
 
-def oracle_replay(hs, seed=51):
-    p, ant, phi, design, psif, m0 = case(seed=seed)
+def oracle_replay(hs, seed=51, terms=wl.TERM_ALL):
+    p, ant, phi, design, psif, m0 = case(seed=seed, terms=terms)
     sim = omm.Sim(p, antenna=ant)
     psi = ols.levelset_to_psi(phi, 3.0, design, psif)
     obj = oadj.Objective(oadj.OBJ_ENERGY_AREA, E_ref=1e-18, lam=0.7, area=0.4)
@@ -91,6 +91,22 @@ def test_adaptive_fp32_matches_oracle_replay_of_its_steps():
     assert rel_l2(g["dphi"], o["dphi"]) <= 1e-3
 
 
+def test_adaptive_without_demag_matches_oracle_fp64():
+    """Exchange, Zeeman with drive and anisotropy only: the field evaluations
+    have no transforms, and each stage's state sum stands alone in the launch."""
+    terms = wl.TERM_EXCH | wl.TERM_ZEEMAN | wl.TERM_ANIS
+    g = gpu_run("f64", 3e-12, 2e-13, 1e-7, terms=terms)
+    o = oracle_replay(g["hs"], terms=terms)
+    _, hs_o, rej_o = odp.integrate_adaptive(o["sim"], o["m0"], o["psi"], 0.0, 3e-12, 2e-13, 1e-7, 1e-7)
+    say("adaptive f64 without demag:", len(g["hs"]), "steps,", g["nrej"], "rejected; dJ/dphi rel L2",
+        rel_l2(g["dphi"], o["dphi"]))
+    assert len(g["hs"]) == len(hs_o) and g["nrej"] == rej_o
+    assert np.allclose(g["hs"], hs_o, rtol=1e-6, atol=0)
+    assert rel_max(g["mT"], o["mT"]) <= 1e-10
+    assert rel_l2(g["dphi"], o["dphi"]) <= 1e-9
+    assert rel_l2(g["dm0"], o["dm0"]) <= 1e-9
+
+
 def test_adaptive_call_checks():
     import torch
     from paper_2411_19109_amd import llg
@@ -109,15 +125,16 @@ def test_adaptive_call_checks():
     s.close()
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-7), ("f32", 1e-4)])
-def test_kept_stages_give_bitwise_the_same_gradient(dtype, tol):
+@pytest.mark.parametrize("dtype,tol,terms", [("f64", 1e-7, wl.TERM_ALL), ("f32", 1e-4, wl.TERM_ALL),
+                                              ("f32", 1e-4, wl.TERM_EXCH | wl.TERM_ZEEMAN | wl.TERM_ANIS)])
+def test_kept_stages_give_bitwise_the_same_gradient(dtype, tol, terms):
     """With the stage store the adjoint reads the forward's stage states and
     fields instead of recomputing them: the same accepted steps, m(t_end),
     dJ/dpsi and dJ/dm0, bit for bit (runs with rejected trials included); the
     store stays valid for the run that filled it."""
     import torch
     from paper_2411_19109_amd import llg
-    p, ant, phi, design, psif, m0 = case()
+    p, ant, phi, design, psif, m0 = case(terms=terms)
     out = {}
     for keep in (False, True):
         s = llg.Solver(p, dtype=dtype, max_steps=400, antenna=ant, design=design)

@@ -173,3 +173,13 @@ def test_rbf_work_len_and_host_side_rejections():
 def test_shape_penalty_rejects_null_handle():
     L = llg.lib()
     assert L.llg_shape_penalty(None, None, 0.05, 30.0, 1.0, 0.0, 0.0, None, None, None) == llg.LLG_EINVAL
+
+
+def test_adaptive_entries_reject_null_handle():
+    """The stage-store switch and both adaptive adjoints check their handle
+    before touching the device."""
+    L = llg.lib()
+    assert L.llg_set_keep_stages(None, 1) == llg.LLG_EINVAL
+    assert "NULL" in L.llg_last_error().decode()
+    assert L.llg_adjoint_adaptive(None, None, None, None, None, None, None) == llg.LLG_EINVAL
+    assert L.llg_adjoint_continuous(None, None, None, None, 2, None, None, None) == llg.LLG_EINVAL

@@ -145,6 +145,11 @@ struct BwdL {
     void* ext_ys;
     void* ext_B;
     void* ext_lacc;
+    // seed stage of a single-instance transpose: l = sum_j lin_c[j] lin_src[j] (fused multiply-adds from zero,
+    // in this order) instead of lambda' from lamp
+    const void* lin_src[7];
+    double lin_c[7];
+    int lin_nt;
 };
 
 // Resolved per-instance arguments (built inside the kernels).

@@ -844,7 +844,7 @@ __device__ __forceinline__ BwdIn<T> load_bwd(const StageBwdArgs<T>& a, int N, in
     return d;
 }
 
-template <typename T, int MR>
+template <typename T, int MR, bool LIN = false>
 __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const BwdL L) {
     using C = cplx<T>;
     constexpr int NV = 7;  // u_x, u_y, u_z, psi, m_x, m_y, m_z (stage state y_s)
@@ -900,7 +900,16 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
             const T pi = d.pi;
             V3<T> un = v3<T>(0, 0, 0);
             if (seed) {
-                const V3<T> ell = a.seed_unit ? d.lam : (dt / (T)6) * d.lam;
+                V3<T> ell = a.seed_unit ? d.lam : (dt / (T)6) * d.lam;
+                if constexpr (LIN) {
+                    // the same fused multiply-adds, in the same order, as the stage-sum kernel from zero
+                    ell = v3<T>(0, 0, 0);
+                    for (int j = 0; j < L.lin_nt; ++j) {
+                        const V3<T> sj = ld3(static_cast<const T*>(L.lin_src[j]), N, i);
+                        const T c = (T)L.lin_c[j];
+                        ell = v3<T>(fma(c, sj.x, ell.x), fma(c, sj.y, ell.y), fma(c, sj.z, ell.z));
+                    }
+                }
                 st3(a.ell, N, i, ell);
                 un = field_adjoint(p, ell, d.yprev, x, iy, iz, pi);
                 st3(a.u_next, N, i, un);
@@ -1789,8 +1798,12 @@ static void stage_fwd_r(const BatchDev<T>& b, const FwdL& L, hipStream_t s, hipE
 }
 template <typename T, int MR>
 static void stage_bwd_r(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((k_stage_bwd<T, MR>), dim3(b.nloc), dim3(b.bwd_threads), (uint32_t)b.bwd_lds, s, e0, e1, 0,
-                          bargs(b, b.work_loc), L);
+    if (L.lin_nt > 0)
+        hipExtLaunchKernelGGL((k_stage_bwd<T, MR, true>), dim3(b.nloc), dim3(b.bwd_threads), (uint32_t)b.bwd_lds, s, e0,
+                              e1, 0, bargs(b, b.work_loc), L);
+    else
+        hipExtLaunchKernelGGL((k_stage_bwd<T, MR>), dim3(b.nloc), dim3(b.bwd_threads), (uint32_t)b.bwd_lds, s, e0, e1,
+                              0, bargs(b, b.work_loc), L);
 }
 template <typename T, int NZ, int MR>
 static void col_r(const BatchDev<T>& b, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -2014,6 +2027,9 @@ hipError_t set_lds_limits(size_t bytes) {
     LLG_ATTR((k_stage_bwd<T, 4>))
     LLG_ATTR((k_stage_bwd<T, 8>))
     LLG_ATTR((k_stage_bwd<T, RT>))
+    LLG_ATTR((k_stage_bwd<T, 4, true>))
+    LLG_ATTR((k_stage_bwd<T, 8, true>))
+    LLG_ATTR((k_stage_bwd<T, RT, true>))
     LLG_ATTR((k_col_conv<T, 1, 4>))
     LLG_ATTR((k_col_conv<T, 2, 4>))
     LLG_ATTR((k_col_conv<T, 4, 4>))

@@ -998,13 +998,18 @@ struct Ops {
         });
     }
 
-    // mu = J_f(Y)^T kappa for the state Y with field Bf = B(Y) and kappa in the role buffer L0: the field
-    // adjoint u and its spectrum (seed with a unit scale), the column pass, then the transpose (stage 0 without
+    // mu = J_f(Y)^T kappa for the state Y with field Bf = B(Y) and kappa = sum_q kap.c[q] kap.src[q], formed by
+    // the seed launch: the field adjoint u and its spectrum, the column pass, then the transpose (stage 0 without
     // a next stage), written to mu_out; dJ/dpsi gains kappa . df/dpsi(Y).  Y and Bf are read where they are.
-    int stage_transpose(const T* Y, const T* Bf, void* mu_out) {
+    int stage_transpose(const T* Y, const T* Bf, const LinTerms<T>& kap, void* mu_out) {
         BwdL Ls{};
         Ls.stage = -2;
         Ls.seed_unit = 1;
+        for (int q = 0; q < kap.nt; ++q) {
+            Ls.lin_src[q] = kap.src[q];
+            Ls.lin_c[q] = kap.c[q];
+        }
+        Ls.lin_nt = kap.nt;
         Ls.j = Ls.prev_j = 0;
         Ls.prev_st = 0;
         Ls.ucur = -1;
@@ -1031,14 +1036,13 @@ struct Ops {
         Lf.ext_lacc = mu_out;
         return bwd(Lf);
     }
-    int kappa(std::initializer_list<std::pair<double, const void*>> terms) {
+    static LinTerms<T> kappa(std::initializer_list<std::pair<double, const void*>> terms) {
         LinTerms<T> lt{};
         for (auto& tm : terms) {
             lt.src[lt.nt] = static_cast<const T*>(tm.second);
             lt.c[lt.nt++] = tm.first;
         }
-        T* kap = static_cast<T*>(h->inst[0].tab.b[B_L0]);
-        return run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), kap, nullptr, lt, s); });
+        return lt;
     }
 
     // Cubic Hermite interpolant of the kept states on [t_n, t_n + h] at t_n + th h into Y:
@@ -1092,14 +1096,17 @@ struct Ops {
                 }
                 // kappa_s = w_s hsub A_s gives mu_s = w_s hsub G_s: A2 = a + 3 mu1, A3 = a + 1.5 mu2,
                 // A4 = a + 3 mu3, and a <- a + mu1 + mu2 + mu3 + mu4
-                if (int rc = kappa({{hsub / 6.0, D.lam}})) return rc;
-                if (int rc = stage_transpose(slot(B_YS, up), slot(B_BS, up), D.mu[0])) return rc;
-                if (int rc = kappa({{hsub / 3.0, D.lam}, {hsub, D.mu[0]}})) return rc;
-                if (int rc = stage_transpose(slot(B_YS, 1), slot(B_BS, 1), D.mu[1])) return rc;
-                if (int rc = kappa({{hsub / 3.0, D.lam}, {hsub / 2.0, D.mu[1]}})) return rc;
-                if (int rc = stage_transpose(slot(B_YS, 1), slot(B_BS, 1), D.mu[2])) return rc;
-                if (int rc = kappa({{hsub / 6.0, D.lam}, {hsub / 2.0, D.mu[2]}})) return rc;
-                if (int rc = stage_transpose(slot(B_YS, lo), slot(B_BS, lo), D.mu[3])) return rc;
+                if (int rc = stage_transpose(slot(B_YS, up), slot(B_BS, up), kappa({{hsub / 6.0, D.lam}}), D.mu[0]))
+                    return rc;
+                if (int rc = stage_transpose(slot(B_YS, 1), slot(B_BS, 1), kappa({{hsub / 3.0, D.lam}, {hsub, D.mu[0]}}),
+                                             D.mu[1]))
+                    return rc;
+                if (int rc = stage_transpose(slot(B_YS, 1), slot(B_BS, 1),
+                                             kappa({{hsub / 3.0, D.lam}, {hsub / 2.0, D.mu[1]}}), D.mu[2]))
+                    return rc;
+                if (int rc = stage_transpose(slot(B_YS, lo), slot(B_BS, lo),
+                                             kappa({{hsub / 6.0, D.lam}, {hsub / 2.0, D.mu[2]}}), D.mu[3]))
+                    return rc;
                 LinTerms<T> lt{};
                 for (int q = 0; q < 4; ++q) {
                     lt.src[q] = P(D.mu[q]);
@@ -1144,7 +1151,7 @@ struct Ops {
                 }
             }
             for (int st = 5; st >= 0; --st) {
-                // kappa_s = h (b_s lambda' + sum_{i>s} a_is mu_i) into the role buffer L0
+                // kappa_s = h (b_s lambda' + sum_{i>s} a_is mu_i), formed by the transpose's seed launch
                 LinTerms<T> lt{};
                 lt.src[lt.nt] = P(D.lam);
                 lt.c[lt.nt++] = hstep * kB5[st];
@@ -1153,10 +1160,7 @@ struct Ops {
                         lt.src[lt.nt] = P(D.mu[i]);
                         lt.c[lt.nt++] = hstep * kA[i][st];
                     }
-                T* kap = static_cast<T*>(h->inst[0].tab.b[B_L0]);
-                if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_lincomb<T>((int)n3(), kap, nullptr, lt, s); }))
-                    return rc;
-                if (int rc = stage_transpose(Ys[st], Bs[st], D.mu[st])) return rc;
+                if (int rc = stage_transpose(Ys[st], Bs[st], lt, D.mu[st])) return rc;
             }
             // lambda_n = lambda' + sum_s mu_s
             LinTerms<T> lt{};

@@ -141,6 +141,7 @@ struct llg_handle {
         void* mu[6] = {};
         void* lam = nullptr;
         double* err = nullptr;   // [0] norm, [8..] block maxima
+        double* err_host = nullptr;  // pinned host copy of the norm, read after each trial step
         std::vector<double> hs, ts;
         bool valid = false;
         // optional store of every accepted step's stages, 11 state vectors per step n:
@@ -1908,6 +1909,7 @@ int llg_destroy(llg_handle* h) {
     if (h->g_in) (void)hipEventDestroy(h->g_in);
     if (h->g_out) (void)hipEventDestroy(h->g_out);
     if (h->gstream) (void)hipStreamDestroy(h->gstream);
+    if (h->dp.err_host) (void)hipHostFree(h->dp.err_host);
     free_all(h);
     delete h;
     return LLG_OK;
@@ -2098,6 +2100,14 @@ namespace {
 // Buffers of the adaptive integrator (first use; sized for max_steps accepted steps).
 int ensure_dopri(llg_handle* h) {
     auto& D = h->dp;
+    if (!D.err_host) {
+        void* ph = nullptr;
+        if (hipHostMalloc(&ph, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LLG_ENOMEM, "hipHostMalloc of the error-norm readback failed");
+        }
+        D.err_host = static_cast<double*>(ph);
+    }
     if (D.keep && !D.stages) {
         const size_t nb = (size_t)3 * h->inst[0].N * h->tsz;
         if (int rc = alloc(h, &D.stages, nb * 11 * (size_t)(h->max_steps + 1))) return rc;
@@ -2136,9 +2146,9 @@ int forward_adaptive(llg_handle* h, double t0, double t_end, double h0, double r
         const T* m = snaps + D.hs.size() * n3;
         if (int rc = o.dp_trial((int64_t)D.hs.size(), m, t, hstep, rtol, atol, have_k0)) return rc;
         have_k0 = true;  // a rejection keeps (m, t); an acceptance moves k[6] = f(y5, t + h) into k[0]
-        double err = 0.0;
-        HIPCHK(hipMemcpyAsync(&err, D.err, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(D.err_host, D.err, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        const double err = *D.err_host;
         if (!std::isfinite(err)) return fail(LLG_ENONFINITE, "non-finite error estimate");
         double f = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(err, -0.2)));
         if (err <= 1.0) {

@@ -40,8 +40,9 @@ class Objective:
                                    W = {n : n_start < n <= n_steps}
              OBJ_PORT_SPECTRAL  -> J = sum_q coef[0, q] |X_1(f_q)| + coef[1, q] |X_2(f_q)|
                                    (Eq. 10 with its frequency windows; see spectral_value)
-             OBJ_MAG_CURVE      -> J = sum_{n in W} weight_n |M_x(n) - target_n|
-                                   (Eq. 8; see curve_value)."""
+             OBJ_MAG_CURVE      -> J = sum_{n in W} weight_n |M_x(n) - target_n|,
+                                   M_x the psi-weighted mean of m_x (Eq. 8;
+                                   see curve_series)."""
 
     def __init__(self, kind, E_ref=1.0, lam=1.0, area=0.4, n_start=0, port1=None, port2=None, freqs=None,
                  coef=None, target=None, weight=None):
@@ -157,12 +158,17 @@ def spectral_source_field(g, m, obj):
 # -- magnetisation-curve objective (Eq. 8) -------------------------------------
 #
 # Eq. 8 sums, over the steps of a run whose applied field ramps linearly from 0
-# to 0.3 Ms, the relative distance between the particle's mean magnetisation
-# M_x and a target curve.  Readings: M_x(n) = 1/N sum_i psi_i m_x,i(n) over all
-# N nodes (the magnetic moment along x in units of Ms times the domain volume;
-# air contributes nothing), for the states m_n of the window W; the weights
-# weight_n = 1 / (M^target_n |W|) and the target are inputs; |.| takes the zero
-# subgradient at 0.  J depends on psi explicitly through M_x.
+# to 0.3 Ms, the distance between the particle's average magnetisation M_x and
+# the target curve, each term divided by the target and by the number of steps.
+# The Stoner-Wohlfarth section takes M_x as the particle's average x component:
+# here M_x(n) = sum_i psi_i m_x,i(n) / sum_i psi_i (the material-weighted mean of
+# m_x, in units of Ms; 0 when there is no material), for the states m_n of the
+# window W.  The weights weight_n = 1 / (M^target_n N) and the target are inputs
+# (the section's target is M = 2 H_ext, i.e. 0.6 n / N in units of Ms along the
+# ramp; the n = 0 term, whose target is 0, is left out).  |.| takes the zero
+# subgradient at 0.  J depends on psi explicitly through M_x:
+#   dM_x(n)/dm_x,i = psi_i / S,   dM_x(n)/dpsi_i = (m_x,i(n) - M_x(n)) / S,
+# with S = sum_i psi_i.
 
 def _absr(z):
     """|z| for real z, continued analytically for complex-step perturbations."""
@@ -170,8 +176,12 @@ def _absr(z):
 
 
 def curve_series(traj, psi, obj, n_steps):
+    """M_x(n) for the window states: the psi-weighted mean of m_x."""
     win = range(obj.n_start + 1, n_steps + 1)
-    return np.array([(psi * traj[n][0]).sum() / psi.size for n in win])
+    S = psi.sum()
+    if np.real(S) == 0:
+        return np.zeros(len(win), dtype=np.result_type(psi, traj[0]))
+    return np.array([(psi * traj[n][0]).sum() / S for n in win])
 
 
 def curve_value(M, obj):
@@ -266,14 +276,16 @@ def gradient(sim, m0, psi, n_steps, obj, t0=0.0):
         lam = lam + spectral_source_field(g_ser[:, -1], traj[n_steps], obj)
     curve = obj.kind == OBJ_MAG_CURVE and n_steps > obj.n_start
     if curve:
-        # dJ/dm_x,i(n) = g_n psi_i / N and dJ/dpsi_i += g_n m_x,i(n) / N
-        g_cur = curve_sources(curve_series(traj, psi, obj, n_steps), obj) / psi.size
+        # with c_n = dJ/dM(n) / S: dJ/dm_x,i(n) = c_n psi_i and dJ/dpsi_i += c_n (m_x,i(n) - M(n))
+        M_cur = curve_series(traj, psi, obj, n_steps)
+        S = psi.sum()
+        g_cur = curve_sources(M_cur, obj) / S if np.real(S) != 0 else np.zeros_like(M_cur)
 
-        def curve_terms(g, m):
+        def curve_terms(g, m, M):
             gm = np.zeros(m.shape, dtype=np.result_type(m, psi, g))
             gm[0] = g * psi
-            return gm, g * m[0]
-        gm, gp = curve_terms(g_cur[-1], traj[n_steps])
+            return gm, g * (m[0] - M)
+        gm, gp = curve_terms(g_cur[-1], traj[n_steps], M_cur[-1])
         lam = lam + gm
         g_psi = g_psi + gp
     for n in range(n_steps - 1, -1, -1):
@@ -294,7 +306,8 @@ def gradient(sim, m0, psi, n_steps, obj, t0=0.0):
         if spec and obj.n_start < n:
             lam = lam + spectral_source_field(g_ser[:, n - obj.n_start - 1], traj[n], obj)
         if curve and obj.n_start < n:
-            gm, gp = curve_terms(g_cur[n - obj.n_start - 1], traj[n])
+            k = n - obj.n_start - 1
+            gm, gp = curve_terms(g_cur[k], traj[n], M_cur[k])
             lam = lam + gm
             g_psi = g_psi + gp
     return J, g_psi, lam

@@ -339,9 +339,10 @@ def sw_particle_curve(seed: int = 6, n_steps: int = 2000, nx: int = 30, ny: int 
     (Ms = 800 kA/m, A = 13 pJ/m), alpha = 0.5, the applied field ramped linearly
     along x from 0 to 0.3 Ms over the run; phi is seeded smooth noise (max |phi| = 1),
     and extra["rbf"] the 20x20 RBF array over the mesh with 3x3 holes for the
-    design loop.  Target M_x: a seeded smooth
-    monotone curve from 0.1 to 0.6 (synthetic; the paper's target is shown only
-    as a figure); weights 1 / (target |W|), window = the whole run."""
+    design loop.  Target: the Stoner-Wohlfarth section's M = 2 H_ext, which is
+    0.6 n / N in units of Ms at step n of the N-step ramp; weights
+    1 / (target N); window = steps 1..N (the n = 0 term, whose target is 0, is
+    left out)."""
     rng = np.random.default_rng(seed)
     dt = 1e-13
     mu0 = 4e-7 * math.pi
@@ -354,9 +355,7 @@ def sw_particle_curve(seed: int = 6, n_steps: int = 2000, nx: int = 30, ny: int 
     m0[1] = 1.0
     m0 += rng.normal(0.0, 1e-3, m0.shape)
     m0 = _normalise(m0)
-    u = np.arange(1, n_steps + 1) / n_steps
-    bend = rng.uniform(0.5, 1.5)
-    target = 0.1 + 0.5 * u ** bend
+    target = 2.0 * 0.3 * np.arange(1, n_steps + 1) / n_steps
     ones8 = np.ones(sh, np.uint8)
     zeros8 = np.zeros(sh, np.uint8)
     phi = random_design_phi(rng, ny, nx, (0, 0, min(nx, ny)))

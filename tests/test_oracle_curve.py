@@ -1,7 +1,9 @@
 """Pins of the oracle's magnetisation-curve objective (Eq. 8) and the field
-ramp: the Stoner-Wohlfarth hard-axis law under a slow ramp, the psi weighting
-of M_x, and the discrete adjoint (with the objective's explicit psi
-dependence) against complex-step directional derivatives."""
+ramp: the Stoner-Wohlfarth hard-axis law under a slow ramp, M_x as the
+particle's average (invariant to a uniform psi, the plain mean over the nodes
+of a binary particle), the paper's target, and the discrete adjoint (with the
+objective's explicit psi dependence) against complex-step directional
+derivatives."""
 import numpy as np
 import pytest
 
@@ -43,9 +45,10 @@ def test_slow_ramp_follows_the_hard_axis_law():
     assert M[-1] == pytest.approx(0.5, abs=0.01)
 
 
-def test_curve_measure_is_psi_weighted():
-    """psi = 0.5 everywhere leaves the dynamics unchanged (Ms, A and K scale
-    together) and halves M_x."""
+def test_curve_measure_is_the_particle_average():
+    """M_x is the particle's average magnetisation: psi = 0.5 everywhere leaves
+    the dynamics unchanged (Ms, A and K scale together) and leaves M_x
+    unchanged too (a mean over the domain volume would halve it)."""
     p, m0, psi1, bk, n = sw_particle(1.0)
     _, _, psi2, _, _ = sw_particle(0.5)
     n = 200
@@ -53,7 +56,39 @@ def test_curve_measure_is_psi_weighted():
     obj = adj.Objective(adj.OBJ_MAG_CURVE, n_start=0, target=np.zeros(n), weight=np.ones(n))
     M1 = adj.curve_series(sim.integrate(m0, psi1, n, keep=True)[1], psi1, obj, n)
     M2 = adj.curve_series(sim.integrate(m0, psi2, n, keep=True)[1], psi2, obj, n)
-    np.testing.assert_allclose(M2, 0.5 * M1, rtol=1e-12, atol=1e-15)
+    assert np.abs(M1).max() > 0.02
+    np.testing.assert_allclose(M2, M1, rtol=1e-12, atol=1e-15)
+
+
+def test_curve_measure_of_a_binary_particle_is_the_mean_over_its_nodes():
+    """psi = 1 on a few nodes and 0 elsewhere: M_x is the plain mean of m_x over
+    those nodes, whatever the air nodes hold (brute force over the nodes)."""
+    rng = np.random.default_rng(4)
+    shape = (1, 5, 7)
+    psi = np.zeros(shape)
+    mag = [(0, 1, 2), (0, 1, 3), (0, 3, 5), (0, 4, 0)]
+    for k in mag:
+        psi[k] = 1.0
+    traj = [rng.standard_normal((3,) + shape) for _ in range(4)]
+    obj = adj.Objective(adj.OBJ_MAG_CURVE, n_start=1, target=np.zeros(2), weight=np.ones(2))
+    M = adj.curve_series(traj, psi, obj, 3)
+    want = [sum(traj[n][0][k] for k in mag) / len(mag) for n in (2, 3)]
+    np.testing.assert_allclose(M, want, rtol=1e-14)
+    # no material at all: M_x = 0
+    assert np.all(adj.curve_series(traj, np.zeros(shape), obj, 3) == 0.0)
+
+
+def test_paper_target_of_the_particle_workload():
+    """The particle workload's target is M = 2 H_ext along the ramp 0 -> 0.3 Ms
+    (0.6 n / N in units of Ms at step n of N) and its weights 1 / (M^target N)."""
+    w = wl.sw_particle_curve(n_steps=400)
+    tg, wt = w.extra["target"], w.extra["weight"]
+    n = np.arange(1, 401)
+    np.testing.assert_allclose(tg, 0.6 * n / 400, rtol=1e-15)
+    np.testing.assert_allclose(wt, 1.0 / (tg * 400), rtol=1e-15)
+    # the ramp itself reaches mu0 * 0.3 Ms along x at the last step
+    assert w.problem.b_rf[0] == pytest.approx(4e-7 * np.pi * 0.3 * w.problem.Ms, rel=1e-15)
+    assert w.problem.t_ramp == pytest.approx(400 * w.problem.dt, rel=1e-15)
 
 
 def test_curve_adjoint_matches_complex_step():

@@ -5,9 +5,16 @@ n RK4 steps of the LLG equation with checkpoints, the objective, the
 checkpointed discrete adjoint back to t0, and the chain rule to dJ/dphi.
 Inputs are resident in device memory before the timed region starts.
 
+The default workload is the batched sweep: 32 seeded demultiplexer designs x
+2 drive frequencies = 64 instances on ragged grids (128..256 x 64..128 nodes,
+1.15 M nodes in all), 10 000 RK4 steps each, FP32, one launch sequence for
+the whole batch.  Beside it the same 64 instances are solved one after the
+other as plain single-instance calls (the batched-over-plain ratio), and the
+float64 oracle is timed on the host's cores.
+
   python bench.py [--steps K] [--warmup W]
-                  [--workload particle|particle_curve|particle_adaptive|waveguide|demux|demux_spectral|device3d|sweep|
-                              probe|rbf]
+                  [--workload sweep|particle|particle_curve|particle_adaptive|waveguide|demux|demux_spectral|
+                              device3d|probe|rbf]
 
 Prints ONE JSON line.  The metric is LLG cell-steps per second of the forward
 + adjoint run: nodes * RK4 steps / wall time of one gradient evaluation.
@@ -27,6 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "LLG cell-steps/s fwd+adjoint; grad time/iter, batched vs plain at stated tol"
+SWEEP_NAME = "yig_demux_sweep_64x_10000steps_grad"
 HBM_PEAK_GBS = 8000.0
 
 
@@ -114,10 +122,14 @@ class SweepStep:
         self.n_steps = n_steps
         dev = torch.device("cuda:0")
         t = lambda a: torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=torch.float32, device=dev)
+        t0 = time.perf_counter()
         self.batch = llg.Batch([w.problem for w in self.ws], dtype="f32", max_steps=n_steps,
                                masks=[dict(antenna=w.antenna, port1=w.port1, port2=w.port2, design=w.design)
                                       for w in self.ws])
+        torch.cuda.synchronize()
+        self.t_create = time.perf_counter() - t0
         self.batch.set_graphs(graphs)
+        t0 = time.perf_counter()
         if launch_file and os.path.exists(launch_file):
             self.batch.set_launch_config(*[int(v) for v in open(launch_file).read().split()])
             self.launch = self.batch.launch_config()
@@ -126,6 +138,8 @@ class SweepStep:
             if launch_file:
                 with open(launch_file, "w") as fh:
                     fh.write(" ".join(str(v) for v in self.launch) + "\n")
+        torch.cuda.synchronize()
+        self.t_tune = time.perf_counter() - t0
         self.phi = [t(w.phi) for w in self.ws]
         self.psif = [t(w.psi_fixed) for w in self.ws]
         self.m0 = [t(w.m0) for w in self.ws]
@@ -150,6 +164,107 @@ def sweep_plain(n_steps, count, graphs=True, tune=True):
         w.obj_n_start = n_steps // 2
         steps.append(GradientStep(w, graphs, tune))
     return steps, sum(w.problem.n for w in ws[:count])
+
+
+def _profile_supported(solver):
+    """False while a profiler collects hardware counters (the library refuses
+    event-timed dispatches then, LLG_ENOTSUP)."""
+    from paper_2411_19109_amd import llg
+    try:
+        solver.profile(True)
+    except llg.LLGError as e:
+        if e.code == llg.LLG_ENOTSUP:
+            print(f"[bench] kernel event timing off: {e}", file=sys.stderr, flush=True)
+            return False
+        raise
+    solver.profile(False)
+    return True
+
+
+def _oracle_worker(idx, n_steps, n_designs_steps):
+    """Child process: the float64 oracle's gradient (forward + adjoint, store-all)
+    of sweep instance idx over its first n_steps RK4 steps; prints one JSON
+    line {"cells": nodes * n_steps, "secs": wall seconds}."""
+    from oracle import adjoint as oadj
+    from oracle import levelset as ols
+    from oracle import micromag as omm
+    from paper_2411_19109_amd import workloads as wl
+    w = wl.yig_demux_sweep(n_steps=n_designs_steps)[idx]
+    sim = omm.Sim(w.problem, antenna=w.antenna)
+    psi = ols.levelset_to_psi(w.phi, w.heaviside_a, w.design, w.psi_fixed)
+    obj = oadj.Objective(w.objective, n_start=0, port1=w.port1, port2=w.port2)
+    print("ready", flush=True)
+    sys.stdin.readline()  # the parent starts every worker's timed work at once
+    t0 = time.perf_counter()
+    oadj.gradient(sim, w.m0, psi, n_steps, obj)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"cells": w.problem.n * n_steps, "secs": dt, "nodes": w.problem.n}), flush=True)
+
+
+def _host_workers():
+    """Worker processes for the host baseline: the CPUs this process may use,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline_sweep(n_run, budget_s=10.0):
+    """The oracle as it stands, on the host's cores: each worker process (one
+    thread each) runs the float64 oracle's gradient of one sweep instance over a
+    prefix of its RK4 steps.  One worker alone gives the one-core rate, then
+    one worker per core runs concurrently (instances 0..P-1) for the all-core
+    rate (sum of cell-steps / wall time of the slowest).  Worker processes are
+    plain children that never touch the GPU."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="", ROCR_VISIBLE_DEVICES="")
+
+    def spawn(idx, n):
+        return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker", str(idx), str(n),
+                                 str(n_run)], stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env,
+                                 cwd=ROOT)
+
+    def result(p):
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed ({p.returncode})")
+        return json.loads(out.strip().splitlines()[-1])
+
+    def go(procs):
+        for p in procs:
+            if p.stdout.readline().strip() != "ready":
+                raise RuntimeError("oracle worker did not start")
+        for p in procs:
+            p.stdin.write("go\n")
+            p.stdin.flush()
+    probe = spawn(0, 4)
+    go([probe])
+    per_step = result(probe)["secs"] / 4
+    n = max(4, min(n_run, int(budget_s / max(per_step, 1e-3))))
+    one = spawn(0, n)
+    go([one])
+    one = result(one)
+    P = _host_workers()
+    procs = [spawn(i, n) for i in range(P)]
+    go_ready = [p.stdout.readline().strip() == "ready" for p in procs]  # inputs and oracle objects set up
+    if not all(go_ready):
+        raise RuntimeError("oracle worker did not start")
+    t0 = time.perf_counter()
+    for p in procs:
+        p.stdin.write("go\n")
+        p.stdin.flush()
+    res = [result(p) for p in procs]
+    wall = time.perf_counter() - t0
+    cells = sum(r["cells"] for r in res)
+    return dict(value=cells / wall, unit="cell-steps/s", cores=P, kind="oracle",
+                one_core_value=one["cells"] / one["secs"],
+                sample=f"float64 NumPy oracle, forward+adjoint of the first {n} of {n_run} RK4 steps of sweep "
+                       f"instances 0..{P - 1} ({res[0]['nodes']}..{max(r['nodes'] for r in res)} nodes), one "
+                       f"single-threaded process per core, {P} concurrently ({wall:.1f} s wall); one core alone: "
+                       f"instance 0, {one['secs']:.1f} s")
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -183,13 +298,15 @@ def cpu_baseline(w, budget_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="particle")
+    ap.add_argument("--workload", default="sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--sweep-steps", type=int, default=200, help="RK4 steps per instance of the sweep workload")
-    ap.add_argument("--sweep-plain", type=int, default=8, help="instances timed one after the other for the plain rate")
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work per host worker")
+    ap.add_argument("--sweep-steps", type=int, default=10000, help="RK4 steps per instance of the sweep workload")
+    ap.add_argument("--plain-steps", type=int, default=1000,
+                    help="RK4 steps per instance of the plain (one instance per call) sweep; 0 skips it")
+    ap.add_argument("--oracle-worker", nargs=3, type=int, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--n-steps", type=int, default=0,
                     help="override the workload's RK4 step count (short profiling runs; not a bench line)")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay forward/adjoint as captured HIP graphs")
@@ -203,6 +320,8 @@ def main():
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="skip the per-kernel event timing pass (counter runs need only the dispatches)")
     args = ap.parse_args()
+    if args.oracle_worker:
+        return _oracle_worker(*args.oracle_worker)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
@@ -268,7 +387,7 @@ def main():
 
     # per-kernel device time over one more gradient with event bracketing
     roofline = None
-    if not args.no_kernel_events:
+    if not args.no_kernel_events and _profile_supported(step.solver):
         s = step.solver
         s.profile(True)
         step()
@@ -354,47 +473,91 @@ def _kernel_stats(solver):
 
 
 def run_sweep(args):
-    """Batched vs plain on the sweep workload (prefix of --sweep-steps RK4 steps
-    per instance; the per-step cost is constant, so the ratio holds for the full run)."""
+    """The default bench line: the batched sweep at full length (64 instances x
+    --sweep-steps RK4 steps, forward + adjoint gradient per step), the kernel
+    averages of the timed steps (HIP events bound to each dispatch, on the
+    launch streams), the plain path over all 64 instances (one single-instance
+    gradient after the other, --plain-steps RK4 steps each: the per-step cost
+    of a run does not depend on its length), and the oracle on the host."""
     import torch
     from paper_2411_19109_amd import llg
     n = args.sweep_steps
     step = SweepStep(n, bool(args.graphs), bool(args.autotune), args.launch_file)
-    print(f"[bench] sweep: {len(step.ws)} instances, {step.nodes} nodes, {n} steps, launch {step.launch}",
-          file=sys.stderr, flush=True)
+    print(f"[bench] sweep: {len(step.ws)} instances, {step.nodes} nodes, {n} steps, launch {step.launch}, "
+          f"setup {step.t_create:.2f} s + tuning {step.t_tune:.2f} s", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    prof = not args.no_kernel_events and _profile_supported(step.batch)
+    kinds = {}
+    if prof:
+        step.batch.profile(True)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
+    ev[0].record()
     for i in range(args.steps):
-        step()
+        J, g = step()
+        ev[i + 1].record()
+        if prof:
+            # sum the event-timed kernel durations of this step (reading them waits for the step to end)
+            for name, v in _kernel_stats(step.batch).items():
+                acc = kinds.setdefault(name, dict(ms=0.0, launches=0, bytes=0.0))
+                acc["ms"] += v["ms"]
+                acc["launches"] += v["launches"]
+                acc["bytes"] += v["bytes"]
+        print(f"[bench] timed step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / args.steps
-    print(f"[bench] batched: {tb * 1e3:.1f} ms per sweep gradient", file=sys.stderr, flush=True)
-    step.batch.profile(True)
-    step()
-    torch.cuda.synchronize()
-    step.batch.profile(False)
-    kinds = _kernel_stats(step.batch)
-    for name, v in kinds.items():
-        print(f"[bench] batched {name}: {v['launches']} launches, avg {v['avg_us']:.2f} us, "
-              f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
-    dom = max(kinds, key=lambda k: kinds[k]["ms"])
-    d = kinds[dom]
+    if prof:
+        step.batch.profile(False)
+    per_step = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
     rate_b = step.nodes * n / tb
-    rate_p, tp, plain = None, None, []
-    if args.sweep_plain > 0:
-        plain, nodes_p = sweep_plain(n, args.sweep_plain, bool(args.graphs), bool(args.autotune))
-        for p in plain:  # first call of each instance captures its graphs
+    print(f"[bench] batched: {tb * 1e3:.1f} ms per sweep gradient (median {np.median(per_step):.1f} ms), "
+          f"{rate_b:.4g} cell-steps/s", file=sys.stderr, flush=True)
+    roofline = None
+    if kinds:
+        for v in kinds.values():
+            v["avg_us"] = 1e3 * v["ms"] / v["launches"]
+            v["gbs"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+        for name, v in kinds.items():
+            print(f"[bench] batched {name}: {v['launches']} launches, avg {v['avg_us']:.2f} us, "
+                  f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
+        dom = max(kinds, key=lambda k: kinds[k]["ms"])
+        d = kinds[dom]
+        roofline = dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(d["gbs"] / HBM_PEAK_GBS, 5),
+                        traffic=measured_traffic(SWEEP_NAME, dom, step.launch), kernel=dom,
+                        avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"]))
+    J_mean = float(J.double().mean().item())
+    del g
+    rate_p, tp, n_plain, nplain_steps = None, None, 0, args.plain_steps
+    if nplain_steps > 0:
+        t_setup = time.perf_counter()
+        plain, nodes_p = sweep_plain(nplain_steps, len(step.ws), bool(args.graphs), bool(args.autotune))
+        for p in plain:  # first call of each instance (its graphs are captured here when graphs are on)
             p()
         torch.cuda.synchronize()
+        print(f"[bench] plain: {len(plain)} single-instance handles ready in {time.perf_counter() - t_setup:.1f} s",
+              file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         for p in plain:
             p()
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
-        rate_p = nodes_p * n / tp
-        print(f"[bench] plain: {tp * 1e3:.1f} ms for {len(plain)} sequential instances", file=sys.stderr, flush=True)
+        n_plain = len(plain)
+        rate_p = nodes_p * nplain_steps / tp
+        print(f"[bench] plain: {tp * 1e3:.1f} ms for {n_plain} sequential instances x {nplain_steps} steps, "
+              f"{rate_p:.4g} cell-steps/s", file=sys.stderr, flush=True)
+        for p in plain:
+            p.solver.close()
+        del plain
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_sweep(n, args.cpu_budget)
+        print(f"[bench] cpu baseline: {cpu['value']:.4g} cell-steps/s on {cpu['cores']} cores "
+              f"({cpu['one_core_value']:.4g} on one); {cpu['sample']}", file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
         "value": rate_b,
@@ -408,13 +571,16 @@ def run_sweep(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"yig_demux_sweep_64x_prefix{n}", "instances": len(step.ws), "nodes": step.nodes,
-                   "rk4_steps": n, "plain_cell_steps_per_s": rate_p, "plain_instances_timed": len(plain),
+        "config": {"workload": SWEEP_NAME if n == 10000 else f"yig_demux_sweep_64x_{n}steps_grad",
+                   "instances": len(step.ws), "nodes": step.nodes, "rk4_steps": n, "checkpoint": "sqrt",
+                   "grad_ms": round(tb * 1e3, 3), "grad_ms_median": round(float(np.median(per_step)), 3),
+                   "plain_cell_steps_per_s": rate_p, "plain_instances_timed": n_plain,
+                   "plain_rk4_steps_per_instance": nplain_steps if n_plain else None,
                    "batched_over_plain": rate_b / rate_p if rate_p else None, "hip_graphs": bool(args.graphs),
-                   "launch": list(step.launch)},
-        "roofline": dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                         frac=round(d["gbs"] / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
-                         avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"])),
+                   "launch": list(step.launch), "objective_J_mean": J_mean,
+                   "setup_s": {"create": round(step.t_create, 3), "launch_tuning": round(step.t_tune, 3)}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -454,7 +620,7 @@ def run_probe(args):
     sec = (time.perf_counter() - t0) / args.steps
     name = "yig_film_probe_4x1024x1024_forward"
     roofline, kinds = None, {}
-    if not args.no_kernel_events:
+    if not args.no_kernel_events and _profile_supported(b):
         b.profile(True)
         b.forward(psis, m0, n, want_m=False)
         torch.cuda.synchronize()
@@ -570,7 +736,7 @@ def run_adaptive(args):
           f"(kept stages: {sec * 1e3:.1f} ms), bitwise equal: {compare['recomputed_stages_bitwise_equal']}",
           file=sys.stderr, flush=True)
     roofline, kinds = None, {}
-    if not args.no_kernel_events:
+    if not args.no_kernel_events and _profile_supported(s):
         s.profile(True)
         step()
         torch.cuda.synchronize()
@@ -730,7 +896,7 @@ def run_rbf(args):
         print(f"[bench] rbf {name}: {small[name]} us per update", file=sys.stderr, flush=True)
 
     roofline, kinds = None, {}
-    if not args.no_kernel_events:
+    if not args.no_kernel_events and os.environ.get("ROCPROF_COUNTER_COLLECTION") is None:
         llg.rbf_profile(True)
         step()
         torch.cuda.synchronize()

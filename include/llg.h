@@ -87,7 +87,10 @@ extern "C" {
  * (frequency windows around f1 and f2 are sets of sample frequencies f_q with coefficients +-1) */
 #define LLG_OBJ_PORT_SPECTRAL 3
 /* Eq. 8: J = sum_{n in W} weight[n'] |M_x(n) - target[n']|, n' = n - n_start - 1, with
- * M_x(n) = 1/N sum_i psi_i m_x,i(n) over all N nodes (explicit in psi as well as in m) */
+ * M_x(n) = sum_i psi_i m_x,i(n) / sum_i psi_i the particle's average x component in units of Ms
+ * (0 without material; explicit in psi as well as in m).  The Stoner-Wohlfarth section's
+ * target M = 2 H_ext along the ramp 0 -> 0.3 Ms is target[n'] = 0.6 n / n_steps with
+ * weight[n'] = 1 / (target[n'] n_steps). */
 #define LLG_OBJ_MAG_CURVE 4
 
 /* ---- problem description --------------------------------------------- */
@@ -341,9 +344,26 @@ int llg_autotune(llg_handle* h, hipStream_t stream);
  * recorded events and returns, for one kernel class, the summed device time
  * (ms), the number of launches, and the algorithmic HBM bytes of those
  * launches (every array element the kernel must read or write counted once).
- * reset != 0 clears the class's totals after reading. */
+ * reset != 0 clears the class's totals after reading.
+ * llg_profile(h, 1) returns LLG_ENOTSUP while a profiler collects hardware
+ * counters from the process (ROCPROF_COUNTER_COLLECTION set, as rocprofv3
+ * --pmc does): event-timed dispatches are not combined with counter
+ * collection, under which one run crashed in the HIP launch path. */
 int llg_profile(llg_handle* h, int enable);
 int llg_profile_read(llg_handle* h, int32_t kind, double* ms, int64_t* launches, double* bytes, int reset);
+
+/* The demagnetising tensor the library builds the dipole-dipole field term
+ * from (Methods: the effective field's demagnetising part), host only, float64:
+ * the cell-averaged tensor N(r) = (1/V) int T(s) D(r + s) ds between two cells
+ * of edges dx, dy, dz (m) whose centres are (X, Y, Z) apart, with
+ * T(s) = prod_d (h_d - |s_d|)_+ and D(p) = -(3 p p^T / |p|^2 - I) / (4 pi |p|^3);
+ * the mean field in one cell is -N(r) M of the other's uniform M.
+ * out[6] = N_xx, N_yy, N_zz, N_xy, N_xz, N_yz.  method 0: what the library uses
+ * (Newell, Williams & Dunlop's closed form for centres less than two largest
+ * cell edges apart, Gauss-Jacobi quadrature of the tent integral beyond);
+ * 1: the closed form at any offset; 2: the quadrature (centres at least two
+ * largest edges apart).  No device work.  Errors: LLG_EINVAL. */
+int llg_demag_tensor(double dx, double dy, double dz, double X, double Y, double Z, int32_t method, double* out);
 
 /* Padded FFT sizes the handle uses (Px, Py, Pz); of the first instance of a batch. */
 int llg_fft_sizes(const llg_handle* h, int32_t* P3);
@@ -392,7 +412,7 @@ int llg_rbf_levelset_vjp(int32_t dtype, int32_t nx, int32_t ny, int32_t n_rbf, c
 #define LLG_RBF_KIND_PNORM 1 /* pass 2: max-scaled p-norm per node                    */
 #define LLG_RBF_KIND_VJP 2   /* dJ/ds partial sums over node chunks                   */
 #define LLG_RBF_KIND_COUNT 3
-int llg_rbf_profile(int enable);
+int llg_rbf_profile(int enable); /* LLG_ENOTSUP under counter collection, as llg_profile */
 int llg_rbf_profile_read(int32_t kind, double* ms, int64_t* launches, double* pairs, int reset);
 
 /* One Adam step on n device doubles, in place (the amplitude update of Eq. 5

@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
 
 #include <vector>
 
@@ -109,7 +111,7 @@ struct FwdL {
     int ys, mn, acc, ynext;  // BufId roles (-1 = none)
     int store_j;          // >= 0: copy ys and B(ys) to slot store_j of YS / BS
     int port;             // stage 3: 1 accumulate the port m_y^2 sums; write, for window step pstep, 2 the port
-                          // m_y sums (spectral objective), 3 the psi m_x sums over all nodes (curve objective)
+                          // m_y sums (spectral objective), 3 the psi m_x and psi sums over all nodes (curve objective)
     int pstep;            // window index of the state this launch produces (port == 2)
     int do_inv, do_fwd;   // inverse x-FFT of S (demag in) / forward x-FFT of psi*ynext into S
     int spec;             // BufId of S (B_S or B_S2)
@@ -192,8 +194,8 @@ struct StageBwdArgs {
     const uint8_t* port1;
     const uint8_t* port2;
     T src1, src2;         // port sources (port 2 carries its sign)
-    int src_lin;          // 0 lambda.y += src m_y; 1 lambda.y += src (spectral); 2 lambda.x += src psi and
-                          // dJ/dpsi += src m_x on every node (curve)
+    int src_lin;          // 0 lambda.y += src m_y; 1 lambda.y += src (spectral); 2 lambda.x += src1 psi and
+                          // dJ/dpsi += src1 m_x - src2 on every node (curve)
     int seed_unit;
     int do_inv;
     int do_fwd;
@@ -289,11 +291,23 @@ template <typename T> hipError_t set_lds_limits(size_t bytes);
 // Records msg as the text llg_last_error() returns on this thread; returns code.
 int set_error(int code, const char* msg);
 
+// True while a profiler collects hardware counters from this process
+// (rocprofv3 --pmc / counter groups export ROCPROF_COUNTER_COLLECTION).  The
+// libraries' event-timed dispatches (hipExtLaunchKernelGGL with start/stop
+// events) are refused then: one such run ended in a segmentation fault inside
+// the HIP launch path, and counter runs need only the dispatches themselves.
+inline bool counter_collection_active() {
+    const char* v = getenv("ROCPROF_COUNTER_COLLECTION");
+    return v && *v && strcmp(v, "0") != 0 && strcmp(v, "False") != 0 && strcmp(v, "false") != 0;
+}
+
 // Host side: tensor spectrum (float64) in the kernel layout, scaled by -mu0 Ms / (Px Py Pz).
 void build_tensor_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, int Px, int Py, int Pz,
                            double scale, std::vector<double>& out, int& ncomp);
 
-// Newell tensor at one physical offset (6 components xx,yy,zz,xy,xz,yz).
+// Newell tensor at one physical offset (6 components xx,yy,zz,xy,xz,yz);
+// mode 0 = closed form near, quadrature far; 1 = closed form; 2 = quadrature.
 void tensor_at(double X, double Y, double Z, double hx, double hy, double hz, double out[6]);
+void tensor_at_mode(double X, double Y, double Z, double hx, double hy, double hz, int mode, double out[6]);
 
 }  // namespace llg

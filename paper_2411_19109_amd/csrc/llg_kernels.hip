@@ -613,7 +613,7 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     const int nitem = v1 ? 2 * nx : nx;
     V3<T> pre_acc = v3<T>(0, 0, 0), pre_mn = v3<T>(0, 0, 0);
     uint8_t pre_ant = 0, pre_p1 = 0, pre_p2 = 0;
-    const bool need_acc = a.stage >= 1 && a.stage <= 3, need_mn = a.stage == 1 || a.stage == 2;
+    const bool need_acc = a.stage >= 1 && a.stage <= 3, need_mn = a.stage >= 1 && a.stage <= 3;
     if ((int)threadIdx.x < nitem) {
         const int i = r0 * nx + threadIdx.x;  // rows r0, r0+1 are contiguous
         if (need_acc) pre_acc = ld3(a.acc, N, i);
@@ -707,7 +707,9 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             } else if (a.stage < 0) {
                 yn = f;  // field evaluation: rhs out
             } else if (a.stage == 0) {
-                st3(a.acc, N, i, m + (dt / (T)6) * f);
+                // acc holds the step's increment dt/6 (k1 + 2 k2 + 2 k3), added to m_n once at stage 3:
+                // one rounding of the O(1) state per step instead of four
+                st3(a.acc, N, i, (dt / (T)6) * f);
                 yn = m + (dt / (T)2) * f;
             } else if (a.stage == 1) {
                 st3(a.acc, N, i, accv + (dt / (T)3) * f);
@@ -716,7 +718,7 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
                 st3(a.acc, N, i, accv + (dt / (T)3) * f);
                 yn = mnv + dt * f;
             } else {
-                yn = accv + (dt / (T)6) * f;
+                yn = mnv + (accv + (dt / (T)6) * f);
             }
             if (a.ynext) st3(a.ynext, N, i, yn);
             if constexpr (LIN) {
@@ -736,7 +738,8 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             }
             if (a.port_part) {
                 if (a.port_lin == 2) {
-                    s1 += (double)pi * (double)yn.x;  // curve objective: psi m_x over every node
+                    s1 += (double)pi * (double)yn.x;  // curve objective: psi m_x and psi over every node
+                    s2 += (double)pi;
                 } else {
                     const double v = a.port_lin ? (double)yn.y : (double)yn.y * (double)yn.y;
                     const bool first_it = it == (int)threadIdx.x;
@@ -966,8 +969,8 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                     const V3<T> ua = v3<T>(p.u[0], p.u[1], p.u[2]);
                     mu = mu + (p.anis * dot(uk, ua)) * ua;
                 }
-                // curve objective at stage 0: its explicit psi dependence, dJ/dpsi_i += g_n m_x,i
-                if (a.port1 && a.src_lin == 2) g += (double)a.src1 * (double)m.x;
+                // curve objective at stage 0: its explicit psi dependence, dJ/dpsi_i += c_n m_x,i - c_n M(n)
+                if (a.port1 && a.src_lin == 2) g += (double)a.src1 * (double)m.x - (double)a.src2;
                 glb(a.gpsi)[i] = d.g0 + g;
                 const V3<T> lsum = (a.stage == 3 ? d.lam : d.lacc) + mu;
                 if (a.stage > 0) {
@@ -979,7 +982,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                 } else {
                     V3<T> lam = lsum;
                     if (a.port1 && a.src_lin == 2) {
-                        lam.x = lam.x + a.src1 * pi;  // curve objective: dJ/dm_x,i = g_n psi_i
+                        lam.x = lam.x + a.src1 * pi;  // curve objective: dJ/dm_x,i = c_n psi_i
                     } else if (a.port1) {
                         // source dJ/dm_n of the port objective (y component)
                         const T src = (d.p1 ? a.src1 : (T)0) + (d.p2 ? a.src2 : (T)0);
@@ -1018,6 +1021,251 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
 }
 
 // ---------------------------------------------------------------------------
+// column kernel of a single-layer grid (nz = 1): the first and the last pass of
+// the y transforms work on global memory directly
+// ---------------------------------------------------------------------------
+// The y transform of length L = Py = 2^lL starts with a pass of radix
+// R1 = 2^min(log2 MR, lL) and the inverse ends with one; the passes in between
+// are those of fft_lds, so the factorisation depends only on (L, MR) and every
+// tiling computes the same bits.
+//  - The first forward pass (no twiddles) reads its inputs from the x-spectrum
+//    in global memory: its inputs j + r L/R1 with r >= R1/2 lie at rows
+//    >= L/2 >= ny, the zero padding, and are not read.
+//  - The last inverse pass writes the rows y < ny straight to global memory;
+//    its outputs with r >= R1/2 lie in the padding and are not stored.
+// Against staging the columns in LDS and copying them out this saves one LDS
+// round trip and one barrier at each end.
+
+// Stockham passes from lNs = lb to lNs = le, largest radix first (as fft_lds).
+template <typename C, bool INV, int MAXREG>
+__device__ __forceinline__ void fft_lds_range(C* buf, const SigMap sm, int lL, int lb, int le, int nsig,
+                                              const C* __restrict__ tw) {
+    int lNs = lb;
+    while (lNs < le) {
+        const int rem = le - lNs;
+        if constexpr (MAXREG >= 16) {
+            if (rem >= 4) {
+                fft_pass<C, INV, 16, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+                lNs += 4;
+                continue;
+            }
+        }
+        if constexpr (MAXREG >= 8) {
+            if (rem >= 3) {
+                fft_pass<C, INV, 8, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+                lNs += 3;
+                continue;
+            }
+        }
+        if (rem >= 2) {
+            fft_pass<C, INV, 4, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+            lNs += 2;
+        } else {
+            fft_pass<C, INV, 2, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+            lNs += 1;
+        }
+    }
+}
+
+// F1: radix-R1 first forward pass from global memory into LDS.  Work item
+// (component c, bin tk, j): inputs at rows j + r L/R1, r < R1/2 (rows >= ny
+// read as zero), outputs to positions j R1 + r.
+template <typename C, int R1>
+__device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, size_t cs, int TK, int ltk, int lL,
+                                            int ny, int plane) {
+    constexpr int LR = ilog2(R1);
+    constexpr int TW = 128 / (int)sizeof(C);
+    const int lnb = lL - LR;
+    const int total = 3 << (ltk + lnb);
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int tk = it & (TK - 1);
+        const int j = (it >> ltk) & ((1 << lnb) - 1);
+        const int c = it >> (ltk + lnb);
+        const C* src = Sk + (size_t)c * cs + tk;
+        C v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int y = j + (r << lnb);
+            v[r] = (r < R1 / 2 && y < ny) ? gld(src + (size_t)y * TW) : cmk<C>(0, 0);
+        }
+        dft_small<C, false, R1>(v);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) Z[lp(c * plane + ((j << LR) + r) * TK + tk)] = v[r];
+    }
+    __syncthreads();
+}
+
+// Last inverse pass (radix R1, Ns = L/R1) from LDS straight to global memory:
+// outputs at rows j + r L/R1 for r < R1/2 and rows < ny.
+template <typename C, int R1>
+__device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, size_t cs, int TK, int ltk, int lL, int ny,
+                                           int plane, int kvalid, const C* __restrict__ tw) {
+    constexpr int LR = ilog2(R1);
+    constexpr int TW = 128 / (int)sizeof(C);
+    const int lnb = lL - LR;
+    const int total = 3 << (ltk + lnb);
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int tk = it & (TK - 1);
+        const int j = (it >> ltk) & ((1 << lnb) - 1);
+        const int c = it >> (ltk + lnb);
+        C v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) v[r] = Z[lp(c * plane + (j + (r << lnb)) * TK + tk)];
+        // twiddles of the last pass: index r * j (Ns = L / R1, so jm = j)
+#pragma unroll
+        for (int r = 1; r < R1; ++r) v[r] = cmul(v[r], cconj(tw[r * j]));
+        dft_small<C, true, R1>(v);
+        if (tk < kvalid) {
+            C* dst = Sw + (size_t)c * cs + tk;
+#pragma unroll
+            for (int r = 0; r < R1 / 2; ++r) {
+                const int y = j + (r << lnb);
+                if (y < ny) gst(dst + (size_t)y * TW, v[r]);
+            }
+        }
+    }
+}
+
+// Tensor multiply of the transformed columns in place, one work item per
+// (ky, x-bin) with the three components (2D tensor: xx, yy, zz, xy; xy odd in ky).
+template <typename T>
+__device__ __forceinline__ void col2d_mul(cplx<T>* Z, int TK, int ltk, int plane, int Py, int k0, int Kx, const T* Nt,
+                                          const T* __restrict__ Nk, int nt_lds, int Ky2) {
+    using C = cplx<T>;
+    constexpr int TW = spec_tile<T>();
+    const int total = Py << ltk;
+    const int cstr = Ky2 * TK;
+    const size_t gstr = (size_t)Ky2 * TW;
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int tk = it & (TK - 1);
+        const int ky = it >> ltk;
+        if (k0 + tk >= Kx) continue;
+        const bool fy = ky > Py / 2;
+        const int kyr = fy ? Py - ky : ky;
+        auto NT = [&](int comp) -> T {
+            return nt_lds ? Nt[comp * cstr + kyr * TK + tk] : glb(Nk)[comp * gstr + (size_t)kyr * TW + tk];
+        };
+        const T nxx = NT(0), nyy = NT(1), nzz = NT(2);
+        const T nxy = fy ? -NT(3) : NT(3);
+        const int e = ky * TK + tk;
+        const C a = Z[lp(e)], b = Z[lp(plane + e)], z = Z[lp(2 * plane + e)];
+        Z[lp(e)] = cmk<C>(nxx * a.x + nxy * b.x, nxx * a.y + nxy * b.y);
+        Z[lp(plane + e)] = cmk<C>(nxy * a.x + nyy * b.x, nxy * a.y + nyy * b.y);
+        Z[lp(2 * plane + e)] = cmk<C>(nzz * z.x, nzz * z.y);
+    }
+    __syncthreads();
+}
+
+// The whole column computation of one block for a single-layer instance.
+template <typename T, int MR>
+__device__ __forceinline__ void col2d_body(const KParams<T>& p, const InstTab& tb, int k0, int TK, int sid, int nt_lds,
+                                           unsigned char* smem_raw) {
+    using C = cplx<T>;
+    C* __restrict__ S = role<C>(tb, sid);
+    const T* __restrict__ nhat = role<T>(tb, B_NHAT);
+    const C* __restrict__ twy = role<C>(tb, B_TWY);
+    const int Py = p.Py, ny = p.ny;
+    constexpr int TW = spec_tile<T>();
+    const int kt = k0 / TW, ko = k0 % TW;
+    const size_t cs = (size_t)p.ktiles * p.nrows * TW;
+    C* __restrict__ Sk = S + (size_t)kt * p.nrows * TW + ko;  // bin k0 of row 0, component 0
+    const int NR = p.ncomp * p.Kz2 * p.Ky2;
+    const T* __restrict__ Nk = nhat + (size_t)kt * NR * TW + ko;
+    if (Py == 1) {
+        // a single row: no y transform, the multiply alone (ky = 0)
+        for (int tk = threadIdx.x; tk < TK; tk += blockDim.x) {
+            if (k0 + tk >= p.Kx) continue;
+            const auto N = glb(Nk);
+            const T nxx = N[tk], nyy = N[TW + tk], nzz = N[2 * TW + tk], nxy = N[3 * TW + tk];
+            const C a = gld(Sk + tk), b = gld(Sk + cs + tk), z = gld(Sk + 2 * cs + tk);
+            gst(Sk + tk, cmk<C>(nxx * a.x + nxy * b.x, nxx * a.y + nxy * b.y));
+            gst(Sk + cs + tk, cmk<C>(nxy * a.x + nyy * b.x, nxy * a.y + nyy * b.y));
+            gst(Sk + 2 * cs + tk, cmk<C>(nzz * z.x, nzz * z.y));
+        }
+        return;
+    }
+    const int plane = Py * TK;
+    C* Z = reinterpret_cast<C*>(smem_raw);
+    C* Tw = Z + lds_pad(3 * plane);
+    T* Nt = reinterpret_cast<T*>(Tw + Py);
+    // the tensor-spectrum tile (when kept in LDS) and the twiddles
+    constexpr int RPU = 16 / sizeof(T);
+    const int lnr = TK > RPU ? ilog2_rt(TK / RPU) : 0;
+    const int rcnt = TK < RPU ? TK : RPU;
+    const int ntu = nt_lds ? (p.ncomp * p.Ky2) << lnr : 0;
+    struct RUnit {
+        T r[RPU];
+    };
+    auto ltile = [&](int e) {
+        RUnit u;
+        const int ro = (e & ((1 << lnr) - 1)) * RPU, q = e >> lnr;
+        const auto src = glb(Nk + (size_t)q * TW + ro);
+        if (rcnt == RPU) {
+            if constexpr (sizeof(T) == 4) {
+                const vec4<float> v = *(const __attribute__((address_space(1))) vec4<float>*)src;
+                u.r[0] = v.x, u.r[1] = v.y, u.r[2] = v.z, u.r[3] = v.w;
+            } else {
+                const vec2<double> v = *(const __attribute__((address_space(1))) vec2<double>*)src;
+                u.r[0] = v.x, u.r[1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < RPU; ++k) u.r[k] = k < rcnt ? src[k] : (T)0;
+        }
+        return u;
+    };
+    auto stile = [&](int e, const RUnit& u) {
+        const int ro = (e & ((1 << lnr) - 1)) * RPU, q = e >> lnr;
+#pragma unroll
+        for (int k = 0; k < RPU; ++k)
+            if (k < rcnt) Nt[q * TK + ro + k] = u.r[k];
+    };
+    auto ltw = [&](int k) { return gld(twy + k); };
+    auto stw = [&](int k, C w) { Tw[k] = w; };
+    auto lnone = [&](int) { return 0; };
+    auto snone = [&](int, int) {};
+    gather3<4, 1, 1, RUnit, C, int>(ntu, ltile, stile, Py, ltw, stw, 0, lnone, snone);
+    __syncthreads();
+
+    const int lL = ilog2_rt(Py);
+    const int ltk = ilog2_rt(TK);
+    constexpr int LMR = ilog2(MR);
+    const int lR1 = lL < LMR ? lL : LMR;
+    const SigMap smy{ltk, plane, 1, TK};
+    // forward: the first pass from global memory, the rest in LDS
+    switch (lR1) {
+        case 1: col2d_first<C, 2>(Z, Sk, cs, TK, ltk, lL, ny, plane); break;
+        case 2: col2d_first<C, 4>(Z, Sk, cs, TK, ltk, lL, ny, plane); break;
+        case 3: col2d_first<C, 8>(Z, Sk, cs, TK, ltk, lL, ny, plane); break;
+        default:
+            if constexpr (MR >= 16) col2d_first<C, 16>(Z, Sk, cs, TK, ltk, lL, ny, plane);
+            break;
+    }
+    fft_lds_range<C, false, MR>(Z, smy, lL, lR1, lL, 3 * TK, Tw);
+    col2d_mul<T>(Z, TK, ltk, plane, Py, k0, p.Kx, Nt, Nk, nt_lds, p.Ky2);
+    // inverse: every pass but the last in LDS, the last to global memory
+    fft_lds_range<C, true, MR>(Z, smy, lL, 0, lL - lR1, 3 * TK, Tw);
+    const int kvalid = p.Kx - k0;
+    switch (lR1) {
+        case 1: col2d_last<C, 2>(Z, Sk, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
+        case 2: col2d_last<C, 4>(Z, Sk, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
+        case 3: col2d_last<C, 8>(Z, Sk, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
+        default:
+            if constexpr (MR >= 16) col2d_last<C, 16>(Z, Sk, cs, TK, ltk, lL, ny, plane, kvalid, Tw);
+            break;
+    }
+}
+
+template <typename T, int MR>
+__global__ void __launch_bounds__(MR >= 16 ? 512 : 768) k_col2d(const BatchArgs<T> ba, int TK, int sid, int nt_lds) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int2 wk = ba.work[blockIdx.x];  // (instance, first bin); XCD-grouped order, also for one instance
+    if (wk.y >= (1 << 30)) return;      // empty item that keeps the grouping stride
+    const KParams<T> p = ba.ptab[wk.x];
+    col2d_body<T, MR>(p, ba.itab[wk.x], wk.y, TK, sid, nt_lds, smem_raw);
+}
+
+// ---------------------------------------------------------------------------
 // column kernel: y (and z) transforms + tensor-spectrum multiply, in place
 // shared memory: Z [c][z < nz][y < Py][tk] complex (padded, see lp), Tw [Py] complex,
 //                Nt [comp][kz <= Pz/2][ky <= Py/2][tk] real
@@ -1032,6 +1280,11 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
     if (wk.y >= (1 << 30)) return;      // empty item that keeps the grouping stride
     const KParams<T> p = ba.ptab[wk.x];
     const InstTab& tb = ba.itab[wk.x];
+    if (p.nz == 1) {
+        // a single-layer instance of a batch with thicker ones: the same computation as its own handle runs
+        col2d_body<T, MR>(p, tb, wk.y, TK, sid, nt_lds, smem_raw);
+        return;
+    }
     C* __restrict__ S = role<C>(tb, sid);
     const T* __restrict__ nhat = role<T>(tb, B_NHAT);
     const C* __restrict__ twy = role<C>(tb, B_TWY);
@@ -1270,10 +1523,10 @@ __global__ void k_adj_init(const KParams<T>* __restrict__ ptab, const InstTab* _
     }
     if (port == 3 && W > 0) {
         // curve objective: sources of the last window state m_N (the psi term adds to the cleared dJ/dpsi)
-        const double g = role<double>(tb, B_PSRC)[2 * (size_t)(W - 1)];
+        const double* g = role<double>(tb, B_PSRC) + 2 * (size_t)(W - 1);
         const T pi = role<T>(tb, B_PSI)[i];
-        l.x = l.x + (T)g * pi;
-        role<double>(tb, B_GPSI)[i] += g * (double)role<T>(tb, B_M)[i];
+        l.x = l.x + (T)g[0] * pi;
+        role<double>(tb, B_GPSI)[i] += g[0] * (double)role<T>(tb, B_M)[i] - g[1];
     }
     if (port == 2 && W > 0 && (p.n_p1 + p.n_p2) > 0) {
         // spectral objective: the stored source of the last window state m_N
@@ -1473,9 +1726,11 @@ __global__ __launch_bounds__(256) void k_spec_src(const KParams<T>* __restrict__
     out[1] = p.n_p2 > 0 ? g2 / ((double)W * p.n_p2) : 0.0;
 }
 
-// Curve objective (Eq. 8): per window step n, M(n) = sum over the row-pair
-// blocks of the stored psi m_x sums / N (block order) and the source
-// g_n = weight_n sign(M(n) - target_n) / N.  grid (ceil(W / 256), instances).
+// Curve objective (Eq. 8): per window step n, the particle average
+// M(n) = sum psi m_x / sum psi from the row-pair blocks' stored sums (block
+// order; M = 0 without material) and the sources c_n = weight_n sign(M(n) -
+// target_n) / sum psi and c_n M(n): dJ/dm_x,i(n) = c_n psi_i and
+// dJ/dpsi_i += c_n m_x,i(n) - c_n M(n).  grid (ceil(W / 256), instances).
 template <typename T>
 __global__ __launch_bounds__(256) void k_curve_series(const KParams<T>* __restrict__ ptab,
                                                       const InstTab* __restrict__ itab,
@@ -1486,14 +1741,18 @@ __global__ __launch_bounds__(256) void k_curve_series(const KParams<T>* __restri
     const KParams<T>& p = ptab[inst];
     const InstTab& tb = itab[inst];
     const double* part = role<double>(tb, B_PSER) + (size_t)n * 2 * p.nloc;
-    double s = 0.0;
-    for (int b = 0; b < p.nloc; ++b) s += part[2 * b];
-    const double M = s / p.N;
+    double s = 0.0, S = 0.0;
+    for (int b = 0; b < p.nloc; ++b) {
+        s += part[2 * b];
+        S += part[2 * b + 1];
+    }
+    const double M = S != 0.0 ? s / S : 0.0;
     const double d = M - tw[n];
     role<double>(tb, B_SER)[2 * (size_t)n] = M;
     double* g = role<double>(tb, B_PSRC) + 2 * (size_t)n;
-    g[0] = tw[W + n] * (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) / p.N;
-    g[1] = 0.0;
+    const double c = S != 0.0 ? tw[W + n] * (d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0)) / S : 0.0;
+    g[0] = c;
+    g[1] = c * M;
 }
 
 // One block per instance: J = sum_n weight_n |M(n) - target_n|, fixed order.
@@ -1807,8 +2066,12 @@ static void stage_bwd_r(const BatchDev<T>& b, const BwdL& L, hipStream_t s, hipE
 }
 template <typename T, int NZ, int MR>
 static void col_r(const BatchDev<T>& b, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL((k_col_conv<T, NZ, MR>), dim3(b.ncol), dim3(b.col_threads), (uint32_t)b.col_lds, s, e0, e1, 0,
-                          bargs(b, b.work_col), b.col_tk, spec, b.col_nt_lds);
+    if constexpr (NZ == 1)
+        hipExtLaunchKernelGGL((k_col2d<T, MR>), dim3(b.ncol), dim3(b.col_threads), (uint32_t)b.col_lds, s, e0, e1, 0,
+                              bargs(b, b.work_col), b.col_tk, spec, b.col_nt_lds);
+    else
+        hipExtLaunchKernelGGL((k_col_conv<T, NZ, MR>), dim3(b.ncol), dim3(b.col_threads), (uint32_t)b.col_lds, s, e0,
+                              e1, 0, bargs(b, b.work_col), b.col_tk, spec, b.col_nt_lds);
 }
 template <typename T, int NZ>
 static void col_nz(const BatchDev<T>& b, int spec, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
@@ -1867,7 +2130,10 @@ int col_conv_vgprs(int max_nz, int radix) {
         f = r == 4 ? reinterpret_cast<const void*>(k_col_conv<T, Z, 4>)                               \
                    : r == 8 ? reinterpret_cast<const void*>(k_col_conv<T, Z, 8>)                      \
                             : reinterpret_cast<const void*>(k_col_conv<T, Z, RT>);
-    LLG_PICK(1) else LLG_PICK(2) else LLG_PICK(4) else LLG_PICK(8)
+    if (z == 1)
+        f = r == 4 ? reinterpret_cast<const void*>(k_col2d<T, 4>)
+                   : r == 8 ? reinterpret_cast<const void*>(k_col2d<T, 8>) : reinterpret_cast<const void*>(k_col2d<T, RT>);
+    else LLG_PICK(2) else LLG_PICK(4) else LLG_PICK(8)
 #undef LLG_PICK
     hipFuncAttributes at;
     if (hipFuncGetAttributes(&at, f) != hipSuccess) {
@@ -2030,15 +2296,15 @@ hipError_t set_lds_limits(size_t bytes) {
     LLG_ATTR((k_stage_bwd<T, 4, true>))
     LLG_ATTR((k_stage_bwd<T, 8, true>))
     LLG_ATTR((k_stage_bwd<T, RT, true>))
-    LLG_ATTR((k_col_conv<T, 1, 4>))
+    LLG_ATTR((k_col2d<T, 4>))
+    LLG_ATTR((k_col2d<T, 8>))
+    LLG_ATTR((k_col2d<T, RT>))
     LLG_ATTR((k_col_conv<T, 2, 4>))
     LLG_ATTR((k_col_conv<T, 4, 4>))
     LLG_ATTR((k_col_conv<T, 8, 4>))
-    LLG_ATTR((k_col_conv<T, 1, 8>))
     LLG_ATTR((k_col_conv<T, 2, 8>))
     LLG_ATTR((k_col_conv<T, 4, 8>))
     LLG_ATTR((k_col_conv<T, 8, 8>))
-    LLG_ATTR((k_col_conv<T, 1, RT>))
     LLG_ATTR((k_col_conv<T, 2, RT>))
     LLG_ATTR((k_col_conv<T, 4, RT>))
     LLG_ATTR((k_col_conv<T, 8, RT>))

@@ -481,6 +481,8 @@ int llg_rbf_levelset_vjp(int32_t dtype, int32_t nx, int32_t ny, int32_t n_rbf, c
 }
 
 int llg_rbf_profile(int enable) {
+    if (enable && llg::counter_collection_active())
+        return llg::set_error(LLG_ENOTSUP, "event-timed dispatches are not used while hardware counters are collected");
     if (int rc = prof_drain()) return rc;
     RbfProf& P = prof();
     std::lock_guard<std::mutex> g(P.mu);

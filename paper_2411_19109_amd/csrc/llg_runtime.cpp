@@ -730,7 +730,7 @@ struct Ops {
         switch (L.stage) {
             case 0: b += n * 6 * t; break;
             case 1: case 2: b += n * 12 * t; break;
-            case 3: b += n * 6 * t; break;
+            case 3: b += n * 9 * t; break;
             case -1: b += n * 3 * t * (L.ext_ynext ? 2 : 1); break;
             default: break;
         }
@@ -1980,6 +1980,8 @@ int llg_set_graphs(llg_handle* h, int enable) {
 
 int llg_profile(llg_handle* h, int enable) {
     if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (enable && counter_collection_active())
+        return fail(LLG_ENOTSUP, "event-timed dispatches are not used while hardware counters are collected");
     if (int rc = drain_profile(h)) return rc;
     h->prof_on = enable != 0;
     return LLG_OK;
@@ -1997,6 +1999,18 @@ int llg_profile_read(llg_handle* h, int32_t kind, double* ms, int64_t* launches,
         h->prof_n[kind] = 0;
         h->prof_bytes[kind] = 0;
     }
+    return LLG_OK;
+}
+
+int llg_demag_tensor(double dx, double dy, double dz, double X, double Y, double Z, int32_t method, double* out) {
+    if (!out) return fail(LLG_EINVAL, "out is NULL");
+    if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !std::isfinite(dx) || !std::isfinite(dy) || !std::isfinite(dz))
+        return fail(LLG_EINVAL, "cell edges must be finite and > 0");
+    if (!std::isfinite(X) || !std::isfinite(Y) || !std::isfinite(Z)) return fail(LLG_EINVAL, "non-finite offset");
+    if (method < 0 || method > 2) return fail(LLG_EINVAL, "method must be 0, 1 or 2");
+    if (method == 2 && std::sqrt(X * X + Y * Y + Z * Z) < 2.0 * std::fmax(dx, std::fmax(dy, dz)))
+        return fail(LLG_EINVAL, "quadrature needs centres at least two largest cell edges apart");
+    tensor_at_mode(X, Y, Z, dx, dy, dz, method, out);
     return LLG_OK;
 }
 

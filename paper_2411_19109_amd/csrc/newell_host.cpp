@@ -5,8 +5,9 @@
 // autocorrelation T(s) = prod (h_d - |s_d|)_+ and D(p) = -(3 p p^T/|p|^2 - I)/(4 pi |p|^3);
 // it discretises the paper's dipole-dipole field term (Methods).  Close cells
 // use Newell, Williams & Dunlop's closed form (J. Geophys. Res. 98, 9551, 1993);
-// separated cells use Gauss-Legendre quadrature of the integral, split at the
-// tent's kink, because the closed form cancels catastrophically (~eps R^6).
+// separated cells use Gauss-Jacobi quadrature of the integral on each half of
+// the tent (weight (h - s) on [0, h]), because the closed form cancels
+// catastrophically (~eps R^6).
 //
 // The spectrum is the DFT of the zero-padded kernel.  The diagonal components
 // are even in every offset and the off-diagonal ones odd in their two axes, so
@@ -70,113 +71,151 @@ void closed_form(double X, double Y, double Z, double hx, double hy, double hz, 
     o[5] = c * second_diff(newell_g, Y, Z, X, hy, hz, hx);
 }
 
-// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
-void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+// Far field: the tent integral by Gauss-Jacobi quadrature.  On each half of
+// the tent, int_0^h (h - s) f(s) ds = (h^2 / 4) int_{-1}^{1} (1 - x) f(h (1 + x) / 2) dx,
+// a Jacobi weight (1 - x)^1 (1 + x)^0.  Its n-point Gauss rule (exact for
+// polynomials of degree 2n - 1) has nodes at the eigenvalues of the Jacobi
+// matrix of the monic recurrence, here diagonal a_k = -1 / ((2k + 1)(2k + 3))
+// and off-diagonal b_k = sqrt(k (k + 1)) / (2k + 1); the nodes are found by
+// Sturm-sequence bisection and the weights from the orthonormal polynomials,
+// w_i = mu_0 / sum_k q_k(x_i)^2 with mu_0 = int (1 - x) dx = 2.
+struct Rule1 {
+    std::vector<double> s, w;  // nodes on [-h, h] and weights of int (h - |s|) f(s) ds
+};
+
+void jacobi10_rule(int n, std::vector<double>& x, std::vector<double>& w) {
+    std::vector<double> a(n), b(n, 0.0);  // b[k] couples rows k-1 and k
+    for (int k = 0; k < n; ++k) {
+        a[k] = -1.0 / ((2.0 * k + 1.0) * (2.0 * k + 3.0));
+        if (k > 0) b[k] = std::sqrt((double)k * (k + 1.0)) / (2.0 * k + 1.0);
+    }
+    // number of eigenvalues below t (Sturm sequence of the leading minors)
+    auto below = [&](double t) {
+        int cnt = 0;
+        double d = 1.0;
+        for (int k = 0; k < n; ++k) {
+            d = (a[k] - t) - (k > 0 ? b[k] * b[k] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    };
     x.assign(n, 0.0);
     w.assign(n, 0.0);
     for (int i = 0; i < n; ++i) {
-        double t = std::cos(kPi * (i + 0.75) / (n + 0.5));
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1.0, p1 = t;
-            for (int k = 2; k <= n; ++k) {
-                double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            // p1 = P_n(t), p0 = P_{n-1}(t)
-            double dp = n * (t * p1 - p0) / (t * t - 1.0);
-            double dt = p1 / dp;
-            t -= dt;
-            if (std::fabs(dt) < 1e-16) break;
+        double lo = -1.0, hi = 1.0;  // every node lies inside (-1, 1)
+        for (int it = 0; it < 200 && hi - lo > 4e-17; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (below(mid) > i) hi = mid; else lo = mid;
         }
-        double p0 = 1.0, p1 = t;
-        for (int k = 2; k <= n; ++k) {
-            double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
-            p0 = p1;
-            p1 = p2;
+        const double t = 0.5 * (lo + hi);
+        // orthonormal polynomials q_k(t): q_0 = 1 / sqrt(mu_0) up to the common factor
+        double q0 = 1.0, q1 = (t - a[0]) / (n > 1 ? b[1] : 1.0), sum = 1.0;
+        if (n > 1) sum += q1 * q1;
+        for (int k = 1; k + 1 < n; ++k) {
+            const double q2 = ((t - a[k]) * q1 - b[k] * q0) / b[k + 1];
+            sum += q2 * q2;
+            q0 = q1;
+            q1 = q2;
         }
-        double dp = n * (t * p1 - p0) / (t * t - 1.0);
         x[i] = t;
-        w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+        w[i] = 2.0 / sum;
     }
 }
 
-// Nodes s and weights on [-h, h] for int (h - |s|) f(s) ds, n points per half.
-void tent_rule(double h, int n, std::vector<double>& s, std::vector<double>& ws) {
-    std::vector<double> t, w;
-    gauss_legendre(n, t, w);
-    s.resize(2 * n);
-    ws.resize(2 * n);
+// Both halves of the tent on [-h, h], n nodes each.
+void tent_jacobi(double h, int n, Rule1& r) {
+    std::vector<double> x, w;
+    jacobi10_rule(n, x, w);
+    r.s.assign(2 * n, 0.0);
+    r.w.assign(2 * n, 0.0);
     for (int i = 0; i < n; ++i) {
-        double si = 0.5 * h * (t[i] + 1.0);
-        double wi = 0.5 * h * w[i] * (h - si);
-        s[i] = si;
-        ws[i] = wi;
-        s[n + i] = -si;
-        ws[n + i] = wi;
+        const double si = 0.5 * h * (1.0 + x[i]);
+        const double wi = 0.25 * h * h * w[i];
+        r.s[i] = si;
+        r.w[i] = wi;
+        r.s[n + i] = -si;
+        r.w[n + i] = wi;
     }
 }
 
-struct Rule {
-    std::vector<double> sx, wx, sy, wy, sz, wz;
+struct Rule3 {
+    Rule1 x, y, z;
 };
 
-void quadrature(double X, double Y, double Z, double V, const Rule& q, double o[6]) {
-    double a[6] = {0, 0, 0, 0, 0, 0};
-    for (size_t i = 0; i < q.sx.size(); ++i) {
-        const double px = X + q.sx[i];
-        for (size_t j = 0; j < q.sy.size(); ++j) {
-            const double py = Y + q.sy[j];
-            const double wij = q.wx[i] * q.wy[j];
-            for (size_t k = 0; k < q.sz.size(); ++k) {
-                const double pz = Z + q.sz[k];
-                const double r2 = px * px + py * py + pz * pz;
-                const double ir = 1.0 / std::sqrt(r2);
-                const double ir3 = ir / r2, ir5 = ir3 / r2;
-                const double w = wij * q.wz[k];
-                a[0] += w * (ir3 - 3.0 * px * px * ir5);
-                a[1] += w * (ir3 - 3.0 * py * py * ir5);
-                a[2] += w * (ir3 - 3.0 * pz * pz * ir5);
-                a[3] += w * (-3.0 * px * py * ir5);
-                a[4] += w * (-3.0 * px * pz * ir5);
-                a[5] += w * (-3.0 * py * pz * ir5);
+// N(r) = (1/V) sum_ijk W_i W_j W_k D(r + (s_i, s_j, s_k)), D(p) = (I/|p|^3 - 3 p p^T/|p|^5) / (4 pi).
+void tent_sum(double X, double Y, double Z, double V, const Rule3& q, double o[6]) {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (size_t k = 0; k < q.z.s.size(); ++k) {
+        const double pz = Z + q.z.s[k];
+        for (size_t j = 0; j < q.y.s.size(); ++j) {
+            const double py = Y + q.y.s[j];
+            const double wjk = q.y.w[j] * q.z.w[k];
+            for (size_t i = 0; i < q.x.s.size(); ++i) {
+                const double px = X + q.x.s[i];
+                const double p2 = px * px + py * py + pz * pz;
+                const double inv = 1.0 / (p2 * std::sqrt(p2));  // |p|^-3
+                const double w = wjk * q.x.w[i] * inv;
+                const double w3 = 3.0 * w / p2;                  // 3 w |p|^-2
+                acc[0] += w - w3 * px * px;
+                acc[1] += w - w3 * py * py;
+                acc[2] += w - w3 * pz * pz;
+                acc[3] -= w3 * px * py;
+                acc[4] -= w3 * px * pz;
+                acc[5] -= w3 * py * pz;
             }
         }
     }
     const double c = 1.0 / (4.0 * kPi * V);
-    for (int i = 0; i < 6; ++i) o[i] = a[i] * c;
+    for (int i = 0; i < 6; ++i) o[i] = acc[i] * c;
 }
 
-const Rule& rule_for(double hx, double hy, double hz, int n) {
-    // small cache keyed on (h, n); problems use a single cell shape
-    struct Entry { double hx, hy, hz; int n; Rule r; };
+const Rule3& rule3(double hx, double hy, double hz, int n) {
+    // per-thread cache keyed on the cell and the order; a problem uses one cell shape
+    struct Entry {
+        double hx, hy, hz;
+        int n;
+        Rule3 r;
+    };
     static thread_local std::vector<Entry> cache;
     for (auto& e : cache)
         if (e.hx == hx && e.hy == hy && e.hz == hz && e.n == n) return e.r;
     Entry e{hx, hy, hz, n, {}};
-    tent_rule(hx, n, e.r.sx, e.r.wx);
-    tent_rule(hy, n, e.r.sy, e.r.wy);
-    tent_rule(hz, n, e.r.sz, e.r.wz);
+    tent_jacobi(hx, n, e.r.x);
+    tent_jacobi(hy, n, e.r.y);
+    tent_jacobi(hz, n, e.r.z);
     cache.push_back(std::move(e));
     return cache.back().r;
 }
 
+// Nodes per tent half for centres q = |r| / h_max apart (q >= 2).  The
+// integrand's singularity at r + s = 0 moves away from the integration box as q
+// grows, so Gauss convergence is geometric in q; the orders keep the rule's
+// error near 1e-14 of the largest component (checked against the closed form
+// and against 96-point Gauss-Legendre quadrature of the same integral).
+int far_order(double q) {
+    return q < 2.0 ? 20 : (q < 3.0 ? 16 : (q < 5.0 ? 12 : (q < 10.0 ? 8 : (q < 24.0 ? 6 : (q < 64.0 ? 4 : 3)))));
+}
+
 }  // namespace
 
-void tensor_at(double X, double Y, double Z, double hx, double hy, double hz, double out[6]) {
-    // Euclidean distance of the nearest point of the integrand's support from
-    // the origin, in units of the largest edge: closed form below 1.5,
-    // quadrature above (8 / 5 / 4 points per half-axis as the gap grows).
-    const double gx = std::fmax(std::fabs(X) - hx, 0.0);
-    const double gy = std::fmax(std::fabs(Y) - hy, 0.0);
-    const double gz = std::fmax(std::fabs(Z) - hz, 0.0);
-    const double q = std::sqrt(gx * gx + gy * gy + gz * gz) / std::fmax(hx, std::fmax(hy, hz));
-    if (q < 1.5) {
+void tensor_at_mode(double X, double Y, double Z, double hx, double hy, double hz, int mode, double out[6]) {
+    // mode 0: closed form for centres less than two largest cell edges apart,
+    // the tent quadrature beyond (there it is accurate to ~1e-14 while the
+    // closed form's cancellation grows like the sixth power of the distance);
+    // 1: closed form only; 2: quadrature only.
+    const double hm = std::fmax(hx, std::fmax(hy, hz));
+    const double q = std::sqrt(X * X + Y * Y + Z * Z) / hm;
+    const bool closed = mode == 1 || (mode == 0 && q < 2.0);
+    if (closed) {
         closed_form(X, Y, Z, hx, hy, hz, out);
         return;
     }
-    const int n = q <= 8.0 ? 8 : (q <= 30.0 ? 5 : 4);
-    quadrature(X, Y, Z, hx * hy * hz, rule_for(hx, hy, hz, n), out);
+    tent_sum(X, Y, Z, hx * hy * hz, rule3(hx, hy, hz, far_order(q)), out);
+}
+
+void tensor_at(double X, double Y, double Z, double hx, double hy, double hz, double out[6]) {
+    tensor_at_mode(X, Y, Z, hx, hy, hz, 0, out);
 }
 
 void build_tensor_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, int Px, int Py, int Pz,

@@ -30,7 +30,7 @@ EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_le
            "llg_batch_forward", "llg_batch_adjoint", "llg_rbf_work_len", "llg_rbf_levelset", "llg_rbf_levelset_vjp",
            "llg_adam_step", "llg_rbf_profile", "llg_rbf_profile_read", "llg_shape_penalty", "llg_forward_adaptive",
            "llg_adaptive_steps", "llg_adjoint_adaptive", "llg_adjoint_continuous",
-           "llg_set_keep_stages"]
+           "llg_set_keep_stages", "llg_demag_tensor"]
 RBF_KIND_NAMES = {0: "k_rbf_cones", 1: "k_rbf_pnorm", 2: "k_rbf_vjp"}
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
 KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col_conv", KIND_STAGE_BWD: "k_stage_bwd"}
@@ -122,6 +122,7 @@ def lib():
         "llg_adjoint_adaptive": [vp, vp, vp, vp, vp, vp, vp],
         "llg_adjoint_continuous": [vp, vp, vp, vp, ctypes.c_int, vp, vp, vp],
         "llg_set_keep_stages": [vp, ctypes.c_int],
+        "llg_demag_tensor": [dbl, dbl, dbl, dbl, dbl, dbl, i32, ctypes.POINTER(dbl)],
         "llg_rbf_profile_read": [i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.c_int],
     }
     for name, args in sig.items():
@@ -212,6 +213,17 @@ def query_recompute(n_steps, policy=LLG_CKPT_SQRT, ckpt_param=0) -> int:
     v = ctypes.c_int64(0)
     check(lib().llg_query_recompute(n_steps, policy, ckpt_param, ctypes.byref(v)))
     return v.value
+
+
+def demag_tensor(h, r, method=0):
+    """The library's demagnetising tensor between cells of edges h = (dx, dy, dz)
+    whose centres are r = (X, Y, Z) apart (host float64): N_xx, N_yy, N_zz,
+    N_xy, N_xz, N_yz.  method 0 as the library builds it, 1 closed form,
+    2 quadrature."""
+    out = (ctypes.c_double * 6)()
+    check(lib().llg_demag_tensor(float(h[0]), float(h[1]), float(h[2]), float(r[0]), float(r[1]), float(r[2]),
+                                 int(method), out))
+    return np.array(out[:], dtype=np.float64)
 
 
 def _ptr(t):

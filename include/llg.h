@@ -230,6 +230,20 @@ int llg_adjoint(llg_handle* h, const void* psi, const void* dJdm_T, const double
 int llg_shape_penalty(llg_handle* h, const void* psi, double xi, double S_target, double nu, double x0, double y0,
                       double* J_dev, double* dJdpsi_out, hipStream_t stream);
 
+/* llg_shape_penalty for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels and results, but its block partial sums live in a
+ * static device array of the library (one per GPU, 786 496 bytes, held until
+ * the process ends) instead of the handle's scratch, which llg_shape_penalty
+ * allocates on its first call.  Nothing is allocated: the array's device
+ * address is looked up once per device.  At most 8 388 608 nodes (2^23);
+ * larger grids return LLG_ENOMEM before any device work.  Every call on a GPU
+ * uses that GPU's one array and nothing in it carries over between calls (each
+ * call writes what it reads), but calls that overlap in time on one GPU (other
+ * streams, other threads) race on it: order them on one stream. */
+int llg_shape_penalty_noalloc(llg_handle* h, const void* psi, double xi, double S_target, double nu, double x0,
+                              double y0, double* J_dev, double* dJdpsi_out, hipStream_t stream);
+
 /* ---- adaptive integration --------------------------------------------
  * The Methods integrate adaptively: embedded Dormand-Prince 5(4) steps (fifth
  * order carried, fourth order for the estimate) from m0 at t0 to exactly t_end,

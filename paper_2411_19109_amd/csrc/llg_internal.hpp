@@ -277,6 +277,12 @@ template <typename T>
 hipError_t launch_shape(const T* psi, int nx, int ny, int nz, double xi, double S_target, double nu, double x0,
                         double y0, double* work, double* J, double* g, hipStream_t s);
 template <typename T> hipError_t launch_curve(const BatchDev<T>& b, const double* tw, int W, hipStream_t s);
+
+// Allocation-free shape penalty: nodes its static scratch covers, and the
+// device address of that scratch on the current device (looked up once per
+// device with hipGetSymbolAddress; no allocation).
+constexpr int kShapeMaxNodes = 1 << 23;
+hipError_t shape_scratch_ptr(double** out);
 template <typename T>
 hipError_t launch_spectral(const BatchDev<T>& b, const double* fc, int K, int W, double t0, int64_t n_start, double dt,
                            hipStream_t s);

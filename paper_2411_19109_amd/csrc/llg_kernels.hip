@@ -2232,6 +2232,33 @@ hipError_t launch_shape(const T* psi, int nx, int ny, int nz, double xi, double 
     if (g) hipLaunchKernelGGL(k_shape_grad, dim3(nb), dim3(256), 0, s, nx, ny, N, work, g);
     return hipGetLastError();
 }
+// File-scope scratch of the allocation-free shape-penalty call: the block
+// partial sums (3 per 256 nodes) and the five finishing coefficients of at most
+// kShapeMaxNodes nodes.  One copy per GPU, held until the process ends.  Host
+// code never passes `scratch` itself to a kernel (in host code the name is a
+// host-side stand-in); it passes the per-device address that
+// hipGetSymbolAddress returns.
+constexpr int kShapeScratchDoubles = 8 + 3 * ((kShapeMaxNodes + 255) / 256);
+static __device__ __align__(256) double scratch[kShapeScratchDoubles];
+
+hipError_t shape_scratch_ptr(double** out) {
+    static std::mutex mu;
+    static double* ptrs[64] = {nullptr};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptrs[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptrs[dev] = static_cast<double*>(p);
+    }
+    *out = ptrs[dev];
+    return hipSuccess;
+}
+
 template <typename T>
 hipError_t launch_curve(const BatchDev<T>& b, const double* tw, int W, hipStream_t s) {
     hipLaunchKernelGGL(k_curve_series<T>, dim3((W + 255) / 256, b.ninst), dim3(256), 0, s, b.ptab, b.itab, tw, W);

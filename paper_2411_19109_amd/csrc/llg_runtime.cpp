@@ -2311,4 +2311,29 @@ int llg_shape_penalty(llg_handle* h, const void* psi, double xi, double S_target
     return LLG_OK;
 }
 
+int llg_shape_penalty_noalloc(llg_handle* h, const void* psi, double xi, double S_target, double nu, double x0,
+                              double y0, double* J_dev, double* dJdpsi_out, hipStream_t stream) {
+    int rc;
+    if (!h) return fail(LLG_EINVAL, "handle is NULL");
+    if (h->inst.size() != 1) return fail(LLG_EINVAL, "single-instance call on a batch");
+    if ((rc = check_ptr(psi, "psi")) || (rc = check_ptr(J_dev, "J_dev"))) return rc;
+    const double vals[] = {xi, S_target, nu, x0, y0};
+    for (double v : vals)
+        if (!std::isfinite(v)) return fail(LLG_EINVAL, "constraint parameters must be finite");
+    const llg_problem& q = h->inst[0].prob;
+    const size_t N = h->inst[0].N;
+    if (N > (size_t)kShapeMaxNodes)
+        return fail(LLG_ENOMEM, "llg_shape_penalty_noalloc: " + std::to_string(N) + " nodes exceed its scratch (" +
+                                    std::to_string(kShapeMaxNodes) + " nodes)");
+    double* work = nullptr;
+    hipError_t e = shape_scratch_ptr(&work);
+    if (e != hipSuccess) return fail(LLG_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+    e = h->dtype == LLG_F32 ? launch_shape<float>((const float*)psi, q.nx, q.ny, q.nz, xi, S_target, nu, x0, y0, work,
+                                                  J_dev, dJdpsi_out, stream)
+                            : launch_shape<double>((const double*)psi, q.nx, q.ny, q.nz, xi, S_target, nu, x0, y0,
+                                                   work, J_dev, dJdpsi_out, stream);
+    if (e != hipSuccess) return fail(LLG_EHIP, std::string("shape constraint launch: ") + hipGetErrorString(e));
+    return LLG_OK;
+}
+
 }  // extern "C"

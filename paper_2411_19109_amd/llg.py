@@ -30,7 +30,7 @@ EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_le
            "llg_batch_forward", "llg_batch_adjoint", "llg_rbf_work_len", "llg_rbf_levelset", "llg_rbf_levelset_vjp",
            "llg_adam_step", "llg_rbf_profile", "llg_rbf_profile_read", "llg_shape_penalty", "llg_forward_adaptive",
            "llg_adaptive_steps", "llg_adjoint_adaptive", "llg_adjoint_continuous",
-           "llg_set_keep_stages", "llg_demag_tensor"]
+           "llg_set_keep_stages", "llg_demag_tensor", "llg_shape_penalty_noalloc"]
 RBF_KIND_NAMES = {0: "k_rbf_cones", 1: "k_rbf_pnorm", 2: "k_rbf_vjp"}
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
 KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col_conv", KIND_STAGE_BWD: "k_stage_bwd"}
@@ -117,6 +117,7 @@ def lib():
         "llg_adam_step": [i32, vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, vp],
         "llg_rbf_profile": [ctypes.c_int],
         "llg_shape_penalty": [vp, vp, dbl, dbl, dbl, dbl, dbl, vp, vp, vp],
+        "llg_shape_penalty_noalloc": [vp, vp, dbl, dbl, dbl, dbl, dbl, vp, vp, vp],
         "llg_forward_adaptive": [vp, vp, vp, dbl, dbl, dbl, dbl, dbl, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp],
         "llg_adaptive_steps": [vp, ctypes.POINTER(dbl), i64],
         "llg_adjoint_adaptive": [vp, vp, vp, vp, vp, vp, vp],
@@ -380,6 +381,14 @@ class Solver:
         g = torch.empty(self.N, dtype=torch.float64, device=psi.device) if want_grad else None
         check(lib().llg_shape_penalty(self.h, _ptr(psi), float(xi), float(S_target), float(nu), float(x0), float(y0),
                                       _ptr(J), _ptr(g), _stream()))
+        return J, g
+
+    def shape_penalty_noalloc(self, psi, xi, S_target, nu, x0, y0, J, g=None):
+        """shape_penalty into caller-provided J (1 double) and g (N doubles or
+        None), through the entry point that allocates no device memory."""
+        self._t(psi, self.N)
+        check(lib().llg_shape_penalty_noalloc(self.h, _ptr(psi), float(xi), float(S_target), float(nu), float(x0),
+                                              float(y0), _ptr(J), _ptr(g), _stream()))
         return J, g
 
     def field(self, psi, m, t=0.0, want_rhs=False):

@@ -457,7 +457,8 @@ def measured_traffic(workload, kernel, launch, source="llg_kernels.hip"):
     if rec.get("launch") is not None and list(rec["launch"]) != list(launch):
         return None
     for name, v in rec["kernels"].items():
-        if name.split("<")[0] == kernel:
+        base = name.split("<")[0]
+        if base == kernel or (kernel == "k_col" and base.startswith("k_col")):
             return round(v["hbm_bytes"])
     return None
 

@@ -247,9 +247,11 @@ template <typename T>
 hipError_t launch_adj_init(const BatchDev<T>& b, int lam_sel, int use_djdm, int port, int W, hipStream_t s);
 template <typename T> hipError_t launch_psi_grad_out(const BatchDev<T>& b, int use_expl, hipStream_t s);
 template <typename T> hipError_t launch_zero(const BatchDev<T>& b, int sel, int what, hipStream_t s);
-template <typename T> hipError_t launch_fill(const BatchDev<T>& b, int sel, int mult, double v, hipStream_t s);
+// role[off N + e] = v for e < mult N (a fill kernel, also under graph capture)
 template <typename T>
-hipError_t launch_copy(const BatchDev<T>& b, int src, int src_slot, int dst, int dst_slot, hipStream_t s);
+hipError_t launch_fill(const BatchDev<T>& b, int sel, int mult, double v, hipStream_t s, int off = 0);
+template <typename T>
+hipError_t launch_copy(const BatchDev<T>& b, int src, int src_slot, int dst, int dst_slot, int mult, hipStream_t s);
 template <typename T> hipError_t launch_port_finish(const BatchDev<T>& b, int W, hipStream_t s);
 // Spectral objective after a forward run: series from the per-step partials, DFT
 // parts at the K sample frequencies, J, and the per-step adjoint sources.  fc

@@ -203,6 +203,14 @@ template <typename T> __device__ __forceinline__ V3<T> cross(V3<T> a, V3<T> b) {
     return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 template <typename T> __device__ __forceinline__ T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+// Knuth's error-free two-sum: s = fl(x + y) and x + y = s + e exactly
+template <typename T> __device__ __forceinline__ T two_sum(T x, T y, T& e) {
+    const T s = x + y;
+    const T bp = s - x;
+    const T ap = s - bp;
+    e = (x - ap) + (y - bp);
+    return s;
+}
 
 // The buffers behind the tables and launch descriptors are device global
 // memory.  Accessing them through global-space pointers gives global rather
@@ -717,6 +725,15 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             } else if (a.stage == 2) {
                 st3(a.acc, N, i, accv + (dt / (T)3) * f);
                 yn = mnv + dt * f;
+            } else if constexpr (sizeof(T) == 4) {
+                // float state kept as hi + lo (lo at offset 3N of the state buffer): m_{n+1} = hi + (lo + increment)
+                // by an error-free two-sum, so that rounding to float does not accumulate over the steps
+                const V3<T> d = accv + (dt / (T)6) * f;
+                const V3<T> lo = ld3(a.mn + (size_t)3 * N, N, i);
+                V3<T> e;
+                yn = v3<T>(two_sum(mnv.x, d.x + lo.x, e.x), two_sum(mnv.y, d.y + lo.y, e.y),
+                           two_sum(mnv.z, d.z + lo.z, e.z));
+                st3(a.ynext + (size_t)3 * N, N, i, e);
             } else {
                 yn = mnv + (accv + (dt / (T)6) * f);
             }
@@ -1557,20 +1574,21 @@ __global__ void k_zero(const KParams<T>* __restrict__ ptab, const InstTab* __res
     if (i < n) role<double>(itab[inst], sel)[i] = 0.0;
 }
 
-// role[e] = v for e < mult * N of every instance
+// role[off * N + e] = v for e < mult * N of every instance
 template <typename T>
-__global__ void k_fill(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, int sel, int mult, T v) {
+__global__ void k_fill(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, int sel, int mult, T v,
+                       int off) {
     const int inst = blockIdx.y;
     const size_t n = (size_t)mult * ptab[inst].N;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) role<T>(itab[inst], sel)[i] = v;
+    if (i < n) role<T>(itab[inst], sel)[(size_t)off * ptab[inst].N + i] = v;
 }
 
 template <typename T>
 __global__ void k_copy(const KParams<T>* __restrict__ ptab, const InstTab* __restrict__ itab, int src, int src_slot,
-                       int dst, int dst_slot) {
+                       int dst, int dst_slot, int mult) {
     const int inst = blockIdx.y;
-    const size_t n3 = (size_t)3 * ptab[inst].N;
+    const size_t n3 = (size_t)3 * mult * ptab[inst].N;
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n3) return;
     const InstTab& tb = itab[inst];
@@ -2196,13 +2214,15 @@ hipError_t launch_zero(const BatchDev<T>& b, int sel, int what, hipStream_t s) {
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_fill(const BatchDev<T>& b, int sel, int mult, double v, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill<T>, elem_grid(b, mult * (b.max_n3 / 3)), dim3(256), 0, s, b.ptab, b.itab, sel, mult, (T)v);
+hipError_t launch_fill(const BatchDev<T>& b, int sel, int mult, double v, hipStream_t s, int off) {
+    hipLaunchKernelGGL(k_fill<T>, elem_grid(b, mult * (b.max_n3 / 3)), dim3(256), 0, s, b.ptab, b.itab, sel, mult, (T)v,
+                       off);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_copy(const BatchDev<T>& b, int src, int src_slot, int dst, int dst_slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy<T>, elem_grid(b, b.max_n3), dim3(256), 0, s, b.ptab, b.itab, src, src_slot, dst, dst_slot);
+hipError_t launch_copy(const BatchDev<T>& b, int src, int src_slot, int dst, int dst_slot, int mult, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy<T>, elem_grid(b, mult * b.max_n3), dim3(256), 0, s, b.ptab, b.itab, src, src_slot, dst,
+                       dst_slot, mult);
     return hipGetLastError();
 }
 template <typename T>
@@ -2352,8 +2372,8 @@ hipError_t set_lds_limits(size_t bytes) {
     template hipError_t launch_adj_init<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                     \
     template hipError_t launch_psi_grad_out<T>(const BatchDev<T>&, int, hipStream_t);                               \
     template hipError_t launch_zero<T>(const BatchDev<T>&, int, int, hipStream_t);                                  \
-    template hipError_t launch_fill<T>(const BatchDev<T>&, int, int, double, hipStream_t);                         \
-    template hipError_t launch_copy<T>(const BatchDev<T>&, int, int, int, int, hipStream_t);                        \
+    template hipError_t launch_fill<T>(const BatchDev<T>&, int, int, double, hipStream_t, int);                         \
+    template hipError_t launch_copy<T>(const BatchDev<T>&, int, int, int, int, int, hipStream_t);                        \
     template hipError_t launch_port_finish<T>(const BatchDev<T>&, int, hipStream_t);                                \
     template hipError_t launch_curve<T>(const BatchDev<T>&, const double*, int, hipStream_t);                      \
     template hipError_t launch_lincomb<T>(int, T*, const T*, const LinTerms<T>&, hipStream_t);                    \

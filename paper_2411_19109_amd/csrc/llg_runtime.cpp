@@ -573,6 +573,10 @@ int validate_problem(const llg_problem* p) {
     return LLG_OK;
 }
 
+// Arrays of 3N in the state buffer and in each snapshot: a float state is kept
+// as hi + lo (the low part carries what rounding hi to float dropped).
+int state_mult(const llg_handle* h) { return h->dtype == LLG_F32 ? 2 : 1; }
+
 int take_events(llg_handle* h, hipEvent_t* a, hipEvent_t* b) {
     for (hipEvent_t* e : {a, b}) {
         if (!h->ev_pool.empty()) {
@@ -730,7 +734,7 @@ struct Ops {
         switch (L.stage) {
             case 0: b += n * 6 * t; break;
             case 1: case 2: b += n * 12 * t; break;
-            case 3: b += n * 9 * t; break;
+            case 3: b += n * (state_mult(h) > 1 ? 15 : 9) * t; break;  // + lo r/w of a float state
             case -1: b += n * 3 * t * (L.ext_ynext ? 2 : 1); break;
             default: break;
         }
@@ -764,8 +768,12 @@ struct Ops {
     int bwd(const BwdL& L) {
         return run(LLG_KIND_STAGE_BWD, bwd_bytes(L), [&](hipEvent_t a, hipEvent_t b) { return launch_stage_bwd<T>(B(), L, s, a, b); });
     }
+    // copies of the state m_n to and from the snapshots; a float state is hi + lo (twice 3N)
     int copy(int src, int src_slot, int dst, int dst_slot) {
-        return run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_copy<T>(B(), src, src_slot, dst, dst_slot, s); });
+        const int mult = state_mult(h);
+        return run(-1, 0, [&](hipEvent_t, hipEvent_t) {
+            return launch_copy<T>(B(), src, src_slot, dst, dst_slot, mult, s);
+        });
     }
 
     FwdL fwd_launch(int stage) const {
@@ -830,6 +838,9 @@ struct Ops {
         }
         if (mode == 1 && port)
             if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_zero<T>(B(), B_PPART, 1, s); })) return rc;
+        if (state_mult(h) > 1)  // the caller's m0 is a float state: its low part is zero
+            if (int rc = run(-1, 0, [&](hipEvent_t, hipEvent_t) { return launch_fill<T>(B(), B_M, 3, 0.0, s, 3); }))
+                return rc;
         if (int rc = prologue()) return rc;
         int64_t k = 0;
         if (h->policy == LLG_CKPT_BINOMIAL) {
@@ -1510,7 +1521,7 @@ int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_ha
     int rc;
     for (int i = 0; i < n; ++i) {
         Instance& I = h->inst[i];
-        const size_t t = h->tsz, N = I.N, N3b = 3 * N * t;
+        const size_t t = h->tsz, N = I.N, N3b = 3 * N * t, sm = (size_t)state_mult(h);
         // masks
         const llg_masks* mk = masks ? &masks[i] : nullptr;
         const uint8_t* src[4] = {mk ? mk->antenna : nullptr, mk ? mk->port1 : nullptr, mk ? mk->port2 : nullptr,
@@ -1534,15 +1545,17 @@ int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_ha
             if (k == 3) I.has_design = cnt > 0;
         }
         const std::pair<int, size_t> sizes[] = {
-            {B_PSI, N * t}, {B_PHI, N * t}, {B_PSIF, N * t}, {B_M, N3b}, {B_ACC, N3b}, {B_YA, N3b}, {B_YB, N3b},
+            {B_PSI, N * t}, {B_PHI, N * t}, {B_PSIF, N * t}, {B_M, sm * N3b}, {B_ACC, N3b}, {B_YA, N3b}, {B_YB, N3b},
             {B_S, h->demag ? (size_t)3 * I.nrows * I.ktiles * spec_tile_of((int)t) * 2 * t : 0},
             {B_S2, h->demag && h->halves > 1 ? (size_t)3 * I.nrows * I.ktiles * spec_tile_of((int)t) * 2 * t : 0},
-            {B_SNAP, (size_t)h->nsnap * N3b}, {B_YS, (size_t)(h->K * h->halves) * 4 * N3b},
+            {B_SNAP, (size_t)h->nsnap * sm * N3b}, {B_YS, (size_t)(h->K * h->halves) * 4 * N3b},
             {B_BS, (size_t)(h->K * h->halves) * 4 * N3b}, {B_ELL, N3b}, {B_U0, N3b}, {B_U1, N3b},
             {B_L0, N3b}, {B_L1, N3b}, {B_GPSI, N * 8}, {B_DJDM, N3b}, {B_DPSIE, N * 8}, {B_DPSI, N * 8},
             {B_DPHI, N * 8}, {B_PPART, (size_t)I.nloc * 2 * 8}, {B_EPART, (size_t)I.nloc * 5 * 8}, {B_SCAL, 8 * 8}};
         for (auto& sz : sizes)
             if ((rc = alloc(h, &I.tab.b[sz.first], sz.second))) return bail(rc);
+        // the low part of a float state starts at zero (forward runs clear it again)
+        if (hipMemset(I.tab.b[B_M], 0, sm * N3b) != hipSuccess) return bail(fail(LLG_EHIP, "state clear failed"));
         // spectrum bins past Kx inside the last x-bin tile are read by the column
         // kernel's vector loads and never written: keep them zero
         for (int id : {B_S, B_S2})
@@ -1875,7 +1888,7 @@ int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int3
         return fail(LLG_EINVAL, "unknown policy");
     if (ckpt_param < 0) return fail(LLG_EINVAL, "ckpt_param must be >= 0");
     const int64_t N3 = 3LL * p->nx * p->ny * p->nz;
-    *bytes = store_bytes(N3, p->dtype == LLG_F64 ? 8 : 4, n_steps, policy, ckpt_param);
+    *bytes = store_bytes(N3, p->dtype == LLG_F64 ? 8 : 4, n_steps, policy, ckpt_param, p->dtype == LLG_F64 ? 1 : 2);
     return LLG_OK;
 }
 

@@ -90,12 +90,12 @@ int binomial_slots(int64_t n, int32_t param) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(s, n));
 }
 
-size_t store_bytes(int64_t N3, size_t tsz, int64_t n, int32_t policy, int32_t param) {
-    if (policy == LLG_CKPT_BINOMIAL) return (size_t)(binomial_slots(n, param) * N3 + 8 * N3) * tsz;
+size_t store_bytes(int64_t N3, size_t tsz, int64_t n, int32_t policy, int32_t param, int state_mult) {
+    if (policy == LLG_CKPT_BINOMIAL) return (size_t)(binomial_slots(n, param) * state_mult * N3 + 8 * N3) * tsz;
     const int64_t K = segment_length(n, policy, param);
     const int64_t nsnap = (n + K - 1) / K;
     const int64_t halves = nsnap > 1 ? 2 : 1;
-    return (size_t)(nsnap * N3 + 8 * K * N3 * halves) * tsz;
+    return (size_t)(nsnap * state_mult * N3 + 8 * K * N3 * halves) * tsz;
 }
 
 int64_t recompute_steps(int64_t n, int32_t policy, int32_t param) {

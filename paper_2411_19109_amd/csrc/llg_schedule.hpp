@@ -55,8 +55,9 @@ int64_t segment_length(int64_t n, int32_t policy, int32_t param);
 // Snapshot slots of the BINOMIAL policy (param 0 -> 32, at most n).
 int binomial_slots(int64_t n, int32_t param);
 
-// Device bytes of the checkpoint store: snapshots and stage-state slots.
-size_t store_bytes(int64_t N3, size_t tsz, int64_t n, int32_t policy, int32_t param);
+// Device bytes of the checkpoint store: snapshots (state_mult arrays of N3 each:
+// a float state is kept as hi + lo) and stage-state slots.
+size_t store_bytes(int64_t N3, size_t tsz, int64_t n, int32_t policy, int32_t param, int state_mult);
 
 // Forward steps the adjoint recomputes (after the forward pass) under a policy.
 int64_t recompute_steps(int64_t n, int32_t policy, int32_t param);

@@ -33,7 +33,9 @@ EXPORTS = ["llg_last_error", "llg_version", "llg_create", "llg_destroy", "llg_le
            "llg_set_keep_stages", "llg_demag_tensor", "llg_shape_penalty_noalloc"]
 RBF_KIND_NAMES = {0: "k_rbf_cones", 1: "k_rbf_pnorm", 2: "k_rbf_vjp"}
 KIND_STAGE_FWD, KIND_COLUMN, KIND_STAGE_BWD = 0, 1, 2
-KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col_conv", KIND_STAGE_BWD: "k_stage_bwd"}
+# kernel classes of llg_profile_read; the column class runs k_col2d on single-layer
+# grids and k_col_conv on thicker ones
+KIND_NAMES = {KIND_STAGE_FWD: "k_stage_fwd", KIND_COLUMN: "k_col", KIND_STAGE_BWD: "k_stage_bwd"}
 
 
 class LLGError(RuntimeError):

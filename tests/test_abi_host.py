@@ -70,18 +70,20 @@ def test_query_memory_matches_checkpoint_layout():
     K = math.ceil(math.sqrt(n))
     nsnap = math.ceil(n / K)
     N3 = 3 * p.n
+    # a float snapshot holds the state's high and low parts (2 * N3 floats), a double one N3 doubles;
     # several segments: the stage store is double-buffered (recompute / transpose overlap)
-    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT) == (nsnap * N3 + 2 * 8 * K * N3) * 4
-    assert llg.query_memory(p, n, llg.LLG_CKPT_ALL) == (N3 + 8 * n * N3) * 4
+    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT) == (2 * nsnap * N3 + 2 * 8 * K * N3) * 4
+    assert llg.query_memory(p, n, llg.LLG_CKPT_ALL) == (2 * N3 + 8 * n * N3) * 4
     assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT, dtype="f64") == (nsnap * N3 + 2 * 8 * K * N3) * 8
-    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT, ckpt_param=n) == (N3 + 8 * n * N3) * 4
+    assert llg.query_memory(p, n, llg.LLG_CKPT_SQRT, ckpt_param=n) == (2 * N3 + 8 * n * N3) * 4
     # sqrt(n) growth: 100x more steps costs ~10x the store
     r = llg.query_memory(p, 200000, llg.LLG_CKPT_SQRT) / llg.query_memory(p, 2000, llg.LLG_CKPT_SQRT)
     assert 8 < r < 12
     # binomial: s snapshots + one step's stage states, independent of n
     for steps in (64, 2000, 50000):
-        assert llg.query_memory(p, steps, llg.LLG_CKPT_BINOMIAL, 32) == (32 * N3 + 8 * N3) * 4
-    assert llg.query_memory(p, 10, llg.LLG_CKPT_BINOMIAL, 32) == (10 * N3 + 8 * N3) * 4
+        assert llg.query_memory(p, steps, llg.LLG_CKPT_BINOMIAL, 32) == (2 * 32 * N3 + 8 * N3) * 4
+    assert llg.query_memory(p, 10, llg.LLG_CKPT_BINOMIAL, 32) == (2 * 10 * N3 + 8 * N3) * 4
+    assert llg.query_memory(p, 10, llg.LLG_CKPT_BINOMIAL, 32, dtype="f64") == (10 * N3 + 8 * N3) * 8
 
 
 def test_memory_report_large_3d_device():
@@ -94,9 +96,9 @@ def test_memory_report_large_3d_device():
     full = llg.query_memory(p, n, llg.LLG_CKPT_ALL)
     sq = llg.query_memory(p, n, llg.LLG_CKPT_SQRT)
     bi = llg.query_memory(p, n, llg.LLG_CKPT_BINOMIAL, 32)
-    assert full == (N3 + 8 * n * N3) * 4 and full > 288e9
-    assert sq < 25e9 and bi < 0.3e9
-    assert bi == 40 * N3 * 4
+    assert full == (2 * N3 + 8 * n * N3) * 4 and full > 288e9
+    assert sq < 26e9 and bi < 0.5e9
+    assert bi == (2 * 32 + 8) * N3 * 4
 
 
 def _optimal_reversal_steps(l, s):

@@ -134,33 +134,93 @@ def test_device3d_full_binomial_gradient_and_memory():
     assert full > 288e9 > sq > bi
 
 
-def test_device3d_fp32_error_within_conditioning():
-    """Over long runs the 512x256x4 device amplifies any 1e-7-level difference
-    (stiff exchange modes at 4 nm cells; FP64 from two initial states 1e-7
-    apart differs by 5e-2 after 5 000 steps and 4e-3 after 50 000), so the
-    FP32 state cannot track the FP64 one to 1e-4 at the full step count.  What
-    FP32 must do is stay inside that envelope: after 5 000 steps its distance to
-    the FP64 run is at most ten times that of the perturbed FP64 run, and |m| on
-    the magnetic nodes stays within 1e-4 of 1."""
+def test_device3d_full_grid_field_fp64():
+    """Effective field and LL right-hand side on the device's own grid
+    (512x256x4 nodes, 3D demag on the padded 1024x512x8 grid, the column
+    kernel's global-memory tensor path) against the oracle at 1e-12."""
+    w = wl.yig_device_3d(n_steps=10)
+    say("3D device 512x256x4 field fp64")
+    s = gpu_solver(w, "f64")
+    psi = oracle_psi(w)
+    rng = np.random.default_rng(4)
+    m = np.asarray(w.m0, np.float64) + 0.3 * rng.standard_normal(w.m0.shape)
+    m /= np.sqrt((m ** 2).sum(0))
+    t = 3.7e-11
+    B, rhs = s.field(to_dev(psi, "f64"), to_dev(m, "f64"), t, want_rhs=True)
+    s.close()
+    sim = oracle_sim(w)
+    Bref = sim.field(m, psi, t)
+    fref = sim.rhs_from_field(m, Bref, psi)
+    eb = np.abs(to_np(B) - Bref.reshape(-1)).max() / np.abs(Bref).max()
+    ef = np.abs(to_np(rhs) - fref.reshape(-1)).max() / np.abs(fref).max()
+    say("rel max err field", eb, "rhs", ef)
+    assert eb <= 1e-12 and ef <= 1e-12
+
+
+def _relaxed_m0():
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("relax", os.path.join(here, "make_device3d_relaxed_m0.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    m, meta = mod.load()
+    return m, meta
+
+
+def _runs(w, psi, starts, n):
     import torch
+    out = {}
+    for key, (dtype, m0) in starts.items():
+        s = gpu_solver(w, dtype, max_steps=n, tune=(dtype == "f32"))
+        mT, _ = s.forward(to_dev(psi, dtype), to_dev(m0, dtype), n)
+        torch.cuda.synchronize()
+        out[key] = to_np(mT).reshape(3, -1)
+        s.close()
+    return out
+
+
+def test_device3d_conditioning_unrelaxed_vs_relaxed_start():
+    """Where the FP32 / FP64 gap of the unrelaxed device came from.  From m = z
+    (not an equilibrium: the edge stray fields tilt the pattern at once) the
+    lightest level-set interface nodes are thrown far from z and drag the
+    magnetic nodes (psi >= 1e-3) with them: two FP64 runs 1e-7 apart differ by
+    more than 1e-3 there after 5 000 steps.  From the relaxed state (oracle,
+    strongly damped) the same perturbation stays below 1e-5."""
     n = 5000
-    w = wl.yig_device_3d(n_steps=n)
+    w = wl.yig_device_3d(n_steps=50000)
     psi = oracle_psi(w)
     mag = psi.reshape(-1) >= 1e-3
     rng = np.random.default_rng(1)
-    m0 = np.asarray(w.m0, np.float64).reshape(3, -1)
-    pert = m0 + 1e-7 * rng.standard_normal(m0.shape)
-    pert /= np.sqrt((pert ** 2).sum(0))
-    runs = {}
-    for key, dt, start in (("f64", "f64", m0), ("f64 perturbed", "f64", pert), ("f32", "f32", m0)):
-        s = gpu_solver(w, dt, max_steps=n, tune=(dt == "f32"))
-        mT, _ = s.forward(to_dev(psi, dt), to_dev(start, dt), n)
-        torch.cuda.synchronize()
-        runs[key] = to_np(mT).reshape(3, -1)[:, mag]
-        s.close()
-    e_pert = np.abs(runs["f64 perturbed"] - runs["f64"]).max()
-    e32 = np.abs(runs["f32"] - runs["f64"]).max()
-    say("after", n, "steps: |m32 - m64|", e32, "|m64(m0 + 1e-7) - m64|", e_pert)
-    assert e_pert > 1e-4  # the conditioning that rules out a 1e-4 comparison
-    assert e32 <= 10 * e_pert
-    assert np.abs(np.sqrt((runs["f32"] ** 2).sum(0)) - 1).max() <= 1e-4
+    z = np.asarray(w.m0, np.float64).reshape(3, -1)
+    mr, meta = _relaxed_m0()
+    say("relaxed start:", meta)
+    gaps = {}
+    for name, m0 in (("unrelaxed", z), ("relaxed", mr)):
+        pert = m0 + 1e-7 * rng.standard_normal(m0.shape)
+        pert /= np.sqrt((pert ** 2).sum(0))
+        r = _runs(w, psi, {"a": ("f64", m0), "b": ("f64", pert)}, n)
+        gaps[name] = np.abs(r["a"] - r["b"])[:, mag].max()
+        say(name, "start: |m(m0 + 1e-7) - m(m0)| on magnetic nodes after", n, "steps", gaps[name])
+    assert gaps["unrelaxed"] > 1e-3
+    assert gaps["relaxed"] < 1e-5
+
+
+def test_device3d_fp32_tracks_fp64_after_50000_steps():
+    """The full run (50 000 RK4 steps, frequency switch at half time) from the
+    relaxed state: FP32 (autotuned launch) against the FP64 GPU path, validated
+    against the oracle above, within 1e-4 in m on the magnetic nodes, and |m|
+    within 1e-5 of 1 there."""
+    n = 50000
+    w = wl.yig_device_3d(n_steps=n)
+    psi = oracle_psi(w)
+    mag = psi.reshape(-1) >= 1e-3
+    mr, _ = _relaxed_m0()
+    say("3D device 512x256x4, FP32 vs FP64 over", n, "steps from the relaxed state")
+    r = _runs(w, psi, {"f64": ("f64", mr), "f32": ("f32", mr)}, n)
+    e = np.abs(r["f32"] - r["f64"])[:, mag].max()
+    dn = np.abs(np.sqrt((r["f32"][:, mag] ** 2).sum(0)) - 1).max()
+    tilt = np.degrees(np.arccos(np.clip(r["f64"][2][mag], -1, 1))).max()
+    say("max |m32 - m64| on magnetic nodes", e, "| ||m32| - 1|", dn, "| largest tilt from z (deg)", tilt)
+    assert e <= 1e-4
+    assert dn <= 1e-5

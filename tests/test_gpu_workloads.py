@@ -193,3 +193,31 @@ def test_demux_full_length_fp32_against_fp64():
     assert np.abs(np.sqrt((m64 ** 2).sum(0)) - 1).max() <= 1e-9
     assert np.abs(np.sqrt((m32 ** 2).sum(0)) - 1).max() <= 1e-4
     assert abs(out["f32"][1] - out["f64"][1]) <= 1e-3 * abs(out["f64"][1])
+
+
+def test_sweep_instances_fp32_vs_fp64_10000_steps():
+    """Two instances of the batched sweep (its smallest and largest grid) at the
+    sweep's full length: the FP32 batch launch against FP64, within 1e-4 in m on
+    the magnetic nodes."""
+    import torch
+    from paper_2411_19109_amd import llg
+    n = 10000
+    ws = wl.yig_demux_sweep(n_steps=n)
+    sizes = [w.problem.n for w in ws]
+    pick = [ws[int(np.argmin(sizes))], ws[int(np.argmax(sizes))]]
+    outs = {}
+    for dtype in ("f32", "f64"):
+        b = llg.Batch([w.problem for w in pick], dtype=dtype, max_steps=n,
+                      masks=[dict(antenna=w.antenna, port1=w.port1, port2=w.port2, design=w.design) for w in pick])
+        if dtype == "f32":
+            say("sweep pair launch", b.autotune())
+        psis = [to_dev(oracle_psi(w), dtype) for w in pick]
+        ms, _ = b.forward(psis, [to_dev(w.m0, dtype) for w in pick], n)
+        torch.cuda.synchronize()
+        outs[dtype] = [to_np(m).reshape(3, -1) for m in ms]
+        b.close()
+    for k, w in enumerate(pick):
+        mag = oracle_psi(w).reshape(-1) >= 1e-3
+        e = np.abs(outs["f32"][k] - outs["f64"][k])[:, mag].max()
+        say("sweep instance", w.problem.nx, "x", w.problem.ny, "|m32 - m64| on magnetic nodes", e)
+        assert e <= 1e-4

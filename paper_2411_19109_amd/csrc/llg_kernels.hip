@@ -108,6 +108,65 @@ __device__ __forceinline__ void dft_small(C* v) {
     }
 }
 
+// R-point DFT of v whose upper half v[R/2 .. R-1] is zero (decimation in
+// frequency, first stage without its additions): X[2k] = DFT_{R/2}(v)[k],
+// X[2k+1] = DFT_{R/2}(v[r] w^r)[k], w = exp(-+2 pi i / R).
+template <typename C, bool INV, int R>
+__device__ __forceinline__ void dft_half_in(C* v) {
+    using T = decltype(C().x);
+    constexpr int H = R / 2;
+    C a[H], b[H];
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+        a[r] = v[r];
+        const int m = r * (16 / R);
+        if (m == 0) {
+            b[r] = v[r];
+        } else if (m == 4) {
+            b[r] = INV ? cmul_i(v[r]) : cmul_mi(v[r]);
+        } else {
+            b[r] = cmul(v[r], cmk<C>((T)kC16[m], INV ? (T)kS16[m] : -(T)kS16[m]));
+        }
+    }
+    dft_small<C, INV, H>(a);
+    dft_small<C, INV, H>(b);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        v[2 * k] = a[k];
+        v[2 * k + 1] = b[k];
+    }
+}
+
+// The lower half X[0 .. R/2-1] of the R-point DFT of v (decimation in time,
+// last stage without its subtractions): X[k] = E[k] + w^k O[k] with E, O the
+// DFTs of the even and odd samples.  X[R/2 ..] is left unset.
+template <typename C, bool INV, int R>
+__device__ __forceinline__ void dft_half_out(C* v) {
+    using T = decltype(C().x);
+    constexpr int H = R / 2;
+    C e[H], o[H];
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+        e[r] = v[2 * r];
+        o[r] = v[2 * r + 1];
+    }
+    dft_small<C, INV, H>(e);
+    dft_small<C, INV, H>(o);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const int m = k * (16 / R);
+        C t;
+        if (m == 0) {
+            t = o[k];
+        } else if (m == 4) {
+            t = INV ? cmul_i(o[k]) : cmul_mi(o[k]);
+        } else {
+            t = cmul(o[k], cmk<C>((T)kC16[m], INV ? (T)kS16[m] : -(T)kS16[m]));
+        }
+        v[k] = cadd(e[k], t);
+    }
+}
+
 // One Stockham pass of radix R over nsig signals of length L = 2^lL (in place
 // via registers).  Requires nsig * L <= MAXREG * blockDim.x.
 template <typename C, bool INV, int R, int MAXREG>
@@ -203,6 +262,11 @@ template <typename T> __device__ __forceinline__ V3<T> cross(V3<T> a, V3<T> b) {
     return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 template <typename T> __device__ __forceinline__ T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+// 1/s: the hardware reciprocal in float (1 ulp), a correctly rounded division in double
+template <typename T> __device__ __forceinline__ T recip(T s) {
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(s);
+    else return (T)1 / s;
+}
 // Knuth's error-free two-sum: s = fl(x + y) and x + y = s + e exactly
 template <typename T> __device__ __forceinline__ T two_sum(T x, T y, T& e) {
     const T s = x + y;
@@ -619,13 +683,15 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     // and step-start state of this thread's first item are requested first, so
     // their latency overlaps the staging and the inverse FFT.
     const int nitem = v1 ? 2 * nx : nx;
-    V3<T> pre_acc = v3<T>(0, 0, 0), pre_mn = v3<T>(0, 0, 0);
+    V3<T> pre_acc = v3<T>(0, 0, 0), pre_mn = v3<T>(0, 0, 0), pre_lo = v3<T>(0, 0, 0);
     uint8_t pre_ant = 0, pre_p1 = 0, pre_p2 = 0;
     const bool need_acc = a.stage >= 1 && a.stage <= 3, need_mn = a.stage >= 1 && a.stage <= 3;
+    const bool need_lo = sizeof(T) == 4 && a.stage == 3;  // low part of a float state
     if ((int)threadIdx.x < nitem) {
         const int i = r0 * nx + threadIdx.x;  // rows r0, r0+1 are contiguous
         if (need_acc) pre_acc = ld3(a.acc, N, i);
         if (need_mn) pre_mn = ld3(a.mn, N, i);
+        if (need_lo) pre_lo = ld3(a.mn + (size_t)3 * N, N, i);
         if (a.antenna) pre_ant = glb(a.antenna)[i];
         if (a.port_part) {
             pre_p1 = glb(a.port1)[i];
@@ -678,7 +744,7 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
                 V3<T> Be = v3<T>(0, 0, 0);
                 auto add = [&](V3<T> mj, T pj, T w) {
                     const T s = pi + pj;
-                    if (s != (T)0) Be = Be + (w * pj / s) * (mj - m);
+                    if (s != (T)0) Be = Be + (w * pj * recip(s)) * (mj - m);
                 };
                 if (x > 0) add(RM(q, x - 1), RP(q, x - 1), p.exw[0]);
                 if (x < nx - 1) add(RM(q, x + 1), RP(q, x + 1), p.exw[0]);
@@ -729,7 +795,7 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
                 // float state kept as hi + lo (lo at offset 3N of the state buffer): m_{n+1} = hi + (lo + increment)
                 // by an error-free two-sum, so that rounding to float does not accumulate over the steps
                 const V3<T> d = accv + (dt / (T)6) * f;
-                const V3<T> lo = ld3(a.mn + (size_t)3 * N, N, i);
+                const V3<T> lo = first ? pre_lo : ld3(a.mn + (size_t)3 * N, N, i);
                 V3<T> e;
                 yn = v3<T>(two_sum(mnv.x, d.x + lo.x, e.x), two_sum(mnv.y, d.y + lo.y, e.y),
                            two_sum(mnv.z, d.z + lo.z, e.z));
@@ -962,7 +1028,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                     auto nb = [&](V3<T> uj, T pj, V3<T> mj, T w) {
                         const T s = pi + pj;
                         if (s != (T)0) {
-                            const T is = (T)1 / s;
+                            const T is = recip(s);
                             mu = mu + (w * pi * is) * uj - (w * pj * is) * uk;
                             g -= (double)(w * pj * is * is) * (double)dot(uk + uj, mj - m);
                         }
@@ -1105,7 +1171,7 @@ __device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, size
             const int y = j + (r << lnb);
             v[r] = (r < R1 / 2 && y < ny) ? gld(src + (size_t)y * TW) : cmk<C>(0, 0);
         }
-        dft_small<C, false, R1>(v);
+        dft_half_in<C, false, R1>(v);
 #pragma unroll
         for (int r = 0; r < R1; ++r) Z[lp(c * plane + ((j << LR) + r) * TK + tk)] = v[r];
     }
@@ -1131,7 +1197,7 @@ __device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, size_
         // twiddles of the last pass: index r * j (Ns = L / R1, so jm = j)
 #pragma unroll
         for (int r = 1; r < R1; ++r) v[r] = cmul(v[r], cconj(tw[r * j]));
-        dft_small<C, true, R1>(v);
+        dft_half_out<C, true, R1>(v);
         if (tk < kvalid) {
             C* dst = Sw + (size_t)c * cs + tk;
 #pragma unroll

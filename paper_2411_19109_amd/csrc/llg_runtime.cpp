@@ -1745,6 +1745,11 @@ int ensure_spectral(llg_handle* h, const llg_objective_spec* obj) {
     int rc;
     if ((rc = ensure_series(h, &tabs))) return rc;
     if (K > h->spec_cap) {
+        // captured graphs pass spec_fc by value: they must not outlive the buffer they point to
+        if (!h->graphs.empty()) {
+            if (h->gstream) HIPCHK(hipStreamSynchronize(h->gstream));
+            drop_graphs(h);
+        }
         const int cap = std::max(K, 64);
         void* p;
         if ((rc = alloc(h, &p, (size_t)cap * 3 * 8))) return rc;

@@ -189,16 +189,22 @@ def test_spectral_graph_replays_match_eager_and_follow_new_frequencies():
     obj_b = llg.make_objective(wl.OBJ_PORT_SPECTRAL, n_start=w.obj_n_start, freqs=f_b, coef=c_b)
     mk = lambda: llg.Solver(w.problem, dtype="f32", max_steps=n, antenna=w.antenna, port1=w.port1, port2=w.port2,
                             design=w.design, ckpt_param=5)
+    # more sample frequencies than the first allocation holds (64): the buffer grows and the
+    # graphs captured with the old one are dropped
+    f_c, c_c = wl.demux_windows(2.5e12, 3.9e12, 0.3e12, 36)
+    obj_c = llg.make_objective(wl.OBJ_PORT_SPECTRAL, n_start=w.obj_n_start, freqs=f_c, coef=c_c)
     s = mk()
     ref_a = _run_on(s, w, "f32", n, obj_a)
     ref_b = _run_on(s, w, "f32", n, obj_b)
+    ref_c = _run_on(s, w, "f32", n, obj_c)
     s.close()
-    assert ref_a["J"] != ref_b["J"]
+    assert ref_a["J"] != ref_b["J"] and len(f_c) > 64
     s = mk()
     s.set_graphs(True)
     say("spectral objective under graph replay")
     for rep in range(3):
-        for obj, ref in ((obj_a, ref_a), (obj_b, ref_b)):
+        seq = ((obj_a, ref_a), (obj_b, ref_b)) + (((obj_c, ref_c), (obj_a, ref_a)) if rep == 1 else ())
+        for obj, ref in seq:
             g = _run_on(s, w, "f32", n, obj)
             assert g["J"] == ref["J"]
             assert np.array_equal(g["dphi"], ref["dphi"]) and np.array_equal(g["mT"], ref["mT"])

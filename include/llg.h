@@ -353,12 +353,13 @@ int llg_autotune(llg_handle* h, hipStream_t stream);
 #define LLG_KIND_STAGE_BWD 2 /* backward local kernel of the discrete adjoint              */
 #define LLG_KIND_COUNT 3
 
-/* Profiling: while enabled, every kernel launch of the handle is bracketed by
- * two HIP events on the call's stream; llg_profile_read synchronises on the
+/* Profiling: llg_profile(h, k) with k > 0 brackets every k-th launch of each
+ * kernel class (k = 1: every launch) by two HIP events bound to the dispatch
+ * on the call's stream; k = 0 stops.  llg_profile_read synchronises on the
  * recorded events and returns, for one kernel class, the summed device time
- * (ms), the number of launches, and the algorithmic HBM bytes of those
- * launches (every array element the kernel must read or write counted once).
- * reset != 0 clears the class's totals after reading.
+ * (ms), the number of bracketed launches, and the algorithmic HBM bytes of
+ * those launches (every array element the kernel must read or write counted
+ * once).  reset != 0 clears the class's totals after reading.
  * llg_profile(h, 1) returns LLG_ENOTSUP while a profiler collects hardware
  * counters from the process (ROCPROF_COUNTER_COLLECTION set, as rocprofv3
  * --pmc does): event-timed dispatches are not combined with counter

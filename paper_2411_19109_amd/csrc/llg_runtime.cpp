@@ -117,6 +117,8 @@ struct llg_handle {
     // per-kernel profiling
     struct ProfRec { int kind; double bytes; hipEvent_t a, b; };
     bool prof_on = false;
+    int prof_stride = 1;                      // bracket every prof_stride-th launch of each class
+    int64_t prof_seen[LLG_KIND_COUNT] = {0};  // launches of each class since profiling was enabled
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> ev_pool;
     double prof_ms[LLG_KIND_COUNT] = {0};
@@ -716,7 +718,7 @@ struct Ops {
     template <typename F>
     int run(int kind, double bytes, F&& launch) {
         hipEvent_t a = nullptr, b = nullptr;
-        const bool rec = h->prof_on && kind >= 0;
+        const bool rec = h->prof_on && kind >= 0 && (h->prof_seen[kind]++ % h->prof_stride) == 0;
         if (rec)
             if (int rc = take_events(h, &a, &b)) return rc;
         hipError_t e = launch(a, b);
@@ -2001,7 +2003,11 @@ int llg_profile(llg_handle* h, int enable) {
     if (enable && counter_collection_active())
         return fail(LLG_ENOTSUP, "event-timed dispatches are not used while hardware counters are collected");
     if (int rc = drain_profile(h)) return rc;
-    h->prof_on = enable != 0;
+    h->prof_on = enable > 0;
+    if (enable > 0) {
+        h->prof_stride = enable;
+        for (auto& v : h->prof_seen) v = 0;
+    }
     return LLG_OK;
 }
 

@@ -285,8 +285,9 @@ class Solver:
             raise ValueError(f"expected a contiguous cuda tensor of {n} {self.tdtype}")
         return x
 
-    def profile(self, enable: bool):
-        check(lib().llg_profile(self.h, int(enable)))
+    def profile(self, enable, stride=1):
+        """Event-time every stride-th launch of each kernel class while enable."""
+        check(lib().llg_profile(self.h, int(stride) if enable else 0))
 
     def set_graphs(self, enable: bool):
         """Capture forward / adjoint launch sequences in HIP graphs and replay them."""
@@ -485,8 +486,9 @@ class Batch:
         except Exception:
             pass
 
-    def profile(self, enable: bool):
-        check(lib().llg_profile(self.h, int(enable)))
+    def profile(self, enable, stride=1):
+        """Event-time every stride-th launch of each kernel class while enable."""
+        check(lib().llg_profile(self.h, int(stride) if enable else 0))
 
     def set_graphs(self, enable: bool):
         """Capture forward / adjoint launch sequences in HIP graphs and replay them."""

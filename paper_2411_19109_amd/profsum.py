@@ -3,11 +3,14 @@
     python -m paper_2411_19109_amd.profsum stats DIR   # --kernel-trace --stats run
     python -m paper_2411_19109_amd.profsum pmc DIR     # --pmc COUNTER run
     python -m paper_2411_19109_amd.profsum traffic FETCH_DIR WRITE_DIR [LAUNCH_FILE|-] [SOURCE]  # HBM bytes per dispatch
+    python -m paper_2411_19109_amd.profsum gaps DIR    # --kernel-trace run: device busy vs idle time
 
 ``stats`` prints, per kernel, the call count and the average / total device
 time from the *_kernel_stats.csv file.  ``pmc`` prints, per kernel, the number
 of dispatches and the mean and largest counter value per dispatch from the
 *_counter_collection.csv file (FETCH_SIZE / WRITE_SIZE are in KiB).
+``gaps`` reads the *_kernel_trace.csv file and splits the span of the solver
+kernels into time with at least one kernel running and idle time between them.
 """
 from __future__ import annotations
 
@@ -59,6 +62,31 @@ def _per_kernel(d: str, counter: str):
     return agg
 
 
+def gaps(d: str) -> str:
+    """Device busy time (the union of all kernel intervals) against the idle
+    time between kernels, over the span from the first to the last solver
+    kernel (names k_*) of the trace."""
+    f = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)[0]
+    iv = []
+    with open(f) as fh:
+        for r in csv.DictReader(fh):
+            iv.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short(r["Kernel_Name"])))
+    iv.sort()
+    solver = [i for i, v in enumerate(iv) if v[2].startswith("k_")]
+    iv = iv[solver[0]:solver[-1] + 1]
+    busy, idle, end, n_gap = 0, 0, iv[0][0], 0
+    for s0, s1, _ in iv:
+        if s0 > end:
+            idle += s0 - end
+            n_gap += 1
+        busy += max(0, s1 - max(s0, end))
+        end = max(end, s1)
+    span = end - iv[0][0]
+    return (f"kernels {len(iv)} | span_ms {span / 1e6:.2f} | busy_ms {busy / 1e6:.2f} | idle_ms {idle / 1e6:.2f} | "
+            f"idle_gaps {n_gap} | mean_gap_us {idle / max(n_gap, 1) / 1e3:.2f} | "
+            f"busy_per_kernel_us {busy / len(iv) / 1e3:.2f}")
+
+
 def kernel_source_hash(source: str = "llg_kernels.hip") -> str:
     """sha256 of the kernel source the counters belong to."""
     import hashlib
@@ -98,4 +126,4 @@ if __name__ == "__main__":
         print(traffic(sys.argv[2], sys.argv[3], launch, source=sys.argv[5] if len(sys.argv) > 5 else "llg_kernels.hip"))
     else:
         d = sys.argv[2]
-        print(stats(d) if mode == "stats" else pmc(d))
+        print({"stats": stats, "pmc": pmc, "gaps": gaps}[mode](d))

@@ -86,6 +86,7 @@ struct KParams {
     int nx, ny, nz, N, nrows;      // nodes; rows = ny*nz lines along x
     int Px, Kx, Py, Pz, Ky2, Kz2;  // padded FFT sizes; Kx = Px/2+1; Ky2 = Py/2+1; Kz2 = Pz/2+1
     int ktiles;                    // x-bin tiles of the stored spectra, ceil(Kx / TW)
+    int pack;                      // 1: the block of bin 0 also transforms bin Px/2 (alone in the last tile)
     int ncomp;                     // stored tensor-spectrum components (4 in 2D, 6 in 3D)
     int terms;
     int nloc;                      // row-pair blocks of this instance

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "llg_internal.hpp"
 
@@ -1118,6 +1119,18 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
 //    its outputs with r >= R1/2 lie in the padding and are not stored.
 // Against staging the columns in LDS and copying them out this saves one LDS
 // round trip and one barrier at each end.
+//
+// The x-spectrum columns of bins 0 and Kx - 1 = Px/2 are real (the x DFT of
+// real rows at those bins), so one block transforms both as one complex column
+// P = X(0) + i X(Px/2).  After the forward y transform the two parts separate
+// by their Hermitian symmetry, A(ky) = (P(ky) + conj P(-ky)) / 2 and
+// B(ky) = (P(ky) - conj P(-ky)) / 2i; each is multiplied by its own bin's
+// tensor spectrum, and Q = A' + i B' (rebuilt for -ky from the symmetry of the
+// real results) is transformed back: its real part is the field column of bin
+// 0, its imaginary part that of bin Px/2.  An instance packs (p.pack) where
+// bin Px/2 is the only bin of the last spectrum tile (Kx > TW) and the launch
+// is large; that tile then needs no block of its own, and a launch of Kx
+// columns becomes one of Kx - 1, a multiple of the CU count on the large grids.
 
 // Stockham passes from lNs = lb to lNs = le, largest radix first (as fft_lds).
 template <typename C, bool INV, int MAXREG>
@@ -1153,9 +1166,10 @@ __device__ __forceinline__ void fft_lds_range(C* buf, const SigMap sm, int lL, i
 // F1: radix-R1 first forward pass from global memory into LDS.  Work item
 // (component c, bin tk, j): inputs at rows j + r L/R1, r < R1/2 (rows >= ny
 // read as zero), outputs to positions j R1 + r.
+// Sk1: bin Px/2 of row 0, component 0, where bin tk = 0 is the packed pair (else null).
 template <typename C, int R1>
-__device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, size_t cs, int TK, int ltk, int lL,
-                                            int ny, int plane) {
+__device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, const C* __restrict__ Sk1, size_t cs,
+                                            int TK, int ltk, int lL, int ny, int plane) {
     constexpr int LR = ilog2(R1);
     constexpr int TW = 128 / (int)sizeof(C);
     const int lnb = lL - LR;
@@ -1171,6 +1185,14 @@ __device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, size
             const int y = j + (r << lnb);
             v[r] = (r < R1 / 2 && y < ny) ? gld(src + (size_t)y * TW) : cmk<C>(0, 0);
         }
+        if (Sk1 != nullptr && tk == 0) {
+            // the packed pair: imaginary part from bin Px/2 (its real column)
+#pragma unroll
+            for (int r = 0; r < R1 / 2; ++r) {
+                const int y = j + (r << lnb);
+                if (y < ny) v[r].y = gld(Sk1 + (size_t)c * cs + (size_t)y * TW).x;
+            }
+        }
         dft_half_in<C, false, R1>(v);
 #pragma unroll
         for (int r = 0; r < R1; ++r) Z[lp(c * plane + ((j << LR) + r) * TK + tk)] = v[r];
@@ -1181,8 +1203,8 @@ __device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, size
 // Last inverse pass (radix R1, Ns = L/R1) from LDS straight to global memory:
 // outputs at rows j + r L/R1 for r < R1/2 and rows < ny.
 template <typename C, int R1>
-__device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, size_t cs, int TK, int ltk, int lL, int ny,
-                                           int plane, int kvalid, const C* __restrict__ tw) {
+__device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, C* __restrict__ Sw1, size_t cs, int TK,
+                                           int ltk, int lL, int ny, int plane, int kvalid, const C* __restrict__ tw) {
     constexpr int LR = ilog2(R1);
     constexpr int TW = 128 / (int)sizeof(C);
     const int lnb = lL - LR;
@@ -1198,7 +1220,17 @@ __device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, size_
 #pragma unroll
         for (int r = 1; r < R1; ++r) v[r] = cmul(v[r], cconj(tw[r * j]));
         dft_half_out<C, true, R1>(v);
-        if (tk < kvalid) {
+        if (Sw1 != nullptr && tk == 0) {
+            // the packed pair: real part to bin 0, imaginary part to bin Px/2
+#pragma unroll
+            for (int r = 0; r < R1 / 2; ++r) {
+                const int y = j + (r << lnb);
+                if (y < ny) {
+                    gst(Sw + (size_t)c * cs + (size_t)y * TW, cmk<C>(v[r].x, 0));
+                    gst(Sw1 + (size_t)c * cs + (size_t)y * TW, cmk<C>(v[r].y, 0));
+                }
+            }
+        } else if (tk < kvalid) {
             C* dst = Sw + (size_t)c * cs + tk;
 #pragma unroll
             for (int r = 0; r < R1 / 2; ++r) {
@@ -1209,20 +1241,68 @@ __device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, size_
     }
 }
 
+// Tensor multiply of the packed pair of bins 0 and Px/2 (bin tk = 0 of its
+// block): one work item per (ky, -ky), ky <= Py/2.  Nk1: bin Px/2's tensor.
+template <typename T>
+__device__ __forceinline__ void col2d_mul_pair(cplx<T>* Z, int TK, int plane, int Py, const T* Nt,
+                                               const T* __restrict__ Nk, const T* __restrict__ Nk1, int nt_lds,
+                                               int Ky2) {
+    using C = cplx<T>;
+    constexpr int TW = spec_tile<T>();
+    const int cstr = Ky2 * TK;
+    const size_t gstr = (size_t)Ky2 * TW;
+    for (int ky = threadIdx.x; ky <= Py / 2; ky += blockDim.x) {
+        auto NT = [&](int comp) -> T { return nt_lds ? Nt[comp * cstr + ky * TK] : glb(Nk)[comp * gstr + (size_t)ky * TW]; };
+        auto NT1 = [&](int comp) -> T { return glb(Nk1)[comp * gstr + (size_t)ky * TW]; };
+        const T axx = NT(0), ayy = NT(1), azz = NT(2), axy = NT(3);
+        const T bxx = NT1(0), byy = NT1(1), bzz = NT1(2), bxy = NT1(3);
+        const int e = ky * TK, em = ((Py - ky) & (Py - 1)) * TK;
+        const C u0 = Z[lp(e)], u1 = Z[lp(plane + e)], u2 = Z[lp(2 * plane + e)];
+        if (em == e) {
+            // ky = 0 or Py/2: both parts are real, A = Re P and B = Im P
+            Z[lp(e)] = cmk<C>(axx * u0.x + axy * u1.x, bxx * u0.y + bxy * u1.y);
+            Z[lp(plane + e)] = cmk<C>(axy * u0.x + ayy * u1.x, bxy * u0.y + byy * u1.y);
+            Z[lp(2 * plane + e)] = cmk<C>(azz * u2.x, bzz * u2.y);
+            continue;
+        }
+        const C v0 = Z[lp(em)], v1 = Z[lp(plane + em)], v2 = Z[lp(2 * plane + em)];
+        const T h = (T)0.5;
+        // A = (u + conj v) / 2, B = (u - conj v) / 2i
+        const C A0 = cmk<C>(h * (u0.x + v0.x), h * (u0.y - v0.y)), B0 = cmk<C>(h * (u0.y + v0.y), h * (v0.x - u0.x));
+        const C A1 = cmk<C>(h * (u1.x + v1.x), h * (u1.y - v1.y)), B1 = cmk<C>(h * (u1.y + v1.y), h * (v1.x - u1.x));
+        const C A2 = cmk<C>(h * (u2.x + v2.x), h * (u2.y - v2.y)), B2 = cmk<C>(h * (u2.y + v2.y), h * (v2.x - u2.x));
+        const C qa0 = cmk<C>(axx * A0.x + axy * A1.x, axx * A0.y + axy * A1.y);
+        const C qa1 = cmk<C>(axy * A0.x + ayy * A1.x, axy * A0.y + ayy * A1.y);
+        const C qa2 = cmk<C>(azz * A2.x, azz * A2.y);
+        const C qb0 = cmk<C>(bxx * B0.x + bxy * B1.x, bxx * B0.y + bxy * B1.y);
+        const C qb1 = cmk<C>(bxy * B0.x + byy * B1.x, bxy * B0.y + byy * B1.y);
+        const C qb2 = cmk<C>(bzz * B2.x, bzz * B2.y);
+        // Q(ky) = A' + i B', Q(-ky) = conj A' + i conj B'
+        Z[lp(e)] = cmk<C>(qa0.x - qb0.y, qa0.y + qb0.x);
+        Z[lp(plane + e)] = cmk<C>(qa1.x - qb1.y, qa1.y + qb1.x);
+        Z[lp(2 * plane + e)] = cmk<C>(qa2.x - qb2.y, qa2.y + qb2.x);
+        Z[lp(em)] = cmk<C>(qa0.x + qb0.y, qb0.x - qa0.y);
+        Z[lp(plane + em)] = cmk<C>(qa1.x + qb1.y, qb1.x - qa1.y);
+        Z[lp(2 * plane + em)] = cmk<C>(qa2.x + qb2.y, qb2.x - qa2.y);
+    }
+}
+
 // Tensor multiply of the transformed columns in place, one work item per
 // (ky, x-bin) with the three components (2D tensor: xx, yy, zz, xy; xy odd in ky).
+// Nk1: tensor spectrum of bin Px/2 where bin tk = 0 is the packed pair (else null).
 template <typename T>
 __device__ __forceinline__ void col2d_mul(cplx<T>* Z, int TK, int ltk, int plane, int Py, int k0, int Kx, const T* Nt,
-                                          const T* __restrict__ Nk, int nt_lds, int Ky2) {
+                                          const T* __restrict__ Nk, const T* __restrict__ Nk1, int nt_lds, int Ky2) {
     using C = cplx<T>;
     constexpr int TW = spec_tile<T>();
     const int total = Py << ltk;
     const int cstr = Ky2 * TK;
     const size_t gstr = (size_t)Ky2 * TW;
+    const int tk0 = Nk1 != nullptr ? 1 : 0;  // the packed pair's bin is done apart
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
         const int tk = it & (TK - 1);
         const int ky = it >> ltk;
-        if (k0 + tk >= Kx) continue;
+        if (k0 + tk >= Kx || tk < tk0) continue;
         const bool fy = ky > Py / 2;
         const int kyr = fy ? Py - ky : ky;
         auto NT = [&](int comp) -> T {
@@ -1236,6 +1316,7 @@ __device__ __forceinline__ void col2d_mul(cplx<T>* Z, int TK, int ltk, int plane
         Z[lp(plane + e)] = cmk<C>(nxy * a.x + nyy * b.x, nxy * a.y + nyy * b.y);
         Z[lp(2 * plane + e)] = cmk<C>(nzz * z.x, nzz * z.y);
     }
+    if (Nk1 != nullptr) col2d_mul_pair<T>(Z, TK, plane, Py, Nt, Nk, Nk1, nt_lds, Ky2);
     __syncthreads();
 }
 
@@ -1254,16 +1335,22 @@ __device__ __forceinline__ void col2d_body(const KParams<T>& p, const InstTab& t
     C* __restrict__ Sk = S + (size_t)kt * p.nrows * TW + ko;  // bin k0 of row 0, component 0
     const int NR = p.ncomp * p.Kz2 * p.Ky2;
     const T* __restrict__ Nk = nhat + (size_t)kt * NR * TW + ko;
+    // bins 0 and Px/2 as one complex column (block of bin 0, where Px/2 is alone in the last tile)
+    const bool pk = k0 == 0 && p.pack;
+    C* __restrict__ Sk1 = pk ? S + (size_t)((p.Kx - 1) / TW) * p.nrows * TW : nullptr;
+    const T* __restrict__ Nk1 = pk ? nhat + (size_t)((p.Kx - 1) / TW) * NR * TW : nullptr;
     if (Py == 1) {
-        // a single row: no y transform, the multiply alone (ky = 0)
-        for (int tk = threadIdx.x; tk < TK; tk += blockDim.x) {
-            if (k0 + tk >= p.Kx) continue;
-            const auto N = glb(Nk);
-            const T nxx = N[tk], nyy = N[TW + tk], nzz = N[2 * TW + tk], nxy = N[3 * TW + tk];
-            const C a = gld(Sk + tk), b = gld(Sk + cs + tk), z = gld(Sk + 2 * cs + tk);
-            gst(Sk + tk, cmk<C>(nxx * a.x + nxy * b.x, nxx * a.y + nxy * b.y));
-            gst(Sk + cs + tk, cmk<C>(nxy * a.x + nyy * b.x, nxy * a.y + nyy * b.y));
-            gst(Sk + 2 * cs + tk, cmk<C>(nzz * z.x, nzz * z.y));
+        // a single row: no y transform, the multiply alone (ky = 0); the packed
+        // block also multiplies bin Px/2 (item tk = TK)
+        for (int tk = threadIdx.x; tk < TK + (pk ? 1 : 0); tk += blockDim.x) {
+            if (tk < TK && k0 + tk >= p.Kx) continue;
+            C* const sk = tk < TK ? Sk + tk : Sk1;
+            const auto N = glb(tk < TK ? Nk + tk : Nk1);
+            const T nxx = N[0], nyy = N[TW], nzz = N[2 * TW], nxy = N[3 * TW];
+            const C a = gld(sk), b = gld(sk + cs), z = gld(sk + 2 * cs);
+            gst(sk, cmk<C>(nxx * a.x + nxy * b.x, nxx * a.y + nxy * b.y));
+            gst(sk + cs, cmk<C>(nxy * a.x + nyy * b.x, nxy * a.y + nyy * b.y));
+            gst(sk + 2 * cs, cmk<C>(nzz * z.x, nzz * z.y));
         }
         return;
     }
@@ -1317,24 +1404,24 @@ __device__ __forceinline__ void col2d_body(const KParams<T>& p, const InstTab& t
     const SigMap smy{ltk, plane, 1, TK};
     // forward: the first pass from global memory, the rest in LDS
     switch (lR1) {
-        case 1: col2d_first<C, 2>(Z, Sk, cs, TK, ltk, lL, ny, plane); break;
-        case 2: col2d_first<C, 4>(Z, Sk, cs, TK, ltk, lL, ny, plane); break;
-        case 3: col2d_first<C, 8>(Z, Sk, cs, TK, ltk, lL, ny, plane); break;
+        case 1: col2d_first<C, 2>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane); break;
+        case 2: col2d_first<C, 4>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane); break;
+        case 3: col2d_first<C, 8>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane); break;
         default:
-            if constexpr (MR >= 16) col2d_first<C, 16>(Z, Sk, cs, TK, ltk, lL, ny, plane);
+            if constexpr (MR >= 16) col2d_first<C, 16>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane);
             break;
     }
     fft_lds_range<C, false, MR>(Z, smy, lL, lR1, lL, 3 * TK, Tw);
-    col2d_mul<T>(Z, TK, ltk, plane, Py, k0, p.Kx, Nt, Nk, nt_lds, p.Ky2);
+    col2d_mul<T>(Z, TK, ltk, plane, Py, k0, p.Kx, Nt, Nk, Nk1, nt_lds, p.Ky2);
     // inverse: every pass but the last in LDS, the last to global memory
     fft_lds_range<C, true, MR>(Z, smy, lL, 0, lL - lR1, 3 * TK, Tw);
     const int kvalid = p.Kx - k0;
     switch (lR1) {
-        case 1: col2d_last<C, 2>(Z, Sk, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
-        case 2: col2d_last<C, 4>(Z, Sk, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
-        case 3: col2d_last<C, 8>(Z, Sk, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
+        case 1: col2d_last<C, 2>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
+        case 2: col2d_last<C, 4>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
+        case 3: col2d_last<C, 8>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
         default:
-            if constexpr (MR >= 16) col2d_last<C, 16>(Z, Sk, cs, TK, ltk, lL, ny, plane, kvalid, Tw);
+            if constexpr (MR >= 16) col2d_last<C, 16>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane, kvalid, Tw);
             break;
     }
 }
@@ -1384,6 +1471,10 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
     const C* __restrict__ Sk = S + (size_t)kt * p.nrows * TW + ko;  // bin k0 of row 0, component 0
     const int NR = p.ncomp * p.Kz2 * p.Ky2;
     const T* __restrict__ Nk = nhat + (size_t)kt * NR * TW + ko;
+    // bins 0 and Px/2 as one complex column (as in the single-layer kernel)
+    const bool pk = k0 == 0 && p.pack;
+    C* __restrict__ Sk1 = pk ? S + (size_t)((Kx - 1) / TW) * p.nrows * TW : nullptr;
+    const T* __restrict__ Nk1 = pk ? nhat + (size_t)((Kx - 1) / TW) * NR * TW : nullptr;
     // The columns (zero-padded in y), the tensor-spectrum tile and the
     // twiddles, in batched chunks of 16-byte loads: the TK bins of a tile row
     // are contiguous in memory (a unit holds 2 float bins or 1 double bin; a
@@ -1422,6 +1513,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
             } else {
                 u.c[0] = gld(src);
             }
+            if (pk && uo == 0) u.c[0].y = gld(Sk1 + srow(cz, y)).x;
         }
         return u;
     };
@@ -1471,22 +1563,43 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
     __syncthreads();
     const SigMap smy{ilog2_rt(TK), plane, 1, TK};
     if (Py > 1) fft_lds<C, false, MR>(Z, smy, Py, 3 * nz * TK, Tw);
+    // packed pair, 0 < ky < Py/2: A(ky) goes to position ky, B(ky) to position Py - ky
+    const int hpy = Py / 2 - 1;
+    if (pk && hpy > 0) {
+        for (int e = threadIdx.x; e < 3 * nz * hpy; e += blockDim.x) {
+            const int ky = 1 + e % hpy, cz = e / hpy;
+            const int i0 = lp(cz * plane + ky * TK), i1 = lp(cz * plane + (Py - ky) * TK);
+            const C u = Z[i0], v = Z[i1];
+            const T h = (T)0.5;
+            Z[i0] = cmk<C>(h * (u.x + v.x), h * (u.y - v.y));
+            Z[i1] = cmk<C>(h * (u.y + v.y), h * (v.x - u.x));
+        }
+        __syncthreads();
+    }
 
-    // per (ky, tk): z transform in registers, tensor multiply, inverse z transform
-    const int npair = Py * TK;
+    // per (ky, tk): z transform in registers, tensor multiply, inverse z transform.
+    // Packed column (tk = 0 of the packed block): positions ky < Py/2 hold A with
+    // bin 0's tensor (mode 0), positions ky > Py/2 hold B(Py - ky) with bin Px/2's
+    // (mode 1).  At ky = 0 and Py/2 both parts are real sequences in z: the real
+    // part is transformed with bin 0's tensor (mode 2), the imaginary part with
+    // bin Px/2's (mode 3), each keeping its result's real part; the two read and
+    // write disjoint halves of the column, so they run as separate work items.
     const int cstr = p.Kz2 * p.Ky2 * TK;
-    for (int e = threadIdx.x; e < npair; e += blockDim.x) {
-        const int tk = e % TK, ky = e / TK;
-        const int kx = k0 + tk;
-        if (kx >= Kx) continue;
+    auto zcol = [&](const int ky, const int tk, auto mode_c) {
+        constexpr int mode = decltype(mode_c)::value;
         C X[3][NZ];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int z = 0; z < NZ; ++z)
+            for (int z = 0; z < NZ; ++z) {
                 X[c][z] = z < nz ? Z[lp((c * nz + z) * plane + ky * TK + tk)] : cmk<C>(0, 0);
-        const bool fy = ky > Py / 2;
-        const int kyr = fy ? Py - ky : ky;
+                if constexpr (mode >= 2) X[c][z] = cmk<C>(mode == 2 ? X[c][z].x : X[c][z].y, 0);
+            }
+        const bool fy = mode == 0 && ky > Py / 2;
+        const int kyr = ky > Py / 2 ? Py - ky : ky;
+        constexpr bool use1 = mode == 1 || mode == 3;  // bin Px/2's tensor, from memory
+        const T* __restrict__ Nsel = use1 ? Nk1 : Nk;
+        const bool lds_t = !use1 && nt_lds;
         C Y[3][NZ];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -1507,7 +1620,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
             const int kzr = fz ? Pz - kz : kz;
             const int base = (kzr * p.Ky2 + kyr) * TK + tk;
             const size_t gbase = (size_t)(kzr * p.Ky2 + kyr) * TW + tk, gstr = (size_t)p.Kz2 * p.Ky2 * TW;
-            auto NT = [&](int comp) -> T { return nt_lds ? Nt[comp * cstr + base] : glb(Nk)[comp * gstr + gbase]; };
+            auto NT = [&](int comp) -> T { return lds_t ? Nt[comp * cstr + base] : glb(Nsel)[comp * gstr + gbase]; };
             const T nxx = NT(0), nyy = NT(1), nzz = NT(2);
             const T nxy = fy ? -NT(3) : NT(3);
             T nxz = 0, nyz = 0;
@@ -1529,13 +1642,54 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
                 Y[2][z] = cadd(Y[2][z], cmul(hz, w));
             }
         }
+        T* const zr = reinterpret_cast<T*>(Z);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int z = 0; z < NZ; ++z)
-                if (z < nz) Z[lp((c * nz + z) * plane + ky * TK + tk)] = Y[c][z];
+            for (int z = 0; z < NZ; ++z) {
+                if (z >= nz) break;
+                const int i = lp((c * nz + z) * plane + ky * TK + tk);
+                if constexpr (mode < 2)
+                    Z[i] = Y[c][z];
+                else
+                    zr[2 * i + (mode - 2)] = Y[c][z].x;
+            }
+    };
+    const int npair = Py * TK;
+    for (int e = threadIdx.x; e < npair; e += blockDim.x) {
+        const int tk = e % TK, ky = e / TK;
+        if (k0 + tk >= Kx) continue;
+        if (pk && tk == 0 && (ky == 0 || 2 * ky >= Py)) continue;  // packed: below
+        zcol(ky, tk, std::integral_constant<int, 0>());
+    }
+    if (pk) {
+        // B at ky > Py/2, then the real and imaginary parts at ky = 0 and Py/2
+        const int nhi = Py / 2 - 1 > 0 ? Py / 2 - 1 : 0;
+        const int nself = Py > 1 ? 4 : 2;
+        for (int e = threadIdx.x; e < nhi + nself; e += blockDim.x) {
+            if (e < nhi) {
+                zcol(Py / 2 + 1 + e, 0, std::integral_constant<int, 1>());
+            } else {
+                const int q = e - nhi;
+                if (q & 1)
+                    zcol((q >> 1) * (Py / 2), 0, std::integral_constant<int, 3>());
+                else
+                    zcol((q >> 1) * (Py / 2), 0, std::integral_constant<int, 2>());
+            }
+        }
     }
     __syncthreads();
+    // packed pair: Q(ky) = A' + i B', Q(Py - ky) = conj A' + i conj B'
+    if (pk && hpy > 0) {
+        for (int e = threadIdx.x; e < 3 * nz * hpy; e += blockDim.x) {
+            const int ky = 1 + e % hpy, cz = e / hpy;
+            const int i0 = lp(cz * plane + ky * TK), i1 = lp(cz * plane + (Py - ky) * TK);
+            const C a = Z[i0], b = Z[i1];
+            Z[i0] = cmk<C>(a.x - b.y, a.y + b.x);
+            Z[i1] = cmk<C>(a.x + b.y, b.x - a.y);
+        }
+        __syncthreads();
+    }
     if (Py > 1) fft_lds<C, true, MR>(Z, smy, Py, 3 * nz * TK, Tw);
     const int ltk = ilog2_rt(TK);
     const int ncolel = 3 * nz * Py * TK;
@@ -1544,7 +1698,15 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
         const int tk = e & (TK - 1);
         const int t = e >> ltk;
         const int y = t & (Py - 1), cz = t >> lpy;
-        if (y < ny && k0 + tk < Kx) gst(Sw + srow(cz, y) + tk, Z[lp(e)]);
+        if (y < ny && k0 + tk < Kx) {
+            const C v = Z[lp(e)];
+            if (pk && tk == 0) {
+                gst(Sw + srow(cz, y), cmk<C>(v.x, 0));
+                gst(Sk1 + srow(cz, y), cmk<C>(v.y, 0));
+            } else {
+                gst(Sw + srow(cz, y) + tk, v);
+            }
+        }
     }
 }
 

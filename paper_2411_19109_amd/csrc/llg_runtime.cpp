@@ -65,6 +65,7 @@ struct Instance {
     llg_problem prob{};
     int N = 0, nrows = 0, Px = 1, Py = 1, Pz = 1, Kx = 1, ncomp = 4;
     int ktiles = 1;  // x-bin tiles of the stored spectra
+    int pack = 0;    // bins 0 and Px/2 transformed as one column (see column_work)
     int nloc = 0;
     long long n_p1 = 0, n_p2 = 0;
     bool has_ant = false, has_design = false;
@@ -205,6 +206,7 @@ void fill_params(Instance& I) {
     p.Ky2 = I.Py / 2 + 1;
     p.Kz2 = I.Pz / 2 + 1;
     p.ktiles = I.ktiles;
+    p.pack = I.pack;
     p.ncomp = I.ncomp;
     p.terms = q.terms;
     p.nloc = I.nloc;
@@ -397,7 +399,7 @@ int default_cfg(const llg_handle* h, LaunchCfg& c) {
     if (loc_lds_bytes(h, 4) > 163840) return fail(LLG_ESHAPE, "row kernels need more than 160 KiB of LDS");
     auto blocks_of = [&](int tk) {
         long long b = 0;
-        for (auto& I : h->inst) b += (I.Kx + tk - 1) / tk;
+        for (auto& I : h->inst) b += (I.Kx - I.pack + tk - 1) / tk;
         return b;
     };
     int tk = std::min(8, spec_tile_of((int)h->tsz));
@@ -420,12 +422,18 @@ int default_cfg(const llg_handle* h, LaunchCfg& c) {
 // of one 128-byte spectrum tile read the same cache lines, so they are placed
 // 8 items apart: thread blocks are dealt round-robin to the 8 XCDs, and this
 // keeps a spectrum tile's blocks on one XCD (one L2) and close in time.
+// Where an instance packs its real bins (bin Px/2 alone in the last spectrum
+// tile, Kx > TW), the block of bin 0 transforms bin Px/2 together with bin 0,
+// and that tile gets no item.  Each instance's tiles start at a rotated position so
+// that the blocks of bin 0 (which carry the second column) spread over the XCDs.
 std::vector<int2> column_work(const llg_handle* h, int tk) {
     const int TW = spec_tile_of((int)h->tsz);
     const int nsub = TW / tk;
     std::vector<int2> tiles;  // (instance, spectrum tile)
-    for (int i = 0; i < (int)h->inst.size(); ++i)
-        for (int t = 0; t < h->inst[i].ktiles; ++t) tiles.push_back(make_int2(i, t));
+    for (int i = 0; i < (int)h->inst.size(); ++i) {
+        const int nt = h->inst[i].pack ? h->inst[i].ktiles - 1 : h->inst[i].ktiles;
+        for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(i, (t + i) % nt));
+    }
     // items past an instance's last bin stay in place as empty blocks (k0 = kNoBin)
     // so that every group keeps the stride of 8
     constexpr int kNoBin = 1 << 30;
@@ -1520,6 +1528,12 @@ int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_ha
         h->max_nz = std::max(h->max_nz, I.prob.nz);
         if (I.Pz > 16) return bail(fail(LLG_ESHAPE, "nz too large"));
     }
+    // The packed pair of the real bins pays on wide rows (its block carries a
+    // second column, which on a launch of a few dozen blocks lengthens the
+    // critical path): from Px = 512 on.  The choice depends on the instance
+    // alone, not on the batch or the launch tiling, so a batch computes the
+    // bits of its instances' own handles and every tiling the same bits.
+    for (auto& I : h->inst) I.pack = I.Kx >= 257 && I.Kx > spec_tile_of((int)h->tsz) ? 1 : 0;
     int rc;
     for (int i = 0; i < n; ++i) {
         Instance& I = h->inst[i];

@@ -157,14 +157,18 @@ const char* llg_last_error(void);
 /* Library version string. */
 const char* llg_version(void);
 
-/* Create a solver for one problem: validates the parameters, allocates the
- * workspace on the current HIP device, builds the Newell tensor (float64 on
- * the host) and its Fourier spectrum, and copies the masks.  Blocks the host.
+/* Create a solver for one problem (Methods, micromagnetic simulations: the
+ * nodal finite-difference discretisation of Eq. 11 with the Zeeman, demag and
+ * exchange fields, plus uniaxial anisotropy): validates the parameters,
+ * allocates the workspace on the current HIP device, builds the Newell tensor
+ * of the cell (float64 on the host) and its Fourier spectrum on the padded
+ * grid, and copies the masks.  Blocks the host.
  * Errors: LLG_EINVAL (bad parameter), LLG_ESHAPE (grid larger than the FFT
  * kernels support), LLG_ENOMEM, LLG_EHIP. */
 int llg_create(const llg_problem* p, const llg_masks* masks, llg_handle** out);
 
-/* Free the handle and its workspace (synchronises the device).  NULL is a no-op. */
+/* Free the handle and its workspace (synchronises the device).  NULL is a
+ * no-op.  (Lifetime only; no passage of the method.) */
 int llg_destroy(llg_handle* h);
 
 /* Material map of the level set (Eq. 4 and the paragraph after it):
@@ -181,8 +185,11 @@ int llg_levelset_to_Ms_vjp(llg_handle* h, const void* phi, const double* dJdpsi,
                            double* dJdphi_out, hipStream_t stream);
 
 /* Effective field B (T, 3N) at the state m (3N) and time t, from the enabled
- * terms; the LL right-hand side dm/dt (3N) too if rhs_out is not NULL.
- * Nodes with psi = 0 have dm/dt = 0. */
+ * terms (Methods: Zeeman with the drive at t, demag, exchange; anisotropy),
+ * with Ms, A and K scaled by psi (the paragraph after Eq. 4); the LL
+ * right-hand side of Eq. 11, dm/dt (3N), too if rhs_out is not NULL.
+ * Nodes with psi = 0 have dm/dt = 0.  psi (N) and m are device arrays of the
+ * handle's precision, component-major (all x, then all y, then all z). */
 int llg_field(llg_handle* h, const void* psi, const void* m, double t, void* B_out, void* rhs_out,
               hipStream_t stream);
 
@@ -196,7 +203,9 @@ int llg_field(llg_handle* h, const void* psi, const void* m, double t, void* B_o
 int llg_forward(llg_handle* h, const void* psi, const void* m0, double t0, int64_t n_steps,
                 const llg_objective_spec* obj, void* m_out, double* J_dev, hipStream_t stream);
 
-/* Terminal objective at the state m (3N): for LLG_OBJ_ENERGY_AREA writes J to
+/* Terminal objective at the state m (3N) (the objectives of the Results
+ * sections; t is the time of m, which the Zeeman energy of a driven run
+ * needs): for LLG_OBJ_ENERGY_AREA writes J to
  * *J_dev, dJ/dm to dJdm_out (3N, handle precision) and the explicit dJ/dpsi
  * to dJdpsi_out (N, float64); energies_dev (device double[5]: exchange, demag,
  * Zeeman at t, anisotropy, total; J) receives the energy terms when not NULL.
@@ -302,7 +311,11 @@ int llg_adjoint_continuous(llg_handle* h, const void* psi, const void* dJdm_T, c
                            double* dJdpsi_out, void* dJdm0_out, hipStream_t stream);
 
 /* Device bytes the checkpoint store needs for n_steps under a policy
- * (snapshots + recomputed stage states), without allocating anything. */
+ * (snapshots + recomputed stage states), without allocating anything.  The
+ * adjoint of Eqs. 6-7 runs backwards over the forward trajectory, which is
+ * stored (ALL) or recomputed from snapshots (SQRT, BINOMIAL).  It takes the
+ * problem rather than a handle so that a caller can size the store, and pick
+ * a policy, before creating the handle that would allocate it. */
 int llg_query_memory(const llg_problem* p, int64_t n_steps, int32_t policy, int32_t ckpt_param, size_t* bytes);
 
 /* Forward RK4 steps that llg_adjoint recomputes after a forward run of n_steps

@@ -179,18 +179,33 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
     const int total = nsig << lnbf;
     const int lmask = (1 << sm.ln0) - 1;
     C v[IPT][R];
+    // Where a stride between the R points is a multiple of 16 elements, the
+    // padded index is linear in r: lp(a + r S) = lp(a) + r (S + S / 16).  The
+    // radix-8 and radix-16 kernel variants (the large grids) take that path;
+    // the radix-4 variants keep the shorter code.
+    constexpr bool kLin = MAXREG >= 8;
+    const int Sld = nbf * sm.es;
+    const bool lin_ld = kLin && (Sld & 15) == 0;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
         if (it < total) {
             const int j = (it >> sm.ln0) & (nbf - 1);
             const int o = (it >> (sm.ln0 + lnbf)) * sm.s1 + (it & lmask) * sm.s0;
+            if (lin_ld) {
+                const int a0 = lp(o + j * sm.es), d = Sld + (Sld >> 4);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[lp(o + (j + (r << lnbf)) * sm.es)];
+                for (int r = 0; r < R; ++r) v[q][r] = buf[a0 + r * d];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[q][r] = buf[lp(o + (j + (r << lnbf)) * sm.es)];
+            }
         }
     }
     __syncthreads();
     const int lstride = lL - lNs - LR;  // twiddle index step L / (Ns R)
+    const int Sst = (1 << lNs) * sm.es;
+    const bool lin_st = kLin && (Sst & 15) == 0;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
@@ -206,8 +221,14 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
             }
             dft_small<C, INV, R>(v[q]);
             const int base = ((j - jm) << LR) + jm;
+            if (lin_st) {
+                const int a0 = lp(o + base * sm.es), d = Sst + (Sst >> 4);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[lp(o + (base + (r << lNs)) * sm.es)] = v[q][r];
+                for (int r = 0; r < R; ++r) buf[a0 + r * d] = v[q][r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[lp(o + (base + (r << lNs)) * sm.es)] = v[q][r];
+            }
         }
     }
     __syncthreads();

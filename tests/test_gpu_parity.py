@@ -116,6 +116,33 @@ def test_field_at_extreme_extents(dtype, shape):
         s.close()
 
 
+# rows of 256 or more nodes (Px >= 512): the column kernels transform the two
+# real x-bins 0 and Px/2 as one complex column; the shapes reach its special
+# cases: a single row (no y transform), 4-point columns, and 3D columns of one
+# and of two rows (self-paired ky only / one ky pair)
+PACKED_SHAPES = [(300, 1, 1), (260, 2, 1), (256, 7, 1), (257, 1, 3), (300, 2, 2), (256, 5, 2)]
+
+
+@pytest.mark.parametrize("dtype,shape", [(d, s) for d in ("f64", "f32") for s in PACKED_SHAPES])
+def test_field_with_packed_real_bins(dtype, shape):
+    nx, ny, nz = shape
+    w = tiny_workload(nx, ny, nz)
+    say("field packed real bins", dtype, shape)
+    psi = oracle_psi(w)
+    sim = oracle_sim(w)
+    t = 2.3e-11
+    Bref = sim.field(w.m0, psi, t)
+    fref = sim.rhs_from_field(w.m0, Bref, psi)
+    tol = 1e-12 if dtype == "f64" else 2e-6
+    for tune in (False, True):
+        s = gpu_solver(w, dtype, tune=tune)
+        B, rhs = s.field(to_dev(psi, dtype), to_dev(w.m0, dtype), t, want_rhs=True)
+        say("  launch", s.launch_config(), "rel max err", rel_max(to_np(B), Bref.reshape(-1)))
+        assert rel_max(to_np(B), Bref.reshape(-1)) <= tol, tune
+        assert rel_max(to_np(rhs), fref.reshape(-1)) <= tol, tune
+        s.close()
+
+
 def test_extents_beyond_the_kernels_are_rejected():
     from paper_2411_19109_amd import llg
     for dtype, shape in [("f32", (1025, 2, 1)), ("f32", (2, 1025, 1)), ("f64", (513, 2, 1)), ("f64", (2, 1025, 1))]:

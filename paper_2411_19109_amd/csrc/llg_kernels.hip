@@ -45,12 +45,14 @@ template <typename C> __device__ __forceinline__ C cmul_mi(C a) { return cmk<C>(
 // 64 lanes of a wave spread over all banks.
 __device__ __forceinline__ int lp(int a) { return a + (a >> 4); }
 
-// Signal b occupies logical positions (b >> ln0) * s1 + (b & (2^ln0 - 1)) * s0 + e * es, e in [0, L).
-// Work items are ordered with the low ln0 bits of the signal index fastest,
-// then the butterfly index, so adjacent lanes touch adjacent elements both for
-// contiguous signals (ln0 = 0, es = 1) and for signals interleaved with s0 = 1.
+// Signal b occupies logical positions ((b >> l0) << ls1) + (b & (2^l0 - 1)) + (e << l0),
+// e in [0, L): contiguous signals 2^ls1 apart (l0 = 0, the rows), or 2^l0
+// signals interleaved element by element (the TK bins of a column tile).  Work
+// items are ordered with the low l0 bits of the signal index fastest, then the
+// butterfly index, so adjacent lanes touch adjacent elements.  Every stride is
+// a power of two, so the indices take shifts and masks, no multiplies.
 struct SigMap {
-    int ln0, s1, s0, es;
+    int l0, ls1;
 };
 
 // cos / sin of 2 pi m / 16, m = 0..15 (exact constants)
@@ -175,43 +177,29 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
     constexpr int IPT = MAXREG / R;
     constexpr int LR = ilog2(R);
     const int lnbf = lL - LR;
-    const int nbf = 1 << lnbf;
     const int total = nsig << lnbf;
-    const int lmask = (1 << sm.ln0) - 1;
+    // work item it: signal / butterfly bits below k = l0 + lnbf, the rest the
+    // signal group; its R inputs lie 2^k apart
+    const int k = sm.l0 + lnbf;
+    const int mk = (1 << k) - 1, m0 = (1 << sm.l0) - 1;
     C v[IPT][R];
-    // Where a stride between the R points is a multiple of 16 elements, the
-    // padded index is linear in r: lp(a + r S) = lp(a) + r (S + S / 16).  The
-    // radix-8 and radix-16 kernel variants (the large grids) take that path;
-    // the radix-4 variants keep the shorter code.
-    constexpr bool kLin = MAXREG >= 8;
-    const int Sld = nbf * sm.es;
-    const bool lin_ld = kLin && (Sld & 15) == 0;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
         if (it < total) {
-            const int j = (it >> sm.ln0) & (nbf - 1);
-            const int o = (it >> (sm.ln0 + lnbf)) * sm.s1 + (it & lmask) * sm.s0;
-            if (lin_ld) {
-                const int a0 = lp(o + j * sm.es), d = Sld + (Sld >> 4);
+            const int a0 = ((it >> k) << sm.ls1) + (it & mk);
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[q][r] = buf[a0 + r * d];
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[q][r] = buf[lp(o + (j + (r << lnbf)) * sm.es)];
-            }
+            for (int r = 0; r < R; ++r) v[q][r] = buf[lp(a0 + (r << k))];
         }
     }
     __syncthreads();
     const int lstride = lL - lNs - LR;  // twiddle index step L / (Ns R)
-    const int Sst = (1 << lNs) * sm.es;
-    const bool lin_st = kLin && (Sst & 15) == 0;
+    const int ko = lNs + sm.l0;         // outputs lie 2^ko apart
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
         if (it < total) {
-            const int j = (it >> sm.ln0) & (nbf - 1);
-            const int o = (it >> (sm.ln0 + lnbf)) * sm.s1 + (it & lmask) * sm.s0;
+            const int j = (it >> sm.l0) & ((1 << lnbf) - 1);
             const int jm = j & ((1 << lNs) - 1);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
@@ -220,15 +208,9 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
                 v[q][r] = cmul(v[q][r], w);
             }
             dft_small<C, INV, R>(v[q]);
-            const int base = ((j - jm) << LR) + jm;
-            if (lin_st) {
-                const int a0 = lp(o + base * sm.es), d = Sst + (Sst >> 4);
+            const int b0 = ((it >> k) << sm.ls1) + (it & m0) + ((((j - jm) << LR) + jm) << sm.l0);
 #pragma unroll
-                for (int r = 0; r < R; ++r) buf[a0 + r * d] = v[q][r];
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) buf[lp(o + (base + (r << lNs)) * sm.es)] = v[q][r];
-            }
+            for (int r = 0; r < R; ++r) buf[lp(b0 + (r << ko))] = v[q][r];
         }
     }
     __syncthreads();
@@ -698,7 +680,7 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     T* R = LS.R;
     const int r0 = 2 * wk.y;
     const bool v1 = r0 + 1 < p.nrows;
-    const SigMap sm{0, Px, 0, 1};
+    const SigMap sm{0, ilog2_rt(Px)};
 
     // Work items are (row, x) pairs of the two rows, item = rr * nx + x, so a
     // narrow row pair still spreads over twice as many lanes.  The accumulator
@@ -971,7 +953,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
     T* R = LS.R;
     const int r0 = 2 * wk.y;
     const bool v1 = r0 + 1 < p.nrows;
-    const SigMap sm{0, Px, 0, 1};
+    const SigMap sm{0, ilog2_rt(Px)};
     // work items are (row, x) pairs of the two rows, item = rr * nx + x; the
     // inputs of this thread's first item are requested before the staging
     // (in float; the float64 inputs would not fit the registers across the FFT)
@@ -1216,7 +1198,7 @@ __device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, cons
         }
         dft_half_in<C, false, R1>(v);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) Z[lp(c * plane + ((j << LR) + r) * TK + tk)] = v[r];
+        for (int r = 0; r < R1; ++r) Z[lp((c << (lL + ltk)) + (((j << LR) + r) << ltk) + tk)] = v[r];
     }
     __syncthreads();
 }
@@ -1236,7 +1218,7 @@ __device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, C* __
         const int c = it >> (ltk + lnb);
         C v[R1];
 #pragma unroll
-        for (int r = 0; r < R1; ++r) v[r] = Z[lp(c * plane + (j + (r << lnb)) * TK + tk)];
+        for (int r = 0; r < R1; ++r) v[r] = Z[lp((c << (lL + ltk)) + ((j + (r << lnb)) << ltk) + tk)];
         // twiddles of the last pass: index r * j (Ns = L / R1, so jm = j)
 #pragma unroll
         for (int r = 1; r < R1; ++r) v[r] = cmul(v[r], cconj(tw[r * j]));
@@ -1327,11 +1309,11 @@ __device__ __forceinline__ void col2d_mul(cplx<T>* Z, int TK, int ltk, int plane
         const bool fy = ky > Py / 2;
         const int kyr = fy ? Py - ky : ky;
         auto NT = [&](int comp) -> T {
-            return nt_lds ? Nt[comp * cstr + kyr * TK + tk] : glb(Nk)[comp * gstr + (size_t)kyr * TW + tk];
+            return nt_lds ? Nt[comp * cstr + (kyr << ltk) + tk] : glb(Nk)[comp * gstr + (size_t)kyr * TW + tk];
         };
         const T nxx = NT(0), nyy = NT(1), nzz = NT(2);
         const T nxy = fy ? -NT(3) : NT(3);
-        const int e = ky * TK + tk;
+        const int e = (ky << ltk) + tk;
         const C a = Z[lp(e)], b = Z[lp(plane + e)], z = Z[lp(2 * plane + e)];
         Z[lp(e)] = cmk<C>(nxx * a.x + nxy * b.x, nxx * a.y + nxy * b.y);
         Z[lp(plane + e)] = cmk<C>(nxy * a.x + nyy * b.x, nxy * a.y + nyy * b.y);
@@ -1422,7 +1404,7 @@ __device__ __forceinline__ void col2d_body(const KParams<T>& p, const InstTab& t
     const int ltk = ilog2_rt(TK);
     constexpr int LMR = ilog2(MR);
     const int lR1 = lL < LMR ? lL : LMR;
-    const SigMap smy{ltk, plane, 1, TK};
+    const SigMap smy{ltk, ilog2_rt(plane)};
     // forward: the first pass from global memory, the rest in LDS
     switch (lR1) {
         case 1: col2d_first<C, 2>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane); break;
@@ -1582,7 +1564,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
     auto stw = [&](int k, C w) { Tw[k] = w; };
     gather3<4, 4, 1, Unit, RUnit, C>(ncolu, lcol, scol, ntu, ltile, stile, Py, ltw, stw);
     __syncthreads();
-    const SigMap smy{ilog2_rt(TK), plane, 1, TK};
+    const SigMap smy{ilog2_rt(TK), ilog2_rt(plane)};
     if (Py > 1) fft_lds<C, false, MR>(Z, smy, Py, 3 * nz * TK, Tw);
     // packed pair, 0 < ky < Py/2: A(ky) goes to position ky, B(ky) to position Py - ky
     const int hpy = Py / 2 - 1;
@@ -2169,7 +2151,7 @@ __global__ void __launch_bounds__(512) k_energy(const BatchArgs<T> ba, double t,
     if (demag) {
         unpack_rows_to_lds(p, role<C>(tb, B_S), r0, v1, Z);
         __syncthreads();
-        fft_lds<C, true, MR>(Z, SigMap{0, Px, 0, 1}, Px, 3, role<C>(tb, B_TWX));
+        fft_lds<C, true, MR>(Z, SigMap{0, ilog2_rt(Px)}, Px, 3, role<C>(tb, B_TWX));
     }
     const T drv = (T)drive_value(p.f1, p.f2, p.t_switch, p.drive_kind, p.t_ramp, t);
     const int N = p.N, nx = p.nx;

@@ -185,8 +185,9 @@ def test_device3d_conditioning_unrelaxed_vs_relaxed_start():
     (not an equilibrium: the edge stray fields tilt the pattern at once) the
     lightest level-set interface nodes are thrown far from z and drag the
     magnetic nodes (psi >= 1e-3) with them: two FP64 runs 1e-7 apart differ by
-    more than 1e-3 there after 5 000 steps.  From the relaxed state (oracle,
-    strongly damped) the same perturbation stays below 1e-5."""
+    more than 1e-3 there after 5 000 steps, and with those light nodes frozen
+    the same start does not amplify.  From the relaxed state (oracle, strongly
+    damped) the same perturbation stays below 1e-5."""
     n = 5000
     w = wl.yig_device_3d(n_steps=50000)
     psi = oracle_psi(w)
@@ -195,15 +196,18 @@ def test_device3d_conditioning_unrelaxed_vs_relaxed_start():
     z = np.asarray(w.m0, np.float64).reshape(3, -1)
     mr, meta = _relaxed_m0()
     say("relaxed start:", meta)
+    # the same unrelaxed start with the light interface nodes (0 < psi < 1e-3) frozen (psi = 0 exactly)
+    psi_frozen = np.where(psi < 1e-3, 0.0, psi)
     gaps = {}
-    for name, m0 in (("unrelaxed", z), ("relaxed", mr)):
+    for name, m0, ps in (("unrelaxed", z, psi), ("relaxed", mr, psi), ("unrelaxed, light nodes frozen", z, psi_frozen)):
         pert = m0 + 1e-7 * rng.standard_normal(m0.shape)
         pert /= np.sqrt((pert ** 2).sum(0))
-        r = _runs(w, psi, {"a": ("f64", m0), "b": ("f64", pert)}, n)
+        r = _runs(w, ps, {"a": ("f64", m0), "b": ("f64", pert)}, n)
         gaps[name] = np.abs(r["a"] - r["b"])[:, mag].max()
         say(name, "start: |m(m0 + 1e-7) - m(m0)| on magnetic nodes after", n, "steps", gaps[name])
     assert gaps["unrelaxed"] > 1e-3
     assert gaps["relaxed"] < 1e-5
+    assert gaps["unrelaxed, light nodes frozen"] < 1e-5
 
 
 def test_device3d_fp32_tracks_fp64_after_50000_steps():

@@ -201,11 +201,14 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
         if (it < total) {
             const int j = (it >> sm.l0) & ((1 << lnbf) - 1);
             const int jm = j & ((1 << lNs) - 1);
+            // the first pass (Ns = 1) has every twiddle equal to 1: skipped (a product with exactly 1 is exact)
+            if (lNs > 0) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                C w = tw[(r * jm) << lstride];
-                if (INV) w = cconj(w);
-                v[q][r] = cmul(v[q][r], w);
+                for (int r = 1; r < R; ++r) {
+                    C w = tw[(r * jm) << lstride];
+                    if (INV) w = cconj(w);
+                    v[q][r] = cmul(v[q][r], w);
+                }
             }
             dft_small<C, INV, R>(v[q]);
             const int b0 = ((it >> k) << sm.ls1) + (it & m0) + ((((j - jm) << LR) + jm) << sm.l0);

@@ -310,6 +310,8 @@ def main():
     ap.add_argument("--n-steps", type=int, default=0,
                     help="override the workload's RK4 step count (short profiling runs; not a bench line)")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay forward/adjoint as captured HIP graphs")
+    ap.add_argument("--plain-graphs", type=int, default=1,
+                    help="sweep: 1 (default) replays the plain path's per-instance launches as HIP graphs, its fastest form")
     ap.add_argument("--autotune", type=int, default=1, help="1: pick launch tiles with the library's autotuner at setup")
     ap.add_argument("--launch-file", default=None,
                     help="read the launch configuration from this file if it exists, else write the chosen one")
@@ -479,7 +481,9 @@ def run_sweep(args):
     averages of the timed steps (HIP events bound to each dispatch, on the
     launch streams), the plain path over all 64 instances (one single-instance
     gradient after the other, --plain-steps RK4 steps each: the per-step cost
-    of a run does not depend on its length), and the oracle on the host."""
+    of a run does not depend on its length; in its fastest form, per-instance
+    launches replayed as HIP graphs, unless --plain-graphs 0), and the oracle
+    on the host."""
     import torch
     from paper_2411_19109_amd import llg
     n = args.sweep_steps
@@ -538,7 +542,7 @@ def run_sweep(args):
     rate_p, tp, n_plain, nplain_steps = None, None, 0, args.plain_steps
     if nplain_steps > 0:
         t_setup = time.perf_counter()
-        plain, nodes_p = sweep_plain(nplain_steps, len(step.ws), bool(args.graphs), bool(args.autotune))
+        plain, nodes_p = sweep_plain(nplain_steps, len(step.ws), bool(args.plain_graphs), bool(args.autotune))
         for p in plain:  # first call of each instance (its graphs are captured here when graphs are on)
             p()
         torch.cuda.synchronize()
@@ -580,6 +584,7 @@ def run_sweep(args):
                    "plain_cell_steps_per_s": rate_p, "plain_instances_timed": n_plain,
                    "plain_rk4_steps_per_instance": nplain_steps if n_plain else None,
                    "batched_over_plain": rate_b / rate_p if rate_p else None, "hip_graphs": bool(args.graphs),
+                   "plain_hip_graphs": bool(args.plain_graphs) if n_plain else None,
                    "launch": list(step.launch), "objective_J_mean": J_mean,
                    "setup_s": {"create": round(step.t_create, 3), "launch_tuning": round(step.t_tune, 3)}},
         "roofline": roofline,

@@ -1175,13 +1175,13 @@ __device__ __forceinline__ void fft_lds_range(C* buf, const SigMap sm, int lL, i
 // Sk1: bin Px/2 of row 0, component 0, where bin tk = 0 is the packed pair (else null).
 template <typename C, int R1>
 __device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, const C* __restrict__ Sk1, size_t cs,
-                                            int TK, int ltk, int lL, int ny, int plane) {
+                                            int ltk, int lL, int ny) {
     constexpr int LR = ilog2(R1);
     constexpr int TW = 128 / (int)sizeof(C);
     const int lnb = lL - LR;
     const int total = 3 << (ltk + lnb);
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
-        const int tk = it & (TK - 1);
+        const int tk = it & ((1 << ltk) - 1);
         const int j = (it >> ltk) & ((1 << lnb) - 1);
         const int c = it >> (ltk + lnb);
         const C* src = Sk + (size_t)c * cs + tk;
@@ -1209,14 +1209,14 @@ __device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, cons
 // Last inverse pass (radix R1, Ns = L/R1) from LDS straight to global memory:
 // outputs at rows j + r L/R1 for r < R1/2 and rows < ny.
 template <typename C, int R1>
-__device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, C* __restrict__ Sw1, size_t cs, int TK,
-                                           int ltk, int lL, int ny, int plane, int kvalid, const C* __restrict__ tw) {
+__device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, C* __restrict__ Sw1, size_t cs, int ltk,
+                                           int lL, int ny, int kvalid, const C* __restrict__ tw) {
     constexpr int LR = ilog2(R1);
     constexpr int TW = 128 / (int)sizeof(C);
     const int lnb = lL - LR;
     const int total = 3 << (ltk + lnb);
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
-        const int tk = it & (TK - 1);
+        const int tk = it & ((1 << ltk) - 1);
         const int j = (it >> ltk) & ((1 << lnb) - 1);
         const int c = it >> (ltk + lnb);
         C v[R1];
@@ -1410,11 +1410,11 @@ __device__ __forceinline__ void col2d_body(const KParams<T>& p, const InstTab& t
     const SigMap smy{ltk, ilog2_rt(plane)};
     // forward: the first pass from global memory, the rest in LDS
     switch (lR1) {
-        case 1: col2d_first<C, 2>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane); break;
-        case 2: col2d_first<C, 4>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane); break;
-        case 3: col2d_first<C, 8>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane); break;
+        case 1: col2d_first<C, 2>(Z, Sk, Sk1, cs, ltk, lL, ny); break;
+        case 2: col2d_first<C, 4>(Z, Sk, Sk1, cs, ltk, lL, ny); break;
+        case 3: col2d_first<C, 8>(Z, Sk, Sk1, cs, ltk, lL, ny); break;
         default:
-            if constexpr (MR >= 16) col2d_first<C, 16>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane);
+            if constexpr (MR >= 16) col2d_first<C, 16>(Z, Sk, Sk1, cs, ltk, lL, ny);
             break;
     }
     fft_lds_range<C, false, MR>(Z, smy, lL, lR1, lL, 3 * TK, Tw);
@@ -1423,11 +1423,11 @@ __device__ __forceinline__ void col2d_body(const KParams<T>& p, const InstTab& t
     fft_lds_range<C, true, MR>(Z, smy, lL, 0, lL - lR1, 3 * TK, Tw);
     const int kvalid = p.Kx - k0;
     switch (lR1) {
-        case 1: col2d_last<C, 2>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
-        case 2: col2d_last<C, 4>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
-        case 3: col2d_last<C, 8>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane, kvalid, Tw); break;
+        case 1: col2d_last<C, 2>(Z, Sk, Sk1, cs, ltk, lL, ny, kvalid, Tw); break;
+        case 2: col2d_last<C, 4>(Z, Sk, Sk1, cs, ltk, lL, ny, kvalid, Tw); break;
+        case 3: col2d_last<C, 8>(Z, Sk, Sk1, cs, ltk, lL, ny, kvalid, Tw); break;
         default:
-            if constexpr (MR >= 16) col2d_last<C, 16>(Z, Sk, Sk1, cs, TK, ltk, lL, ny, plane, kvalid, Tw);
+            if constexpr (MR >= 16) col2d_last<C, 16>(Z, Sk, Sk1, cs, ltk, lL, ny, kvalid, Tw);
             break;
     }
 }

@@ -330,7 +330,9 @@ int llg_query_recompute(int64_t n_steps, int32_t policy, int32_t ckpt_param, int
  * per-launch host work remains.  Up to 8 graphs are cached per handle; the
  * copies of the caller's arrays in and out stay ordinary stream operations.
  * Disabling synchronises the handle's graph stream and frees the graphs.
- * Profiling (llg_profile) runs the sequences without graphs.
+ * Profiling (llg_profile) runs the sequences without graphs, and so do calls
+ * of more than 2 000 RK4 steps (graphs of that many nodes are not supported);
+ * either way the results are the same bits.
  * Errors: LLG_EINVAL (NULL handle), LLG_EHIP (capture or instantiation failed). */
 int llg_set_graphs(llg_handle* h, int enable);
 

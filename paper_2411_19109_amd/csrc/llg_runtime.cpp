@@ -658,9 +658,14 @@ void drop_graphs(llg_handle* h) {
 // handle buffers -- either directly on s or, with graphs enabled, as a cached
 // HIP graph on the handle's graph stream, ordered after s's prior work and
 // before its later work.  body returns an int status and sets *result.
+// Sequences of more than kGraphMaxSteps RK4 steps run directly: graphs of
+// that length (~10^5 nodes) are not supported.
+constexpr int64_t kGraphMaxSteps = 2000;
+
 template <typename F>
-int run_sequence(llg_handle* h, hipStream_t s, const std::vector<double>& key, int* result, F&& body) {
-    if (!h->graphs_on || h->prof_on) return body(s, result);
+int run_sequence(llg_handle* h, hipStream_t s, const std::vector<double>& key, int64_t n_steps, int* result,
+                 F&& body) {
+    if (!h->graphs_on || h->prof_on || n_steps > kGraphMaxSteps) return body(s, result);
     if (!h->gstream) {
         HIPCHK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&h->g_in, hipEventDisableTiming));
@@ -1819,7 +1824,7 @@ int b_forward(llg_handle* h, const void* const* psi, const void* const* m0, doub
                                      obj ? (double)obj->n_start : -1.0,
                                      obj && obj->kind == LLG_OBJ_PORT_SPECTRAL ? (double)obj->n_freq : 0.0};
     int res = 0;
-    int rc = run_sequence(h, s, key, &res, [&](hipStream_t st, int* r) {
+    int rc = run_sequence(h, s, key, n_steps, &res, [&](hipStream_t st, int* r) {
         *r = 0;
         return h->dtype == LLG_F32 ? Ops<float>{h, st}.forward(t0, n_steps, obj)
                                    : Ops<double>{h, st}.forward(t0, n_steps, obj);
@@ -1870,7 +1875,7 @@ int b_adjoint(llg_handle* h, const void* const* psi, const void* const* dJdm_T, 
     const std::vector<double> key = {1.0, (double)h->n_steps, h->t0, obj ? (double)obj->kind : -1.0,
                                      obj ? (double)obj->n_start : -1.0, (double)use_djdm, (double)use_expl};
     int lam0 = B_L0;
-    int rc0 = run_sequence(h, s, key, &lam0, [&](hipStream_t st, int* r) {
+    int rc0 = run_sequence(h, s, key, h->n_steps, &lam0, [&](hipStream_t st, int* r) {
         if (h->dtype == LLG_F32) {
             Ops<float> o{h, st};
             const int rc = o.adjoint(obj, use_djdm, use_expl);

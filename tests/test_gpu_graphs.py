@@ -83,3 +83,23 @@ def test_batch_graph_replays_match_eager():
                 assert np.array_equal(out[i][k], ref[i][k]), (rep, i, k)
         _eager_work()
     b.close()
+
+
+def test_long_calls_run_without_graphs():
+    """Calls of more than 2 000 RK4 steps run their launches directly even with
+    graphs enabled (longer sequences are not captured): same bits as with graphs
+    off, and a 2 000-step call on the same handle still replays."""
+    from test_gpu_parity import tiny_workload
+    w = tiny_workload(7, 5, 1, kind=wl.OBJ_ENERGY_AREA, n_steps=2001)
+    say("graphs enabled, 2001- and 2000-step calls")
+    ref = gpu_gradient(w, "f32", n_steps=2001)
+    ref["solver"].close()
+    ref2 = gpu_gradient(w, "f32", n_steps=2000)
+    ref2["solver"].close()
+    s = gpu_solver(w, "f32", max_steps=2001)
+    s.set_graphs(True)
+    for rep in range(2):
+        _same(gpu_gradient(w, "f32", n_steps=2001, solver=s), ref)
+        _same(gpu_gradient(w, "f32", n_steps=2000, solver=s), ref2)
+        _eager_work()
+    s.close()

@@ -147,3 +147,37 @@ def test_sweep_full_length_batch_equals_single_samples():
         assert np.array_equal(to_np(m1), bm[i]), i
         assert float(J1.item()) == bJ[i], i
         s.close()
+
+
+def test_sweep_pair_full_length_objective_and_gradient_conditioning():
+    """The sweep's smallest and largest instance as a batch over the full 10 000
+    steps (port objective over the second half, sqrt-checkpointed adjoint):
+    the objective is well-conditioned there -- the autotuned FP32 batch matches
+    FP64 within 1e-4, and a 1e-9 change of m0 moves the FP64 J by less than
+    1e-3 -- while the exact gradient of the discrete map is not: the same 1e-9
+    change of m0 moves the FP64 dJ/dphi by more than 10 % (relative L2).  The
+    driven dynamics of the light interface nodes (0 < psi < 1e-3) amplifies
+    any difference, so at this length no arithmetic reproduces the gradient to
+    the 1e-3 gradient tolerance; that tolerance is checked on prefixes (against
+    the oracle and FP32 against FP64)."""
+    ws = wl.yig_demux_sweep()
+    sizes = [w.problem.n for w in ws]
+    pick = [ws[int(np.argmin(sizes))], ws[int(np.argmax(sizes))]]
+    n = pick[0].n_steps
+    assert n == 10000
+    say("sweep pair", [(w.problem.nx, w.problem.ny) for w in pick], n, "steps: objective and gradient conditioning")
+    g32 = run_batch(pick, "f32", n, tune=True)
+    g64 = run_batch(pick, "f64", n)
+    rng = np.random.default_rng(0)
+    for w in pick:
+        m = w.m0 + 1e-9 * rng.standard_normal(w.m0.shape)
+        w.m0 = m / np.sqrt((m ** 2).sum(0))
+    g64p = run_batch(pick, "f64", n)
+    for a, b, c, w in zip(g32, g64, g64p, pick):
+        cond = rel_l2(c["dphi"], b["dphi"])
+        say("  instance", w.problem.nx, "x", w.problem.ny, "J f32 / f64 / f64 perturbed", a["J"], b["J"], c["J"],
+            "| dJ/dphi f64 perturbed vs f64", cond, "f32 vs f64", rel_l2(a["dphi"], b["dphi"]))
+        assert abs(b["J"]) > 0
+        assert abs(a["J"] - b["J"]) <= 1e-4 * abs(b["J"])
+        assert abs(c["J"] - b["J"]) <= 1e-3 * abs(b["J"])
+        assert cond > 0.1

@@ -118,6 +118,12 @@ typedef struct llg_problem {
                                  BINOMIAL: snapshot slots (0 = 32)                            */
     int32_t drive_kind;       /* LLG_DRIVE_*                                                */
     double t_ramp;            /* LLG_DRIVE_RAMP: time at which the drive reaches b_rf, s (> 0) */
+    double psi_freeze;        /* nodes with psi <= psi_freeze carry no dynamics (dm/dt = 0); their psi
+                                 still weights the exchange and the demag source.  0 (the method as
+                                 stated): only psi = 0 is frozen.  An option beyond the paper: a small
+                                 threshold (1e-3) keeps long driven runs' gradients reproducible, which
+                                 the nearly massless interface nodes of a smoothed level set otherwise
+                                 make chaotic.  0 <= psi_freeze < 1. */
 } llg_problem;
 
 /* Drive waveforms on the antenna mask */

@@ -199,7 +199,7 @@ def rhs_vjp(sim, m, B, psi, v):
     """(mu, g_psi): J_f(m)^T v and v . df/dpsi at the state m with field B."""
     gp_ = sim.gp
     al = sim.alpha
-    frozen = (psi == 0)
+    frozen = sim.frozen(psi)
     w = cross(v, m)
     c = cross(m, B)
     u = -gp_ * (w + al * cross(w, m))

@@ -17,8 +17,10 @@ K_i = K*psi_i.  The energy of the discrete state is
 and the effective field is B_i = -(1/(Ms_i V)) dE/dm_i (tesla).  Time
 evolution is the LLG equation (Eq. 11) in its explicit Landau-Lifshitz form
 dm/dt = -gamma' [m x B + alpha m x (m x B)], gamma' = gamma/(1+alpha^2), which
-equals Eq. 11 for |m| = 1; nodes with psi = 0 are frozen.  Time stepping is
-the classic fourth-order Runge-Kutta method with a fixed step.
+equals Eq. 11 for |m| = 1; nodes with psi = 0 are frozen (optionally every
+node with psi <= psi_freeze, a threshold beyond the paper that removes the
+dynamics of nearly massless interface nodes).  Time stepping is the classic
+fourth-order Runge-Kutta method with a fixed step.
 """
 from __future__ import annotations
 
@@ -127,6 +129,7 @@ class Sim:
         self.antenna = np.zeros(self.shape) if antenna is None else np.asarray(antenna, float)
         self.alpha = self._alpha_map()
         self.gp = prob.gamma / (1.0 + self.alpha ** 2)
+        self.psi_freeze = float(getattr(prob, "psi_freeze", 0.0))
         self.demag = DemagKernel(prob.nx, prob.ny, prob.nz, self.h, pad) if prob.terms & TERM_DEMAG else None
         ku = np.asarray(prob.ku, float)
         self.u = ku / np.linalg.norm(ku) if np.linalg.norm(ku) > 0 else ku
@@ -240,10 +243,17 @@ class Sim:
         return B
 
     # -- dynamics ---------------------------------------------------------
+    def frozen(self, psi):
+        """Nodes without dynamics: psi = 0, or psi <= psi_freeze when that is set
+        (compared on the real part, so complex steps do not move the set)."""
+        if self.psi_freeze > 0:
+            return np.real(psi) <= self.psi_freeze
+        return psi == 0
+
     def rhs_from_field(self, m, B, psi):
         c = cross(m, B)
         f = -self.gp * (c + self.alpha * cross(m, c))
-        return np.where(psi == 0, 0.0, f)
+        return np.where(self.frozen(psi), 0.0, f)
 
     def rhs(self, m, psi, t):
         B = self.field(m, psi, t)

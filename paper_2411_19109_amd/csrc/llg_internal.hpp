@@ -103,6 +103,7 @@ struct KParams {
     double f1, f2, t_switch;
     int drive_kind;                // 0 sine, 1 ramp t / t_ramp
     double t_ramp;
+    T psi_freeze;                  // nodes with psi <= psi_freeze are frozen (0: psi = 0 only)
 };
 
 // One forward-stage launch (shared by every instance of the batch).

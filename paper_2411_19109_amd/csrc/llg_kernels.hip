@@ -771,7 +771,7 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
                 B = B + (p.anis * dot(m, u)) * u;
             }
             V3<T> f = v3<T>(0, 0, 0);
-            if (pi != (T)0) {
+            if (pi > p.psi_freeze) {  // psi >= 0: with psi_freeze = 0 every node but psi = 0 moves
                 const T al = node_alpha(p, x, iy, iz);
                 const T gp = p.gamma / ((T)1 + al * al);
                 const V3<T> c = cross(m, B);
@@ -895,7 +895,7 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ V3<T> field_adjoint(const KParams<T>& p, V3<T> ell, V3<T> m, int ix, int iy, int iz, T psi_i) {
-    if (psi_i == (T)0) return v3<T>(0, 0, 0);
+    if (!(psi_i > p.psi_freeze)) return v3<T>(0, 0, 0);  // frozen node: no dynamics to transpose
     const T al = node_alpha(p, ix, iy, iz);
     const T gp = p.gamma / ((T)1 + al * al);
     const V3<T> w = cross(ell, m);
@@ -1012,7 +1012,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                 const V3<T> v = d.v;
                 const V3<T> uk = d.uk;
                 V3<T> mu = v3<T>(0, 0, 0);
-                if (pi != (T)0) {
+                if (pi > p.psi_freeze) {
                     const T al = node_alpha(p, x, iy, iz);
                     const T gp = p.gamma / ((T)1 + al * al);
                     const V3<T> w = cross(v, m);

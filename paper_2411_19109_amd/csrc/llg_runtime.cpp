@@ -234,6 +234,7 @@ void fill_params(Instance& I) {
     p.t_switch = q.t_switch;
     p.drive_kind = q.drive_kind;
     p.t_ramp = q.t_ramp;
+    p.psi_freeze = (T)q.psi_freeze;
 }
 
 template <typename T>
@@ -580,6 +581,7 @@ int validate_problem(const llg_problem* p) {
         if (!std::isfinite(*v)) return fail(LLG_EINVAL, "non-finite parameter");
     if (p->drive_kind != LLG_DRIVE_SINE && p->drive_kind != LLG_DRIVE_RAMP) return fail(LLG_EINVAL, "unknown drive kind");
     if (p->drive_kind == LLG_DRIVE_RAMP && !(p->t_ramp > 0)) return fail(LLG_EINVAL, "t_ramp must be > 0");
+    if (!(p->psi_freeze >= 0 && p->psi_freeze < 1)) return fail(LLG_EINVAL, "psi_freeze must lie in [0, 1)");
     return LLG_OK;
 }
 

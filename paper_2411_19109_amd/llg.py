@@ -55,7 +55,7 @@ class Problem_c(ctypes.Structure):
                 ("f1", ctypes.c_double), ("f2", ctypes.c_double), ("t_switch", ctypes.c_double),
                 ("terms", ctypes.c_int32), ("dtype", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("max_steps", ctypes.c_int64), ("ckpt_policy", ctypes.c_int32), ("ckpt_param", ctypes.c_int32),
-                ("drive_kind", ctypes.c_int32), ("t_ramp", ctypes.c_double)]
+                ("drive_kind", ctypes.c_int32), ("t_ramp", ctypes.c_double), ("psi_freeze", ctypes.c_double)]
 
 
 class Masks_c(ctypes.Structure):
@@ -162,6 +162,7 @@ def make_problem(prob, dtype="f32", max_steps=1, ckpt_policy=LLG_CKPT_SQRT, ckpt
     c.ckpt_param = ckpt_param
     c.drive_kind = getattr(prob, "drive_kind", LLG_DRIVE_SINE)
     c.t_ramp = getattr(prob, "t_ramp", 0.0)
+    c.psi_freeze = getattr(prob, "psi_freeze", 0.0)
     return c
 
 

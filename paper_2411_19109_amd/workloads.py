@@ -68,6 +68,7 @@ class Problem:
     dt: float = 1e-13
     drive_kind: int = 0         # 0: sine (switch / two tones as above); 1: linear ramp t / t_ramp
     t_ramp: float = 0.0         # duration of the ramp (drive_kind 1), s
+    psi_freeze: float = 0.0     # nodes with psi <= psi_freeze carry no dynamics (0: psi = 0 only)
 
     @property
     def n(self) -> int:

@@ -146,13 +146,21 @@ class SweepStep:
         self.obj = llg.make_objective(wl.OBJ_PORT_MY2, n_start=n_steps // 2)
         self.nodes = sum(w.problem.n for w in self.ws)
 
-    def __call__(self):
+    def forward(self):
+        """Level set and forward run with checkpoints (enqueued); (psis, J)."""
         b = self.batch
-        a = self.ws[0].heaviside_a
-        psis = b.levelset_to_psi(self.phi, a, self.psif)
+        psis = b.levelset_to_psi(self.phi, self.ws[0].heaviside_a, self.psif)
         _, J = b.forward(psis, self.m0, self.n_steps, obj=self.obj, want_m=False)
-        g = b.adjoint(psis, self.obj)
-        return J, b.levelset_vjp(self.phi, g, a)
+        return psis, J
+
+    def backward(self, psis):
+        """Adjoint of the last forward run and the level-set VJP (enqueued); dJ/dphi."""
+        g = self.batch.adjoint(psis, self.obj)
+        return self.batch.levelset_vjp(self.phi, g, self.ws[0].heaviside_a)
+
+    def __call__(self):
+        psis, J = self.forward()
+        return J, self.backward(psis)
 
 
 def sweep_plain(n_steps, count, graphs=True, tune=True):
@@ -478,8 +486,9 @@ def _kernel_stats(solver):
 def run_sweep(args):
     """The default bench line: the batched sweep at full length (64 instances x
     --sweep-steps RK4 steps, forward + adjoint gradient per step), the kernel
-    averages of the timed steps (HIP events bound to each dispatch, on the
-    launch streams), the plain path over all 64 instances (one single-instance
+    averages of the timed steps (HIP events bound to every 7th dispatch of each
+    kernel class, on its stream; the roofline from the forward phase, where one
+    stream runs alone), the plain path over all 64 instances (one single-instance
     gradient after the other, --plain-steps RK4 steps each: the per-step cost
     of a run does not depend on its length; in its fastest form, per-instance
     launches replayed as HIP graphs, unless --plain-graphs 0), and the oracle
@@ -495,25 +504,34 @@ def run_sweep(args):
         torch.cuda.synchronize()
         print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     prof = not args.no_kernel_events and _profile_supported(step.batch)
-    kinds = {}
+    kinds, kinds_adj = {}, {}
     if prof:
         # every 7th launch of each kernel class carries the event pair (7 is prime to the 4 RK4 stages,
         # so every stage is sampled); bracketing all of them costs the sweep about 4 %
         step.batch.profile(True, stride=7)
     torch.cuda.synchronize()
+
+    def collect(into):
+        for name, v in _kernel_stats(step.batch).items():
+            acc = into.setdefault(name, dict(ms=0.0, launches=0, bytes=0.0))
+            acc["ms"] += v["ms"]
+            acc["launches"] += v["launches"]
+            acc["bytes"] += v["bytes"]
+
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
     ev[0].record()
     for i in range(args.steps):
-        J, g = step()
+        psis, J = step.forward()
+        if prof:
+            # the forward runs on one stream: its launches are timed alone (reading waits for it to end).
+            # In the adjoint the recompute stream overlaps the transposes, and an event pair there also
+            # times the other stream's kernels sharing the CUs; those averages are reported apart.
+            collect(kinds)
+        g = step.backward(psis)
         ev[i + 1].record()
         if prof:
-            # sum the event-timed kernel durations of this step (reading them waits for the step to end)
-            for name, v in _kernel_stats(step.batch).items():
-                acc = kinds.setdefault(name, dict(ms=0.0, launches=0, bytes=0.0))
-                acc["ms"] += v["ms"]
-                acc["launches"] += v["launches"]
-                acc["bytes"] += v["bytes"]
+            collect(kinds_adj)
         print(f"[bench] timed step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / args.steps
@@ -525,18 +543,19 @@ def run_sweep(args):
           f"{rate_b:.4g} cell-steps/s", file=sys.stderr, flush=True)
     roofline = None
     if kinds:
-        for v in kinds.values():
-            v["avg_us"] = 1e3 * v["ms"] / v["launches"]
-            v["gbs"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9
-        for name, v in kinds.items():
-            print(f"[bench] batched {name}: {v['launches']} timed launches, avg {v['avg_us']:.2f} us, "
-                  f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
+        for phase, kk in (("forward", kinds), ("adjoint (two streams)", kinds_adj)):
+            for name, v in kk.items():
+                v["avg_us"] = 1e3 * v["ms"] / v["launches"]
+                v["gbs"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+                print(f"[bench] batched {phase} {name}: {v['launches']} timed launches, avg {v['avg_us']:.2f} us, "
+                      f"{v['gbs']:.1f} GB/s algorithmic", file=sys.stderr, flush=True)
         dom = max(kinds, key=lambda k: kinds[k]["ms"])
         d = kinds[dom]
         roofline = dict(bound="hbm", achieved=round(d["gbs"], 2), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(d["gbs"] / HBM_PEAK_GBS, 5),
                         traffic=measured_traffic(SWEEP_NAME, dom, step.launch), kernel=dom,
-                        avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"]))
+                        avg_launch_us=round(d["avg_us"], 3), bytes_per_launch=round(d["bytes"] / d["launches"]),
+                        timed="forward phase (one stream), every 7th launch")
     J_mean = float(J.double().mean().item())
     del g
     rate_p, tp, n_plain, nplain_steps = None, None, 0, args.plain_steps
@@ -588,6 +607,9 @@ def run_sweep(args):
                    "launch": list(step.launch), "objective_J_mean": J_mean,
                    "setup_s": {"create": round(step.t_create, 3), "launch_tuning": round(step.t_tune, 3)}},
         "roofline": roofline,
+        "kernels": {"forward": {k: dict(avg_us=round(v["avg_us"], 2), gbs=round(v["gbs"], 1)) for k, v in kinds.items()},
+                    "adjoint_two_streams": {k: dict(avg_us=round(v["avg_us"], 2), gbs=round(v["gbs"], 1))
+                                            for k, v in kinds_adj.items()}} if kinds else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -44,6 +44,10 @@ template <typename C> __device__ __forceinline__ C cmul_mi(C a) { return cmk<C>(
 // R*Ns elements; without the pad those land in one bank group, with it the
 // 64 lanes of a wave spread over all banks.
 __device__ __forceinline__ int lp(int a) { return a + (a >> 4); }
+// For a and b with no common set bit, lp(a + b) = lp(a) + lp(b) (the shift of
+// a bitwise union is the union of the shifts): with a row (column) length P a
+// power of two and x < P, lp(s P + x) = lp(x) + lp(s P), a lane index plus a
+// uniform offset.
 
 // Signal b occupies logical positions ((b >> l0) << ls1) + (b & (2^l0 - 1)) + (e << l0),
 // e in [0, L): contiguous signals 2^ls1 apart (l0 = 0, the rows), or 2^l0
@@ -172,6 +176,11 @@ __device__ __forceinline__ void dft_half_out(C* v) {
 
 // One Stockham pass of radix R over nsig signals of length L = 2^lL (in place
 // via registers).  Requires nsig * L <= MAXREG * blockDim.x.
+// A butterfly reads its R points at a0 + r 2^k and writes them at b0 + r 2^ko,
+// where a0 has no bit set in [k, k + log2 R) and b0 none in [ko, ko + log2 R).
+// For disjoint bit sets (A + X) >> 4 = (A >> 4) + (X >> 4), so the pad splits
+// exactly: lp(A + X) = lp(A) + X + (X >> 4), one lane address plus a
+// block-uniform offset per point.
 template <typename C, bool INV, int R, int MAXREG>
 __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lNs, int nsig, const C* __restrict__ tw) {
     constexpr int IPT = MAXREG / R;
@@ -187,9 +196,9 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
         if (it < total) {
-            const int a0 = ((it >> k) << sm.ls1) + (it & mk);
+            const C* pb = buf + lp(((it >> k) << sm.ls1) + (it & mk));
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[lp(a0 + (r << k))];
+            for (int r = 0; r < R; ++r) v[q][r] = pb[(r << k) + ((r << k) >> 4)];
         }
     }
     __syncthreads();
@@ -212,8 +221,9 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
             }
             dft_small<C, INV, R>(v[q]);
             const int b0 = ((it >> k) << sm.ls1) + (it & m0) + ((((j - jm) << LR) + jm) << sm.l0);
+            C* pb = buf + lp(b0);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[lp(b0 + (r << ko))] = v[q][r];
+            for (int r = 0; r < R; ++r) pb[(r << ko) + ((r << ko) >> 4)] = v[q][r];
         }
     }
     __syncthreads();
@@ -399,8 +409,8 @@ __device__ __forceinline__ void unpack_rows_to_lds(const KParams<T>& p, const cp
             bx = cconj(bx); by = cconj(by); bz = cconj(bz);
         }
         Z[lp(k)] = cadd(ax, cmul_i(ay));
-        Z[lp(Px + k)] = cadd(bx, cmul_i(by));
-        Z[lp(2 * Px + k)] = cadd(az, cmul_i(bz));
+        Z[lp(k) + lp(Px)] = cadd(bx, cmul_i(by));
+        Z[lp(k) + lp(2 * Px)] = cadd(az, cmul_i(bz));
     }
 }
 
@@ -417,8 +427,8 @@ __device__ __forceinline__ void pack_lds_to_rows(const KParams<T>& p, cplx<T>* _
         C out[6];
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const C a = Z[lp(s * Px + k)];
-            const C b = cconj(Z[lp(s * Px + kn)]);
+            const C a = Z[lp(k) + lp(s * Px)];
+            const C b = cconj(Z[lp(kn) + lp(s * Px)]);
             const C sum = cadd(a, b), dif = csub(a, b);
             out[2 * s] = cmk<C>(h * sum.x, h * sum.y);       // spectrum of the real part
             out[2 * s + 1] = cmk<C>(h * dif.y, -h * dif.x);  // spectrum of the imaginary part
@@ -579,8 +589,8 @@ __device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v
             }
         }
         Z[lp(k)] = cadd(b.a[0], cmul_i(b.a[1]));
-        Z[lp(Px + k)] = cadd(b.b[0], cmul_i(b.b[1]));
-        Z[lp(2 * Px + k)] = cadd(b.a[2], cmul_i(b.b[2]));
+        Z[lp(k) + lp(Px)] = cadd(b.b[0], cmul_i(b.b[1]));
+        Z[lp(k) + lp(2 * Px)] = cadd(b.a[2], cmul_i(b.b[2]));
     };
     auto ltw = [&](int k) { return gld(tw + k); };
     auto stw = [&](int k, C w) { Tw[k] = w; };
@@ -742,8 +752,8 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             const T pi = RP(q, x);
             V3<T> B = v3<T>(0, 0, 0);
             if (demag_in) {
-                const C z01 = Z[lp(rr * Px + x)];
-                const C z2 = Z[lp(2 * Px + x)];
+                const C z01 = Z[lp(x) + lp(rr * Px)];
+                const C z2 = Z[lp(x) + lp(2 * Px)];
                 B = v3<T>(z01.x, z01.y, rr == 0 ? z2.x : z2.y);
             }
             if (p.terms & 1) {
@@ -840,11 +850,11 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
             if (a.do_fwd) {
                 // packed forward-FFT input: (x, y) of each row, z of row 0 + i z of row 1
                 T* zr = reinterpret_cast<T*>(Z);
-                Z[lp(rr * Px + x)] = cmk<C>(pi * yn.x, pi * yn.y);
-                zr[2 * lp(2 * Px + x) + rr] = pi * yn.z;
+                Z[lp(x) + lp(rr * Px)] = cmk<C>(pi * yn.x, pi * yn.y);
+                zr[2 * (lp(x) + lp(2 * Px)) + rr] = pi * yn.z;
                 if (!v1) {
-                    Z[lp(Px + x)] = cmk<C>(0, 0);
-                    zr[2 * lp(2 * Px + x) + 1] = (T)0;
+                    Z[lp(x) + lp(Px)] = cmk<C>(0, 0);
+                    zr[2 * (lp(x) + lp(2 * Px)) + 1] = (T)0;
                 }
             }
         }
@@ -879,8 +889,8 @@ __global__ void __launch_bounds__(512) k_stage_fwd(const BatchArgs<T> ba, const 
     if (a.do_fwd) {
         for (int x = nx + threadIdx.x; x < Px; x += blockDim.x) {
             Z[lp(x)] = cmk<C>(0, 0);
-            Z[lp(Px + x)] = cmk<C>(0, 0);
-            Z[lp(2 * Px + x)] = cmk<C>(0, 0);
+            Z[lp(x) + lp(Px)] = cmk<C>(0, 0);
+            Z[lp(x) + lp(2 * Px)] = cmk<C>(0, 0);
         }
         __syncthreads();
         fft_lds<C, false, MR>(Z, sm, Px, 3, LS.Tw);
@@ -1049,8 +1059,8 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                     if (iz < p.nz - 1) nb(ld3(a.u_cur, N, i + sl), glb(a.psi)[i + sl], ld3(a.ys, N, i + sl), p.exw[2]);
                 }
                 if (demag_in) {
-                    const C z01 = Z[lp(rr * Px + x)];
-                    const C z2 = Z[lp(2 * Px + x)];
+                    const C z01 = Z[lp(x) + lp(rr * Px)];
+                    const C z2 = Z[lp(x) + lp(2 * Px)];
                     const V3<T> cu = v3<T>(z01.x, z01.y, rr == 0 ? z2.x : z2.y);
                     mu = mu + pi * cu;
                     g += (double)dot(m, cu);
@@ -1089,11 +1099,11 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
             }
             if (a.do_fwd) {
                 T* zr = reinterpret_cast<T*>(Z);
-                Z[lp(rr * Px + x)] = cmk<C>(un.x, un.y);
-                zr[2 * lp(2 * Px + x) + rr] = un.z;
+                Z[lp(x) + lp(rr * Px)] = cmk<C>(un.x, un.y);
+                zr[2 * (lp(x) + lp(2 * Px)) + rr] = un.z;
                 if (!v1) {
-                    Z[lp(Px + x)] = cmk<C>(0, 0);
-                    zr[2 * lp(2 * Px + x) + 1] = (T)0;
+                    Z[lp(x) + lp(Px)] = cmk<C>(0, 0);
+                    zr[2 * (lp(x) + lp(2 * Px)) + 1] = (T)0;
                 }
             }
         }
@@ -1101,8 +1111,8 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
     if (a.do_fwd) {
         for (int x = nx + threadIdx.x; x < Px; x += blockDim.x) {
             Z[lp(x)] = cmk<C>(0, 0);
-            Z[lp(Px + x)] = cmk<C>(0, 0);
-            Z[lp(2 * Px + x)] = cmk<C>(0, 0);
+            Z[lp(x) + lp(Px)] = cmk<C>(0, 0);
+            Z[lp(x) + lp(2 * Px)] = cmk<C>(0, 0);
         }
         __syncthreads();
         fft_lds<C, false, MR>(Z, sm, Px, 3, LS.Tw);
@@ -1200,8 +1210,10 @@ __device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, cons
             }
         }
         dft_half_in<C, false, R1>(v);
+        // the point offset r 2^ltk shares no bit with the base, so the pad splits (as in fft_pass)
+        C* pz = Z + lp((c << (lL + ltk)) + ((j << LR) << ltk) + tk);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) Z[lp((c << (lL + ltk)) + (((j << LR) + r) << ltk) + tk)] = v[r];
+        for (int r = 0; r < R1; ++r) pz[(r << ltk) + ((r << ltk) >> 4)] = v[r];
     }
     __syncthreads();
 }
@@ -1220,8 +1232,10 @@ __device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, C* __
         const int j = (it >> ltk) & ((1 << lnb) - 1);
         const int c = it >> (ltk + lnb);
         C v[R1];
+        const C* pz = Z + lp((c << (lL + ltk)) + (j << ltk) + tk);
+        const int ks = lnb + ltk;
 #pragma unroll
-        for (int r = 0; r < R1; ++r) v[r] = Z[lp((c << (lL + ltk)) + ((j + (r << lnb)) << ltk) + tk)];
+        for (int r = 0; r < R1; ++r) v[r] = pz[(r << ks) + ((r << ks) >> 4)];
         // twiddles of the last pass: index r * j (Ns = L / R1, so jm = j)
 #pragma unroll
         for (int r = 1; r < R1; ++r) v[r] = cmul(v[r], cconj(tw[r * j]));
@@ -1257,21 +1271,24 @@ __device__ __forceinline__ void col2d_mul_pair(cplx<T>* Z, int TK, int plane, in
     constexpr int TW = spec_tile<T>();
     const int cstr = Ky2 * TK;
     const size_t gstr = (size_t)Ky2 * TW;
+    const int pp = lp(plane), pp2 = lp(2 * plane);  // lp(c plane + e) = lp(e) + lp(c plane), e < plane
     for (int ky = threadIdx.x; ky <= Py / 2; ky += blockDim.x) {
         auto NT = [&](int comp) -> T { return nt_lds ? Nt[comp * cstr + ky * TK] : glb(Nk)[comp * gstr + (size_t)ky * TW]; };
         auto NT1 = [&](int comp) -> T { return glb(Nk1)[comp * gstr + (size_t)ky * TW]; };
         const T axx = NT(0), ayy = NT(1), azz = NT(2), axy = NT(3);
         const T bxx = NT1(0), byy = NT1(1), bzz = NT1(2), bxy = NT1(3);
         const int e = ky * TK, em = ((Py - ky) & (Py - 1)) * TK;
-        const C u0 = Z[lp(e)], u1 = Z[lp(plane + e)], u2 = Z[lp(2 * plane + e)];
+        C* const ze = Z + lp(e);
+        const C u0 = ze[0], u1 = ze[pp], u2 = ze[pp2];
         if (em == e) {
             // ky = 0 or Py/2: both parts are real, A = Re P and B = Im P
-            Z[lp(e)] = cmk<C>(axx * u0.x + axy * u1.x, bxx * u0.y + bxy * u1.y);
-            Z[lp(plane + e)] = cmk<C>(axy * u0.x + ayy * u1.x, bxy * u0.y + byy * u1.y);
-            Z[lp(2 * plane + e)] = cmk<C>(azz * u2.x, bzz * u2.y);
+            ze[0] = cmk<C>(axx * u0.x + axy * u1.x, bxx * u0.y + bxy * u1.y);
+            ze[pp] = cmk<C>(axy * u0.x + ayy * u1.x, bxy * u0.y + byy * u1.y);
+            ze[pp2] = cmk<C>(azz * u2.x, bzz * u2.y);
             continue;
         }
-        const C v0 = Z[lp(em)], v1 = Z[lp(plane + em)], v2 = Z[lp(2 * plane + em)];
+        C* const zm = Z + lp(em);
+        const C v0 = zm[0], v1 = zm[pp], v2 = zm[pp2];
         const T h = (T)0.5;
         // A = (u + conj v) / 2, B = (u - conj v) / 2i
         const C A0 = cmk<C>(h * (u0.x + v0.x), h * (u0.y - v0.y)), B0 = cmk<C>(h * (u0.y + v0.y), h * (v0.x - u0.x));
@@ -1284,12 +1301,12 @@ __device__ __forceinline__ void col2d_mul_pair(cplx<T>* Z, int TK, int plane, in
         const C qb1 = cmk<C>(bxy * B0.x + byy * B1.x, bxy * B0.y + byy * B1.y);
         const C qb2 = cmk<C>(bzz * B2.x, bzz * B2.y);
         // Q(ky) = A' + i B', Q(-ky) = conj A' + i conj B'
-        Z[lp(e)] = cmk<C>(qa0.x - qb0.y, qa0.y + qb0.x);
-        Z[lp(plane + e)] = cmk<C>(qa1.x - qb1.y, qa1.y + qb1.x);
-        Z[lp(2 * plane + e)] = cmk<C>(qa2.x - qb2.y, qa2.y + qb2.x);
-        Z[lp(em)] = cmk<C>(qa0.x + qb0.y, qb0.x - qa0.y);
-        Z[lp(plane + em)] = cmk<C>(qa1.x + qb1.y, qb1.x - qa1.y);
-        Z[lp(2 * plane + em)] = cmk<C>(qa2.x + qb2.y, qb2.x - qa2.y);
+        ze[0] = cmk<C>(qa0.x - qb0.y, qa0.y + qb0.x);
+        ze[pp] = cmk<C>(qa1.x - qb1.y, qa1.y + qb1.x);
+        ze[pp2] = cmk<C>(qa2.x - qb2.y, qa2.y + qb2.x);
+        zm[0] = cmk<C>(qa0.x + qb0.y, qb0.x - qa0.y);
+        zm[pp] = cmk<C>(qa1.x + qb1.y, qb1.x - qa1.y);
+        zm[pp2] = cmk<C>(qa2.x + qb2.y, qb2.x - qa2.y);
     }
 }
 
@@ -1316,11 +1333,13 @@ __device__ __forceinline__ void col2d_mul(cplx<T>* Z, int TK, int ltk, int plane
         };
         const T nxx = NT(0), nyy = NT(1), nzz = NT(2);
         const T nxy = fy ? -NT(3) : NT(3);
-        const int e = (ky << ltk) + tk;
-        const C a = Z[lp(e)], b = Z[lp(plane + e)], z = Z[lp(2 * plane + e)];
-        Z[lp(e)] = cmk<C>(nxx * a.x + nxy * b.x, nxx * a.y + nxy * b.y);
-        Z[lp(plane + e)] = cmk<C>(nxy * a.x + nyy * b.x, nxy * a.y + nyy * b.y);
-        Z[lp(2 * plane + e)] = cmk<C>(nzz * z.x, nzz * z.y);
+        // e < plane, a power of two: lp(c plane + e) = lp(e) + lp(c plane)
+        C* const ze = Z + lp((ky << ltk) + tk);
+        const int pp = lp(plane), pp2 = lp(2 * plane);
+        const C a = ze[0], b = ze[pp], z = ze[pp2];
+        ze[0] = cmk<C>(nxx * a.x + nxy * b.x, nxx * a.y + nxy * b.y);
+        ze[pp] = cmk<C>(nxy * a.x + nyy * b.x, nxy * a.y + nyy * b.y);
+        ze[pp2] = cmk<C>(nzz * z.x, nzz * z.y);
     }
     if (Nk1 != nullptr) col2d_mul_pair<T>(Z, TK, plane, Py, Nt, Nk, Nk1, nt_lds, Ky2);
     __syncthreads();
@@ -1593,12 +1612,15 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
     const int cstr = p.Kz2 * p.Ky2 * TK;
     auto zcol = [&](const int ky, const int tk, auto mode_c) {
         constexpr int mode = decltype(mode_c)::value;
+        // ky TK + tk < plane, a power of two, so lp(m plane + e) = lp(e) + m plane + (m plane) / 16
+        const int ib = lp(ky * TK + tk);
+        auto zoff = [&](int m) { return m * plane + ((m * plane) >> 4); };
         C X[3][NZ];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int z = 0; z < NZ; ++z) {
-                X[c][z] = z < nz ? Z[lp((c * nz + z) * plane + ky * TK + tk)] : cmk<C>(0, 0);
+                X[c][z] = z < nz ? Z[ib + zoff(c * nz + z)] : cmk<C>(0, 0);
                 if constexpr (mode >= 2) X[c][z] = cmk<C>(mode == 2 ? X[c][z].x : X[c][z].y, 0);
             }
         const bool fy = mode == 0 && ky > Py / 2;
@@ -1654,7 +1676,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
 #pragma unroll
             for (int z = 0; z < NZ; ++z) {
                 if (z >= nz) break;
-                const int i = lp((c * nz + z) * plane + ky * TK + tk);
+                const int i = ib + zoff(c * nz + z);
                 if constexpr (mode < 2)
                     Z[i] = Y[c][z];
                 else
@@ -2169,8 +2191,8 @@ __global__ void __launch_bounds__(512) k_energy(const BatchArgs<T> ba, double t,
             const T pi = psi[i];
             V3<T> Bd = v3<T>(0, 0, 0), Bex = v3<T>(0, 0, 0);
             if (demag) {
-                const C z01 = Z[lp(rr * Px + x)];
-                const C z2 = Z[lp(2 * Px + x)];
+                const C z01 = Z[lp(x) + lp(rr * Px)];
+                const C z2 = Z[lp(x) + lp(2 * Px)];
                 Bd = v3<T>(z01.x, z01.y, rr == 0 ? z2.x : z2.y);
             }
             double gp = 0.0;

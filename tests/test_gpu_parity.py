@@ -251,3 +251,40 @@ def test_energy_terms_match_oracle():
     assert rel_max(to_np(dJdm), gm.reshape(-1)) <= 1e-12
     assert rel_max(to_np(dJdpsi), gp.reshape(-1)) <= 1e-12
     assert abs(float(J.item()) - oadj.energy_area_value(oracle_sim(w), w.m0, psi, o)) <= 1e-12
+
+
+# column tiles whose LDS plane (Py x TK complex values) is smaller than the
+# 16-element pad period: the component planes then sit at padded offsets that
+# are not multiples of one plane's (plane 8: the third starts at lp(16) = 17,
+# not 2 lp(8) = 16); plain and packed-bin columns, every column tile width and
+# both column radices
+SMALL_TILE_SHAPES = [(20, 2, 1), (20, 3, 1), (300, 3, 1), (260, 2, 1)]
+
+
+@pytest.mark.parametrize("dtype,shape", [(d, s) for d in ("f64", "f32") for s in SMALL_TILE_SHAPES])
+def test_field_small_column_tiles(dtype, shape):
+    from paper_2411_19109_amd import llg
+    nx, ny, nz = shape
+    w = tiny_workload(nx, ny, nz)
+    say("field small column tiles", dtype, shape)
+    psi = oracle_psi(w)
+    sim = oracle_sim(w)
+    t = 1.1e-11
+    Bref = sim.field(w.m0, psi, t)
+    tol = 1e-12 if dtype == "f64" else 2e-6
+    s = gpu_solver(w, dtype)
+    base = s.launch_config()
+    tried = 0
+    for tk in (1, 2, 4, 8):
+        for cr in (4, 8):
+            try:
+                s.set_launch_config(tk, 64, cr, *base[3:])
+            except llg.LLGError:
+                continue
+            B, _ = s.field(to_dev(psi, dtype), to_dev(w.m0, dtype), t, want_rhs=True)
+            e = rel_max(to_np(B), Bref.reshape(-1))
+            say("  launch", s.launch_config(), "rel max err", e)
+            assert e <= tol, (tk, cr)
+            tried += 1
+    assert tried >= 6
+    s.close()

@@ -49,6 +49,40 @@ __device__ __forceinline__ int lp(int a) { return a + (a >> 4); }
 // power of two and x < P, lp(s P + x) = lp(x) + lp(s P), a lane index plus a
 // uniform offset.
 
+// Byte offsets lp(r 2^k) * SZ of the points of a butterfly (r < 16, k < 16),
+// one row per k: a pass reads its R offsets with one uniform (scalar) load
+// instead of computing them.
+template <int SZ> struct alignas(64) LpOffsets {
+    int v[16][16];
+    constexpr LpOffsets() : v() {
+        for (int k = 0; k < 16; ++k)
+            for (int r = 0; r < 16; ++r) v[k][r] = ((r << k) + ((r << k) >> 4)) * SZ;
+    }
+};
+__device__ constexpr LpOffsets<8> kLpOff8{};
+__device__ constexpr LpOffsets<16> kLpOff16{};
+template <int N> struct OffRow {
+    int o[N];
+};
+// the first N offsets of row k, read in 16-byte pieces
+template <typename C, int N> __device__ __forceinline__ OffRow<N> lp_offsets(int k) {
+    const int* row;
+    if constexpr (sizeof(C) == 8) row = kLpOff8.v[k];
+    else row = kLpOff16.v[k];
+    OffRow<N> r;
+    if constexpr (N >= 4) {
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i) {
+            const int4 t = reinterpret_cast<const int4*>(row)[i];
+            r.o[4 * i] = t.x, r.o[4 * i + 1] = t.y, r.o[4 * i + 2] = t.z, r.o[4 * i + 3] = t.w;
+        }
+    } else {
+        const int2 t = *reinterpret_cast<const int2*>(row);
+        r.o[0] = t.x, r.o[1] = t.y;
+    }
+    return r;
+}
+
 // Signal b occupies logical positions ((b >> l0) << ls1) + (b & (2^l0 - 1)) + (e << l0),
 // e in [0, L): contiguous signals 2^ls1 apart (l0 = 0, the rows), or 2^l0
 // signals interleaved element by element (the TK bins of a column tile).  Work
@@ -191,19 +225,21 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
     // signal group; its R inputs lie 2^k apart
     const int k = sm.l0 + lnbf;
     const int mk = (1 << k) - 1, m0 = (1 << sm.l0) - 1;
+    const OffRow<R> ol = lp_offsets<C, R>(k);
     C v[IPT][R];
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
         if (it < total) {
-            const C* pb = buf + lp(((it >> k) << sm.ls1) + (it & mk));
+            const char* pb = reinterpret_cast<const char*>(buf + lp(((it >> k) << sm.ls1) + (it & mk)));
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = pb[(r << k) + ((r << k) >> 4)];
+            for (int r = 0; r < R; ++r) v[q][r] = *reinterpret_cast<const C*>(pb + ol.o[r]);
         }
     }
     __syncthreads();
     const int lstride = lL - lNs - LR;  // twiddle index step L / (Ns R)
     const int ko = lNs + sm.l0;         // outputs lie 2^ko apart
+    const OffRow<R> os = lp_offsets<C, R>(ko);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int it = threadIdx.x + q * blockDim.x;
@@ -221,9 +257,9 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
             }
             dft_small<C, INV, R>(v[q]);
             const int b0 = ((it >> k) << sm.ls1) + (it & m0) + ((((j - jm) << LR) + jm) << sm.l0);
-            C* pb = buf + lp(b0);
+            char* pb = reinterpret_cast<char*>(buf + lp(b0));
 #pragma unroll
-            for (int r = 0; r < R; ++r) pb[(r << ko) + ((r << ko) >> 4)] = v[q][r];
+            for (int r = 0; r < R; ++r) *reinterpret_cast<C*>(pb + os.o[r]) = v[q][r];
         }
     }
     __syncthreads();

@@ -19,8 +19,13 @@ namespace llg {
 
 constexpr double kMu0 = 4e-7 * 3.14159265358979323846;
 
-// Stored size of an LDS array of n complex values padded by one element per 16.
-__host__ __device__ inline int lds_pad(int n) { return n + (n >> 4) + 1; }
+// LDS arrays of complex values are padded by one element per 2^kLdsPadShift.
+// 32 complex values fill the 64 four-byte banks once, so the pad shifts each
+// such run by one element: a run of 32 contiguous points (a half wave of
+// 8-byte accesses) stays on distinct banks, and strided runs rotate.
+constexpr int kLdsPadShift = 5;
+// Stored size of an LDS array of n padded complex values.
+__host__ __device__ inline int lds_pad(int n) { return n + (n >> kLdsPadShift) + 1; }
 
 // Spectra are stored in x-bin tiles of 128 bytes (16 float or 8 double
 // complex bins): S[((c * ktiles + t) * nrows + row) * TW + o] for bin kx =

@@ -39,11 +39,11 @@ template <typename C> __device__ __forceinline__ C cmul_mi(C a) { return cmk<C>(
 // ---------------------------------------------------------------------------
 // LDS Stockham FFT
 // ---------------------------------------------------------------------------
-// LDS arrays of complex values are padded by one element per 16 (lp maps the
-// logical index to the stored one).  The passes write with strides of R or
-// R*Ns elements; without the pad those land in one bank group, with it the
-// 64 lanes of a wave spread over all banks.
-__device__ __forceinline__ int lp(int a) { return a + (a >> 4); }
+// LDS arrays of complex values are padded by one element per 2^kLdsPadShift
+// (lp maps the logical index to the stored one).  The passes write with
+// strides of R or R*Ns elements; without the pad those land in one bank group,
+// with it the lanes of a wave spread over the banks.
+__device__ __forceinline__ int lp(int a) { return a + (a >> kLdsPadShift); }
 // For a and b with no common set bit, lp(a + b) = lp(a) + lp(b) (the shift of
 // a bitwise union is the union of the shifts): with a row (column) length P a
 // power of two and x < P, lp(s P + x) = lp(x) + lp(s P), a lane index plus a
@@ -56,7 +56,7 @@ template <int SZ> struct alignas(64) LpOffsets {
     int v[16][16];
     constexpr LpOffsets() : v() {
         for (int k = 0; k < 16; ++k)
-            for (int r = 0; r < 16; ++r) v[k][r] = ((r << k) + ((r << k) >> 4)) * SZ;
+            for (int r = 0; r < 16; ++r) v[k][r] = ((r << k) + ((r << k) >> kLdsPadShift)) * SZ;
     }
 };
 __device__ constexpr LpOffsets<8> kLpOff8{};
@@ -212,8 +212,8 @@ __device__ __forceinline__ void dft_half_out(C* v) {
 // via registers).  Requires nsig * L <= MAXREG * blockDim.x.
 // A butterfly reads its R points at a0 + r 2^k and writes them at b0 + r 2^ko,
 // where a0 has no bit set in [k, k + log2 R) and b0 none in [ko, ko + log2 R).
-// For disjoint bit sets (A + X) >> 4 = (A >> 4) + (X >> 4), so the pad splits
-// exactly: lp(A + X) = lp(A) + X + (X >> 4), one lane address plus a
+// For disjoint bit sets (A + X) >> s = (A >> s) + (X >> s), so the pad splits
+// exactly: lp(A + X) = lp(A) + lp(X), one lane address plus a
 // block-uniform offset per point.
 template <typename C, bool INV, int R, int MAXREG>
 __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lNs, int nsig, const C* __restrict__ tw) {
@@ -1249,7 +1249,7 @@ __device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, cons
         // the point offset r 2^ltk shares no bit with the base, so the pad splits (as in fft_pass)
         C* pz = Z + lp((c << (lL + ltk)) + ((j << LR) << ltk) + tk);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) pz[(r << ltk) + ((r << ltk) >> 4)] = v[r];
+        for (int r = 0; r < R1; ++r) pz[lp(r << ltk)] = v[r];
     }
     __syncthreads();
 }
@@ -1271,7 +1271,7 @@ __device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, C* __
         const C* pz = Z + lp((c << (lL + ltk)) + (j << ltk) + tk);
         const int ks = lnb + ltk;
 #pragma unroll
-        for (int r = 0; r < R1; ++r) v[r] = pz[(r << ks) + ((r << ks) >> 4)];
+        for (int r = 0; r < R1; ++r) v[r] = pz[lp(r << ks)];
         // twiddles of the last pass: index r * j (Ns = L / R1, so jm = j)
 #pragma unroll
         for (int r = 1; r < R1; ++r) v[r] = cmul(v[r], cconj(tw[r * j]));
@@ -1650,7 +1650,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
         constexpr int mode = decltype(mode_c)::value;
         // ky TK + tk < plane, a power of two, so lp(m plane + e) = lp(e) + m plane + (m plane) / 16
         const int ib = lp(ky * TK + tk);
-        auto zoff = [&](int m) { return m * plane + ((m * plane) >> 4); };
+        auto zoff = [&](int m) { return lp(m * plane); };
         C X[3][NZ];
 #pragma unroll
         for (int c = 0; c < 3; ++c)

@@ -253,11 +253,11 @@ def test_energy_terms_match_oracle():
     assert abs(float(J.item()) - oadj.energy_area_value(oracle_sim(w), w.m0, psi, o)) <= 1e-12
 
 
-# column tiles whose LDS plane (Py x TK complex values) is smaller than the
-# 16-element pad period: the component planes then sit at padded offsets that
-# are not multiples of one plane's (plane 8: the third starts at lp(16) = 17,
-# not 2 lp(8) = 16); plain and packed-bin columns, every column tile width and
-# both column radices
+# column tiles whose LDS plane (Py x TK complex values) is at or below the pad
+# period (one element per 32): the component planes then sit at padded offsets
+# that are not multiples of one plane's (plane 16: the third starts at
+# lp(32) = 33, not 2 lp(16) = 32); plain and packed-bin columns, every column
+# tile width and both column radices
 SMALL_TILE_SHAPES = [(20, 2, 1), (20, 3, 1), (300, 3, 1), (260, 2, 1)]
 
 

@@ -248,9 +248,12 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
             const int jm = j & ((1 << lNs) - 1);
             // the first pass (Ns = 1) has every twiddle equal to 1: skipped (a product with exactly 1 is exact)
             if (lNs > 0) {
+                // twiddle r sits r u bytes into the table, u = (jm << lstride) sizeof(C) < 2^24
+                const unsigned u = (unsigned)(jm << lstride) * (unsigned)sizeof(C);
+                const char* tb = reinterpret_cast<const char*>(tw);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    C w = tw[(r * jm) << lstride];
+                    C w = *reinterpret_cast<const C*>(tb + __umul24((unsigned)r, u));
                     if (INV) w = cconj(w);
                     v[q][r] = cmul(v[q][r], w);
                 }
@@ -343,6 +346,26 @@ template <typename T>
 using vec2 = T __attribute__((ext_vector_type(2)));
 template <typename T>
 using vec4 = T __attribute__((ext_vector_type(4)));
+// a load at an unsigned 32-bit byte offset from a block-uniform base (the
+// scalar-base addressing form: no 64-bit address arithmetic per lane)
+template <typename T>
+__device__ __forceinline__ T gld_at(const T* base, unsigned byte_off) {
+    return *(const __attribute__((address_space(1))) T*)((const __attribute__((address_space(1))) char*)base + byte_off);
+}
+template <typename C>
+__device__ __forceinline__ C gldc_at(const C* base, unsigned byte_off) {
+    using T = decltype(C().x);
+    const vec2<T> v = *(const __attribute__((address_space(1))) vec2<T>*)((const __attribute__((address_space(1))) char*)base + byte_off);
+    return cmk<C>(v.x, v.y);
+}
+template <typename C>
+__device__ __forceinline__ void gstc_at(C* base, unsigned byte_off, C c) {
+    using T = decltype(C().x);
+    vec2<T> v;
+    v.x = c.x;
+    v.y = c.y;
+    *(__attribute__((address_space(1))) vec2<T>*)((__attribute__((address_space(1))) char*)base + byte_off) = v;
+}
 template <typename C>
 __device__ __forceinline__ C gld(const C* p) {
     using T = decltype(C().x);
@@ -428,17 +451,17 @@ __device__ __forceinline__ void unpack_rows_to_lds(const KParams<T>& p, const cp
     using C = cplx<T>;
     constexpr int TW = spec_tile<T>();
     const int Px = p.Px;
-    const size_t cs = (size_t)p.ktiles * p.nrows * TW;
+    const unsigned cb = (unsigned)((size_t)p.ktiles * p.nrows * TW * sizeof(C));  // component stride in bytes
     for (int k = threadIdx.x; k < Px; k += blockDim.x) {
         const bool cj = k > Px / 2;
         const int kk = cj ? Px - k : k;
-        const C* s0 = S + ((size_t)(kk / TW) * p.nrows + r0) * TW + (kk % TW);
-        C ax = gld(s0), ay = gld(s0 + cs), az = gld(s0 + 2 * cs);
+        const unsigned o = ((unsigned)(kk / TW) * (unsigned)p.nrows + (unsigned)r0) * 128u + (unsigned)(kk % TW) * (unsigned)sizeof(C);
+        C ax = gldc_at(S, o), ay = gldc_at(S, o + cb), az = gldc_at(S, o + 2 * cb);
         C bx = cmk<C>(0, 0), by = bx, bz = bx;
         if (v1) {
-            bx = gld(s0 + TW);
-            by = gld(s0 + TW + cs);
-            bz = gld(s0 + TW + 2 * cs);
+            bx = gldc_at(S, o + 128u);
+            by = gldc_at(S, o + 128u + cb);
+            bz = gldc_at(S, o + 128u + 2 * cb);
         }
         if (cj) {
             ax = cconj(ax); ay = cconj(ay); az = cconj(az);
@@ -456,7 +479,7 @@ __device__ __forceinline__ void pack_lds_to_rows(const KParams<T>& p, cplx<T>* _
     using C = cplx<T>;
     constexpr int TW = spec_tile<T>();
     const int Px = p.Px, Kx = p.Kx;
-    const size_t cs = (size_t)p.ktiles * p.nrows * TW;
+    const unsigned cb = (unsigned)((size_t)p.ktiles * p.nrows * TW * sizeof(C));  // component stride in bytes
     const T h = (T)0.5;
     for (int k = threadIdx.x; k < Kx; k += blockDim.x) {
         const int kn = (Px - k) & (Px - 1);
@@ -469,14 +492,14 @@ __device__ __forceinline__ void pack_lds_to_rows(const KParams<T>& p, cplx<T>* _
             out[2 * s] = cmk<C>(h * sum.x, h * sum.y);       // spectrum of the real part
             out[2 * s + 1] = cmk<C>(h * dif.y, -h * dif.x);  // spectrum of the imaginary part
         }
-        C* d = S + ((size_t)(k / TW) * p.nrows + r0) * TW + (k % TW);
-        gst(d, out[0]);
-        gst(d + cs, out[1]);
-        gst(d + 2 * cs, out[4]);
+        const unsigned o = ((unsigned)(k / TW) * (unsigned)p.nrows + (unsigned)r0) * 128u + (unsigned)(k % TW) * (unsigned)sizeof(C);
+        gstc_at(S, o, out[0]);
+        gstc_at(S, o + cb, out[1]);
+        gstc_at(S, o + 2 * cb, out[4]);
         if (v1) {
-            gst(d + TW, out[2]);
-            gst(d + TW + cs, out[3]);
-            gst(d + TW + 2 * cs, out[5]);
+            gstc_at(S, o + 128u, out[2]);
+            gstc_at(S, o + 128u + cb, out[3]);
+            gstc_at(S, o + 128u + 2 * cb, out[5]);
         }
     }
 }
@@ -600,17 +623,18 @@ __device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v
             }
         }
     };
+    const unsigned cb = (unsigned)(cs * sizeof(C));  // component stride in bytes (a spectrum is below 2^32 bytes)
     auto lspec = [&](int k) {
         Bin b;
         const int kk = k > Px / 2 ? Px - k : k;
-        const C* s0 = S + ((size_t)(kk / TW) * nrows + r0) * TW + (kk % TW);
-        b.a[0] = gld(s0);
-        b.a[1] = gld(s0 + cs);
-        b.a[2] = gld(s0 + 2 * cs);
+        const unsigned o = ((unsigned)(kk / TW) * (unsigned)nrows + (unsigned)r0) * 128u + (unsigned)(kk % TW) * (unsigned)sizeof(C);
+        b.a[0] = gldc_at(S, o);
+        b.a[1] = gldc_at(S, o + cb);
+        b.a[2] = gldc_at(S, o + 2 * cb);
         if (v1) {
-            b.b[0] = gld(s0 + TW);
-            b.b[1] = gld(s0 + TW + cs);
-            b.b[2] = gld(s0 + TW + 2 * cs);
+            b.b[0] = gldc_at(S, o + 128u);
+            b.b[1] = gldc_at(S, o + 128u + cb);
+            b.b[2] = gldc_at(S, o + 128u + 2 * cb);
         } else {
             b.b[0] = b.b[1] = b.b[2] = cmk<C>(0, 0);
         }
@@ -1223,26 +1247,28 @@ template <typename C, int R1>
 __device__ __forceinline__ void col2d_first(C* Z, const C* __restrict__ Sk, const C* __restrict__ Sk1, size_t cs,
                                             int ltk, int lL, int ny) {
     constexpr int LR = ilog2(R1);
-    constexpr int TW = 128 / (int)sizeof(C);
+    constexpr unsigned rb = 128;  // one row of a spectrum tile
+    const unsigned cb = (unsigned)(cs * sizeof(C));
     const int lnb = lL - LR;
     const int total = 3 << (ltk + lnb);
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
         const int tk = it & ((1 << ltk) - 1);
         const int j = (it >> ltk) & ((1 << lnb) - 1);
         const int c = it >> (ltk + lnb);
-        const C* src = Sk + (size_t)c * cs + tk;
+        // byte offsets from the block's base: component c, row y, bin tk (all below 2^32)
+        const unsigned ob = (unsigned)c * cb + (unsigned)tk * (unsigned)sizeof(C);
         C v[R1];
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
             const int y = j + (r << lnb);
-            v[r] = (r < R1 / 2 && y < ny) ? gld(src + (size_t)y * TW) : cmk<C>(0, 0);
+            v[r] = (r < R1 / 2 && y < ny) ? gldc_at(Sk, ob + (unsigned)y * rb) : cmk<C>(0, 0);
         }
         if (Sk1 != nullptr && tk == 0) {
             // the packed pair: imaginary part from bin Px/2 (its real column)
 #pragma unroll
             for (int r = 0; r < R1 / 2; ++r) {
                 const int y = j + (r << lnb);
-                if (y < ny) v[r].y = gld(Sk1 + (size_t)c * cs + (size_t)y * TW).x;
+                if (y < ny) v[r].y = gldc_at(Sk1, (unsigned)c * cb + (unsigned)y * rb).x;
             }
         }
         dft_half_in<C, false, R1>(v);
@@ -1260,7 +1286,8 @@ template <typename C, int R1>
 __device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, C* __restrict__ Sw1, size_t cs, int ltk,
                                            int lL, int ny, int kvalid, const C* __restrict__ tw) {
     constexpr int LR = ilog2(R1);
-    constexpr int TW = 128 / (int)sizeof(C);
+    constexpr unsigned rb = 128;  // one row of a spectrum tile
+    const unsigned cb = (unsigned)(cs * sizeof(C));
     const int lnb = lL - LR;
     const int total = 3 << (ltk + lnb);
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
@@ -1282,16 +1309,17 @@ __device__ __forceinline__ void col2d_last(const C* Z, C* __restrict__ Sw, C* __
             for (int r = 0; r < R1 / 2; ++r) {
                 const int y = j + (r << lnb);
                 if (y < ny) {
-                    gst(Sw + (size_t)c * cs + (size_t)y * TW, cmk<C>(v[r].x, 0));
-                    gst(Sw1 + (size_t)c * cs + (size_t)y * TW, cmk<C>(v[r].y, 0));
+                    const unsigned o = (unsigned)c * cb + (unsigned)y * rb;
+                    gstc_at(Sw, o, cmk<C>(v[r].x, 0));
+                    gstc_at(Sw1, o, cmk<C>(v[r].y, 0));
                 }
             }
         } else if (tk < kvalid) {
-            C* dst = Sw + (size_t)c * cs + tk;
+            const unsigned ob = (unsigned)c * cb + (unsigned)tk * (unsigned)sizeof(C);
 #pragma unroll
             for (int r = 0; r < R1 / 2; ++r) {
                 const int y = j + (r << lnb);
-                if (y < ny) gst(dst + (size_t)y * TW, v[r]);
+                if (y < ny) gstc_at(Sw, ob + (unsigned)y * rb, v[r]);
             }
         }
     }
@@ -1355,28 +1383,39 @@ __device__ __forceinline__ void col2d_mul(cplx<T>* Z, int TK, int ltk, int plane
     using C = cplx<T>;
     constexpr int TW = spec_tile<T>();
     const int total = Py << ltk;
-    const int cstr = Ky2 * TK;
-    const size_t gstr = (size_t)Ky2 * TW;
     const int tk0 = Nk1 != nullptr ? 1 : 0;  // the packed pair's bin is done apart
-    for (int it = threadIdx.x; it < total; it += blockDim.x) {
-        const int tk = it & (TK - 1);
-        const int ky = it >> ltk;
-        if (k0 + tk >= Kx || tk < tk0) continue;
-        const bool fy = ky > Py / 2;
-        const int kyr = fy ? Py - ky : ky;
-        auto NT = [&](int comp) -> T {
-            return nt_lds ? Nt[comp * cstr + (kyr << ltk) + tk] : glb(Nk)[comp * gstr + (size_t)kyr * TW + tk];
-        };
-        const T nxx = NT(0), nyy = NT(1), nzz = NT(2);
-        const T nxy = fy ? -NT(3) : NT(3);
-        // e < plane, a power of two: lp(c plane + e) = lp(e) + lp(c plane)
-        C* const ze = Z + lp((ky << ltk) + tk);
-        const int pp = lp(plane), pp2 = lp(2 * plane);
-        const C a = ze[0], b = ze[pp], z = ze[pp2];
-        ze[0] = cmk<C>(nxx * a.x + nxy * b.x, nxx * a.y + nxy * b.y);
-        ze[pp] = cmk<C>(nxy * a.x + nyy * b.x, nxy * a.y + nyy * b.y);
-        ze[pp2] = cmk<C>(nzz * z.x, nzz * z.y);
-    }
+    const int pp = lp(plane), pp2 = lp(2 * plane);
+    // tensor component comp of row kyr: from the LDS tile, or from memory at an
+    // unsigned 32-bit offset from the block's base (a scalar-base load)
+    auto body = [&](auto lds_c) {
+        constexpr bool LDS = decltype(lds_c)::value;
+        const unsigned cstr = LDS ? (unsigned)(Ky2 * TK) : (unsigned)(Ky2 * TW);
+        const T* __restrict__ nb = LDS ? Nt : Nk;
+        for (int it = threadIdx.x; it < total; it += blockDim.x) {
+            const int tk = it & (TK - 1);
+            const int ky = it >> ltk;
+            if (k0 + tk >= Kx || tk < tk0) continue;
+            const bool fy = ky > Py / 2;
+            const int kyr = fy ? Py - ky : ky;
+            const unsigned o = LDS ? (unsigned)((kyr << ltk) + tk) : (unsigned)(kyr * TW + tk);
+            auto NT = [&](int comp) -> T {
+                if constexpr (LDS) return nb[comp * cstr + o];
+                else return gld_at(nb, (comp * cstr + o) * (unsigned)sizeof(T));
+            };
+            const T nxx = NT(0), nyy = NT(1), nzz = NT(2);
+            const T nxy = fy ? -NT(3) : NT(3);
+            // e < plane, a power of two: lp(c plane + e) = lp(e) + lp(c plane)
+            C* const ze = Z + lp((ky << ltk) + tk);
+            const C a = ze[0], b = ze[pp], z = ze[pp2];
+            ze[0] = cmk<C>(nxx * a.x + nxy * b.x, nxx * a.y + nxy * b.y);
+            ze[pp] = cmk<C>(nxy * a.x + nyy * b.x, nxy * a.y + nyy * b.y);
+            ze[pp2] = cmk<C>(nzz * z.x, nzz * z.y);
+        }
+    };
+    if (nt_lds)
+        body(std::integral_constant<bool, true>());
+    else
+        body(std::integral_constant<bool, false>());
     if (Nk1 != nullptr) col2d_mul_pair<T>(Z, TK, plane, Py, Nt, Nk, Nk1, nt_lds, Ky2);
     __syncthreads();
 }

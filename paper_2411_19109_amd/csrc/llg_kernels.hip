@@ -215,7 +215,7 @@ __device__ __forceinline__ void dft_half_out(C* v) {
 // For disjoint bit sets (A + X) >> s = (A >> s) + (X >> s), so the pad splits
 // exactly: lp(A + X) = lp(A) + lp(X), one lane address plus a
 // block-uniform offset per point.
-template <typename C, bool INV, int R, int MAXREG>
+template <typename C, bool INV, int R, int MAXREG, bool OPQ = true>
 __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lNs, int nsig, const C* __restrict__ tw) {
     constexpr int IPT = MAXREG / R;
     constexpr int LR = ilog2(R);
@@ -226,10 +226,16 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
     const int k = sm.l0 + lnbf;
     const int mk = (1 << k) - 1, m0 = (1 << sm.l0) - 1;
     const OffRow<R> ol = lp_offsets<C, R>(k);
+    // OPQ: the thread index, opaque to the compiler.  Without it the compiler
+    // hoists every radix variant's lane addresses out of the caller's pass loop,
+    // computing (and holding registers for) those of radices that never run; a
+    // caller whose registers sit just below an occupancy step keeps the hoisting
+    int tid = (int)threadIdx.x;
+    if constexpr (OPQ) asm volatile("" : "+v"(tid));
     C v[IPT][R];
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        const int it = threadIdx.x + q * blockDim.x;
+        const int it = tid + q * blockDim.x;
         if (it < total) {
             const char* pb = reinterpret_cast<const char*>(buf + lp(((it >> k) << sm.ls1) + (it & mk)));
 #pragma unroll
@@ -242,7 +248,7 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
     const OffRow<R> os = lp_offsets<C, R>(ko);
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        const int it = threadIdx.x + q * blockDim.x;
+        const int it = tid + q * blockDim.x;
         if (it < total) {
             const int j = (it >> sm.l0) & ((1 << lnbf) - 1);
             const int jm = j & ((1 << lNs) - 1);
@@ -271,7 +277,7 @@ __device__ __forceinline__ void fft_pass(C* buf, const SigMap sm, int lL, int lN
 // Full FFT of length L (power of two) of nsig signals; tw = exp(-2 pi i k / L).
 // Passes of the largest radix the register budget allows (16 in float, 8 in
 // double) while enough points remain, then one pass of the remaining radix.
-template <typename C, bool INV, int MAXREG>
+template <typename C, bool INV, int MAXREG, bool OPQ = true>
 __device__ __forceinline__ void fft_lds(C* buf, const SigMap sm, int L, int nsig, const C* __restrict__ tw) {
     int lL = 0;
     while ((1 << lL) < L) ++lL;
@@ -280,23 +286,23 @@ __device__ __forceinline__ void fft_lds(C* buf, const SigMap sm, int L, int nsig
         const int rem = lL - lNs;
         if constexpr (MAXREG >= 16) {
             if (rem >= 4) {
-                fft_pass<C, INV, 16, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+                fft_pass<C, INV, 16, MAXREG, OPQ>(buf, sm, lL, lNs, nsig, tw);
                 lNs += 4;
                 continue;
             }
         }
         if constexpr (MAXREG >= 8) {
             if (rem >= 3) {
-                fft_pass<C, INV, 8, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+                fft_pass<C, INV, 8, MAXREG, OPQ>(buf, sm, lL, lNs, nsig, tw);
                 lNs += 3;
                 continue;
             }
         }
         if (rem >= 2) {
-            fft_pass<C, INV, 4, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+            fft_pass<C, INV, 4, MAXREG, OPQ>(buf, sm, lL, lNs, nsig, tw);
             lNs += 2;
         } else {
-            fft_pass<C, INV, 2, MAXREG>(buf, sm, lL, lNs, nsig, tw);
+            fft_pass<C, INV, 2, MAXREG, OPQ>(buf, sm, lL, lNs, nsig, tw);
             lNs += 1;
         }
     }
@@ -1662,7 +1668,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
     gather3<4, 4, 1, Unit, RUnit, C>(ncolu, lcol, scol, ntu, ltile, stile, Py, ltw, stw);
     __syncthreads();
     const SigMap smy{ilog2_rt(TK), ilog2_rt(plane)};
-    if (Py > 1) fft_lds<C, false, MR>(Z, smy, Py, 3 * nz * TK, Tw);
+    if (Py > 1) fft_lds<C, false, MR, false>(Z, smy, Py, 3 * nz * TK, Tw);
     // packed pair, 0 < ky < Py/2: A(ky) goes to position ky, B(ky) to position Py - ky
     const int hpy = Py / 2 - 1;
     if (pk && hpy > 0) {
@@ -1793,7 +1799,7 @@ __global__ void __launch_bounds__(MR >= 16 ? 512 : (NZ >= 8 ? 1024 : 768)) k_col
         }
         __syncthreads();
     }
-    if (Py > 1) fft_lds<C, true, MR>(Z, smy, Py, 3 * nz * TK, Tw);
+    if (Py > 1) fft_lds<C, true, MR, false>(Z, smy, Py, 3 * nz * TK, Tw);
     const int ltk = ilog2_rt(TK);
     const int ncolel = 3 * nz * Py * TK;
     C* __restrict__ Sw = S + (size_t)kt * p.nrows * TW + ko;

@@ -1534,6 +1534,10 @@ int create_batch(const llg_problem* probs, const llg_masks* masks, int n, llg_ha
         I.nloc = (I.nrows + 1) / 2;
         h->max_nz = std::max(h->max_nz, I.prob.nz);
         if (I.Pz > 16) return bail(fail(LLG_ESHAPE, "nz too large"));
+        // the kernels address an instance's spectrum (three components) at
+        // unsigned 32-bit byte offsets from its base
+        if ((size_t)3 * I.ktiles * I.nrows * spec_tile_of((int)h->tsz) * 2 * h->tsz >= ((size_t)1 << 32))
+            return bail(fail(LLG_ESHAPE, "spectrum of one instance exceeds 4 GiB"));
     }
     // The packed pair of the real bins pays on wide rows (its block carries a
     // second column, which on a launch of a few dozen blocks lengthens the

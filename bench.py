@@ -450,10 +450,17 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+# the launch-configuration entries each kernel class's tiling depends on
+# (column: x-bins per block, threads, radix; forward rows: threads, radix;
+# backward rows: threads, radix, staged values)
+_LAUNCH_PART = {"k_col": slice(0, 3), "k_stage_fwd": slice(3, 5), "k_stage_bwd": slice(5, 8)}
+
+
 def measured_traffic(workload, kernel, launch, source="llg_kernels.hip"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary of this workload (copy-calibrated), or None when there is
-    none or it was taken on another kernel source or launch configuration."""
+    none or it was taken on another kernel source or another tiling of this
+    kernel class."""
     path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -464,7 +471,8 @@ def measured_traffic(workload, kernel, launch, source="llg_kernels.hip"):
             rec = json.loads(line)
     if not rec or rec.get("kernel_source_sha256") != profsum.kernel_source_hash(source):
         return None
-    if rec.get("launch") is not None and list(rec["launch"]) != list(launch):
+    part = _LAUNCH_PART.get(kernel, slice(None))
+    if rec.get("launch") is not None and list(rec["launch"])[part] != list(launch)[part]:
         return None
     for name, v in rec["kernels"].items():
         base = name.split("<")[0]

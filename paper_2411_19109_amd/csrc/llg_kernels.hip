@@ -358,6 +358,20 @@ template <typename T>
 __device__ __forceinline__ T gld_at(const T* base, unsigned byte_off) {
     return *(const __attribute__((address_space(1))) T*)((const __attribute__((address_space(1))) char*)base + byte_off);
 }
+template <typename T>
+__device__ __forceinline__ void gst_at(T* base, unsigned byte_off, T v) {
+    *(__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)base + byte_off) = v;
+}
+// element i (0 <= i < 2^28) of a per-instance node array: a lane byte offset from
+// the block-uniform base
+template <typename T>
+__device__ __forceinline__ T gat(const T* base, int i) {
+    return gld_at(base, (unsigned)i * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void gput(T* base, int i, T v) {
+    gst_at(base, (unsigned)i * (unsigned)sizeof(T), v);
+}
 template <typename C>
 __device__ __forceinline__ C gldc_at(const C* base, unsigned byte_off) {
     using T = decltype(C().x);
@@ -396,6 +410,20 @@ template <typename T> __device__ __forceinline__ void st3(T* __restrict__ v, int
     g[i] = a.x;
     g[N + i] = a.y;
     g[2 * N + i] = a.z;
+}
+// The same with one lane byte offset (i < N <= 2^28, so i sizeof(T) < 2^32) from
+// three block-uniform component bases: fewer registers where many node vectors
+// are held at once (the backward stage's inputs), but a neighbour's +-1 cannot
+// fold into the instruction's offset, so stencil reads keep the indexed form.
+template <typename T> __device__ __forceinline__ V3<T> ld3u(const T* __restrict__ v, int N, int i) {
+    const unsigned o = (unsigned)i * (unsigned)sizeof(T);
+    return v3(gld_at(v, o), gld_at(v + N, o), gld_at(v + 2 * (size_t)N, o));
+}
+template <typename T> __device__ __forceinline__ void st3u(T* __restrict__ v, int N, int i, V3<T> a) {
+    const unsigned o = (unsigned)i * (unsigned)sizeof(T);
+    gst_at(v, o, a.x);
+    gst_at(v + N, o, a.y);
+    gst_at(v + 2 * (size_t)N, o, a.z);
 }
 
 // Damping of node (ix, iy, iz): linear ramp over ramp_cells nodes from each ramped face.
@@ -586,7 +614,9 @@ __device__ __forceinline__ void gather3(int na, LA&& la, SA&& sa, int nb, LB&& l
 //         rows outside the grid left unset (never read);
 //   the packed spectrum of rows r0, r0+1 (inverse-FFT input) into Z;
 //   the x twiddles into Tw.
-template <typename T, int NV>
+// SB: the staged rows are read at lane byte offsets from block-uniform bases
+// (fewer registers for the loads in flight; the backward kernel holds 28 of them)
+template <typename T, int NV, bool SB = false>
 __device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v1, bool rows, int nvu,
                                              const T* const (&src)[NV], const int (&comp)[NV], T* R,
                                              const cplx<T>* __restrict__ S, cplx<T>* Z,
@@ -613,7 +643,10 @@ __device__ __forceinline__ void stage_inputs(const KParams<T>& p, int r0, bool v
                 const int i = r * nx + x;
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
-                    if (v < nvu) n.v[q][v] = glb(src[v])[comp[v] * N + i];
+                    if (v < nvu) {
+                        if constexpr (SB) n.v[q][v] = gat(src[v] + (size_t)comp[v] * N, i);
+                        else n.v[q][v] = glb(src[v])[comp[v] * N + i];
+                    }
             }
         }
         return n;
@@ -995,21 +1028,21 @@ __device__ __forceinline__ BwdIn<T> load_bwd(const StageBwdArgs<T>& a, int N, in
     d.m = d.B = d.v = d.uk = d.lacc = d.yprev = z;
     d.g0 = 0.0;
     d.p1 = d.p2 = 0;
-    d.pi = glb(a.psi)[i];
-    d.lam = ld3(a.lamp, N, i);
+    d.pi = gat(a.psi, i);
+    d.lam = ld3u(a.lamp, N, i);
     if (!seed) {
-        d.m = ld3(a.ys, N, i);
-        d.B = ld3(a.Bs, N, i);
-        d.v = ld3(a.ell, N, i);
-        d.uk = ld3(a.u_cur, N, i);
-        d.g0 = glb(a.gpsi)[i];
-        if (a.stage < 3 && a.lacc_in) d.lacc = ld3(a.lacc_in, N, i);
+        d.m = ld3u(a.ys, N, i);
+        d.B = ld3u(a.Bs, N, i);
+        d.v = ld3u(a.ell, N, i);
+        d.uk = ld3u(a.u_cur, N, i);
+        d.g0 = gat(a.gpsi, i);
+        if (a.stage < 3 && a.lacc_in) d.lacc = ld3u(a.lacc_in, N, i);
         if (a.stage == 0 && a.port1) {
-            d.p1 = glb(a.port1)[i];
-            d.p2 = glb(a.port2)[i];
+            d.p1 = gat(a.port1, i);
+            d.p2 = gat(a.port2, i);
         }
     }
-    if (a.y_prev) d.yprev = ld3(a.y_prev, N, i);
+    if (a.y_prev) d.yprev = ld3u(a.y_prev, N, i);
     return d;
 }
 
@@ -1044,7 +1077,7 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
     {
         const T* const src[NV] = {a.u_cur, a.u_cur, a.u_cur, a.psi, a.ys, a.ys, a.ys};
         const int comp[NV] = {0, 1, 2, 0, 0, 1, 2};
-        stage_inputs<T, NV>(p, r0, v1, !seed && (p.terms & 1), nvu, src, comp, R, demag_in ? a.S : nullptr, Z,
+        stage_inputs<T, NV, true>(p, r0, v1, !seed && (p.terms & 1), nvu, src, comp, R, demag_in ? a.S : nullptr, Z,
                             demag_any ? twx : nullptr, LS.Tw);
     }
     __syncthreads();
@@ -1079,9 +1112,9 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                         ell = v3<T>(fma(c, sj.x, ell.x), fma(c, sj.y, ell.y), fma(c, sj.z, ell.z));
                     }
                 }
-                st3(a.ell, N, i, ell);
+                st3u(a.ell, N, i, ell);
                 un = field_adjoint(p, ell, d.yprev, x, iy, iz, pi);
-                st3(a.u_next, N, i, un);
+                st3u(a.u_next, N, i, un);
             } else {
                 const V3<T> m = d.m;
                 const V3<T> B = d.B;
@@ -1137,14 +1170,14 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                 }
                 // curve objective at stage 0: its explicit psi dependence, dJ/dpsi_i += c_n m_x,i - c_n M(n)
                 if (a.port1 && a.src_lin == 2) g += (double)a.src1 * (double)m.x - (double)a.src2;
-                glb(a.gpsi)[i] = d.g0 + g;
+                gput(a.gpsi, i, d.g0 + g);
                 const V3<T> lsum = (a.stage == 3 ? d.lam : d.lacc) + mu;
                 if (a.stage > 0) {
-                    st3(a.lacc_out, N, i, lsum);
+                    st3u(a.lacc_out, N, i, lsum);
                     const V3<T> ell = cl * d.lam + cm * mu;
-                    st3(a.ell, N, i, ell);
+                    st3u(a.ell, N, i, ell);
                     un = field_adjoint(p, ell, d.yprev, x, iy, iz, pi);
-                    st3(a.u_next, N, i, un);
+                    st3u(a.u_next, N, i, un);
                 } else {
                     V3<T> lam = lsum;
                     if (a.port1 && a.src_lin == 2) {
@@ -1154,12 +1187,12 @@ __global__ void __launch_bounds__(512) k_stage_bwd(const BatchArgs<T> ba, const 
                         const T src = (d.p1 ? a.src1 : (T)0) + (d.p2 ? a.src2 : (T)0);
                         lam.y = lam.y + (a.src_lin ? src : src * m.y);
                     }
-                    st3(a.lacc_out, N, i, lam);
+                    st3u(a.lacc_out, N, i, lam);
                     if (a.y_prev) {
                         const V3<T> ell = (dt / (T)6) * lam;
-                        st3(a.ell, N, i, ell);
+                        st3u(a.ell, N, i, ell);
                         un = field_adjoint(p, ell, d.yprev, x, iy, iz, pi);
-                        st3(a.u_next, N, i, un);
+                        st3u(a.u_next, N, i, un);
                     }
                 }
             }

@@ -170,7 +170,8 @@ const char* llg_version(void);
  * of the cell (float64 on the host) and its Fourier spectrum on the padded
  * grid, and copies the masks.  Blocks the host.
  * Errors: LLG_EINVAL (bad parameter), LLG_ESHAPE (grid larger than the FFT
- * kernels support), LLG_ENOMEM, LLG_EHIP. */
+ * kernels support, or a spectrum of 4 GiB or more: the kernels address it at
+ * 32-bit byte offsets), LLG_ENOMEM, LLG_EHIP. */
 int llg_create(const llg_problem* p, const llg_masks* masks, llg_handle** out);
 
 /* Free the handle and its workspace (synchronises the device).  NULL is a
